@@ -1,0 +1,179 @@
+/*
+ * bridges.h -- C ABI of libbridges: bridges of a multigraph through sparse
+ * 2-edge-connectivity certificates, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method (Kumar & Singh, "An Efficient Parallel Algorithm for finding Bridges
+ * in a Dense Graph"):
+ *   - a bridge is an edge whose removal increases the number of connected
+ *     components (Section I);
+ *   - the edge list is split into M sets; each set's certificate is a spanning
+ *     forest F plus a spanning forest F' of the remaining edges
+ *     (Algorithm 2, Section IV-B), at most 2(V-1) edges (Lemma 1, Section III);
+ *   - the M certificates are merged pairwise in ceil(log2 M) rounds, each merge
+ *     being the certificate of the union of two certificates (Section III);
+ *   - the bridges of the final certificate, found by a depth-first search
+ *     (Algorithm 1, Section IV-A), are the bridges of the input.
+ *
+ * Conventions for every entry point
+ *   - Vertex ids are int32 in [0, V) with 1 <= V <= 2^31 - 1.
+ *   - An edge list is int32 [E][2] (array of pairs, 8 bytes per edge), each
+ *     undirected edge listed once in either orientation.  Self-loops are
+ *     accepted and never bridges; parallel edges are accepted (multigraph:
+ *     an edge with a parallel copy is never a bridge).
+ *   - Edge counts, capacities and offsets are int64.
+ *   - "d_" pointers are device memory on the context's device, "h_" pointers
+ *     are host memory.  The caller owns every buffer it passes; the library
+ *     never frees or retains them past the call (the server copies what it
+ *     keeps).  The library owns its workspace.
+ *   - A stream argument is a hipStream_t passed as void* (NULL = the null
+ *     stream).  Calls marked "asynchronous" enqueue work on it and return;
+ *     calls marked "synchronous" return after the result is on the host.
+ *   - Return value: BR_OK or a negative BR_E* code; br_last_error() then
+ *     gives a message (thread-local).  Nothing is thrown across the ABI.
+ *   - A context is used by one host thread at a time.
+ *   - Results are canonical: bridges as (min, max) pairs sorted ascending.
+ */
+#ifndef PAPER_2108_07346_BRIDGES_H
+#define PAPER_2108_07346_BRIDGES_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BR_OK 0
+#define BR_EINVAL (-1)    /* null pointer, V < 1, E < 0, M < 1, bad sizes          */
+#define BR_ERANGE (-2)    /* an edge has a vertex id outside [0, V)                 */
+#define BR_ENOMEM (-3)    /* device or host allocation failed                       */
+#define BR_EHIP (-4)      /* a HIP runtime call failed (message names it)           */
+#define BR_EBUSY (-5)     /* server queue full / ticket not finished                */
+#define BR_ECAP (-6)      /* output capacity too small; required size reported      */
+#define BR_EINTERNAL (-7) /* an impossible state was detected (a bug)               */
+
+typedef struct br_ctx br_ctx;
+
+/* Message describing the last failure on this host thread ("" if none). */
+const char* br_last_error(void);
+
+/* Create a context on HIP device `device`.  Owns a growable device workspace,
+ * pinned host staging and the host search buffers. */
+int br_create(br_ctx** ctx, int device);
+int br_destroy(br_ctx* ctx);
+
+/*
+ * br_cert_build -- certificate of a whole edge list through the M-chunk phase
+ * tree (Section III; Algorithm 2 per chunk and per merge).
+ *   d_edges   device int32 [E][2]; chunk i is edges [floor(iE/M), floor((i+1)E/M)),
+ *             M may exceed E (then some chunks are empty).
+ *   d_cert    device int32 [cert_cap][2]; receives F (spanning forest of the
+ *             input) first, then F' (a spanning forest of the edges the merges
+ *             left outside F).  cert_cap >= min(E, 2(V-1)) always suffices.
+ *   d_counts  device int64 [3]: |F|, |F'|, status (BR_OK, or BR_ERANGE if an
+ *             id was out of range; the other values are then meaningless).
+ * Asynchronous.  Returns BR_EINVAL / BR_ECAP (cert_cap too small) / BR_ENOMEM /
+ * BR_EHIP before enqueueing anything.
+ */
+int br_cert_build(br_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t V, int32_t M, int32_t* d_cert,
+                  int64_t cert_cap, int64_t* d_counts, void* stream);
+
+/*
+ * br_cert_merge -- certificate of the union of two edge lists, the merge step
+ * of Section III (usually both lists are certificates; any lists work).
+ *   d_a [Ea][2], d_b [Eb][2], d_out [cap][2], d_counts [3] as for br_cert_build.
+ *   cap >= min(Ea + Eb, 2(V-1)) always suffices.
+ * Asynchronous; errors as for br_cert_build.
+ */
+int br_cert_merge(br_ctx* ctx, const int32_t* d_a, int64_t Ea, const int32_t* d_b, int64_t Eb, int32_t V,
+                  int32_t* d_out, int64_t cap, int64_t* d_counts, void* stream);
+
+/*
+ * br_bridges_find -- the whole path: certificate over M chunks (as
+ * br_cert_build), then Algorithm 1's depth-first search on the final
+ * certificate (on the host, in this library), then canonical order.
+ *   h_bridges host int32 [cap][2]; cap >= V-1 always suffices.
+ *   *n_bridges number of bridges; if it exceeds cap the call returns BR_ECAP
+ *              and writes no pairs.
+ * Synchronous with respect to `stream`.  BR_ERANGE if an id is out of range.
+ */
+int br_bridges_find(br_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t V, int32_t M, int32_t* h_bridges,
+                    int64_t cap, int64_t* n_bridges, void* stream);
+
+/*
+ * br_bridges_find_batched -- br_bridges_find over G independent graphs in one
+ * launch of a persistent kernel (replayed from a captured HIP graph when the
+ * same batch shape repeats).
+ *   d_edges     device int32 [h_edge_off[G]][2], graph g's edges at
+ *               [h_edge_off[g], h_edge_off[g+1]) with graph-local ids in [0, h_V[g]).
+ *   h_edge_off  host int64 [G+1], non-decreasing, h_edge_off[0] = 0.
+ *   h_V         host int32 [G], each >= 1.
+ *   chunk_edges edges per work item (0 = chosen by the built-in tuner).
+ *   h_bridges   host int32 [cap][2]; graph g's bridges at
+ *               [h_bridge_off[g], h_bridge_off[g+1]), canonical per graph.
+ *   h_bridge_off host int64 [G+1].
+ * Synchronous.  BR_ECAP if cap < total bridges (h_bridge_off is still filled).
+ * Graphs with V above the library's in-LDS limit (br_batched_max_v()) are
+ * processed through br_bridges_find inside the call.
+ */
+int br_bridges_find_batched(br_ctx* ctx, const int32_t* d_edges, const int64_t* h_edge_off, const int32_t* h_V,
+                            int32_t G, int32_t chunk_edges, int32_t* h_bridges, int64_t cap, int64_t* h_bridge_off,
+                            void* stream);
+int32_t br_batched_max_v(void);
+
+/*
+ * Phase timings of the last br_bridges_find / br_bridges_find_batched on this
+ * context, in milliseconds, measured with HIP events on the call's stream
+ * (device phases) and a steady clock (host phases).  Filled only when
+ * profiling is enabled with br_set_profiling(ctx, 1) (it adds event records).
+ */
+typedef struct br_profile {
+    double ms_phase0;      /* per-chunk certificate kernel (Section III, phase 0) */
+    double ms_merge;       /* all merge rounds                                     */
+    double ms_cert;        /* whole device part incl. workspace clears            */
+    double ms_d2h;         /* certificate copy to the host                        */
+    double ms_dfs;         /* Algorithm 1 on the certificate, host                */
+    double ms_canon;       /* canonical order                                     */
+    double ms_total;       /* wall clock of the whole call                        */
+    int64_t cert_f1, cert_f2;  /* |F|, |F'| of the final certificate              */
+    int64_t rounds;        /* merge rounds run                                    */
+    int64_t launches;      /* kernel launches                                     */
+} br_profile;
+int br_set_profiling(br_ctx* ctx, int on);
+int br_get_profile(br_ctx* ctx, br_profile* out);
+
+/*
+ * Serving: continuous batching of bridge queries on one device.
+ *   br_server_create  device, device-memory budget in bytes for resident
+ *                     requests (edge lists, union-find state, certificates),
+ *                     max_slots requests in flight on the device at once.
+ *   br_submit         copies h_edges [E][2] (ids in [0,V)) into a host queue
+ *                     and returns a ticket; the request is admitted to the
+ *                     device when a slot and budget free up.  BR_EBUSY if the
+ *                     bounded queue is full; BR_ENOMEM if it can never fit.
+ *   br_poll           *done = 1 when finished; then copies the bridges into
+ *                     h_out [cap][2], sets *n, and releases the ticket
+ *                     (BR_ECAP with *n set if cap is too small; the ticket
+ *                     stays).  *done = 0 otherwise.
+ *   br_wait           blocks until done, then as br_poll.
+ *   br_server_stats   latency percentiles (submit to done, ms) over the
+ *                     requests finished since the last reset.
+ * Submit/poll/wait may be called from several host threads.
+ */
+typedef struct br_server br_server;
+typedef struct br_server_stats_t {
+    int64_t completed;
+    double p50_ms, p99_ms, mean_ms, max_ms;
+    double edges_per_s;    /* edges of completed requests / busy wall time */
+    int64_t peak_inflight; /* most requests resident on the device at once */
+} br_server_stats_t;
+int br_server_create(br_server** srv, int device, int64_t mem_budget, int32_t max_slots);
+int br_submit(br_server* srv, const int32_t* h_edges, int64_t E, int32_t V, uint64_t* ticket);
+int br_poll(br_server* srv, uint64_t ticket, int32_t* h_out, int64_t cap, int64_t* n, int* done);
+int br_wait(br_server* srv, uint64_t ticket, int32_t* h_out, int64_t cap, int64_t* n);
+int br_server_stats(br_server* srv, br_server_stats_t* out, int reset);
+int br_server_destroy(br_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

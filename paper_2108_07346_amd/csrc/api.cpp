@@ -1,0 +1,341 @@
+// C ABI of libbridges: contexts, workspace, the phase tree orchestration
+// (paper, Section III) and the synchronous bridge query.
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "internal.hpp"
+
+namespace br {
+
+static thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    (void)hipGetLastError();
+    return fail(e == hipErrorOutOfMemory ? BR_ENOMEM : BR_EHIP, "%s failed: %s", what, hipGetErrorString(e));
+}
+
+int32_t block_size();
+
+Plan make_plan(int64_t E, int32_t V, int32_t M) {
+    Plan P;
+    P.E = E;
+    P.V = V;
+    P.M = M;
+    while ((int64_t(1) << P.rounds) < M) P.rounds++;
+    P.tile = 4096;
+    const int64_t per = (E + M - 1) / M;   // largest chunk
+    P.tpc = (int32_t)std::max<int64_t>(1, (per + P.tile - 1) / P.tile);
+    P.xcd_map = M >= 8 ? 1 : 0;
+    const int64_t chunk_slots = P.xcd_map ? 8 * ((M + 7) / 8) : M;
+    P.blocks0 = E > 0 ? chunk_slots * P.tpc : 0;
+    auto lo = [&](int64_t i) { return i * (E / M) + (i * (E % M)) / M; };
+    const int64_t bound = 2 * (int64_t(V) - 1);
+    P.off.resize(M);
+    P.cap.resize(M);
+    int64_t acc = 0;
+    for (int64_t i = 0; i < M; i++) {
+        int64_t span = M;   // node 0 ends up covering every chunk
+        if (i != 0) {
+            int z = __builtin_ctzll((unsigned long long)i);
+            span = std::min<int64_t>(int64_t(1) << z, M - i);
+        }
+        const int64_t edges = lo(std::min<int64_t>(M, i + span)) - lo(i);
+        P.cap[i] = std::min(edges, bound);
+        P.off[i] = acc;
+        acc += P.cap[i];
+    }
+    P.cert_pairs = acc;
+    return P;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int ensure_workspace(br_ctx* c, size_t bytes, hipStream_t s) {
+    if (c->ws.size >= bytes) return BR_OK;
+    size_t want = std::max(bytes, c->ws.size + c->ws.size / 4);
+    BR_HIP(hipStreamSynchronize(s));
+    if (c->ws.base) BR_HIP(hipFree(c->ws.base));
+    c->ws.base = nullptr;
+    c->ws.size = 0;
+    hipError_t e = hipMalloc(&c->ws.base, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        e = hipMalloc(&c->ws.base, bytes);
+        want = bytes;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(workspace)");
+    c->ws.size = want;
+    return BR_OK;
+}
+
+int ensure_pinned(br_ctx* c, size_t bytes) {
+    if (c->pinned_size >= bytes) return BR_OK;
+    if (c->pinned) BR_HIP(hipHostFree(c->pinned));
+    c->pinned = nullptr;
+    c->pinned_size = 0;
+    BR_HIP(hipHostMalloc(&c->pinned, bytes, hipHostMallocDefault));
+    c->pinned_size = bytes;
+    return BR_OK;
+}
+
+// Workspace layout: [err | cnt | state | cert | off | cap]
+struct Layout {
+    size_t err, cnt, state, cert, off, cap, total;
+};
+static Layout layout(const Plan& P) {
+    Layout L;
+    size_t o = 0;
+    L.err = o; o += 256;
+    L.cnt = o; o = align256(o + sizeof(uint32_t) * 2 * (size_t)P.M);
+    L.state = o; o = align256(o + sizeof(uint32_t) * 2 * (size_t)P.V * (size_t)P.M);
+    L.cert = o; o = align256(o + sizeof(int2) * (size_t)std::max<int64_t>(P.cert_pairs, 1));
+    L.off = o; o = align256(o + sizeof(int64_t) * (size_t)P.M);
+    L.cap = o; o = align256(o + sizeof(int64_t) * (size_t)P.M);
+    L.total = o;
+    return L;
+}
+
+static void ev_record(br_ctx* c, int k, hipStream_t s) {
+    if (c->profiling) (void)hipEventRecord(c->ev[k], s);
+}
+static double ev_ms(br_ctx* c, int a, int b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev[a], c->ev[b]) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0.0;
+    }
+    return ms;
+}
+
+int run_certificate(br_ctx* c, const int32_t* d_a, int64_t Ea, const int32_t* d_b, int64_t Eb, int32_t V, int32_t M,
+                    hipStream_t s, Plan& P, DevBufs& B) {
+    const int64_t E = Ea + Eb;
+    P = make_plan(E, V, M);
+    const Layout L = layout(P);
+    int rc = ensure_workspace(c, L.total, s);
+    if (rc) return rc;
+    rc = ensure_pinned(c, 64 << 10);
+    if (rc) return rc;
+    char* base = static_cast<char*>(c->ws.base);
+    B.edges = reinterpret_cast<const int2*>(d_a);
+    B.edges2 = reinterpret_cast<const int2*>(d_b);
+    B.split = Ea;
+    B.err = reinterpret_cast<uint32_t*>(base + L.err);
+    B.cnt = reinterpret_cast<uint32_t*>(base + L.cnt);
+    B.state = reinterpret_cast<uint32_t*>(base + L.state);
+    B.cert = reinterpret_cast<int2*>(base + L.cert);
+    B.off = reinterpret_cast<const int64_t*>(base + L.off);
+    B.cap = reinterpret_cast<const int64_t*>(base + L.cap);
+    // node regions: staged through pinned memory (the previous call's copy has
+    // completed: every entry point ends with a stream synchronisation or an
+    // event wait on the staging copy)
+    const size_t meta = sizeof(int64_t) * 2 * (size_t)M;
+    if (c->h_meta_n < 2 * (size_t)M) {
+        if (c->h_meta) BR_HIP(hipHostFree(c->h_meta));
+        c->h_meta = nullptr;
+        c->h_meta_n = 0;
+        BR_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_meta), meta, hipHostMallocDefault));
+        c->h_meta_n = 2 * (size_t)M;
+    }
+    std::memcpy(c->h_meta, P.off.data(), sizeof(int64_t) * M);
+    std::memcpy(c->h_meta + M, P.cap.data(), sizeof(int64_t) * M);
+    ev_record(c, 0, s);
+    BR_HIP(hipMemcpyAsync(base + L.off, c->h_meta, sizeof(int64_t) * M, hipMemcpyHostToDevice, s));
+    BR_HIP(hipMemcpyAsync(base + L.cap, c->h_meta + M, sizeof(int64_t) * M, hipMemcpyHostToDevice, s));
+    BR_HIP(hipEventRecord(c->ev[7], s));
+    // all-singleton forests, zero counters and error word
+    BR_HIP(hipMemsetAsync(base, 0, L.cert, s));
+    c->prof.launches = 1;
+    ev_record(c, 1, s);
+    launch_phase0(P, B, s);
+    BR_HIP(hipGetLastError());
+    ev_record(c, 2, s);
+    for (int32_t step = 1; step < M; step *= 2) {
+        launch_merge_round(P, B, step, s);
+        BR_HIP(hipGetLastError());
+        c->prof.launches++;
+    }
+    ev_record(c, 3, s);
+    c->prof.rounds = P.rounds;
+    return BR_OK;
+}
+
+}  // namespace br
+
+using namespace br;
+
+extern "C" {
+
+const char* br_last_error(void) { return g_err; }
+
+int br_create(br_ctx** out, int device) {
+    if (!out) return fail(BR_EINVAL, "br_create: null output pointer");
+    int n = 0;
+    BR_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(BR_EINVAL, "br_create: device %d not in [0,%d)", device, n);
+    BR_HIP(hipSetDevice(device));
+    br_ctx* c = new br_ctx();
+    c->device = device;
+    for (auto& e : c->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            delete c;
+            return hip_fail(hipGetLastError(), "hipEventCreate");
+        }
+    }
+    *out = c;
+    return BR_OK;
+}
+
+int br_destroy(br_ctx* c) {
+    if (!c) return BR_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    br::batched_release(c);
+    if (c->ws.base) (void)hipFree(c->ws.base);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->h_meta) (void)hipHostFree(c->h_meta);
+    for (auto& e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete c;
+    return BR_OK;
+}
+
+int br_set_profiling(br_ctx* c, int on) {
+    if (!c) return fail(BR_EINVAL, "br_set_profiling: null context");
+    c->profiling = on ? 1 : 0;
+    return BR_OK;
+}
+
+int br_get_profile(br_ctx* c, br_profile* out) {
+    if (!c || !out) return fail(BR_EINVAL, "br_get_profile: null argument");
+    *out = c->prof;
+    return BR_OK;
+}
+
+static int check_common(const void* edges, int64_t E, int32_t V) {
+    if (E < 0) return fail(BR_EINVAL, "E = %lld < 0", (long long)E);
+    if (V < 1) return fail(BR_EINVAL, "V = %d < 1", V);
+    if (E > 0 && !edges) return fail(BR_EINVAL, "null edge list with E = %lld", (long long)E);
+    return BR_OK;
+}
+
+int br_cert_build(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int32_t M, int32_t* d_cert,
+                  int64_t cert_cap, int64_t* d_counts, void* stream) {
+    if (!c || !d_counts || (!d_cert && cert_cap > 0)) return fail(BR_EINVAL, "br_cert_build: null argument");
+    int rc = check_common(d_edges, E, V);
+    if (rc) return rc;
+    if (M < 1) return fail(BR_EINVAL, "M = %d < 1", M);
+    if (cert_cap < 0) return fail(BR_EINVAL, "cert_cap < 0");
+    const int64_t need = std::min<int64_t>(E, 2 * (int64_t(V) - 1));
+    if (cert_cap < need)
+        return fail(BR_ECAP, "br_cert_build: cert_cap %lld < min(E, 2(V-1)) = %lld", (long long)cert_cap,
+                    (long long)need);
+    BR_HIP(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    BR_HIP(hipEventSynchronize(c->ev[7]));
+    Plan P;
+    DevBufs B;
+    rc = run_certificate(c, d_edges, E, nullptr, 0, V, M, s, P, B);
+    if (rc) return rc;
+    launch_copy_out(P, B, d_cert, cert_cap, d_counts, s);
+    BR_HIP(hipGetLastError());
+    return BR_OK;
+}
+
+int br_cert_merge(br_ctx* c, const int32_t* d_a, int64_t Ea, const int32_t* d_b, int64_t Eb, int32_t V,
+                  int32_t* d_out, int64_t cap, int64_t* d_counts, void* stream) {
+    if (!c || !d_counts || (!d_out && cap > 0)) return fail(BR_EINVAL, "br_cert_merge: null argument");
+    if (Ea < 0 || Eb < 0) return fail(BR_EINVAL, "negative edge count");
+    if ((Ea > 0 && !d_a) || (Eb > 0 && !d_b)) return fail(BR_EINVAL, "null edge list");
+    if (V < 1) return fail(BR_EINVAL, "V = %d < 1", V);
+    const int64_t need = std::min<int64_t>(Ea + Eb, 2 * (int64_t(V) - 1));
+    if (cap < need)
+        return fail(BR_ECAP, "br_cert_merge: cap %lld < min(Ea+Eb, 2(V-1)) = %lld", (long long)cap,
+                    (long long)need);
+    BR_HIP(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    BR_HIP(hipEventSynchronize(c->ev[7]));
+    // Certificate(A u B): one fused pass over the concatenation (Section III's
+    // merge step re-runs the certificate algorithm on the union).
+    Plan P;
+    DevBufs B;
+    int rc = run_certificate(c, d_a, Ea, d_b, Eb, V, 1, s, P, B);
+    if (rc) return rc;
+    launch_copy_out(P, B, d_out, cap, d_counts, s);
+    BR_HIP(hipGetLastError());
+    return BR_OK;
+}
+
+int br_bridges_find(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int32_t M, int32_t* h_bridges,
+                    int64_t cap, int64_t* n_bridges, void* stream) {
+    if (!c || !n_bridges || (!h_bridges && cap > 0)) return fail(BR_EINVAL, "br_bridges_find: null argument");
+    int rc = check_common(d_edges, E, V);
+    if (rc) return rc;
+    if (M < 1) return fail(BR_EINVAL, "M = %d < 1", M);
+    if (cap < 0) return fail(BR_EINVAL, "cap < 0");
+    if (V > (1 << 29)) return fail(BR_EINVAL, "V = %d above the host search limit 2^29", V);
+    auto t0 = std::chrono::steady_clock::now();
+    BR_HIP(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    BR_HIP(hipEventSynchronize(c->ev[7]));
+    Plan P;
+    DevBufs B;
+    rc = run_certificate(c, d_edges, E, nullptr, 0, V, M, s, P, B);
+    if (rc) return rc;
+    // node 0's whole region plus its counters and the error word
+    const int64_t cap0 = P.cap[0];
+    const size_t need = sizeof(int2) * (size_t)std::max<int64_t>(cap0, 1) + 64;
+    rc = ensure_pinned(c, need);
+    if (rc) return rc;
+    char* h = static_cast<char*>(c->pinned);
+    uint32_t* hc = reinterpret_cast<uint32_t*>(h);
+    int2* hx = reinterpret_cast<int2*>(h + 64);
+    BR_HIP(hipMemcpyAsync(hc, B.cnt, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    BR_HIP(hipMemcpyAsync(hc + 2, B.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    if (cap0 > 0) BR_HIP(hipMemcpyAsync(hx, B.cert + P.off[0], sizeof(int2) * cap0, hipMemcpyDeviceToHost, s));
+    ev_record(c, 4, s);
+    BR_HIP(hipStreamSynchronize(s));
+    auto t1 = std::chrono::steady_clock::now();
+    const uint32_t n1 = hc[0], n2 = hc[1], err = hc[2];
+    if (err & 1u) return fail(BR_ERANGE, "br_bridges_find: an edge has a vertex id outside [0, %d)", V);
+    if (err != 0 || (int64_t)n1 + n2 > cap0)
+        return fail(BR_EINTERNAL, "br_bridges_find: certificate region overflow (|F|=%u |F'|=%u cap=%lld)", n1, n2,
+                    (long long)cap0);
+    c->keys.clear();
+    certificate_bridges(hx, n1, hx + cap0 - n2, n2, V, c->dfs, c->keys);
+    auto t2 = std::chrono::steady_clock::now();
+    canonical_sort(c->keys);
+    auto t3 = std::chrono::steady_clock::now();
+    const int64_t nb = (int64_t)c->keys.size();
+    *n_bridges = nb;
+    if (c->profiling) {
+        c->prof.ms_phase0 = ev_ms(c, 1, 2);
+        c->prof.ms_merge = ev_ms(c, 2, 3);
+        c->prof.ms_cert = ev_ms(c, 0, 3);
+        c->prof.ms_d2h = ev_ms(c, 3, 4);
+        c->prof.cert_f1 = n1;
+        c->prof.cert_f2 = n2;
+    }
+    c->prof.ms_dfs = std::chrono::duration<double, std::milli>(t2 - t1).count();
+    c->prof.ms_canon = std::chrono::duration<double, std::milli>(t3 - t2).count();
+    c->prof.ms_total = std::chrono::duration<double, std::milli>(t3 - t0).count();
+    if (nb > cap) return fail(BR_ECAP, "br_bridges_find: %lld bridges, capacity %lld", (long long)nb, (long long)cap);
+    for (int64_t i = 0; i < nb; i++) {
+        h_bridges[2 * i] = (int32_t)(c->keys[i] >> 32);
+        h_bridges[2 * i + 1] = (int32_t)(c->keys[i] & 0xffffffffu);
+    }
+    return BR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,249 @@
+// Certificate kernels for gfx950: per-chunk certificates (phase 0) and the
+// pairwise merge rounds of the phase tree (paper, Section III; Algorithm 2).
+//
+// Union-find state.  For every vertex x and forest f (0 = F, 1 = F') one
+// 32-bit word q[2x+f] holds x - parent(x); 0 marks a root, so a zero-filled
+// buffer is the all-singletons state.  Parents always have smaller ids than
+// their children (a root is hooked under the smaller root), which makes
+// every pointer chain strictly decreasing and the structure acyclic.
+//
+// Concurrency.  Many lanes update one chunk's state at once.  Lanes read
+// parent words with plain cached loads; any value they see, however stale,
+// names a vertex of the same component with a smaller id (components only
+// merge, and a word only ever moves to a smaller parent).  So two finds that
+// meet prove the endpoints connected: a rejected edge is never wrongly
+// rejected.  An edge is accepted only by a compare-and-swap that turns a
+// current root into a child of the other endpoint's representative, which
+// merges two distinct components (the representative cannot lie below the
+// root: chains only decrease).  A failed swap returns the root's new parent
+// and the search continues from there, so the larger of the two ids strictly
+// decreases each retry and the loop ends.  Per edge this is one fused pass:
+// offered to F, and if F rejects it, offered to F' (F' is then a maximal
+// forest of the edges F rejected, as Algorithm 2 requires).
+//
+// Certificate regions.  Node i owns pairs [off[i], off[i] + cap[i]); accepted
+// F edges are appended from the front, F' edges from the back, each through
+// one atomic add per wavefront (ballot + popcount + lane rank).
+
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace br {
+
+namespace {
+
+constexpr int kBlock = 512;
+
+__device__ __forceinline__ uint32_t ld(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+__device__ __forceinline__ void st(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+__device__ __forceinline__ uint64_t ld2(const uint32_t* p) {
+    return __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// representative of x in forest F (path halving on the way)
+template <int F>
+__device__ __forceinline__ uint32_t uf_find(uint32_t* q, uint32_t x) {
+    uint32_t d = ld(q + 2 * (size_t)x + F);
+    while (d != 0) {
+        const uint32_t p = x - d;
+        const uint32_t dp = ld(q + 2 * (size_t)p + F);
+        if (dp == 0) return p;
+        st(q + 2 * (size_t)x + F, d + dp);   // x now points at its grandparent
+        x = p - dp;
+        d = ld(q + 2 * (size_t)x + F);
+    }
+    return x;
+}
+
+// true iff this call merged the components of u and v in forest F
+template <int F>
+__device__ __forceinline__ bool uf_unite(uint32_t* q, uint32_t u, uint32_t v) {
+    for (;;) {
+        u = uf_find<F>(q, u);
+        v = uf_find<F>(q, v);
+        if (u == v) return false;
+        if (u < v) { const uint32_t t = u; u = v; v = t; }
+        uint32_t expect = 0;
+        if (__hip_atomic_compare_exchange_strong(q + 2 * (size_t)u + F, &expect, u - v, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            return true;
+        u = u - expect;   // u was hooked meanwhile: continue from its parent
+    }
+}
+
+// Offer edge (u,v) to F, then (if rejected) to F'.  s1u.. are the endpoints'
+// parent words loaded together (one 8-byte load per endpoint).
+__device__ __forceinline__ void offer(uint32_t* q, uint32_t u, uint32_t v, bool& a1, bool& a2) {
+    const uint64_t su = ld2(q + 2 * (size_t)u), sv = ld2(q + 2 * (size_t)v);
+    const uint32_t p1u = u - (uint32_t)su, p1v = v - (uint32_t)sv;
+    a1 = (p1u != p1v) && uf_unite<0>(q, p1u, p1v);
+    a2 = false;
+    if (!a1) {
+        const uint32_t p2u = u - (uint32_t)(su >> 32), p2v = v - (uint32_t)(sv >> 32);
+        a2 = (p2u != p2v) && uf_unite<1>(q, p2u, p2v);
+    }
+}
+
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Append accepted edges of this wavefront to node `node`'s regions.  Every lane
+// of the wavefront must call this (ballots).
+__device__ __forceinline__ void append(const DevBufs& B, int32_t node, bool a1, bool a2, int2 e) {
+    const uint64_t m1 = __ballot(a1), m2 = __ballot(a2);
+    if ((m1 | m2) == 0) return;
+    const int64_t off = B.off[node], cap = B.cap[node];
+    const int lane = __lane_id();
+    if (m1) {
+        const int leader = __ffsll((unsigned long long)m1) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(B.cnt + 2 * node, (uint32_t)__popcll(m1));
+        base = __shfl(base, leader);
+        if (a1) {
+            const int64_t pos = (int64_t)base + lane_rank(m1);
+            if (pos < cap) B.cert[off + pos] = e;
+            else atomicOr(B.err, 2u);
+        }
+    }
+    if (m2) {
+        const int leader = __ffsll((unsigned long long)m2) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(B.cnt + 2 * node + 1, (uint32_t)__popcll(m2));
+        base = __shfl(base, leader);
+        if (a2) {
+            const int64_t pos = (int64_t)base + lane_rank(m2);
+            if (pos < cap) B.cert[off + cap - 1 - pos] = e;
+            else atomicOr(B.err, 2u);
+        }
+    }
+}
+
+__device__ __forceinline__ int64_t chunk_lo(int64_t E, int32_t M, int64_t i) {
+    // floor(i*E/M) without overflow: i*(E/M) + floor(i*(E%M)/M)
+    return i * (E / M) + (i * (E % M)) / M;
+}
+
+// Phase 0: workgroup b certifies one tile of one chunk into that chunk's state.
+__global__ void __launch_bounds__(kBlock) k_phase0(DevBufs B, int64_t E, int32_t V, int32_t M, int32_t tile,
+                                                   int32_t tpc, int32_t xcd_map) {
+    int64_t c, s;
+    const int64_t b = blockIdx.x;
+    if (xcd_map) {       // chunk c lives on XCD c % 8: blocks b with b % 8 == c % 8
+        const int64_t j = b >> 3;
+        c = (b & 7) + 8 * (j / tpc);
+        s = j % tpc;
+    } else {
+        c = b / tpc;
+        s = b % tpc;
+    }
+    if (c >= M) return;
+    const int64_t lo = chunk_lo(E, M, c), hi = chunk_lo(E, M, c + 1);
+    const int64_t t0 = lo + s * (int64_t)tile;
+    const int64_t t1 = min(t0 + (int64_t)tile, hi);
+    if (t0 >= t1) return;
+    uint32_t* q = B.state + (size_t)c * 2 * (size_t)V;
+    for (int64_t base = t0; base < t1; base += kBlock) {
+        const int64_t i = base + threadIdx.x;
+        bool a1 = false, a2 = false;
+        int2 e = make_int2(0, 0);
+        if (i < t1) {
+            e = i < B.split ? B.edges[i] : B.edges2[i - B.split];
+            if ((uint32_t)e.x < (uint32_t)V && (uint32_t)e.y < (uint32_t)V) offer(q, (uint32_t)e.x, (uint32_t)e.y, a1, a2);
+            else atomicOr(B.err, 1u);
+        }
+        append(B, (int32_t)c, a1, a2, e);
+    }
+}
+
+// One merge round with partner distance `step`: node i (i % 2step == 0) keeps
+// its union-find state (which encodes exactly its F and F') and streams the
+// certificate of node i+step through it; the accepted edges extend node i's F
+// and F'.  This equals recomputing the certificate of the union with node i's
+// edges offered first.
+__global__ void __launch_bounds__(kBlock) k_merge(DevBufs B, int32_t V, int32_t M, int32_t step, int32_t tile,
+                                                  int32_t tpm) {
+    const int64_t m = blockIdx.x / tpm, s = blockIdx.x % tpm;
+    const int64_t i = m * 2 * (int64_t)step, j = i + step;
+    if (j >= M) return;
+    const int64_t offj = B.off[j], capj = B.cap[j];
+    // counters past the region mean an overflow already flagged in B.err; clamp
+    // so that no read leaves node j's region
+    const int64_t n1 = min((int64_t)B.cnt[2 * j], capj), n2 = min((int64_t)B.cnt[2 * j + 1], capj - n1);
+    const int64_t total = n1 + n2;
+    const int64_t t0 = s * (int64_t)tile, t1 = min(t0 + (int64_t)tile, total);
+    if (t0 >= t1) return;
+    uint32_t* q = B.state + (size_t)i * 2 * (size_t)V;
+    for (int64_t base = t0; base < t1; base += kBlock) {
+        const int64_t k = base + threadIdx.x;
+        bool a1 = false, a2 = false;
+        int2 e = make_int2(0, 0);
+        if (k < t1) {
+            e = B.cert[k < n1 ? offj + k : offj + capj - n2 + (k - n1)];
+            offer(q, (uint32_t)e.x, (uint32_t)e.y, a1, a2);
+        }
+        append(B, (int32_t)i, a1, a2, e);
+    }
+}
+
+// Node 0's certificate -> caller's buffer (F then F'), plus counts and status.
+__global__ void k_copy_out(DevBufs B, int2* out, int64_t out_cap, int64_t* counts) {
+    const int64_t n1 = B.cnt[0], n2 = B.cnt[1], cap = B.cap[0], off = B.off[0];
+    const uint32_t err = *B.err;
+    const bool ok = err == 0 && n1 + n2 <= cap && n1 + n2 <= out_cap;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; ok && k < n1 + n2;
+         k += (int64_t)gridDim.x * blockDim.x)
+        out[k] = B.cert[k < n1 ? off + k : off + cap - n2 + (k - n1)];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        counts[0] = n1;
+        counts[1] = n2;
+        counts[2] = (err & 1u) ? BR_ERANGE : ((err != 0 || n1 + n2 > cap) ? BR_EINTERNAL : (n1 + n2 > out_cap ? BR_ECAP : BR_OK));
+    }
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        p[k] = v;
+}
+
+}  // namespace
+
+void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
+    if (n <= 0) return;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+}
+
+void launch_phase0(const Plan& P, const DevBufs& B, hipStream_t s) {
+    if (P.blocks0 == 0) return;
+    hipLaunchKernelGGL(k_phase0, dim3((unsigned)P.blocks0), dim3(kBlock), 0, s, B, P.E, P.V, P.M, P.tile, P.tpc,
+                       P.xcd_map);
+}
+
+void launch_merge_round(const Plan& P, const DevBufs& B, int32_t step, hipStream_t s) {
+    const int64_t merges = (P.M - step - 1) / (2 * (int64_t)step) + 1;
+    int64_t maxcap = 0;
+    for (int64_t i = 0; i + step < P.M; i += 2 * (int64_t)step) maxcap = std::max(maxcap, P.cap[i + step]);
+    const int32_t tile = P.tile;
+    const int64_t tpm = std::max<int64_t>(1, (maxcap + tile - 1) / tile);
+    hipLaunchKernelGGL(k_merge, dim3((unsigned)(merges * tpm)), dim3(kBlock), 0, s, B, P.V, P.M, step, tile,
+                       (int32_t)tpm);
+}
+
+void launch_copy_out(const Plan& P, const DevBufs& B, int32_t* d_out, int64_t out_cap, int64_t* d_counts,
+                     hipStream_t s) {
+    int64_t blocks = (P.cap[0] + 255) / 256;
+    blocks = std::max<int64_t>(1, std::min<int64_t>(blocks, 4096));
+    hipLaunchKernelGGL(k_copy_out, dim3((unsigned)blocks), dim3(256), 0, s, B, reinterpret_cast<int2*>(d_out),
+                       out_cap, d_counts);
+}
+
+int32_t block_size() { return kBlock; }
+
+}  // namespace br

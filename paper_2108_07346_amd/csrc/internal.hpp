@@ -1,0 +1,101 @@
+// Internal declarations of libbridges (host side).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bridges.h"
+
+namespace br {
+
+// ---- errors -----------------------------------------------------------------
+int fail(int code, const char* fmt, ...);          // sets the thread-local message, returns code
+int hip_fail(hipError_t e, const char* what);      // BR_EHIP (or BR_ENOMEM) with the HIP message
+#define BR_HIP(call)                                      \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return br::hip_fail(e_, #call); \
+    } while (0)
+
+// ---- device geometry shared with the kernels ---------------------------------
+// Chunk i of the phase tree is edges [lo(i), lo(i+1)) with lo(i) = floor(iE/M).
+struct Plan {
+    int64_t E = 0;
+    int32_t V = 0, M = 1;
+    int32_t rounds = 0;            // ceil(log2 M)
+    int32_t tile = 0;              // edges per workgroup tile
+    int32_t tpc = 0;               // tiles per chunk (same for every chunk)
+    int32_t xcd_map = 0;           // keep each chunk's workgroups on one XCD
+    int64_t blocks0 = 0;           // phase-0 grid
+    std::vector<int64_t> off, cap; // per node: certificate region (pairs)
+    int64_t cert_pairs = 0;        // sum of caps
+    std::vector<int64_t> round_cap;// per round: largest sibling cap
+};
+
+// Certificate regions: node i owns pairs [off[i], off[i]+cap[i]); its F1 grows
+// from the front, its F2 from the back; cnt[2i], cnt[2i+1] count them.
+struct DevBufs {
+    const int2* edges = nullptr;   // edge i < split is edges[i]
+    const int2* edges2 = nullptr;  // edge i >= split is edges2[i - split]
+    int64_t split = 0;
+    uint32_t* state = nullptr;     // [M][V][2] offset-encoded parents (0 = root)
+    int2* cert = nullptr;
+    const int64_t* off = nullptr;  // [M]
+    const int64_t* cap = nullptr;  // [M]
+    uint32_t* cnt = nullptr;       // [M][2]
+    uint32_t* err = nullptr;       // bit 0: id out of range; bit 1: region overflow
+};
+
+void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
+void launch_phase0(const Plan& P, const DevBufs& B, hipStream_t s);
+void launch_merge_round(const Plan& P, const DevBufs& B, int32_t step, hipStream_t s);
+void launch_copy_out(const Plan& P, const DevBufs& B, int32_t* d_out, int64_t out_cap, int64_t* d_counts,
+                     hipStream_t s);
+
+Plan make_plan(int64_t E, int32_t V, int32_t M);
+
+// ---- host side of the path --------------------------------------------------
+// Algorithm 1 (iterative) on the certificate; appends canonical keys (min<<32|max).
+struct DfsScratch {
+    std::vector<int32_t> head, adj_to, adj_id, disc, low, st_v, st_pe, st_it;
+};
+void certificate_bridges(const int2* f1, int64_t n1, const int2* f2, int64_t n2, int32_t V, DfsScratch& S,
+                         std::vector<uint64_t>& keys);
+void canonical_sort(std::vector<uint64_t>& keys);
+
+// ---- context ------------------------------------------------------------------
+struct Arena {
+    void* base = nullptr;
+    size_t size = 0;
+};
+
+}  // namespace br
+
+struct br_ctx {
+    int device = 0;
+    br::Arena ws;                  // device workspace
+    void* pinned = nullptr;        // pinned host staging
+    size_t pinned_size = 0;
+    int64_t* h_meta = nullptr;     // pinned: off/cap upload staging
+    size_t h_meta_n = 0;
+    br::DfsScratch dfs;
+    std::vector<uint64_t> keys;
+    int profiling = 0;
+    br_profile prof{};
+    hipEvent_t ev[8] = {};
+    // batched path state
+    void* batched = nullptr;
+};
+
+namespace br {
+int ensure_workspace(br_ctx* c, size_t bytes, hipStream_t s);
+void batched_release(br_ctx* c);
+int ensure_pinned(br_ctx* c, size_t bytes);
+// Run phases a1..a5 on d_edges; on return (asynchronously) node 0 holds the final certificate.
+// The input is the concatenation of d_a [Ea] and d_b [Eb] (d_b may be null with Eb = 0).
+int run_certificate(br_ctx* c, const int32_t* d_a, int64_t Ea, const int32_t* d_b, int64_t Eb, int32_t V, int32_t M,
+                    hipStream_t s, Plan& P, DevBufs& B);
+}  // namespace br

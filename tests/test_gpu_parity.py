@@ -1,0 +1,163 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bridge sets are integer sets: the bar is bit-exact equality of the canonical
+sorted (u < v) pairs.  Certificates are not unique (any maximal forests do),
+so they are judged by the properties every valid certificate has.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_07346_amd as br
+    c = br.Context(0)
+    yield c
+    c.close()
+
+
+def dev(e):
+    return torch.from_numpy(np.ascontiguousarray(e, dtype=np.int32).reshape(-1, 2)).cuda()
+
+
+@pytest.fixture(scope="module")
+def small():
+    return graphgen.config("small")
+
+
+@pytest.fixture(scope="module")
+def dense():
+    g = graphgen.config("dense")
+    return g, oracle.bridges(g.edges, g.V), dev(g.edges)
+
+
+@pytest.mark.parametrize("M", [4, 1, 2, 3, 5, 8, 16, 100, 10051, 10058])
+def test_small_config_bit_exact(ctx, small, M):
+    say("small M=%d" % M)
+    want = oracle.bridges(small.edges, small.V)
+    got = ctx.find(dev(small.edges), small.V, M)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("M", [1, 16, 256, 1024])
+def test_dense_config_bit_exact(ctx, dense, M):
+    g, want, d = dense
+    say("dense M=%d" % M)
+    got = ctx.find(d, g.V, M)
+    assert got.shape == want.shape and np.array_equal(got, want)
+
+
+def test_dense_certificate_properties(ctx, dense):
+    g, want, d = dense
+    for M in (1, 16):
+        say("dense cert M=%d" % M)
+        f1, f2 = ctx.cert_build(d, g.V, M)
+        f1, f2 = f1.cpu().numpy(), f2.cpu().numpy()
+        assert oracle.check_certificate(f1, f2, g.edges, g.V) == []
+
+
+def test_phase0_chunk_certificates_are_maximal(ctx, small):
+    # a single chunk (M = 1): F is maximal in G and F' is maximal in G - F
+    say("phase0 maximality")
+    f1, f2 = ctx.cert_build(dev(small.edges), small.V, 1)
+    f1, f2 = f1.cpu().numpy(), f2.cpu().numpy()
+    assert f1.shape[0] == small.V - oracle.components(small.edges, small.V)
+    keys = lambda e: np.minimum(e[:, 0], e[:, 1]).astype(np.int64) << 32 | np.maximum(e[:, 0], e[:, 1])
+    rest = small.edges[~np.isin(keys(small.edges), keys(f1))]        # simple graph: F removed by key
+    assert f2.shape[0] == small.V - oracle.components(rest, small.V)
+    assert oracle.check_certificate(f1, f2, small.edges, small.V) == []
+
+
+def test_cert_merge_of_two_certificates(ctx, dense):
+    g, want, d = dense
+    say("cert_merge")
+    h = g.E // 2
+    a1, a2 = ctx.cert_build(d[:h].contiguous(), g.V, 4)
+    b1, b2 = ctx.cert_build(d[h:].contiguous(), g.V, 4)
+    xa = torch.cat([a1, a2]).contiguous()
+    xb = torch.cat([b1, b2]).contiguous()
+    m1, m2 = ctx.cert_merge(xa, xb, g.V)
+    s = torch.cat([m1, m2]).cpu().numpy()
+    assert s.shape[0] <= 2 * (g.V - 1)
+    assert np.array_equal(oracle.bridges(s, g.V), want)
+    assert oracle.check_certificate(m1.cpu().numpy(), m2.cpu().numpy(), g.edges, g.V, check_bridges=False) == []
+
+
+def test_random_multigraphs(ctx):
+    rng = np.random.default_rng(21)
+    for t in range(60):
+        V = int(rng.integers(1, 400))
+        E = int(rng.integers(0, 6 * V))
+        e = rng.integers(0, V, size=(E, 2)).astype(np.int32)
+        M = int(rng.choice([1, 2, 3, 7, 64, max(E, 1)]))
+        say("random t=%d V=%d E=%d M=%d" % (t, V, E, M))
+        got = ctx.find(dev(e), V, M)
+        assert np.array_equal(got, oracle.bridges(e, V)), (V, E, M)
+
+
+def test_trees_cycles_and_parallel_edges(ctx):
+    say("closed forms")
+    rng = np.random.default_rng(22)
+    V = 5000
+    par = np.array([rng.integers(0, i) for i in range(1, V)])
+    tree = np.stack([par, np.arange(1, V)], 1).astype(np.int32)
+    for M in (1, 3, 64):
+        assert np.array_equal(ctx.find(dev(tree), V, M), oracle.bridges(tree, V))
+    cyc = np.stack([np.arange(V), (np.arange(V) + 1) % V], 1).astype(np.int32)
+    assert ctx.find(dev(cyc), V, 7).shape[0] == 0
+    dbl = np.concatenate([tree, tree[::2, ::-1]])
+    assert np.array_equal(ctx.find(dev(dbl), V, 5), oracle.bridges(dbl, V))
+
+
+def test_edge_cases(ctx):
+    import paper_2108_07346_amd as br
+    say("edge cases")
+    empty = torch.zeros((0, 2), dtype=torch.int32, device="cuda")
+    assert ctx.find(empty, 1, 1).shape[0] == 0
+    assert ctx.find(empty, 10, 4).shape[0] == 0
+    loops = dev([[0, 0], [3, 3], [3, 3]])
+    assert ctx.find(loops, 4, 2).shape[0] == 0
+    assert np.array_equal(ctx.find(dev([[5, 2]]), 9, 3), [[2, 5]])
+    with pytest.raises(br.BridgeError) as ei:
+        ctx.find(dev([[0, 1], [1, 7]]), 5, 1)
+    assert ei.value.code == br.BR_ERANGE
+    with pytest.raises(br.BridgeError) as ei:
+        ctx.find(dev([[0, 1], [-1, 2]]), 5, 2)
+    assert ei.value.code == br.BR_ERANGE
+    # the context still works after an error
+    assert np.array_equal(ctx.find(dev([[0, 1], [1, 2], [2, 0], [2, 3]]), 4, 1), [[2, 3]])
+    with pytest.raises(br.BridgeError):
+        ctx.find(dev([[0, 1]]), 0, 1)
+    with pytest.raises(br.BridgeError):
+        ctx.find(dev([[0, 1]]), 2, 0)
+
+
+def test_concurrency_stress_same_bridges(ctx, dense):
+    # many interleavings (permutations, chunk counts): certificates vary, bridges must not
+    g, want, _ = dense
+    rng = np.random.default_rng(23)
+    hashes = set()
+    for t in range(6):
+        e = g.edges[rng.permutation(g.E)]
+        d = dev(e)
+        M = [1, 2, 16, 64, 256, 1][t]
+        say("stress t=%d M=%d" % (t, M))
+        assert np.array_equal(ctx.find(d, g.V, M), want)
+        f1, f2 = ctx.cert_build(d, g.V, 1)
+        hashes.add(hash(f1.cpu().numpy().tobytes()))
+    say("distinct certificates over runs: %d" % len(hashes))
