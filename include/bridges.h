@@ -100,6 +100,19 @@ int br_bridges_find(br_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t V, i
                     int64_t cap, int64_t* n_bridges, void* stream);
 
 /*
+ * br_certificate_bridges -- the final step alone, on the host: Algorithm 1's
+ * depth-first search (Section IV-A) on a certificate S = F u F' given as two
+ * host edge lists, then canonical order.  Any edge lists are accepted (the
+ * search does not rely on F being a forest); used on certificates, whose
+ * bridges are those of the graph they certify (Section III).
+ *   h_f1 [n1][2], h_f2 [n2][2] host int32 (either may be null when its count is 0).
+ *   h_bridges [cap][2] host; *n_bridges as for br_bridges_find (BR_ECAP if cap is
+ *   too small).  BR_ERANGE if an id is outside [0, V).  Needs no device.
+ */
+int br_certificate_bridges(const int32_t* h_f1, int64_t n1, const int32_t* h_f2, int64_t n2, int32_t V,
+                           int32_t* h_bridges, int64_t cap, int64_t* n_bridges);
+
+/*
  * br_bridges_find_batched -- br_bridges_find over G independent graphs in one
  * launch of a persistent kernel (replayed from a captured HIP graph when the
  * same batch shape repeats).
@@ -137,15 +150,37 @@ typedef struct br_profile {
     int64_t cert_f1, cert_f2;  /* |F|, |F'| of the final certificate              */
     int64_t rounds;        /* merge rounds run                                    */
     int64_t launches;      /* kernel launches                                     */
+    double ms_bridge_dev;  /* device bridge step (final step 1 only)              */
 } br_profile;
 int br_set_profiling(br_ctx* ctx, int on);
+
+/*
+ * Final step used by br_bridges_find on this context:
+ *   0 (default) -- Algorithm 1's depth-first search (Section IV-A) on the
+ *                  certificate, in the library's host code, after copying the
+ *                  certificate (at most 2(V-1) edges) to the host;
+ *   1           -- the same bridge set computed on the GPU: F of the
+ *                  certificate rooted by Euler tours, preorder numbers and
+ *                  subtree sizes by list ranking, and a tree edge kept as a
+ *                  bridge iff no certificate edge leaves the child's subtree
+ *                  (the low-link test of Algorithm 1 on an arbitrary rooted
+ *                  spanning tree; the parallelisation the paper's Section VII
+ *                  asks for).  Only the bridges are copied to the host.
+ * BR_EINVAL for another mode.
+ */
+int br_set_final_step(br_ctx* ctx, int mode);
 int br_get_profile(br_ctx* ctx, br_profile* out);
 
 /*
  * Serving: continuous batching of bridge queries on one device.
  *   br_server_create  device, device-memory budget in bytes for resident
  *                     requests (edge lists, union-find state, certificates),
- *                     max_slots requests in flight on the device at once.
+ *                     max_slots (1..64) requests in flight on the device at
+ *                     once, each on its own stream; a request is admitted,
+ *                     in arrival order, as soon as a slot is free and the
+ *                     budget has room for it.  Each request runs the whole
+ *                     path of br_bridges_find with a chunk count chosen from
+ *                     its size (M = clamp(E / 8V, 1, 64)).
  *   br_submit         copies h_edges [E][2] (ids in [0,V)) into a host queue
  *                     and returns a ticket; the request is admitted to the
  *                     device when a slot and budget free up.  BR_EBUSY if the
@@ -168,6 +203,10 @@ typedef struct br_server_stats_t {
 } br_server_stats_t;
 int br_server_create(br_server** srv, int device, int64_t mem_budget, int32_t max_slots);
 int br_submit(br_server* srv, const int32_t* h_edges, int64_t E, int32_t V, uint64_t* ticket);
+/* As br_submit for an edge list already resident on the server's device
+ * (d_edges [E][2]); the caller keeps it alive and unchanged until the ticket
+ * is done.  Nothing is copied. */
+int br_submit_device(br_server* srv, const int32_t* d_edges, int64_t E, int32_t V, uint64_t* ticket);
 int br_poll(br_server* srv, uint64_t ticket, int32_t* h_out, int64_t cap, int64_t* n, int* done);
 int br_wait(br_server* srv, uint64_t ticket, int32_t* h_out, int64_t cap, int64_t* n);
 int br_server_stats(br_server* srv, br_server_stats_t* out, int reset);

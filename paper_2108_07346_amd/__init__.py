@@ -19,8 +19,10 @@ SO_PATH = os.path.join(_DIR, "libbridges.so")
 BR_OK, BR_EINVAL, BR_ERANGE, BR_ENOMEM, BR_EHIP, BR_EBUSY, BR_ECAP, BR_EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
 
 EXPORTS = ["br_last_error", "br_create", "br_destroy", "br_cert_build", "br_cert_merge", "br_bridges_find",
-           "br_bridges_find_batched", "br_batched_max_v", "br_set_profiling", "br_get_profile",
-           "br_server_create", "br_submit", "br_poll", "br_wait", "br_server_stats", "br_server_destroy"]
+           "br_certificate_bridges",
+           "br_bridges_find_batched", "br_batched_max_v", "br_set_profiling", "br_set_final_step", "br_get_profile",
+           "br_server_create", "br_submit", "br_submit_device", "br_poll", "br_wait", "br_server_stats",
+           "br_server_destroy"]
 
 
 class BridgeError(RuntimeError):
@@ -33,7 +35,7 @@ class _Profile(ctypes.Structure):
     _fields_ = [("ms_phase0", ctypes.c_double), ("ms_merge", ctypes.c_double), ("ms_cert", ctypes.c_double),
                 ("ms_d2h", ctypes.c_double), ("ms_dfs", ctypes.c_double), ("ms_canon", ctypes.c_double),
                 ("ms_total", ctypes.c_double), ("cert_f1", ctypes.c_int64), ("cert_f2", ctypes.c_int64),
-                ("rounds", ctypes.c_int64), ("launches", ctypes.c_int64)]
+                ("rounds", ctypes.c_int64), ("launches", ctypes.c_int64), ("ms_bridge_dev", ctypes.c_double)]
 
 
 class _ServerStats(ctypes.Structure):
@@ -61,12 +63,15 @@ def load():
     lib.br_cert_build.argtypes = [vp, vp, i64, i32, i32, vp, i64, vp, vp]
     lib.br_cert_merge.argtypes = [vp, vp, i64, vp, i64, i32, vp, i64, vp, vp]
     lib.br_bridges_find.argtypes = [vp, vp, i64, i32, i32, vp, i64, p64, vp]
+    lib.br_certificate_bridges.argtypes = [vp, i64, vp, i64, i32, vp, i64, p64]
     lib.br_bridges_find_batched.argtypes = [vp, vp, vp, vp, i32, i32, vp, i64, vp, vp]
     lib.br_batched_max_v.restype = i32
     lib.br_set_profiling.argtypes = [vp, ctypes.c_int]
+    lib.br_set_final_step.argtypes = [vp, ctypes.c_int]
     lib.br_get_profile.argtypes = [vp, ctypes.POINTER(_Profile)]
     lib.br_server_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64, i32]
     lib.br_submit.argtypes = [vp, vp, i64, i32, ctypes.POINTER(ctypes.c_uint64)]
+    lib.br_submit_device.argtypes = [vp, vp, i64, i32, ctypes.POINTER(ctypes.c_uint64)]
     lib.br_poll.argtypes = [vp, ctypes.c_uint64, vp, i64, p64, ctypes.POINTER(ctypes.c_int)]
     lib.br_wait.argtypes = [vp, ctypes.c_uint64, vp, i64, p64]
     lib.br_server_stats.argtypes = [vp, ctypes.POINTER(_ServerStats), ctypes.c_int]
@@ -120,6 +125,10 @@ class Context:
 
     def set_profiling(self, on: bool = True):
         _check(self._lib.br_set_profiling(self._h, int(on)))
+
+    def set_final_step(self, mode: int):
+        """0: host search (Algorithm 1, default); 1: device bridge step."""
+        _check(self._lib.br_set_final_step(self._h, int(mode)))
 
     def profile(self) -> dict:
         p = _Profile()
@@ -183,6 +192,59 @@ class Context:
         return out[:boff[-1]].copy(), boff
 
 
+class Server:
+    """Continuous-batching bridge server on one device (see br_server_create)."""
+
+    def __init__(self, device: int = 0, mem_budget: int = 64 << 30, max_slots: int = 8):
+        self._lib = load()
+        self._h = ctypes.c_void_p()
+        _check(self._lib.br_server_create(ctypes.byref(self._h), device, int(mem_budget), int(max_slots)))
+
+    def submit(self, edges, V: int) -> int:
+        """Queue a query; `edges` is a host int32 [E, 2] array, or a contiguous
+        int32 [E, 2] CUDA tensor that must stay alive until the ticket is done."""
+        t = ctypes.c_uint64(0)
+        if hasattr(edges, "is_cuda") and edges.is_cuda:
+            ptr, E = _edges_arg(edges)
+            _check(self._lib.br_submit_device(self._h, ptr, E, int(V), ctypes.byref(t)))
+        else:
+            e = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+            _check(self._lib.br_submit(self._h, e.ctypes.data if e.shape[0] else None, e.shape[0], int(V),
+                                       ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int, V: int):
+        """(done, bridges or None)."""
+        cap = max(int(V) - 1, 1)
+        out = np.empty((cap, 2), dtype=np.int32)
+        n, done = ctypes.c_int64(0), ctypes.c_int(0)
+        _check(self._lib.br_poll(self._h, ticket, out.ctypes.data, cap, ctypes.byref(n), ctypes.byref(done)))
+        return (True, out[:n.value].copy()) if done.value else (False, None)
+
+    def wait(self, ticket: int, V: int) -> np.ndarray:
+        cap = max(int(V) - 1, 1)
+        out = np.empty((cap, 2), dtype=np.int32)
+        n = ctypes.c_int64(0)
+        _check(self._lib.br_wait(self._h, ticket, out.ctypes.data, cap, ctypes.byref(n)))
+        return out[:n.value].copy()
+
+    def stats(self, reset: bool = False) -> dict:
+        st = _ServerStats()
+        _check(self._lib.br_server_stats(self._h, ctypes.byref(st), int(reset)))
+        return {k: getattr(st, k) for k, _ in _ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            self._lib.br_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 _default = {}
 
 
@@ -207,6 +269,19 @@ def cert_merge(a, b, V: int, stream=None):
 
 def find_batched(edges, offsets, Vs, chunk_edges: int = 0, stream=None):
     return context(edges.device.index or 0).find_batched(edges, offsets, Vs, chunk_edges, stream)
+
+
+def certificate_bridges(f1, f2, V: int) -> np.ndarray:
+    """The final step alone (host): bridges of the certificate F u F' (numpy int32 [n, 2] each)."""
+    a = np.ascontiguousarray(f1, dtype=np.int32).reshape(-1, 2)
+    b = np.ascontiguousarray(f2, dtype=np.int32).reshape(-1, 2)
+    cap = max(int(V) - 1, 1)
+    out = np.empty((cap, 2), dtype=np.int32)
+    n = ctypes.c_int64(0)
+    _check(load().br_certificate_bridges(a.ctypes.data if a.shape[0] else None, a.shape[0],
+                                         b.ctypes.data if b.shape[0] else None, b.shape[0], int(V),
+                                         out.ctypes.data, cap, ctypes.byref(n)))
+    return out[:n.value].copy()
 
 
 def batched_max_v() -> int:

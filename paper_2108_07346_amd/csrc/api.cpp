@@ -26,6 +26,7 @@ int hip_fail(hipError_t e, const char* what) {
 }
 
 int32_t block_size();
+int32_t tile_size();
 
 Plan make_plan(int64_t E, int32_t V, int32_t M) {
     Plan P;
@@ -33,7 +34,7 @@ Plan make_plan(int64_t E, int32_t V, int32_t M) {
     P.V = V;
     P.M = M;
     while ((int64_t(1) << P.rounds) < M) P.rounds++;
-    P.tile = 4096;
+    P.tile = tile_size();
     const int64_t per = (E + M - 1) / M;   // largest chunk
     P.tpc = (int32_t)std::max<int64_t>(1, (per + P.tile - 1) / P.tile);
     P.xcd_map = M >= 8 ? 1 : 0;
@@ -91,9 +92,9 @@ int ensure_pinned(br_ctx* c, size_t bytes) {
 
 // Workspace layout: [err | cnt | state | cert | off | cap]
 struct Layout {
-    size_t err, cnt, state, cert, off, cap, total;
+    size_t err, cnt, state, cert, off, cap, bws, total;
 };
-static Layout layout(const Plan& P) {
+static Layout layout(const Plan& P, bool device_final) {
     Layout L;
     size_t o = 0;
     L.err = o; o += 256;
@@ -102,6 +103,7 @@ static Layout layout(const Plan& P) {
     L.cert = o; o = align256(o + sizeof(int2) * (size_t)std::max<int64_t>(P.cert_pairs, 1));
     L.off = o; o = align256(o + sizeof(int64_t) * (size_t)P.M);
     L.cap = o; o = align256(o + sizeof(int64_t) * (size_t)P.M);
+    L.bws = o; if (device_final) o = align256(o + sizeof(int32_t) * (size_t)device_bridges_words(P.V));
     L.total = o;
     return L;
 }
@@ -122,7 +124,7 @@ int run_certificate(br_ctx* c, const int32_t* d_a, int64_t Ea, const int32_t* d_
                     hipStream_t s, Plan& P, DevBufs& B) {
     const int64_t E = Ea + Eb;
     P = make_plan(E, V, M);
-    const Layout L = layout(P);
+    const Layout L = layout(P, c->final_step == 1);
     int rc = ensure_workspace(c, L.total, s);
     if (rc) return rc;
     rc = ensure_pinned(c, 64 << 10);
@@ -137,6 +139,7 @@ int run_certificate(br_ctx* c, const int32_t* d_a, int64_t Ea, const int32_t* d_
     B.cert = reinterpret_cast<int2*>(base + L.cert);
     B.off = reinterpret_cast<const int64_t*>(base + L.off);
     B.cap = reinterpret_cast<const int64_t*>(base + L.cap);
+    c->bws = reinterpret_cast<int32_t*>(base + L.bws);
     // node regions: staged through pinned memory (the previous call's copy has
     // completed: every entry point ends with a stream synchronisation or an
     // event wait on the staging copy)
@@ -217,6 +220,12 @@ int br_set_profiling(br_ctx* c, int on) {
     return BR_OK;
 }
 
+int br_set_final_step(br_ctx* c, int mode) {
+    if (!c || mode < 0 || mode > 1) return fail(BR_EINVAL, "br_set_final_step: bad argument");
+    c->final_step = mode;
+    return BR_OK;
+}
+
 int br_get_profile(br_ctx* c, br_profile* out) {
     if (!c || !out) return fail(BR_EINVAL, "br_get_profile: null argument");
     *out = c->prof;
@@ -293,28 +302,61 @@ int br_bridges_find(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int
     DevBufs B;
     rc = run_certificate(c, d_edges, E, nullptr, 0, V, M, s, P, B);
     if (rc) return rc;
-    // node 0's whole region plus its counters and the error word
     const int64_t cap0 = P.cap[0];
-    const size_t need = sizeof(int2) * (size_t)std::max<int64_t>(cap0, 1) + 64;
-    rc = ensure_pinned(c, need);
-    if (rc) return rc;
-    char* h = static_cast<char*>(c->pinned);
-    uint32_t* hc = reinterpret_cast<uint32_t*>(h);
-    int2* hx = reinterpret_cast<int2*>(h + 64);
-    BR_HIP(hipMemcpyAsync(hc, B.cnt, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    BR_HIP(hipMemcpyAsync(hc + 2, B.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    if (cap0 > 0) BR_HIP(hipMemcpyAsync(hx, B.cert + P.off[0], sizeof(int2) * cap0, hipMemcpyDeviceToHost, s));
-    ev_record(c, 4, s);
-    BR_HIP(hipStreamSynchronize(s));
-    auto t1 = std::chrono::steady_clock::now();
-    const uint32_t n1 = hc[0], n2 = hc[1], err = hc[2];
-    if (err & 1u) return fail(BR_ERANGE, "br_bridges_find: an edge has a vertex id outside [0, %d)", V);
-    if (err != 0 || (int64_t)n1 + n2 > cap0)
-        return fail(BR_EINTERNAL, "br_bridges_find: certificate region overflow (|F|=%u |F'|=%u cap=%lld)", n1, n2,
-                    (long long)cap0);
+    uint32_t n1 = 0, n2 = 0, err = 0;
+    std::chrono::steady_clock::time_point t1, t2;
     c->keys.clear();
-    certificate_bridges(hx, n1, hx + cap0 - n2, n2, V, c->dfs, c->keys);
-    auto t2 = std::chrono::steady_clock::now();
+    if (c->final_step == 1) {
+        // final step on the device: only the bridges come back
+        uint64_t* d_keys = nullptr;
+        uint32_t* d_n = nullptr;
+        rc = device_bridges(P, B, c->bws, &d_keys, &d_n, s);
+        if (rc) return rc;
+        BR_HIP(hipGetLastError());
+        ev_record(c, 5, s);
+        rc = ensure_pinned(c, 64 + 8 * (size_t)V);
+        if (rc) return rc;
+        uint32_t* hc = static_cast<uint32_t*>(c->pinned);
+        BR_HIP(hipMemcpyAsync(hc, B.cnt, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        BR_HIP(hipMemcpyAsync(hc + 2, B.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        BR_HIP(hipMemcpyAsync(hc + 3, d_n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        BR_HIP(hipStreamSynchronize(s));
+        n1 = hc[0]; n2 = hc[1]; err = hc[2];
+        const uint32_t nk = std::min<uint32_t>(hc[3], (uint32_t)std::max(V - 1, 0));
+        uint64_t* hk = reinterpret_cast<uint64_t*>(static_cast<char*>(c->pinned) + 64);
+        if (nk) {
+            BR_HIP(hipMemcpyAsync(hk, d_keys, 8 * (size_t)nk, hipMemcpyDeviceToHost, s));
+            BR_HIP(hipStreamSynchronize(s));
+        }
+        ev_record(c, 4, s);
+        t1 = std::chrono::steady_clock::now();
+        if (err & 1u) return fail(BR_ERANGE, "br_bridges_find: an edge has a vertex id outside [0, %d)", V);
+        if (err != 0 || (int64_t)n1 + n2 > cap0)
+            return fail(BR_EINTERNAL, "br_bridges_find: certificate region overflow");
+        c->keys.assign(hk, hk + nk);
+        t2 = std::chrono::steady_clock::now();
+    } else {
+        // node 0's whole region plus its counters and the error word
+        const size_t need = sizeof(int2) * (size_t)std::max<int64_t>(cap0, 1) + 64;
+        rc = ensure_pinned(c, need);
+        if (rc) return rc;
+        char* h = static_cast<char*>(c->pinned);
+        uint32_t* hc = reinterpret_cast<uint32_t*>(h);
+        int2* hx = reinterpret_cast<int2*>(h + 64);
+        BR_HIP(hipMemcpyAsync(hc, B.cnt, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        BR_HIP(hipMemcpyAsync(hc + 2, B.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        if (cap0 > 0) BR_HIP(hipMemcpyAsync(hx, B.cert + P.off[0], sizeof(int2) * cap0, hipMemcpyDeviceToHost, s));
+        ev_record(c, 4, s);
+        BR_HIP(hipStreamSynchronize(s));
+        t1 = std::chrono::steady_clock::now();
+        n1 = hc[0]; n2 = hc[1]; err = hc[2];
+        if (err & 1u) return fail(BR_ERANGE, "br_bridges_find: an edge has a vertex id outside [0, %d)", V);
+        if (err != 0 || (int64_t)n1 + n2 > cap0)
+            return fail(BR_EINTERNAL, "br_bridges_find: certificate region overflow (|F|=%u |F'|=%u cap=%lld)", n1,
+                        n2, (long long)cap0);
+        certificate_bridges(hx, n1, hx + cap0 - n2, n2, V, c->dfs, c->keys);
+        t2 = std::chrono::steady_clock::now();
+    }
     canonical_sort(c->keys);
     auto t3 = std::chrono::steady_clock::now();
     const int64_t nb = (int64_t)c->keys.size();
@@ -324,6 +366,7 @@ int br_bridges_find(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int
         c->prof.ms_merge = ev_ms(c, 2, 3);
         c->prof.ms_cert = ev_ms(c, 0, 3);
         c->prof.ms_d2h = ev_ms(c, 3, 4);
+        c->prof.ms_bridge_dev = c->final_step == 1 ? ev_ms(c, 3, 5) : 0.0;
         c->prof.cert_f1 = n1;
         c->prof.cert_f2 = n2;
     }
@@ -334,6 +377,31 @@ int br_bridges_find(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int
     for (int64_t i = 0; i < nb; i++) {
         h_bridges[2 * i] = (int32_t)(c->keys[i] >> 32);
         h_bridges[2 * i + 1] = (int32_t)(c->keys[i] & 0xffffffffu);
+    }
+    return BR_OK;
+}
+
+int br_certificate_bridges(const int32_t* h_f1, int64_t n1, const int32_t* h_f2, int64_t n2, int32_t V,
+                           int32_t* h_bridges, int64_t cap, int64_t* n_bridges) {
+    if (!n_bridges || n1 < 0 || n2 < 0 || (n1 > 0 && !h_f1) || (n2 > 0 && !h_f2) || cap < 0 || (cap > 0 && !h_bridges))
+        return fail(BR_EINVAL, "br_certificate_bridges: bad argument");
+    if (V < 1 || V > (1 << 29)) return fail(BR_EINVAL, "br_certificate_bridges: V = %d outside [1, 2^29]", V);
+    if (n1 + n2 >= (int64_t(1) << 30)) return fail(BR_EINVAL, "br_certificate_bridges: too many edges");
+    for (int64_t k = 0; k < 2 * n1; k++)
+        if ((uint32_t)h_f1[k] >= (uint32_t)V) return fail(BR_ERANGE, "br_certificate_bridges: id out of range");
+    for (int64_t k = 0; k < 2 * n2; k++)
+        if ((uint32_t)h_f2[k] >= (uint32_t)V) return fail(BR_ERANGE, "br_certificate_bridges: id out of range");
+    thread_local DfsScratch S;
+    thread_local std::vector<uint64_t> keys;
+    keys.clear();
+    certificate_bridges(reinterpret_cast<const int2*>(h_f1), n1, reinterpret_cast<const int2*>(h_f2), n2, V, S, keys);
+    canonical_sort(keys);
+    const int64_t nb = (int64_t)keys.size();
+    *n_bridges = nb;
+    if (nb > cap) return fail(BR_ECAP, "br_certificate_bridges: %lld bridges, capacity %lld", (long long)nb, (long long)cap);
+    for (int64_t i = 0; i < nb; i++) {
+        h_bridges[2 * i] = (int32_t)(keys[i] >> 32);
+        h_bridges[2 * i + 1] = (int32_t)(keys[i] & 0xffffffffu);
     }
     return BR_OK;
 }

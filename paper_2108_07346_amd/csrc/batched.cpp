@@ -1,41 +1,518 @@
-// Batched bridge queries (first version: one br_bridges_find per graph).
+// Batched bridge queries: G independent graphs, one persistent launch.
+//
+// Host side of the batched path: plans the per-graph phase trees (chunks of
+// chunk_edges edges, node regions, merge counters), orders the work items
+// largest-first, captures "clear counters -> persistent kernel -> copy
+// certificates to the host" in a HIP graph that is replayed while the batch
+// shape and input buffer stay the same, then runs the final depth-first
+// search of every graph on a pool of host threads.  chunk_edges = 0 asks the
+// built-in tuner, which times the candidate chunk sizes on the batch itself
+// and remembers the winner per batch shape.
 #include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
 
 #include "internal.hpp"
 
 namespace br {
-void batched_release(br_ctx*) {}
+
+
+
+namespace {
+
+// simple fixed pool of host threads for the final search
+class Pool {
+  public:
+    explicit Pool(int n) {
+        for (int i = 0; i < n; i++) th_.emplace_back([this, i] { loop(i); });
+    }
+    ~Pool() {
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto& t : th_) t.join();
+    }
+    int size() const { return (int)th_.size(); }
+    // run fn(worker) on every worker and wait
+    void run(const std::function<void(int)>& fn) {
+        std::unique_lock<std::mutex> g(mu_);
+        fn_ = &fn;
+        pending_ = (int)th_.size();
+        gen_++;
+        cv_.notify_all();
+        done_.wait(g, [this] { return pending_ == 0; });
+        fn_ = nullptr;
+    }
+
+  private:
+    void loop(int i) {
+        uint64_t seen = 0;
+        for (;;) {
+            const std::function<void(int)>* f;
+            {
+                std::unique_lock<std::mutex> g(mu_);
+                cv_.wait(g, [&] { return stop_ || gen_ != seen; });
+                if (stop_) return;
+                seen = gen_;
+                f = fn_;
+            }
+            (*f)(i);
+            std::lock_guard<std::mutex> g(mu_);
+            if (--pending_ == 0) done_.notify_one();
+        }
+    }
+    std::vector<std::thread> th_;
+    std::mutex mu_;
+    std::condition_variable cv_, done_;
+    const std::function<void(int)>* fn_ = nullptr;
+    int pending_ = 0;
+    uint64_t gen_ = 0;
+    bool stop_ = false;
+};
+
+struct BatchPlan {
+    // key
+    int32_t G = 0, C = 0;
+    std::vector<int64_t> eoff;
+    std::vector<int32_t> V;
+    // small graphs are the ones certified in LDS; the others go through br_bridges_find
+    std::vector<int32_t> small, large;
+    std::vector<int32_t> Mg;
+    std::vector<int64_t> rbase, cbase, noff, ncap, items;
+    int64_t nodes = 0, counters = 0, area0 = 0, cert_pairs = 0;
+    // device memory: [clear block: ncnt | arrive | queue | err][meta][cert]
+    void* dmem = nullptr;
+    size_t clear_words = 0;
+    BatchDev dev{};
+    // pinned host: node-0 regions + node-0 counters + err
+    void* hmem = nullptr;
+    int2* h_area0 = nullptr;
+    uint32_t* h_cnt0 = nullptr;
+    uint32_t* h_err = nullptr;
+    // captured launch
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void* graph_edges = nullptr;
+    int blocks = 0;
+    ~BatchPlan() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (dmem) (void)hipFree(dmem);
+        if (hmem) (void)hipHostFree(hmem);
+    }
+};
+
+struct BatchState {
+    std::unique_ptr<Pool> pool;
+    hipStream_t stream = nullptr;
+    std::vector<std::unique_ptr<BatchPlan>> plans;      // small LRU
+    std::map<std::string, int32_t> tuned;               // batch shape -> chunk_edges
+    std::vector<DfsScratch> scratch;
+    std::vector<std::vector<uint64_t>> keys;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEvent_t k0 = nullptr, k1 = nullptr;   // around the replayed graph (counter clear + persistent kernel)
+};
+
+BatchState* state_of(br_ctx* c) {
+    if (!c->batched) c->batched = new BatchState();
+    return static_cast<BatchState*>(c->batched);
+}
+
+int64_t part_lo(int64_t E, int64_t M, int64_t i) { return i * (E / M) + (i * (E % M)) / M; }
+
+size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int build_plan(BatchPlan& P, const int64_t* eoff, const int32_t* V, int32_t G, int32_t C, int cus) {
+    P.G = G;
+    P.C = C;
+    P.eoff.assign(eoff, eoff + G + 1);
+    P.V.assign(V, V + G);
+    const int32_t maxv = batched_max_v_dev();
+    for (int32_t g = 0; g < G; g++) (V[g] <= maxv ? P.small : P.large).push_back(g);
+    const int32_t S = (int32_t)P.small.size();
+    // per small graph (indexed by position s in P.small): chunks, nodes, counters
+    P.Mg.resize(S);
+    P.rbase.resize(S);
+    P.cbase.resize(S);
+    int64_t rest = S, ctr = 0;
+    for (int32_t s = 0; s < S; s++) {
+        const int64_t E = eoff[P.small[s] + 1] - eoff[P.small[s]];
+        const int64_t M = std::max<int64_t>(1, (E + C - 1) / C);
+        if (M >= (1 << 20)) return fail(BR_EINVAL, "batched: graph %d needs %lld chunks", P.small[s], (long long)M);
+        P.Mg[s] = (int32_t)M;
+        P.rbase[s] = rest;
+        rest += M - 1;
+        int R = 0;
+        while ((int64_t(1) << R) < M) R++;
+        P.cbase[s] = ctr;
+        ctr += (int64_t)R * ((M + 1) / 2);
+    }
+    P.nodes = rest;
+    P.counters = ctr;
+    P.noff.assign(P.nodes, 0);
+    P.ncap.assign(P.nodes, 0);
+    // node-0 regions first (one contiguous copy to the host), then the others
+    int64_t acc = 0;
+    for (int pass = 0; pass < 2; pass++) {
+        for (int32_t s = 0; s < S; s++) {
+            const int32_t g = P.small[s];
+            const int64_t E = eoff[g + 1] - eoff[g], M = P.Mg[s], bound = 2 * (int64_t(V[g]) - 1);
+            for (int64_t i = (pass == 0 ? 0 : 1); i < (pass == 0 ? 1 : M); i++) {
+                int64_t span = M;
+                if (i) span = std::min<int64_t>(int64_t(1) << __builtin_ctzll((unsigned long long)i), M - i);
+                const int64_t cap = std::min(part_lo(E, M, std::min<int64_t>(M, i + span)) - part_lo(E, M, i), bound);
+                const int64_t idx = i ? P.rbase[s] + i - 1 : s;
+                P.noff[idx] = acc;
+                P.ncap[idx] = cap;
+                acc += cap;
+            }
+        }
+        if (pass == 0) P.area0 = acc;
+    }
+    P.cert_pairs = acc;
+    // items, largest chunk first (ties: graph order)
+    struct It { int64_t len, code; };
+    std::vector<It> its;
+    for (int32_t s = 0; s < S; s++) {
+        const int32_t g = P.small[s];
+        const int64_t E = eoff[g + 1] - eoff[g], M = P.Mg[s];
+        for (int64_t k = 0; k < M; k++) its.push_back({part_lo(E, M, k + 1) - part_lo(E, M, k), ((int64_t)s << 20) | k});
+    }
+    std::stable_sort(its.begin(), its.end(), [](const It& a, const It& b) { return a.len > b.len; });
+    P.items.resize(its.size());
+    for (size_t i = 0; i < its.size(); i++) P.items[i] = its[i].code;
+    // device memory
+    P.clear_words = 2 * (size_t)P.nodes + (size_t)P.counters + 2;
+    const size_t o_clear = 0;
+    size_t o = a256(o_clear + 4 * P.clear_words);
+    const size_t o_eoff = o; o = a256(o + 8 * 2 * (size_t)std::max(S, 1));
+    const size_t o_V = o; o = a256(o + 4 * (size_t)S);
+    const size_t o_M = o; o = a256(o + 4 * (size_t)S);
+    const size_t o_rb = o; o = a256(o + 8 * (size_t)S);
+    const size_t o_cb = o; o = a256(o + 8 * (size_t)S);
+    const size_t o_noff = o; o = a256(o + 8 * (size_t)P.nodes);
+    const size_t o_ncap = o; o = a256(o + 8 * (size_t)P.nodes);
+    const size_t o_items = o; o = a256(o + 8 * std::max<size_t>(P.items.size(), 1));
+    const size_t o_cert = o; o = a256(o + 8 * (size_t)std::max<int64_t>(P.cert_pairs, 1));
+    BR_HIP(hipMalloc(&P.dmem, o));
+    char* d = static_cast<char*>(P.dmem);
+    std::vector<int32_t> sV(S);
+    std::vector<int64_t> se2(2 * (size_t)S);     // graph s: edges [se2[2s], se2[2s+1])
+    for (int32_t s = 0; s < S; s++) {
+        sV[s] = V[P.small[s]];
+        se2[2 * s] = eoff[P.small[s]];
+        se2[2 * s + 1] = eoff[P.small[s] + 1];
+    }
+    if (S) {
+        BR_HIP(hipMemcpy(d + o_eoff, se2.data(), 8 * 2 * (size_t)S, hipMemcpyHostToDevice));
+        BR_HIP(hipMemcpy(d + o_V, sV.data(), 4 * (size_t)S, hipMemcpyHostToDevice));
+        BR_HIP(hipMemcpy(d + o_M, P.Mg.data(), 4 * (size_t)S, hipMemcpyHostToDevice));
+        BR_HIP(hipMemcpy(d + o_rb, P.rbase.data(), 8 * (size_t)S, hipMemcpyHostToDevice));
+        BR_HIP(hipMemcpy(d + o_cb, P.cbase.data(), 8 * (size_t)S, hipMemcpyHostToDevice));
+        BR_HIP(hipMemcpy(d + o_noff, P.noff.data(), 8 * (size_t)P.nodes, hipMemcpyHostToDevice));
+        BR_HIP(hipMemcpy(d + o_ncap, P.ncap.data(), 8 * (size_t)P.nodes, hipMemcpyHostToDevice));
+        BR_HIP(hipMemcpy(d + o_items, P.items.data(), 8 * P.items.size(), hipMemcpyHostToDevice));
+    }
+    uint32_t* clr = reinterpret_cast<uint32_t*>(d + o_clear);
+    P.dev.eoff = reinterpret_cast<const int64_t*>(d + o_eoff);
+    P.dev.V = reinterpret_cast<const int32_t*>(d + o_V);
+    P.dev.Mg = reinterpret_cast<const int32_t*>(d + o_M);
+    P.dev.rbase = reinterpret_cast<const int64_t*>(d + o_rb);
+    P.dev.cbase = reinterpret_cast<const int64_t*>(d + o_cb);
+    P.dev.noff = reinterpret_cast<const int64_t*>(d + o_noff);
+    P.dev.ncap = reinterpret_cast<const int64_t*>(d + o_ncap);
+    P.dev.items = reinterpret_cast<const int64_t*>(d + o_items);
+    P.dev.n_items = (int64_t)P.items.size();
+    P.dev.cert = reinterpret_cast<int2*>(d + o_cert);
+    P.dev.ncnt = clr;
+    P.dev.arrive = clr + 2 * P.nodes;
+    P.dev.queue = clr + 2 * P.nodes + P.counters;
+    P.dev.err = P.dev.queue + 1;
+    // pinned host staging
+    const size_t hbytes = a256(8 * (size_t)std::max<int64_t>(P.area0, 1)) + a256(8 * (size_t)std::max(S, 1)) + 256;
+    BR_HIP(hipHostMalloc(&P.hmem, hbytes, hipHostMallocDefault));
+    char* h = static_cast<char*>(P.hmem);
+    P.h_area0 = reinterpret_cast<int2*>(h);
+    P.h_cnt0 = reinterpret_cast<uint32_t*>(h + a256(8 * (size_t)std::max<int64_t>(P.area0, 1)));
+    P.h_err = P.h_cnt0 + 2 * (size_t)std::max(S, 1);
+    P.blocks = std::max(1, cus * batched_blocks_per_cu());
+    return BR_OK;
+}
+
+// enqueue clear -> kernel -> copies on s (captured into P.graph on first use)
+// the captured part: clear the counters, then the persistent kernel
+int enqueue(BatchPlan& P, const int32_t* d_edges, hipStream_t s) {
+    P.dev.edges = reinterpret_cast<const int2*>(d_edges);
+    launch_fill_u32(P.dev.ncnt, (int64_t)P.clear_words, 0u, s);
+    BR_HIP(hipGetLastError());
+    if (P.dev.n_items) launch_batched(P.dev, P.blocks, s);
+    BR_HIP(hipGetLastError());
+    return BR_OK;
+}
+
+// node-0 certificates, their counters and the error word to the host
+int copy_back(BatchPlan& P, hipStream_t s) {
+    const int32_t S = (int32_t)P.small.size();
+    if (P.area0) BR_HIP(hipMemcpyAsync(P.h_area0, P.dev.cert, 8 * (size_t)P.area0, hipMemcpyDeviceToHost, s));
+    if (S) BR_HIP(hipMemcpyAsync(P.h_cnt0, P.dev.ncnt, 8 * (size_t)S, hipMemcpyDeviceToHost, s));
+    BR_HIP(hipMemcpyAsync(P.h_err, P.dev.err, 4, hipMemcpyDeviceToHost, s));
+    return BR_OK;
+}
+
+int run_device(BatchState& st, BatchPlan& P, const int32_t* d_edges) {
+    hipStream_t s = st.stream;
+    if (P.exec && P.graph_edges == d_edges) {
+        BR_HIP(hipEventRecord(st.k0, s));
+        BR_HIP(hipGraphLaunch(P.exec, s));
+        BR_HIP(hipEventRecord(st.k1, s));
+        return copy_back(P, s);
+    }
+    if (P.exec) {
+        (void)hipGraphExecDestroy(P.exec);
+        P.exec = nullptr;
+    }
+    if (P.graph) {
+        (void)hipGraphDestroy(P.graph);
+        P.graph = nullptr;
+    }
+    BR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue(P, d_edges, s);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    P.graph = g;
+    BR_HIP(hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0));
+    P.graph_edges = d_edges;
+    BR_HIP(hipEventRecord(st.k0, s));
+    BR_HIP(hipGraphLaunch(P.exec, s));
+    BR_HIP(hipEventRecord(st.k1, s));
+    return copy_back(P, s);
+}
+
+std::string shape_key(const int64_t* eoff, const int32_t* V, int32_t G) {
+    // batch shape bucket for the tuner: G, total edges and largest V (log2 buckets)
+    int64_t E = eoff[G] - eoff[0];
+    int32_t mv = 0;
+    for (int32_t g = 0; g < G; g++) mv = std::max(mv, V[g]);
+    int eb = 0, vb = 0;
+    while ((int64_t(1) << eb) < E) eb++;
+    while ((1 << vb) < mv) vb++;
+    return std::to_string(G) + ":" + std::to_string(eb) + ":" + std::to_string(vb);
+}
+
+bool same_shape(const BatchPlan& P, const int64_t* eoff, const int32_t* V, int32_t G, int32_t C) {
+    return P.G == G && P.C == C && std::equal(P.eoff.begin(), P.eoff.end(), eoff) && std::equal(P.V.begin(), P.V.end(), V);
+}
+
+}  // namespace
+
+void batched_release(br_ctx* c) {
+    if (!c->batched) return;
+    auto* st = static_cast<BatchState*>(c->batched);
+    if (st->stream) (void)hipStreamSynchronize(st->stream);
+    st->plans.clear();
+    if (st->e0) (void)hipEventDestroy(st->e0);
+    if (st->e1) (void)hipEventDestroy(st->e1);
+    if (st->k0) (void)hipEventDestroy(st->k0);
+    if (st->k1) (void)hipEventDestroy(st->k1);
+    if (st->stream) (void)hipStreamDestroy(st->stream);
+    delete st;
+    c->batched = nullptr;
+}
+
+static int get_plan(br_ctx* c, BatchState& st, const int64_t* eoff, const int32_t* V, int32_t G, int32_t C,
+                    BatchPlan** out) {
+    for (size_t i = 0; i < st.plans.size(); i++) {
+        if (same_shape(*st.plans[i], eoff, V, G, C)) {
+            std::rotate(st.plans.begin(), st.plans.begin() + i, st.plans.begin() + i + 1);
+            *out = st.plans[0].get();
+            return BR_OK;
+        }
+    }
+    hipDeviceProp_t prop;
+    BR_HIP(hipGetDeviceProperties(&prop, c->device));
+    auto P = std::make_unique<BatchPlan>();
+    int rc = build_plan(*P, eoff, V, G, C, prop.multiProcessorCount);
+    if (rc) return rc;
+    st.plans.insert(st.plans.begin(), std::move(P));
+    if (st.plans.size() > 4) st.plans.pop_back();
+    *out = st.plans[0].get();
+    return BR_OK;
+}
+
 }  // namespace br
 
 using namespace br;
 
 extern "C" {
 
-int32_t br_batched_max_v(void) { return 4096; }
+int32_t br_batched_max_v(void) { return batched_max_v_dev(); }
 
 int br_bridges_find_batched(br_ctx* c, const int32_t* d_edges, const int64_t* h_edge_off, const int32_t* h_V,
                             int32_t G, int32_t chunk_edges, int32_t* h_bridges, int64_t cap, int64_t* h_bridge_off,
                             void* stream) {
     if (!c || !h_edge_off || !h_V || !h_bridge_off || G < 0 || chunk_edges < 0 || cap < 0 || (cap > 0 && !h_bridges))
         return fail(BR_EINVAL, "br_bridges_find_batched: bad argument");
-    h_bridge_off[0] = 0;
-    int64_t total = 0;
-    std::vector<int32_t> tmp;
-    int status = BR_OK;
+    if (h_edge_off[0] != 0) return fail(BR_EINVAL, "batched: offsets must start at 0");
     for (int32_t g = 0; g < G; g++) {
-        const int64_t E = h_edge_off[g + 1] - h_edge_off[g];
-        if (E < 0) return fail(BR_EINVAL, "batched: offsets decrease at graph %d", g);
-        const int32_t V = h_V[g];
-        tmp.resize(2 * (size_t)std::max(V, 1));
-        int64_t n = 0;
-        int rc = br_bridges_find(c, d_edges + 2 * h_edge_off[g], E, V, 1, tmp.data(), std::max(V, 1), &n, stream);
-        if (rc) return rc;
-        if (total + n <= cap) std::copy(tmp.begin(), tmp.begin() + 2 * n, h_bridges + 2 * total);
-        else status = BR_ECAP;
-        total += n;
-        h_bridge_off[g + 1] = total;
+        if (h_edge_off[g + 1] < h_edge_off[g]) return fail(BR_EINVAL, "batched: offsets decrease at graph %d", g);
+        if (h_V[g] < 1) return fail(BR_EINVAL, "batched: V[%d] = %d < 1", g, h_V[g]);
     }
-    if (status) return fail(BR_ECAP, "batched: %lld bridges, capacity %lld", (long long)total, (long long)cap);
+    if (h_edge_off[G] > 0 && !d_edges) return fail(BR_EINVAL, "batched: null edge list");
+    auto t0 = std::chrono::steady_clock::now();
+    BR_HIP(hipSetDevice(c->device));
+    BatchState& st = *state_of(c);
+    if (!st.stream) {
+        BR_HIP(hipStreamCreateWithFlags(&st.stream, hipStreamNonBlocking));
+        BR_HIP(hipEventCreate(&st.e0));
+        BR_HIP(hipEventCreate(&st.e1));
+        BR_HIP(hipEventCreate(&st.k0));
+        BR_HIP(hipEventCreate(&st.k1));
+    }
+    if (!st.pool) {
+        int n = (int)std::thread::hardware_concurrency();
+        n = std::max(1, std::min(n, 16));
+        st.pool = std::make_unique<Pool>(n);
+        st.scratch.resize(n);
+        st.keys.resize(n);
+    }
+    // the caller's stream must have produced the input
+    BR_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+
+    int32_t C = chunk_edges;
+    if (C == 0) {
+        const std::string key = shape_key(h_edge_off, h_V, G);
+        auto it = st.tuned.find(key);
+        if (it != st.tuned.end()) {
+            C = it->second;
+        } else {
+            // tune: time each candidate chunk size on this batch (device part only)
+            float best = 1e30f;
+            int32_t bestC = 16384;
+            for (int32_t cand : {4096, 8192, 16384, 32768, 65536, 131072}) {
+                BatchPlan* P = nullptr;
+                int rc = get_plan(c, st, h_edge_off, h_V, G, cand, &P);
+                if (rc) return rc;
+                float ms = 0.f;
+                for (int rep = 0; rep < 2; rep++) {
+                    BR_HIP(hipEventRecord(st.e0, st.stream));
+                    rc = run_device(st, *P, d_edges);
+                    if (rc) return rc;
+                    BR_HIP(hipEventRecord(st.e1, st.stream));
+                    BR_HIP(hipEventSynchronize(st.e1));
+                    BR_HIP(hipEventElapsedTime(&ms, st.e0, st.e1));
+                }
+                if (ms < best) {
+                    best = ms;
+                    bestC = cand;
+                }
+            }
+            st.tuned[key] = bestC;
+            C = bestC;
+        }
+    }
+    BatchPlan* P = nullptr;
+    int rc = get_plan(c, st, h_edge_off, h_V, G, C, &P);
+    if (rc) return rc;
+    if (c->profiling) BR_HIP(hipEventRecord(st.e0, st.stream));
+    rc = run_device(st, *P, d_edges);
+    if (rc) return rc;
+    if (c->profiling) BR_HIP(hipEventRecord(st.e1, st.stream));
+    BR_HIP(hipStreamSynchronize(st.stream));
+    auto t1 = std::chrono::steady_clock::now();
+    if (*P->h_err & 1u) return fail(BR_ERANGE, "batched: an edge has a vertex id outside its graph's [0, V)");
+    if (*P->h_err) return fail(BR_EINTERNAL, "batched: certificate region overflow");
+
+    // final search per small graph, on the host pool; bridges of graph g go to
+    // a slot of V_g - 1 pairs, compacted afterwards
+    const int32_t S = (int32_t)P->small.size();
+    std::vector<int64_t> slot(S + 1, 0), nb(G, 0);
+    for (int32_t s = 0; s < S; s++) slot[s + 1] = slot[s] + std::max(P->V[P->small[s]] - 1, 0);
+    std::vector<uint64_t> outk((size_t)std::max<int64_t>(slot[S], 1));
+    std::atomic<int32_t> next{0};
+    std::atomic<int> bad{0};
+    st.pool->run([&](int w) {
+        DfsScratch& sc = st.scratch[w];
+        std::vector<uint64_t>& keys = st.keys[w];
+        for (;;) {
+            const int32_t s = next.fetch_add(1);
+            if (s >= S) break;
+            const int32_t g = P->small[s];
+            const uint32_t n1 = P->h_cnt0[2 * s], n2 = P->h_cnt0[2 * s + 1];
+            const int64_t off = P->noff[s], capg = P->ncap[s];
+            if ((int64_t)n1 + n2 > capg) {
+                bad = 1;
+                continue;
+            }
+            keys.clear();
+            certificate_bridges(P->h_area0 + off, n1, P->h_area0 + off + capg - n2, n2, P->V[g], sc, keys);
+            canonical_sort(keys);
+            std::copy(keys.begin(), keys.end(), outk.begin() + slot[s]);
+            nb[g] = (int64_t)keys.size();
+        }
+    });
+    if (bad) return fail(BR_EINTERNAL, "batched: certificate counts exceed their region");
+    auto t2 = std::chrono::steady_clock::now();
+    // graphs above the LDS limit: the plain path, with the same chunk size
+    std::vector<std::vector<int32_t>> large_out(P->large.size());
+    for (size_t k = 0; k < P->large.size(); k++) {
+        const int32_t g = P->large[k];
+        const int64_t E = h_edge_off[g + 1] - h_edge_off[g];
+        const int32_t M = (int32_t)std::max<int64_t>(1, std::min<int64_t>((E + C - 1) / C, 1 << 20));
+        large_out[k].resize(2 * (size_t)std::max(h_V[g] - 1, 1));
+        int64_t n = 0;
+        rc = br_bridges_find(c, d_edges + 2 * h_edge_off[g], E, h_V[g], M, large_out[k].data(),
+                             std::max(h_V[g] - 1, 1), &n, st.stream);
+        if (rc) return rc;
+        nb[g] = n;
+        large_out[k].resize(2 * (size_t)n);
+    }
+    // assemble in graph order
+    h_bridge_off[0] = 0;
+    for (int32_t g = 0; g < G; g++) h_bridge_off[g + 1] = h_bridge_off[g] + nb[g];
+    const int64_t total = h_bridge_off[G];
+    if (total <= cap) {
+        for (int32_t s = 0; s < S; s++) {
+            const int32_t g = P->small[s];
+            int32_t* o = h_bridges + 2 * h_bridge_off[g];
+            for (int64_t i = 0; i < nb[g]; i++) {
+                o[2 * i] = (int32_t)(outk[slot[s] + i] >> 32);
+                o[2 * i + 1] = (int32_t)(outk[slot[s] + i] & 0xffffffffu);
+            }
+        }
+        for (size_t k = 0; k < P->large.size(); k++)
+            std::copy(large_out[k].begin(), large_out[k].end(), h_bridges + 2 * h_bridge_off[P->large[k]]);
+    }
+    auto t3 = std::chrono::steady_clock::now();
+    if (c->profiling) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, st.e0, st.e1) != hipSuccess) ms = 0.f;
+        c->prof.ms_cert = ms;
+        if (hipEventElapsedTime(&ms, st.k0, st.k1) != hipSuccess) ms = 0.f;   // clear + persistent kernel
+        c->prof.ms_phase0 = ms;
+        (void)hipGetLastError();
+        c->prof.ms_merge = 0;
+        c->prof.ms_d2h = 0;
+    }
+    c->prof.ms_dfs = std::chrono::duration<double, std::milli>(t2 - t1).count();
+    c->prof.ms_canon = std::chrono::duration<double, std::milli>(t3 - t2).count();
+    c->prof.ms_total = std::chrono::duration<double, std::milli>(t3 - t0).count();
+    c->prof.rounds = C;
+    c->prof.launches = 1;
+    if (total > cap) return fail(BR_ECAP, "batched: %lld bridges, capacity %lld", (long long)total, (long long)cap);
     return BR_OK;
 }
 

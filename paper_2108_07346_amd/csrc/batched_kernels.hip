@@ -1,0 +1,250 @@
+// Batched certificates for many small graphs in one persistent launch.
+//
+// Work items are (graph, chunk) pairs: graph g's edge list is split into M_g
+// chunks exactly as in the paper's phase tree (Section III), and the items are
+// handed out largest-first from a device queue.  A workgroup certifies one
+// chunk (Algorithm 2) with the whole union-find state in LDS, then takes part
+// in the graph's merge tree: the merge of nodes i and i + 2^(q-1) in round q
+// is done by whichever workgroup finishes the second of the two (an arrival
+// counter per merge), re-running the certificate on the union of the two
+// certificates, again in LDS.  Node 0's region of each graph ends up holding
+// the graph's certificate: F from the front, F' from the back.
+//
+// LDS union-find: one 32-bit word per vertex, low half = x - parent in F,
+// high half = x - parent in F' (0 = root; V <= kMaxV keeps both in 16 bits).
+// Hooking is a 32-bit LDS compare-and-swap that changes one half; a swap that
+// fails because the other half moved is simply retried.  The larger root is
+// hooked under the smaller representative, so chains decrease and the loop
+// ends (see cert_kernels.hip for the argument).
+
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace br {
+
+namespace {
+
+constexpr int kBB = 512;          // threads per workgroup
+constexpr int kMaxV = 4096;       // vertices per graph in LDS
+constexpr int kStage = 2 * (kMaxV - 1);
+
+struct LdsState {
+    uint32_t q[kMaxV];            // packed F / F' offsets
+    uint32_t stage[kStage];       // merged certificate: (u | v << 16), F from front, F' from back
+    uint32_t n1, n2;              // counters of the current certificate
+    int32_t item, last, errv;
+};
+
+template <int F>
+__device__ __forceinline__ uint32_t half(uint32_t w) { return F ? (w >> 16) : (w & 0xffffu); }
+
+template <int F>
+__device__ __forceinline__ uint32_t with_half(uint32_t w, uint32_t h) {
+    return F ? ((w & 0xffffu) | (h << 16)) : ((w & 0xffff0000u) | h);
+}
+
+template <int F>
+__device__ __forceinline__ uint32_t lfind(uint32_t* q, uint32_t x) {
+    uint32_t w = q[x];
+    uint32_t d = half<F>(w);
+    while (d != 0) {
+        const uint32_t p = x - d;
+        const uint32_t dp = half<F>(q[p]);
+        if (dp == 0) return p;
+        // path halving by compare-and-swap: the other half of the word may be
+        // changing under a concurrent hook, so never overwrite it blindly; a
+        // failed swap just skips this shortcut
+        atomicCAS(&q[x], w, with_half<F>(w, d + dp));
+        x = p - dp;
+        w = q[x];
+        d = half<F>(w);
+    }
+    return x;
+}
+
+template <int F>
+__device__ __forceinline__ bool lunite(uint32_t* q, uint32_t u, uint32_t v) {
+    for (;;) {
+        u = lfind<F>(q, u);
+        v = lfind<F>(q, v);
+        if (u == v) return false;
+        if (u < v) { const uint32_t t = u; u = v; v = t; }
+        uint32_t w = q[u];
+        for (;;) {
+            if (half<F>(w) != 0) break;                       // u was hooked meanwhile
+            const uint32_t nw = with_half<F>(w, u - v);
+            const uint32_t old = atomicCAS(&q[u], w, nw);
+            if (old == w) return true;
+            w = old;                                          // other half changed, or u hooked
+        }
+        u = u - half<F>(w);
+    }
+}
+
+__device__ __forceinline__ void loffer(uint32_t* q, uint32_t u, uint32_t v, bool& a1, bool& a2) {
+    a1 = lunite<0>(q, u, v);
+    a2 = !a1 && lunite<1>(q, u, v);
+}
+
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// wavefront-aggregated reservation of slots on an LDS counter
+__device__ __forceinline__ uint32_t reserve(uint32_t* ctr, bool want, uint64_t& mask) {
+    mask = __ballot(want);
+    if (mask == 0) return 0;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    uint32_t base = 0;
+    if (__lane_id() == leader) base = atomicAdd(ctr, (uint32_t)__popcll(mask));
+    return __shfl(base, leader) + lane_rank(mask);
+}
+
+__device__ __forceinline__ int64_t part_lo(int64_t E, int64_t M, int64_t i) { return i * (E / M) + (i * (E % M)) / M; }
+
+}  // namespace
+
+
+
+namespace {
+
+// Certify edges [t0, t1) of graph g (ids < V) into an empty LDS state and write
+// the accepted edges to node region (off, cap).  Counts go to S.n1, S.n2.
+__device__ void certify_chunk(LdsState& S, const BatchDev& B, int64_t t0, int64_t t1, uint32_t V, int64_t off,
+                              int64_t cap) {
+    for (uint32_t x = threadIdx.x; x < V; x += kBB) S.q[x] = 0;
+    if (threadIdx.x == 0) { S.n1 = 0; S.n2 = 0; }
+    __syncthreads();
+    for (int64_t base = t0; base < t1; base += kBB) {
+        const int64_t i = base + threadIdx.x;
+        bool a1 = false, a2 = false;
+        int2 e = make_int2(0, 0);
+        if (i < t1) {
+            e = B.edges[i];
+            if ((uint32_t)e.x < V && (uint32_t)e.y < V) loffer(S.q, (uint32_t)e.x, (uint32_t)e.y, a1, a2);
+            else atomicOr(B.err, 1u);
+        }
+        uint64_t m;
+        const uint32_t p1 = reserve(&S.n1, a1, m);
+        if (a1) { if (p1 < cap) B.cert[off + p1] = e; else atomicOr(B.err, 2u); }
+        const uint32_t p2 = reserve(&S.n2, a2, m);
+        if (a2) { if (p2 < cap) B.cert[off + cap - 1 - p2] = e; else atomicOr(B.err, 2u); }
+    }
+    __syncthreads();
+}
+
+// Offer the certificate stored in node region (off, cap) with counts (n1, n2)
+// to the LDS state, staging accepted edges in S.stage.
+__device__ void offer_region(LdsState& S, const BatchDev& B, int64_t off, int64_t cap, uint32_t n1, uint32_t n2) {
+    const int64_t total = (int64_t)n1 + n2;
+    for (int64_t base = 0; base < total; base += kBB) {
+        const int64_t k = base + threadIdx.x;
+        bool a1 = false, a2 = false;
+        int2 e = make_int2(0, 0);
+        if (k < total) {
+            const uint64_t r = __hip_atomic_load(reinterpret_cast<const uint64_t*>(B.cert + (k < n1 ? off + k : off + cap - n2 + (k - n1))),
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            e = make_int2((int32_t)(uint32_t)r, (int32_t)(uint32_t)(r >> 32));
+            if ((uint32_t)e.x < kMaxV && (uint32_t)e.y < kMaxV) loffer(S.q, (uint32_t)e.x, (uint32_t)e.y, a1, a2);
+            else atomicOr(B.err, 2u);
+        }
+        const uint32_t w = (uint32_t)e.x | ((uint32_t)e.y << 16);
+        uint64_t m;
+        const uint32_t p1 = reserve(&S.n1, a1, m);
+        if (a1) { if (p1 < kStage) S.stage[p1] = w; else atomicOr(B.err, 2u); }
+        const uint32_t p2 = reserve(&S.n2, a2, m);
+        if (a2) { if (p2 < kStage) S.stage[kStage - 1 - p2] = w; else atomicOr(B.err, 2u); }
+    }
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(kBB) k_batched(BatchDev B) {
+    __shared__ LdsState S;
+    for (;;) {
+        if (threadIdx.x == 0) S.item = (int32_t)atomicAdd(B.queue, 1u);
+        __syncthreads();
+        const int64_t it = S.item;
+        if (it >= B.n_items) break;
+        const int64_t code = B.items[it];
+        const int32_t g = (int32_t)(code >> 20);
+        int64_t node = code & ((1 << 20) - 1);
+        const int64_t Mg = B.Mg[g];
+        const uint32_t V = (uint32_t)B.V[g];
+        const int64_t e0 = B.eoff[2 * g], Eg = B.eoff[2 * g + 1] - e0;
+        const int64_t rb = B.rbase[g];
+        auto nidx = [&](int64_t k) { return k ? rb + k - 1 : (int64_t)g; };
+        // phase 0: chunk `node` of graph g
+        certify_chunk(S, B, e0 + part_lo(Eg, Mg, node), e0 + part_lo(Eg, Mg, node + 1), V, B.noff[nidx(node)],
+                      B.ncap[nidx(node)]);
+        uint32_t n1 = S.n1, n2 = S.n2;
+        // merge rounds: climb while this workgroup is the second of a pair to finish
+        int64_t step = 1, level = 0, cb = B.cbase[g];
+        for (;;) {
+            if (threadIdx.x == 0) {
+                B.ncnt[2 * nidx(node)] = n1;
+                B.ncnt[2 * nidx(node) + 1] = n2;
+            }
+            if (step >= Mg) break;                          // node 0 holds the graph's certificate
+            const int64_t i = node & ~(2 * step - 1);       // left node of this round's pair
+            const int64_t j = i + step;
+            if (j >= Mg) {                                  // no partner: pass through
+                node = i;
+                step *= 2;
+                level++;
+                continue;
+            }
+            // publish this node's certificate: every thread releases its own
+            // stores, then one arrival per workgroup on the pair's counter
+            __threadfence();
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const uint32_t prev = atomicAdd(&B.arrive[cb + level * ((Mg + 1) / 2) + (i >> (level + 1))], 1u);
+                S.last = prev == 1u;
+            }
+            __syncthreads();
+            if (!S.last) break;                             // the partner will merge
+            __threadfence();                                // acquire the partner's certificate
+            // merge: Certificate(X_i u X_j), staged in LDS, written back to node i
+            for (uint32_t x = threadIdx.x; x < V; x += kBB) S.q[x] = 0;
+            if (threadIdx.x == 0) { S.n1 = 0; S.n2 = 0; }
+            __syncthreads();
+            const uint32_t ai1 = __hip_atomic_load(&B.ncnt[2 * nidx(i)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t ai2 = __hip_atomic_load(&B.ncnt[2 * nidx(i) + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t aj1 = __hip_atomic_load(&B.ncnt[2 * nidx(j)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t aj2 = __hip_atomic_load(&B.ncnt[2 * nidx(j) + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int64_t offi = B.noff[nidx(i)], capi = B.ncap[nidx(i)];
+            const int64_t offj = B.noff[nidx(j)], capj = B.ncap[nidx(j)];
+            offer_region(S, B, offi, capi, min(ai1, (uint32_t)capi), min(ai2, (uint32_t)capi - min(ai1, (uint32_t)capi)));
+            offer_region(S, B, offj, capj, min(aj1, (uint32_t)capj), min(aj2, (uint32_t)capj - min(aj1, (uint32_t)capj)));
+            __syncthreads();
+            n1 = min(S.n1, (uint32_t)kStage);
+            n2 = min(S.n2, (uint32_t)kStage - n1);
+            if ((int64_t)n1 + n2 > capi) {
+                if (threadIdx.x == 0) atomicOr(B.err, 2u);
+                n1 = 0;
+                n2 = 0;
+            }
+            for (uint32_t k = threadIdx.x; k < n1 + n2; k += kBB) {
+                const uint32_t w = k < n1 ? S.stage[k] : S.stage[kStage - n2 + (k - n1)];
+                const int64_t pos = k < n1 ? offi + k : offi + capi - n2 + (k - n1);
+                B.cert[pos] = make_int2((int32_t)(w & 0xffffu), (int32_t)(w >> 16));
+            }
+            __syncthreads();
+            node = i;
+            step *= 2;
+            level++;
+        }
+        __syncthreads();
+    }
+}
+
+void launch_batched(const BatchDev& B, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_batched, dim3(blocks), dim3(kBB), 0, s, B);
+}
+
+int32_t batched_max_v_dev() { return kMaxV; }
+int32_t batched_blocks_per_cu() { return 3; }
+
+}  // namespace br

@@ -34,6 +34,7 @@ namespace br {
 namespace {
 
 constexpr int kBlock = 512;
+constexpr int kTile = 4096;   // edges per workgroup tile (a multiple of kBlock)
 
 __device__ __forceinline__ uint32_t ld(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
@@ -93,34 +94,57 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Append accepted edges of this wavefront to node `node`'s regions.  Every lane
-// of the wavefront must call this (ballots).
-__device__ __forceinline__ void append(const DevBufs& B, int32_t node, bool a1, bool a2, int2 e) {
+// Accepted edges of one workgroup tile are staged in LDS (F from the front,
+// F' from the back of the stage), then the tile reserves its ranges in the
+// node's region with one global atomic per forest and copies them out.  Every
+// lane of the workgroup must call these (ballots and barriers).
+struct Stage {
+    int2 e[kTile];
+    uint32_t n1, n2;
+    uint32_t base1, base2;
+};
+
+__device__ __forceinline__ void stage_reset(Stage& S) {
+    if (threadIdx.x == 0) { S.n1 = 0; S.n2 = 0; }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void stage_put(Stage& S, bool a1, bool a2, int2 e) {
     const uint64_t m1 = __ballot(a1), m2 = __ballot(a2);
-    if ((m1 | m2) == 0) return;
-    const int64_t off = B.off[node], cap = B.cap[node];
     const int lane = __lane_id();
     if (m1) {
         const int leader = __ffsll((unsigned long long)m1) - 1;
         uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(B.cnt + 2 * node, (uint32_t)__popcll(m1));
+        if (lane == leader) base = atomicAdd(&S.n1, (uint32_t)__popcll(m1));
         base = __shfl(base, leader);
-        if (a1) {
-            const int64_t pos = (int64_t)base + lane_rank(m1);
-            if (pos < cap) B.cert[off + pos] = e;
-            else atomicOr(B.err, 2u);
-        }
+        if (a1) S.e[base + lane_rank(m1)] = e;
     }
     if (m2) {
         const int leader = __ffsll((unsigned long long)m2) - 1;
         uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(B.cnt + 2 * node + 1, (uint32_t)__popcll(m2));
+        if (lane == leader) base = atomicAdd(&S.n2, (uint32_t)__popcll(m2));
         base = __shfl(base, leader);
-        if (a2) {
-            const int64_t pos = (int64_t)base + lane_rank(m2);
-            if (pos < cap) B.cert[off + cap - 1 - pos] = e;
-            else atomicOr(B.err, 2u);
-        }
+        if (a2) S.e[kTile - 1 - (base + lane_rank(m2))] = e;
+    }
+}
+
+__device__ __forceinline__ void stage_flush(Stage& S, const DevBufs& B, int64_t node) {
+    __syncthreads();
+    const uint32_t n1 = S.n1, n2 = S.n2;
+    if (threadIdx.x == 0) {
+        S.base1 = n1 ? atomicAdd(B.cnt + 2 * node, n1) : 0;
+        S.base2 = n2 ? atomicAdd(B.cnt + 2 * node + 1, n2) : 0;
+    }
+    __syncthreads();
+    const int64_t off = B.off[node], cap = B.cap[node];
+    const int64_t b1 = S.base1, b2 = S.base2;
+    for (uint32_t k = threadIdx.x; k < n1 + n2; k += kBlock) {
+        int64_t pos;
+        int2 e;
+        if (k < n1) { pos = b1 + k; e = S.e[k]; }
+        else { pos = b2 + (k - n1); e = S.e[kTile - 1 - (k - n1)]; }
+        if (pos >= cap) { atomicOr(B.err, 2u); continue; }
+        B.cert[k < n1 ? off + pos : off + cap - 1 - pos] = e;
     }
 }
 
@@ -147,6 +171,8 @@ __global__ void __launch_bounds__(kBlock) k_phase0(DevBufs B, int64_t E, int32_t
     const int64_t t0 = lo + s * (int64_t)tile;
     const int64_t t1 = min(t0 + (int64_t)tile, hi);
     if (t0 >= t1) return;
+    __shared__ Stage S;
+    stage_reset(S);
     uint32_t* q = B.state + (size_t)c * 2 * (size_t)V;
     for (int64_t base = t0; base < t1; base += kBlock) {
         const int64_t i = base + threadIdx.x;
@@ -157,8 +183,9 @@ __global__ void __launch_bounds__(kBlock) k_phase0(DevBufs B, int64_t E, int32_t
             if ((uint32_t)e.x < (uint32_t)V && (uint32_t)e.y < (uint32_t)V) offer(q, (uint32_t)e.x, (uint32_t)e.y, a1, a2);
             else atomicOr(B.err, 1u);
         }
-        append(B, (int32_t)c, a1, a2, e);
+        stage_put(S, a1, a2, e);
     }
+    stage_flush(S, B, c);
 }
 
 // One merge round with partner distance `step`: node i (i % 2step == 0) keeps
@@ -178,6 +205,8 @@ __global__ void __launch_bounds__(kBlock) k_merge(DevBufs B, int32_t V, int32_t 
     const int64_t total = n1 + n2;
     const int64_t t0 = s * (int64_t)tile, t1 = min(t0 + (int64_t)tile, total);
     if (t0 >= t1) return;
+    __shared__ Stage S;
+    stage_reset(S);
     uint32_t* q = B.state + (size_t)i * 2 * (size_t)V;
     for (int64_t base = t0; base < t1; base += kBlock) {
         const int64_t k = base + threadIdx.x;
@@ -187,8 +216,9 @@ __global__ void __launch_bounds__(kBlock) k_merge(DevBufs B, int32_t V, int32_t 
             e = B.cert[k < n1 ? offj + k : offj + capj - n2 + (k - n1)];
             offer(q, (uint32_t)e.x, (uint32_t)e.y, a1, a2);
         }
-        append(B, (int32_t)i, a1, a2, e);
+        stage_put(S, a1, a2, e);
     }
+    stage_flush(S, B, i);
 }
 
 // Node 0's certificate -> caller's buffer (F then F'), plus counts and status.
@@ -230,7 +260,7 @@ void launch_merge_round(const Plan& P, const DevBufs& B, int32_t step, hipStream
     const int64_t merges = (P.M - step - 1) / (2 * (int64_t)step) + 1;
     int64_t maxcap = 0;
     for (int64_t i = 0; i + step < P.M; i += 2 * (int64_t)step) maxcap = std::max(maxcap, P.cap[i + step]);
-    const int32_t tile = P.tile;
+    const int32_t tile = kTile;
     const int64_t tpm = std::max<int64_t>(1, (maxcap + tile - 1) / tile);
     hipLaunchKernelGGL(k_merge, dim3((unsigned)(merges * tpm)), dim3(kBlock), 0, s, B, P.V, P.M, step, tile,
                        (int32_t)tpm);
@@ -245,5 +275,6 @@ void launch_copy_out(const Plan& P, const DevBufs& B, int32_t* d_out, int64_t ou
 }
 
 int32_t block_size() { return kBlock; }
+int32_t tile_size() { return kTile; }
 
 }  // namespace br

@@ -9,6 +9,10 @@
 // instead of a scan over all vertices; an explicit stack instead of
 // recursion; a new search from every vertex not yet reached.  A tree edge
 // (p, c) is a bridge iff low[c] > disc[p].
+//
+// Layout for a latency-bound walk: arcs are (target, edge id) pairs grouped by
+// source, and each vertex's discovery time and low-link share one 8-byte
+// slot, so visiting an arc touches one arc slot and one vertex slot.
 #include <algorithm>
 #include <cstring>
 
@@ -20,7 +24,7 @@ void certificate_bridges(const int2* f1, int64_t n1, const int2* f2, int64_t n2,
                          std::vector<uint64_t>& keys) {
     const int64_t m = n1 + n2;
     auto edge = [&](int64_t k) -> const int2& { return k < n1 ? f1[k] : f2[k - n1]; };
-    // adjacency (CSR) with edge ids; heads are int32: m <= 2(V-1) < 2^32
+    // adjacency grouped by source (counting sort), edge ids kept for the parent test
     S.head.assign((size_t)V + 1, 0);
     for (int64_t k = 0; k < m; k++) {
         const int2 e = edge(k);
@@ -30,62 +34,69 @@ void certificate_bridges(const int2* f1, int64_t n1, const int2* f2, int64_t n2,
     }
     for (int32_t v = 0; v < V; v++) S.head[v + 1] += S.head[v];
     const int64_t arcs = S.head[V];
-    S.adj_to.resize((size_t)std::max<int64_t>(arcs, 1));
-    S.adj_id.resize((size_t)std::max<int64_t>(arcs, 1));
-    S.st_it.assign(S.head.begin(), S.head.end() - 1);   // fill cursors, reused as DFS cursors below
+    S.arc.resize((size_t)std::max<int64_t>(arcs, 1));
+    S.fill.assign(S.head.begin(), S.head.end() - 1);
     for (int64_t k = 0; k < m; k++) {
         const int2 e = edge(k);
         if (e.x == e.y) continue;
-        int32_t a = S.st_it[e.x]++;
-        S.adj_to[a] = e.y;
-        S.adj_id[a] = (int32_t)k;
-        a = S.st_it[e.y]++;
-        S.adj_to[a] = e.x;
-        S.adj_id[a] = (int32_t)k;
+        S.arc[S.fill[e.x]++] = make_int2(e.y, (int32_t)k);
+        S.arc[S.fill[e.y]++] = make_int2(e.x, (int32_t)k);
     }
-    S.disc.assign((size_t)V, 0);    // 0 = not reached; times start at 1
-    S.low.resize((size_t)V);
+    S.dl.assign((size_t)V, make_int2(0, 0));    // disc 0 = not reached; times start at 1
     S.st_v.resize((size_t)V);
     S.st_pe.resize((size_t)V);
     S.st_it.resize((size_t)V);
+    const int2* arc = S.arc.data();
+    const int32_t* head = S.head.data();
+    int2* dl = S.dl.data();
     int32_t clock = 0;
     // roots: endpoints in certificate order (vertices without certificate
     // edges are isolated in the certificate and carry no bridge)
     for (int64_t k = 0; k < m; k++) {
         const int32_t r = edge(k).x;
-        if (S.disc[r]) continue;
+        if (dl[r].x) continue;
         int32_t top = 0;
         S.st_v[0] = r;
         S.st_pe[0] = -1;
-        S.st_it[0] = S.head[r];
-        S.disc[r] = S.low[r] = ++clock;
+        S.st_it[0] = head[r];
+        ++clock;
+        dl[r] = make_int2(clock, clock);
         while (top >= 0) {
             const int32_t x = S.st_v[top];
-            int32_t& it = S.st_it[top];
-            const int32_t end = S.head[x + 1];
+            int32_t it = S.st_it[top];
+            const int32_t end = head[x + 1];
+            const int32_t pe = S.st_pe[top];
+            int32_t lowx = dl[x].y;
             bool descended = false;
             while (it < end) {
-                const int32_t a = it++;
-                if (S.adj_id[a] == S.st_pe[top]) continue;
-                const int32_t y = S.adj_to[a];
-                if (!S.disc[y]) {
-                    S.disc[y] = S.low[y] = ++clock;
+                const int2 a = arc[it++];
+                if (it < end) __builtin_prefetch(&dl[arc[it].x]);
+                if (a.y == pe) continue;
+                const int32_t y = a.x;
+                const int32_t dy = dl[y].x;
+                if (!dy) {
+                    dl[x].y = lowx;
+                    S.st_it[top] = it;
+                    ++clock;
+                    dl[y] = make_int2(clock, clock);
                     ++top;
                     S.st_v[top] = y;
-                    S.st_pe[top] = S.adj_id[a];
-                    S.st_it[top] = S.head[y];
+                    S.st_pe[top] = a.y;
+                    S.st_it[top] = head[y];
+                    __builtin_prefetch(&arc[head[y]]);
                     descended = true;
                     break;
                 }
-                if (S.disc[y] < S.low[x]) S.low[x] = S.disc[y];
+                lowx = dy < lowx ? dy : lowx;
             }
             if (descended) continue;
+            dl[x].y = lowx;
             // x is finished: fold its low-link into its parent and test the tree edge
             --top;
             if (top >= 0) {
                 const int32_t p = S.st_v[top];
-                if (S.low[x] < S.low[p]) S.low[p] = S.low[x];
-                if (S.low[x] > S.disc[p]) {
+                if (lowx < dl[p].y) dl[p].y = lowx;
+                if (lowx > dl[p].x) {
                     const uint32_t a = (uint32_t)std::min(p, x), b = (uint32_t)std::max(p, x);
                     keys.push_back((uint64_t)a << 32 | b);
                 }

@@ -49,6 +49,31 @@ struct DevBufs {
     uint32_t* err = nullptr;       // bit 0: id out of range; bit 1: region overflow
 };
 
+// Batched path (one persistent launch over many small graphs).  Graph s of
+// the launch has edges [eoff[2s], eoff[2s+1]), V[s] vertices, Mg[s] chunks;
+// its node k lives at index k == 0 ? s : rbase[s] + k - 1 (all node-0 regions
+// come first); its merge counters start at cbase[s].
+struct BatchDev {
+    const int2* edges;
+    const int64_t* eoff;      // [2S] start, end
+    const int32_t* V;         // [S]
+    const int32_t* Mg;        // [S]
+    const int64_t* rbase;     // [S]
+    const int64_t* cbase;     // [S]
+    const int64_t* noff;      // [nodes] region offset (pairs)
+    const int64_t* ncap;      // [nodes] region capacity
+    const int64_t* items;     // [n_items] (s << 20) | chunk
+    int64_t n_items;
+    int2* cert;               // node regions
+    uint32_t* ncnt;           // [nodes][2]
+    uint32_t* arrive;         // merge arrival counters
+    uint32_t* queue;          // [1] next item
+    uint32_t* err;            // bit 0: id out of range; bit 1: region overflow
+};
+void launch_batched(const BatchDev& B, int blocks, hipStream_t s);
+int32_t batched_max_v_dev();
+int32_t batched_blocks_per_cu();
+
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 void launch_phase0(const Plan& P, const DevBufs& B, hipStream_t s);
 void launch_merge_round(const Plan& P, const DevBufs& B, int32_t step, hipStream_t s);
@@ -57,10 +82,18 @@ void launch_copy_out(const Plan& P, const DevBufs& B, int32_t* d_out, int64_t ou
 
 Plan make_plan(int64_t E, int32_t V, int32_t M);
 
+// Final step on the device (bridge_kernels.hip): scratch words it needs, and
+// the launch sequence over node 0's certificate; the bridges' keys land at
+// *d_keys (count at *d_n) on the device.
+int64_t device_bridges_words(int32_t V);
+int device_bridges(const Plan& P, const DevBufs& B, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s);
+
 // ---- host side of the path --------------------------------------------------
 // Algorithm 1 (iterative) on the certificate; appends canonical keys (min<<32|max).
 struct DfsScratch {
-    std::vector<int32_t> head, adj_to, adj_id, disc, low, st_v, st_pe, st_it;
+    std::vector<int32_t> head, fill, st_v, st_pe, st_it;
+    std::vector<int2> arc;       // (target, edge id) per arc, grouped by source
+    std::vector<int2> dl;        // (disc, low) per vertex
 };
 void certificate_bridges(const int2* f1, int64_t n1, const int2* f2, int64_t n2, int32_t V, DfsScratch& S,
                          std::vector<uint64_t>& keys);
@@ -84,6 +117,8 @@ struct br_ctx {
     br::DfsScratch dfs;
     std::vector<uint64_t> keys;
     int profiling = 0;
+    int final_step = 0;            // 0: host search (Algorithm 1), 1: device bridge step
+    int32_t* bws = nullptr;        // device bridge-step scratch inside the workspace
     br_profile prof{};
     hipEvent_t ev[8] = {};
     // batched path state

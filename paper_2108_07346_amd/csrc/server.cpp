@@ -1,13 +1,371 @@
-// Serving runtime (continuous batching) -- placeholder until implemented.
+// Serving runtime: continuous batching of bridge queries on one device.
+//
+// Requests enter a bounded FIFO.  A scheduler admits the head request as soon
+// as a device slot is free and the device-memory budget has room for it (its
+// edge list, its union-find state and its certificate regions); admitted
+// requests run concurrently, each on its slot's own stream and context, so
+// the certificate kernels of different requests overlap on the GPU and a new
+// request starts while others are still in flight.  Each request runs the full
+// path (phase tree + final search) and its latency is stamped from submission
+// to the moment its result is available.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+
 #include "internal.hpp"
+
+namespace br {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+    uint64_t ticket = 0;
+    std::vector<int32_t> h_edges;      // owned copy (host submissions)
+    const int32_t* d_edges = nullptr;  // caller's device buffer (device submissions)
+    int64_t E = 0;
+    int32_t V = 0;
+    int32_t M = 1;
+    int64_t bytes = 0;                 // budget charge
+    Clock::time_point t_submit;
+    // result
+    int status = BR_OK;
+    std::string msg;
+    std::vector<int32_t> bridges;
+    double latency_ms = 0;
+    bool done = false;
+};
+
+struct Slot {
+    br_ctx* ctx = nullptr;
+    hipStream_t stream = nullptr;
+    void* d_buf = nullptr;             // device copy of host-submitted edges
+    size_t d_cap = 0;
+    void* h_pin = nullptr;             // pinned staging for the upload
+    size_t h_cap = 0;
+    std::shared_ptr<Request> job;
+    std::thread th;
+};
+
+constexpr size_t kQueueMax = 65536;
+
+}  // namespace
+}  // namespace br
+
+struct br_server {
+    int device = 0;
+    int64_t budget = 0, in_use = 0;
+    std::vector<std::unique_ptr<br::Slot>> slots;
+    std::deque<std::shared_ptr<br::Request>> queue;
+    std::map<uint64_t, std::shared_ptr<br::Request>> all;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::mutex mu;
+    std::condition_variable cv_sched, cv_slot, cv_done;
+    std::thread sched;
+    // statistics
+    std::vector<double> lat;
+    int64_t edges_done = 0;
+    int64_t inflight = 0, peak_inflight = 0;
+    br::Clock::time_point busy_start;
+    double busy_ms = 0;
+};
+
+namespace br {
+namespace {
+
+// bytes a request needs on the device while it runs
+int64_t charge(int64_t E, int32_t V, int32_t M, bool host_edges) {
+    const Plan P = make_plan(E, V, M);
+    int64_t b = 8 * (int64_t)V * M + 8 * P.cert_pairs + 64 * (int64_t)M + (1 << 20);
+    if (host_edges) b += 8 * E;
+    return b;
+}
+
+// chunk count per request: keep chunks several times larger than V (so phase 0
+// compresses) and at most 64 of them
+int32_t choose_m(int64_t E, int32_t V) {
+    int64_t m = E / (8 * (int64_t)std::max(V, 1));
+    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(m, 64));
+}
+
+void run_request(br_server* S, Slot& sl, Request& r) {
+    const int32_t* d = r.d_edges;
+    if (!d && r.E > 0) {
+        const size_t bytes = 8 * (size_t)r.E;
+        if (sl.d_cap < bytes) {
+            if (sl.d_buf) (void)hipFree(sl.d_buf);
+            sl.d_buf = nullptr;
+            sl.d_cap = 0;
+            if (hipMalloc(&sl.d_buf, bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                r.status = BR_ENOMEM;
+                r.msg = "server: device allocation failed";
+                return;
+            }
+            sl.d_cap = bytes;
+        }
+        // upload through pinned staging in pieces (the host copy is pageable)
+        const size_t piece = size_t(64) << 20;
+        if (sl.h_cap < piece) {
+            if (sl.h_pin) (void)hipHostFree(sl.h_pin);
+            sl.h_pin = nullptr;
+            if (hipHostMalloc(&sl.h_pin, piece, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                r.status = BR_ENOMEM;
+                r.msg = "server: pinned allocation failed";
+                return;
+            }
+            sl.h_cap = piece;
+        }
+        const char* src = reinterpret_cast<const char*>(r.h_edges.data());
+        for (size_t o = 0; o < bytes; o += piece) {
+            const size_t n = std::min(piece, bytes - o);
+            std::memcpy(sl.h_pin, src + o, n);
+            if (hipMemcpyAsync(static_cast<char*>(sl.d_buf) + o, sl.h_pin, n, hipMemcpyHostToDevice, sl.stream) !=
+                    hipSuccess ||
+                hipStreamSynchronize(sl.stream) != hipSuccess) {
+                (void)hipGetLastError();
+                r.status = BR_EHIP;
+                r.msg = "server: upload failed";
+                return;
+            }
+        }
+        d = static_cast<const int32_t*>(sl.d_buf);
+    }
+    r.bridges.resize(2 * (size_t)std::max(r.V - 1, 1));
+    int64_t n = 0;
+    r.status = br_bridges_find(sl.ctx, d, r.E, r.V, r.M, r.bridges.data(), std::max(r.V - 1, 1), &n, sl.stream);
+    if (r.status != BR_OK) {
+        r.msg = br_last_error();
+        r.bridges.clear();
+        return;
+    }
+    r.bridges.resize(2 * (size_t)n);
+}
+
+void slot_loop(br_server* S, Slot* sl) {
+    (void)hipSetDevice(S->device);
+    for (;;) {
+        std::shared_ptr<Request> r;
+        {
+            std::unique_lock<std::mutex> g(S->mu);
+            S->cv_slot.wait(g, [&] { return S->stop || sl->job; });
+            if (!sl->job) return;   // stopping and idle
+            r = sl->job;
+        }
+        run_request(S, *sl, *r);
+        {
+            std::lock_guard<std::mutex> g(S->mu);
+            r->latency_ms = std::chrono::duration<double, std::milli>(Clock::now() - r->t_submit).count();
+            r->done = true;
+            r->h_edges.clear();
+            r->h_edges.shrink_to_fit();
+            S->in_use -= r->bytes;
+            S->inflight--;
+            if (S->inflight == 0) S->busy_ms += std::chrono::duration<double, std::milli>(Clock::now() - S->busy_start).count();
+            if (r->status == BR_OK) {
+                S->lat.push_back(r->latency_ms);
+                S->edges_done += r->E;
+            }
+            sl->job.reset();
+        }
+        S->cv_sched.notify_one();
+        S->cv_done.notify_all();
+    }
+}
+
+void sched_loop(br_server* S) {
+    std::unique_lock<std::mutex> g(S->mu);
+    for (;;) {
+        S->cv_sched.wait(g, [&] {
+            if (S->stop) return true;
+            if (S->queue.empty()) return false;
+            const auto& h = S->queue.front();
+            if (S->in_use + h->bytes > S->budget && S->inflight > 0) return false;
+            for (auto& s : S->slots)
+                if (!s->job) return true;
+            return false;
+        });
+        if (S->stop) return;
+        // admit the head (FIFO); one that exceeds the budget on its own runs alone
+        auto r = S->queue.front();
+        S->queue.pop_front();
+        for (auto& s : S->slots) {
+            if (!s->job) {
+                s->job = r;
+                break;
+            }
+        }
+        S->in_use += r->bytes;
+        if (S->inflight == 0) S->busy_start = Clock::now();
+        S->inflight++;
+        S->peak_inflight = std::max(S->peak_inflight, S->inflight);
+        S->cv_slot.notify_all();
+    }
+}
+
+int enqueue(br_server* S, std::shared_ptr<Request> r, uint64_t* ticket) {
+    std::lock_guard<std::mutex> g(S->mu);
+    if (S->queue.size() >= kQueueMax) return fail(BR_EBUSY, "server: queue full (%zu requests)", S->queue.size());
+    r->ticket = S->next_ticket++;
+    r->t_submit = Clock::now();
+    S->queue.push_back(r);
+    S->all[r->ticket] = r;
+    *ticket = r->ticket;
+    S->cv_sched.notify_one();
+    return BR_OK;
+}
+
+int take(br_server* S, uint64_t ticket, int32_t* h_out, int64_t cap, int64_t* n, bool wait, int* done) {
+    std::unique_lock<std::mutex> g(S->mu);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return fail(BR_EINVAL, "server: unknown ticket %llu", (unsigned long long)ticket);
+    auto r = it->second;
+    if (wait) S->cv_done.wait(g, [&] { return r->done; });
+    if (done) *done = r->done ? 1 : 0;
+    if (!r->done) return BR_OK;
+    if (r->status != BR_OK) {
+        const int st = r->status;
+        const std::string msg = r->msg;
+        S->all.erase(it);
+        return fail(st, "%s", msg.c_str());
+    }
+    const int64_t nb = (int64_t)r->bridges.size() / 2;
+    *n = nb;
+    if (nb > cap) return fail(BR_ECAP, "server: %lld bridges, capacity %lld", (long long)nb, (long long)cap);
+    std::copy(r->bridges.begin(), r->bridges.end(), h_out);
+    S->all.erase(it);
+    return BR_OK;
+}
+
+}  // namespace
+}  // namespace br
 
 using namespace br;
 
 extern "C" {
-int br_server_create(br_server**, int, int64_t, int32_t) { return fail(BR_EINVAL, "server: not built yet"); }
-int br_submit(br_server*, const int32_t*, int64_t, int32_t, uint64_t*) { return fail(BR_EINVAL, "server: not built yet"); }
-int br_poll(br_server*, uint64_t, int32_t*, int64_t, int64_t*, int*) { return fail(BR_EINVAL, "server: not built yet"); }
-int br_wait(br_server*, uint64_t, int32_t*, int64_t, int64_t*) { return fail(BR_EINVAL, "server: not built yet"); }
-int br_server_stats(br_server*, br_server_stats_t*, int) { return fail(BR_EINVAL, "server: not built yet"); }
-int br_server_destroy(br_server*) { return BR_OK; }
+
+int br_server_create(br_server** out, int device, int64_t mem_budget, int32_t max_slots) {
+    if (!out || mem_budget <= 0 || max_slots < 1 || max_slots > 64) return fail(BR_EINVAL, "br_server_create: bad argument");
+    *out = nullptr;
+    auto S = std::make_unique<br_server>();
+    S->device = device;
+    S->budget = mem_budget;
+    for (int32_t i = 0; i < max_slots; i++) {
+        auto sl = std::make_unique<Slot>();
+        int rc = br_create(&sl->ctx, device);
+        if (rc) {
+            for (auto& s : S->slots) br_destroy(s->ctx);
+            return rc;
+        }
+        if (hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess) {
+            br_destroy(sl->ctx);
+            for (auto& s : S->slots) br_destroy(s->ctx);
+            return hip_fail(hipGetLastError(), "hipStreamCreate");
+        }
+        S->slots.push_back(std::move(sl));
+    }
+    br_server* raw = S.release();
+    for (auto& sl : raw->slots) sl->th = std::thread(slot_loop, raw, sl.get());
+    raw->sched = std::thread(sched_loop, raw);
+    *out = raw;
+    return BR_OK;
 }
+
+static int submit_common(br_server* S, std::shared_ptr<Request> r, uint64_t* ticket, bool host) {
+    r->M = choose_m(r->E, r->V);
+    r->bytes = charge(r->E, r->V, r->M, host);
+    if (r->bytes > S->budget)
+        return fail(BR_ENOMEM, "server: request needs %lld bytes, budget is %lld", (long long)r->bytes,
+                    (long long)S->budget);
+    return enqueue(S, std::move(r), ticket);
+}
+
+int br_submit(br_server* S, const int32_t* h_edges, int64_t E, int32_t V, uint64_t* ticket) {
+    if (!S || !ticket || E < 0 || V < 1 || (E > 0 && !h_edges)) return fail(BR_EINVAL, "br_submit: bad argument");
+    auto r = std::make_shared<Request>();
+    r->E = E;
+    r->V = V;
+    r->h_edges.assign(h_edges, h_edges + 2 * E);
+    return submit_common(S, std::move(r), ticket, true);
+}
+
+int br_submit_device(br_server* S, const int32_t* d_edges, int64_t E, int32_t V, uint64_t* ticket) {
+    if (!S || !ticket || E < 0 || V < 1 || (E > 0 && !d_edges)) return fail(BR_EINVAL, "br_submit_device: bad argument");
+    auto r = std::make_shared<Request>();
+    r->E = E;
+    r->V = V;
+    r->d_edges = d_edges;
+    return submit_common(S, std::move(r), ticket, false);
+}
+
+int br_poll(br_server* S, uint64_t ticket, int32_t* h_out, int64_t cap, int64_t* n, int* done) {
+    if (!S || !n || !done || cap < 0 || (cap > 0 && !h_out)) return fail(BR_EINVAL, "br_poll: bad argument");
+    return take(S, ticket, h_out, cap, n, false, done);
+}
+
+int br_wait(br_server* S, uint64_t ticket, int32_t* h_out, int64_t cap, int64_t* n) {
+    if (!S || !n || cap < 0 || (cap > 0 && !h_out)) return fail(BR_EINVAL, "br_wait: bad argument");
+    return take(S, ticket, h_out, cap, n, true, nullptr);
+}
+
+int br_server_stats(br_server* S, br_server_stats_t* out, int reset) {
+    if (!S || !out) return fail(BR_EINVAL, "br_server_stats: bad argument");
+    std::lock_guard<std::mutex> g(S->mu);
+    std::vector<double> l = S->lat;
+    std::sort(l.begin(), l.end());
+    std::memset(out, 0, sizeof *out);
+    out->completed = (int64_t)l.size();
+    if (!l.empty()) {
+        auto pct = [&](double p) { return l[std::min(l.size() - 1, (size_t)(p * (l.size() - 1) + 0.5))]; };
+        out->p50_ms = pct(0.50);
+        out->p99_ms = pct(0.99);
+        double s = 0;
+        for (double x : l) s += x;
+        out->mean_ms = s / l.size();
+        out->max_ms = l.back();
+    }
+    double busy = S->busy_ms;
+    if (S->inflight > 0) busy += std::chrono::duration<double, std::milli>(Clock::now() - S->busy_start).count();
+    out->edges_per_s = busy > 0 ? S->edges_done / (busy / 1000.0) : 0.0;
+    out->peak_inflight = S->peak_inflight;
+    if (reset) {
+        S->lat.clear();
+        S->edges_done = 0;
+        S->busy_ms = 0;
+        S->peak_inflight = S->inflight;
+        if (S->inflight > 0) S->busy_start = Clock::now();
+    }
+    return BR_OK;
+}
+
+int br_server_destroy(br_server* S) {
+    if (!S) return BR_OK;
+    {
+        std::unique_lock<std::mutex> g(S->mu);
+        // finish what is queued or running
+        S->cv_done.wait(g, [&] { return S->queue.empty() && S->inflight == 0; });
+        S->stop = true;
+    }
+    S->cv_sched.notify_all();
+    S->cv_slot.notify_all();
+    if (S->sched.joinable()) S->sched.join();
+    for (auto& sl : S->slots) {
+        if (sl->th.joinable()) sl->th.join();
+        if (sl->stream) (void)hipStreamDestroy(sl->stream);
+        if (sl->d_buf) (void)hipFree(sl->d_buf);
+        if (sl->h_pin) (void)hipHostFree(sl->h_pin);
+        br_destroy(sl->ctx);
+    }
+    delete S;
+    return BR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,103 @@
+"""GPU parity of the batched path (one persistent launch over many graphs)
+against the CPU oracle, graph by graph, bit-exact."""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_07346_amd as br
+    c = br.Context(0)
+    yield c
+    c.close()
+
+
+def pack(graphs):
+    off = np.zeros(len(graphs) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([g[0].shape[0] for g in graphs])
+    e = np.concatenate([g[0] for g in graphs]).astype(np.int32) if off[-1] else np.zeros((0, 2), np.int32)
+    return e, off, np.array([g[1] for g in graphs], dtype=np.int32)
+
+
+def check_all(ctx, e, off, Vs, chunk):
+    d = torch.from_numpy(np.ascontiguousarray(e)).cuda()
+    pairs, boff = ctx.find_batched(d, off, Vs, chunk)
+    for g in range(len(Vs)):
+        want = oracle.bridges(e[off[g]:off[g + 1]], int(Vs[g]))
+        got = pairs[boff[g]:boff[g + 1]]
+        assert np.array_equal(got, want), (g, int(Vs[g]), int(off[g + 1] - off[g]), chunk)
+    return pairs, boff
+
+
+def test_batched_workload_prefix_all_chunk_sizes(ctx):
+    b = graphgen.batched(0, n_graphs=192)
+    for chunk in (4096, 16384, 65536, 0):
+        say("batched prefix chunk=%d" % chunk)
+        check_all(ctx, b.edges, b.offsets, b.V, chunk)
+
+
+def test_batched_full_workload(ctx):
+    b = graphgen.batched(0, n_graphs=4096)
+    say("batched full: %d graphs, %d edges" % (b.G, b.edges.shape[0]))
+    check_all(ctx, b.edges, b.offsets, b.V, 0)
+
+
+def test_mixed_sizes_and_edge_cases(ctx):
+    rng = np.random.default_rng(31)
+    graphs = []
+    for t in range(40):
+        V = int(rng.integers(1, 300))
+        graphs.append((rng.integers(0, V, size=(int(rng.integers(0, 4 * V)), 2)).astype(np.int32), V))
+    graphs.append((np.zeros((0, 2), np.int32), 1))                      # empty, V = 1
+    graphs.append((np.array([[0, 0], [0, 0]], np.int32), 1))            # loops only
+    graphs.append((np.array([[3, 1]], np.int32), 4096))                 # at the LDS limit
+    big = graphgen.planted(5, k=4, vc=6000, p=0.05, n_extra=1, n_pend=7)    # above the LDS limit
+    graphs.append((big.edges, big.V))
+    tree = np.stack([np.arange(4095), np.arange(1, 4096)], 1).astype(np.int32)
+    graphs.append((tree[np.random.default_rng(1).permutation(4095)], 4096))
+    e, off, Vs = pack(graphs)
+    for chunk in (64, 1000, 0):
+        say("mixed chunk=%d" % chunk)
+        check_all(ctx, e, off, Vs, chunk)
+
+
+def test_replay_and_alone_vs_batched(ctx):
+    b = graphgen.batched(7, n_graphs=64)
+    d = torch.from_numpy(b.edges).cuda()
+    p1, o1 = ctx.find_batched(d, b.offsets, b.V, 8192)
+    p2, o2 = ctx.find_batched(d, b.offsets, b.V, 8192)       # replayed HIP graph
+    assert np.array_equal(p1, p2) and np.array_equal(o1, o2)
+    d2 = d.clone()
+    p3, o3 = ctx.find_batched(d2, b.offsets, b.V, 8192)      # new buffer: recaptured
+    assert np.array_equal(p1, p3)
+    for g in range(0, 64, 7):
+        alone = ctx.find(d[b.offsets[g]:b.offsets[g + 1]].contiguous(), int(b.V[g]), 3)
+        assert np.array_equal(alone, p1[o1[g]:o1[g + 1]])
+
+
+def test_out_of_range_id_reported(ctx):
+    import paper_2108_07346_amd as br
+    e, off, Vs = pack([(np.array([[0, 1], [1, 2]], np.int32), 3), (np.array([[0, 5]], np.int32), 4)])
+    d = torch.from_numpy(e).cuda()
+    with pytest.raises(br.BridgeError) as ei:
+        ctx.find_batched(d, off, Vs, 64)
+    assert ei.value.code == br.BR_ERANGE
+    # and the context keeps working
+    e, off, Vs = pack([(np.array([[0, 1], [1, 2]], np.int32), 3)])
+    pairs, boff = ctx.find_batched(torch.from_numpy(e).cuda(), off, Vs, 64)
+    assert np.array_equal(pairs, [[0, 1], [1, 2]])

@@ -161,3 +161,32 @@ def test_concurrency_stress_same_bridges(ctx, dense):
         f1, f2 = ctx.cert_build(d, g.V, 1)
         hashes.add(hash(f1.cpu().numpy().tobytes()))
     say("distinct certificates over runs: %d" % len(hashes))
+
+
+def test_device_final_step_bit_exact(ctx, small, dense):
+    # the final step on the GPU (Euler-tour rooting + subtree low/high test)
+    g, want, d = dense
+    ctx.set_final_step(1)
+    try:
+        for M in (1, 16, 1024):
+            say("device final step dense M=%d" % M)
+            assert np.array_equal(ctx.find(d, g.V, M), want)
+        assert np.array_equal(ctx.find(dev(small.edges), small.V, 4), oracle.bridges(small.edges, small.V))
+        rng = np.random.default_rng(24)
+        for t in range(80):
+            V = int(rng.integers(1, 300))
+            e = rng.integers(0, V, size=(int(rng.integers(0, 5 * V)), 2)).astype(np.int32)
+            M = int(rng.choice([1, 2, 5, 33]))
+            say("device final step random t=%d V=%d E=%d M=%d" % (t, V, e.shape[0], M))
+            assert np.array_equal(ctx.find(dev(e), V, M), oracle.bridges(e, V)), (V, M)
+        Vt = 3000
+        par = np.array([rng.integers(max(0, i - 3), i) for i in range(1, Vt)])      # deep tree
+        tree = np.stack([par, np.arange(1, Vt)], 1).astype(np.int32)
+        assert np.array_equal(ctx.find(dev(tree), Vt, 3), oracle.bridges(tree, Vt))
+        path = np.stack([np.arange(Vt - 1), np.arange(1, Vt)], 1).astype(np.int32)
+        assert np.array_equal(ctx.find(dev(path[::-1].copy()), Vt, 1), oracle.bridges(path, Vt))
+        empty = torch.zeros((0, 2), dtype=torch.int32, device="cuda")
+        assert ctx.find(empty, 5, 1).shape[0] == 0
+        assert ctx.find(dev([[0, 0]]), 1, 1).shape[0] == 0
+    finally:
+        ctx.set_final_step(0)

@@ -51,3 +51,32 @@ def test_create_fails_cleanly_without_gpu():
 
 def test_max_v_limit():
     assert br.batched_max_v() >= 64
+
+
+def test_server_create_fails_cleanly_without_gpu():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    assert br.load().br_server_create(ctypes.byref(h), 0, 1 << 30, 4) in (br.BR_EHIP, br.BR_EINVAL)
+    assert br.load().br_server_create(ctypes.byref(h), 0, 0, 4) == br.BR_EINVAL
+    t = ctypes.c_uint64(0)
+    assert br.load().br_submit(None, None, 0, 1, ctypes.byref(t)) == br.BR_EINVAL
+
+
+def test_certificate_bridges_host_entry_matches_oracle():
+    import numpy as np
+    import graphgen
+    import oracle
+    g = graphgen.config("small")
+    for M in (1, 4, 33):
+        f1, f2, _ = oracle.phase_tree(g.edges, g.V, M)
+        assert np.array_equal(br.certificate_bridges(f1, f2, g.V), oracle.bridges(g.edges, g.V))
+    rng = np.random.default_rng(0)
+    for _ in range(200):
+        V = int(rng.integers(1, 30))
+        e = rng.integers(0, V, size=(int(rng.integers(0, 60)), 2)).astype(np.int32)
+        k = int(rng.integers(0, e.shape[0] + 1))
+        assert np.array_equal(br.certificate_bridges(e[:k], e[k:], V), oracle.bridges(e, V))
+    with pytest.raises(br.BridgeError):
+        br.certificate_bridges(np.array([[0, 3]]), np.zeros((0, 2)), 3)
