@@ -34,12 +34,22 @@ Plan make_plan(int64_t E, int32_t V, int32_t M) {
     P.V = V;
     P.M = M;
     while ((int64_t(1) << P.rounds) < M) P.rounds++;
+    // phase-0 tiles fill the LDS stage; merge rounds size their own tiles
     P.tile = tile_size();
     const int64_t per = (E + M - 1) / M;   // largest chunk
     P.tpc = (int32_t)std::max<int64_t>(1, (per + P.tile - 1) / P.tile);
     P.xcd_map = M >= 8 ? 1 : 0;
     const int64_t chunk_slots = P.xcd_map ? 8 * ((M + 7) / 8) : M;
     P.blocks0 = E > 0 ? chunk_slots * P.tpc : 0;
+    // Stages within each chunk, separated by a full path compression: the
+    // first 2V edges form most components (many hooks, contention), the next
+    // ones up to 8V mostly finish F', and the rest is then mostly rejected by
+    // comparing the endpoints' representatives.  Chunks of at most 2V edges
+    // run in one stage.
+    P.stages = {0};
+    for (int64_t b : {2 * (int64_t)V, 8 * (int64_t)V})
+        if (b < per) P.stages.push_back(b);
+    P.stages.push_back(per);
     auto lo = [&](int64_t i) { return i * (E / M) + (i * (E % M)) / M; };
     const int64_t bound = 2 * (int64_t(V) - 1);
     P.off.resize(M);

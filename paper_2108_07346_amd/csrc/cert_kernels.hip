@@ -154,8 +154,9 @@ __device__ __forceinline__ int64_t chunk_lo(int64_t E, int32_t M, int64_t i) {
 }
 
 // Phase 0: workgroup b certifies one tile of one chunk into that chunk's state.
+// Stage [rel_lo, rel_hi) of every chunk (offsets relative to the chunk start).
 __global__ void __launch_bounds__(kBlock) k_phase0(DevBufs B, int64_t E, int32_t V, int32_t M, int32_t tile,
-                                                   int32_t tpc, int32_t xcd_map) {
+                                                   int32_t tpc, int32_t xcd_map, int64_t rel_lo, int64_t rel_hi) {
     int64_t c, s;
     const int64_t b = blockIdx.x;
     if (xcd_map) {       // chunk c lives on XCD c % 8: blocks b with b % 8 == c % 8
@@ -167,8 +168,8 @@ __global__ void __launch_bounds__(kBlock) k_phase0(DevBufs B, int64_t E, int32_t
         s = b % tpc;
     }
     if (c >= M) return;
-    const int64_t lo = chunk_lo(E, M, c), hi = chunk_lo(E, M, c + 1);
-    const int64_t t0 = lo + s * (int64_t)tile;
+    const int64_t lo = chunk_lo(E, M, c), hi = min(chunk_lo(E, M, c + 1), lo + rel_hi);
+    const int64_t t0 = lo + rel_lo + s * (int64_t)tile;
     const int64_t t1 = min(t0 + (int64_t)tile, hi);
     if (t0 >= t1) return;
     __shared__ Stage S;
@@ -236,6 +237,25 @@ __global__ void k_copy_out(DevBufs B, int2* out, int64_t out_cap, int64_t* count
     }
 }
 
+// Full path compression of the first `slots` chunk states between stages: every
+// vertex points straight at its representative, so that later edges inside a
+// component are rejected by the two-load test in offer() without any search.
+// No hook runs concurrently, so plain stores are safe.
+__global__ void k_compress(uint32_t* state, int32_t V, int64_t slots) {
+    const int64_t n = (int64_t)V * slots;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t* q = state + (size_t)(k / V) * 2 * (size_t)V;
+        const uint32_t x = (uint32_t)(k % V);
+        for (int f = 0; f < 2; f++) {
+            const uint32_t d = q[2 * (size_t)x + f];
+            if (d == 0) continue;
+            uint32_t r = x - d;
+            for (uint32_t e = q[2 * (size_t)r + f]; e != 0; e = q[2 * (size_t)r + f]) r -= e;
+            if (r != x - d) q[2 * (size_t)x + f] = x - r;
+        }
+    }
+}
+
 __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
         p[k] = v;
@@ -251,18 +271,38 @@ void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
 }
 
 void launch_phase0(const Plan& P, const DevBufs& B, hipStream_t s) {
-    if (P.blocks0 == 0) return;
-    hipLaunchKernelGGL(k_phase0, dim3((unsigned)P.blocks0), dim3(kBlock), 0, s, B, P.E, P.V, P.M, P.tile, P.tpc,
-                       P.xcd_map);
+    if (P.E == 0) return;
+    const int64_t per = (P.E + P.M - 1) / P.M;
+    const int64_t chunk_slots = P.xcd_map ? 8 * (((int64_t)P.M + 7) / 8) : P.M;
+    for (size_t k = 0; k + 1 < P.stages.size(); k++) {
+        const int64_t rlo = P.stages[k], rhi = std::min(P.stages[k + 1], per);
+        if (rlo >= rhi) break;
+        if (k > 0) {
+            const int64_t n = (int64_t)P.V * P.M;
+            hipLaunchKernelGGL(k_compress, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536))),
+                               dim3(256), 0, s, B.state, P.V, (int64_t)P.M);
+        }
+        const int64_t tpc = std::max<int64_t>(1, (rhi - rlo + P.tile - 1) / P.tile);
+        hipLaunchKernelGGL(k_phase0, dim3((unsigned)(chunk_slots * tpc)), dim3(kBlock), 0, s, B, P.E, P.V, P.M, P.tile,
+                           (int32_t)tpc, P.xcd_map, rlo, rhi);
+    }
 }
 
 void launch_merge_round(const Plan& P, const DevBufs& B, int32_t step, hipStream_t s) {
     const int64_t merges = (P.M - step - 1) / (2 * (int64_t)step) + 1;
-    int64_t maxcap = 0;
-    for (int64_t i = 0; i + step < P.M; i += 2 * (int64_t)step) maxcap = std::max(maxcap, P.cap[i + step]);
-    const int32_t tile = kTile;
+    int64_t maxcap = 0, total = 0;
+    for (int64_t i = 0; i + step < P.M; i += 2 * (int64_t)step) {
+        maxcap = std::max(maxcap, P.cap[i + step]);
+        total += P.cap[i + step];
+    }
+    // tile sized so that the round spreads over about a thousand workgroups:
+    // small tiles for the few large merges at the top of the tree, larger ones
+    // (fewer reservations on each node's counters) when many merges run at once
+    int64_t tile = (total + 1023) / 1024;
+    tile = (tile + kBlock - 1) / kBlock * kBlock;
+    tile = std::max<int64_t>(kBlock, std::min<int64_t>(tile, kTile));
     const int64_t tpm = std::max<int64_t>(1, (maxcap + tile - 1) / tile);
-    hipLaunchKernelGGL(k_merge, dim3((unsigned)(merges * tpm)), dim3(kBlock), 0, s, B, P.V, P.M, step, tile,
+    hipLaunchKernelGGL(k_merge, dim3((unsigned)(merges * tpm)), dim3(kBlock), 0, s, B, P.V, P.M, step, (int32_t)tile,
                        (int32_t)tpm);
 }
 

@@ -26,10 +26,11 @@ struct Plan {
     int64_t E = 0;
     int32_t V = 0, M = 1;
     int32_t rounds = 0;            // ceil(log2 M)
-    int32_t tile = 0;              // edges per workgroup tile
+    int32_t tile = 0;              // edges per workgroup tile in phase 0
     int32_t tpc = 0;               // tiles per chunk (same for every chunk)
     int32_t xcd_map = 0;           // keep each chunk's workgroups on one XCD
-    int64_t blocks0 = 0;           // phase-0 grid
+    int64_t blocks0 = 0;           // phase-0 grid (single stage)
+    std::vector<int64_t> stages;   // chunk-relative stage boundaries, last = chunk size bound
     std::vector<int64_t> off, cap; // per node: certificate region (pairs)
     int64_t cert_pairs = 0;        // sum of caps
     std::vector<int64_t> round_cap;// per round: largest sibling cap

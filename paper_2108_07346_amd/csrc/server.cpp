@@ -47,8 +47,6 @@ struct Slot {
     hipStream_t stream = nullptr;
     void* d_buf = nullptr;             // device copy of host-submitted edges
     size_t d_cap = 0;
-    void* h_pin = nullptr;             // pinned staging for the upload
-    size_t h_cap = 0;
     std::shared_ptr<Request> job;
     std::thread th;
 };
@@ -111,31 +109,13 @@ void run_request(br_server* S, Slot& sl, Request& r) {
             }
             sl.d_cap = bytes;
         }
-        // upload through pinned staging in pieces (the host copy is pageable)
-        const size_t piece = size_t(64) << 20;
-        if (sl.h_cap < piece) {
-            if (sl.h_pin) (void)hipHostFree(sl.h_pin);
-            sl.h_pin = nullptr;
-            if (hipHostMalloc(&sl.h_pin, piece, hipHostMallocDefault) != hipSuccess) {
-                (void)hipGetLastError();
-                r.status = BR_ENOMEM;
-                r.msg = "server: pinned allocation failed";
-                return;
-            }
-            sl.h_cap = piece;
-        }
-        const char* src = reinterpret_cast<const char*>(r.h_edges.data());
-        for (size_t o = 0; o < bytes; o += piece) {
-            const size_t n = std::min(piece, bytes - o);
-            std::memcpy(sl.h_pin, src + o, n);
-            if (hipMemcpyAsync(static_cast<char*>(sl.d_buf) + o, sl.h_pin, n, hipMemcpyHostToDevice, sl.stream) !=
-                    hipSuccess ||
-                hipStreamSynchronize(sl.stream) != hipSuccess) {
-                (void)hipGetLastError();
-                r.status = BR_EHIP;
-                r.msg = "server: upload failed";
-                return;
-            }
+        // one asynchronous upload from the request's own copy (the runtime
+        // pipelines pageable transfers through its staging buffers)
+        if (hipMemcpyAsync(sl.d_buf, r.h_edges.data(), bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess) {
+            (void)hipGetLastError();
+            r.status = BR_EHIP;
+            r.msg = "server: upload failed";
+            return;
         }
         d = static_cast<const int32_t*>(sl.d_buf);
     }
@@ -361,7 +341,6 @@ int br_server_destroy(br_server* S) {
         if (sl->th.joinable()) sl->th.join();
         if (sl->stream) (void)hipStreamDestroy(sl->stream);
         if (sl->d_buf) (void)hipFree(sl->d_buf);
-        if (sl->h_pin) (void)hipHostFree(sl->h_pin);
         br_destroy(sl->ctx);
     }
     delete S;
