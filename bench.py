@@ -106,6 +106,25 @@ def bench_batched(args):
     chunk = int(ctx.profile()["rounds"])
     phases = {k: v / args.steps for k, v in acc.items()}
     ms_step = 1000 * dt / args.steps
+    # the same batch with the final step on the GPU (one bridge step over all certificates)
+    ctx.set_final_step(1)
+    ctx.set_profiling(True)
+    ctx.find_batched(d, b.offsets, b.V, args.chunk, stream)
+    accd = {"ms_phase0": 0.0, "ms_cert": 0.0, "ms_dfs": 0.0}
+    torch.cuda.synchronize()
+    td = time.perf_counter()
+    for _ in range(args.steps):
+        pd, bd = ctx.find_batched(d, b.offsets, b.V, args.chunk, stream)
+        p = ctx.profile()
+        for k in accd:
+            accd[k] += p[k]
+    torch.cuda.synchronize()
+    dtd = time.perf_counter() - td
+    ctx.set_final_step(0)
+    assert np.array_equal(pd, pairs) and np.array_equal(bd, boff)
+    gpu_final = {"edges_per_s": E * args.steps / dtd, "ms_per_step": 1000 * dtd / args.steps,
+                 "ms_device": round(accd["ms_phase0"] / args.steps, 4)}
+    print("bench: batched, final step on GPU %s" % json.dumps(gpu_final), file=sys.stderr, flush=True)
     # baseline: the plain path, one call (certificate kernels + host search) per graph
     ctx.set_profiling(False)
     views = [d[b.offsets[g]:b.offsets[g + 1]] for g in range(b.G)]
@@ -142,8 +161,63 @@ def bench_batched(args):
         "detail": {"phases_ms": {k: round(v, 4) for k, v in phases.items()},
                    "one_call_per_graph": {"ms": 1000 * t_base, "edges_per_s": E / t_base,
                                           "speedup_of_batched": t_base / (dt / args.steps)},
+                   "final_step_on_gpu": gpu_final,
                    "bridges": int(boff[-1])},
     }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+def bench_figures(args):
+    """The paper's figure experiments (Figs. 2-4) as synthetic sweeps: the
+    whole path per point, both final steps, with the paper's complexity
+    O(E/M + V log M) printed beside each point (no numbers exist in the paper)."""
+    import numpy as np
+    import torch
+    import graphgen
+    import paper_2108_07346_amd as br
+    ctx = br.Context(0)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for fig, points in graphgen.FIGURES.items():
+        rows = []
+        cache = {}
+        for V, E, M in points:
+            if (V, E) not in cache:
+                cache.clear()
+                g = graphgen.figure(V, E)
+                cache[(V, E)] = (g, torch.from_numpy(g.edges).cuda())
+            g, d = cache[(V, E)]
+            row = {"V": g.V, "E": g.E, "M": M, "model_E_over_M_plus_V_log2M": g.E / M + g.V * np.log2(max(M, 2))}
+            for mode in (0, 1):
+                ctx.set_final_step(mode)
+                ctx.set_profiling(False)
+                for _ in range(2):
+                    ctx.find(d, g.V, M, stream)
+                ctx.set_profiling(True)
+                reps = 5
+                acc = 0.0
+                ph = {"ms_phase0": 0.0, "ms_merge": 0.0}
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for _ in range(reps):
+                    ctx.find(d, g.V, M, stream)
+                    p = ctx.profile()
+                    for k in ph:
+                        ph[k] += p[k] / reps
+                torch.cuda.synchronize()
+                ms = 1000 * (time.perf_counter() - t) / reps
+                row["ms_host_search" if mode == 0 else "ms_gpu_final_step"] = round(ms, 4)
+                row.update({k: round(v, 4) for k, v in ph.items()})
+            ctx.set_final_step(0)
+            rows.append(row)
+            print("bench: %s %s" % (fig, json.dumps(row)), file=sys.stderr, flush=True)
+        out[fig] = rows
+    line = {"metric": "paper figures 2-4 as synthetic sweeps (ms per bridge query)", "value": None, "unit": "ms",
+            "n_gpus": 1, "steps": 5, "warmup": 2, "ms_per_step": None, "higher_is_better": False,
+            "scaling": "strong", "vs_baseline": None, "dtype": "int32",
+            "data": "synthetic (seeded planted-cluster generator)", "config": {"workload": "figures"},
+            "roofline": None, "cpu_baseline": None, "detail": out}
     print(json.dumps(line), flush=True)
     ctx.close()
 
@@ -171,6 +245,7 @@ def bench_served(args):
 
     def run(qps, slots, resident):
         srv = br.Server(0, mem_budget=64 << 30, max_slots=slots)
+        srv.set_final_step(args.final_step)
         n = int(min(args.max_requests, max(20, qps * args.seconds)))
         gaps = rng.exponential(1.0 / qps, size=n)
         sched = np.cumsum(gaps)
@@ -218,6 +293,7 @@ def bench_served(args):
         "ms_per_step": head["p50_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int32", "data": "synthetic (seeded planted-cluster generator)",
         "config": {"workload": "served", "pool": len(pool), "slots": args.slots, "qps": qps_list,
+                   "final_step": "gpu" if args.final_step else "host search",
                    "parallelism": "single GPU"},
         "roofline": None, "cpu_baseline": None, "detail": results,
     }
@@ -229,13 +305,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="dense", choices=["small", "dense", "large", "batched", "served"])
+    ap.add_argument("--workload", default="dense", choices=["small", "dense", "large", "batched", "served", "figures"])
     ap.add_argument("--qps", default="100,200,500,1000,2000,5000", help="served: comma-separated QPS")
     ap.add_argument("--seconds", type=float, default=2.0, help="served: seconds per QPS point")
     ap.add_argument("--max-requests", type=int, default=600, help="served: cap per QPS point")
     ap.add_argument("--pool", type=int, default=32, help="served: distinct requests generated")
     ap.add_argument("--slots", type=int, default=8, help="served: device slots")
     ap.add_argument("--resident", action="store_true", help="served: also run with edges resident on the GPU")
+    ap.add_argument("--final-step", type=int, default=0, help="served: 0 host search, 1 bridge step on the GPU")
     ap.add_argument("--graphs", type=int, default=4096, help="batched: number of graphs")
     ap.add_argument("--chunk", type=int, default=0, help="batched: chunk_edges (0 = tuned)")
     ap.add_argument("--M", type=int, default=None)
@@ -268,6 +345,8 @@ def main():
         return bench_batched(args)
     if args.workload == "served":
         return bench_served(args)
+    if args.workload == "figures":
+        return bench_figures(args)
     M = args.M or {"small": 4, "dense": 16, "large": 4096}[args.workload]
     t0 = time.perf_counter()
     g = graphgen.config(args.workload)

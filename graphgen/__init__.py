@@ -196,6 +196,35 @@ def batched(seed: int = 0, n_graphs: int = 4096, threads: int | None = None) -> 
     return Batch(edges, off, np.array([x.V for x in gs], dtype=np.int32), params)
 
 
+def figure_params(V: int, E: int, seed: int = 0) -> dict:
+    """Recipe of the paper's figure workloads (Figs. 2-4 give only |V| and |E|):
+    clusters of 100 vertices holding about a tenth of the edges, the rest
+    uniform between clusters, a cluster tree and V/1000 pendant vertices; V
+    counts all vertices; E is met to within ~2% (the intra-cluster edges are Bernoulli draws)."""
+    pend = max(1, V // 1000)
+    vc = V - pend
+    k = max(2, vc // 100)
+    pairs = k * 100 * 99 / 2 if vc >= 200 else vc * (vc - 1) / 2
+    intra = min(0.1 * E, pairs)
+    p = min(1.0, intra / max(pairs, 1))
+    cross = max(0, E - int(round(p * pairs)) - (k - 1) - pend)
+    return dict(seed=(seed * 0x9E3779B97F4A7C15 + V * 31 + E) & (2**64 - 1), k=k, vc=vc, p=p, n_extra=0,
+                n_cross=cross, n_pend=pend)
+
+
+# Fig. 2: |E| = 10^7, |V| = 10^5, M swept; Fig. 3: |E| = 10^5, M = 10, |V| swept;
+# Fig. 4: |V| = 10^5, M = 10, |E| swept.
+FIGURES = {
+    "fig2": [(100_000, 10_000_000, m) for m in (1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024)],
+    "fig3": [(v, 100_000, 10) for v in (1_000, 3_000, 10_000, 30_000, 100_000)],
+    "fig4": [(100_000, e, 10) for e in (100_000, 300_000, 1_000_000, 3_000_000, 10_000_000)],
+}
+
+
+def figure(V: int, E: int, seed: int = 0) -> Graph:
+    return planted(**figure_params(V, E, seed))
+
+
 def served_params(seed: int, r: int) -> dict:
     """Recipe of request r of the served workload."""
     s = _key2(seed ^ 0x5E77ED, r)

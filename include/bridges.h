@@ -100,6 +100,20 @@ int br_bridges_find(br_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t V, i
                     int64_t cap, int64_t* n_bridges, void* stream);
 
 /*
+ * br_two_edge_components -- the 2-edge-connected classes of the graph (its
+ * vertices grouped by "still connected after removing any one edge", i.e.
+ * the components left once the bridges of Section I are removed), through the
+ * same certificate path: the certificate keeps every single-edge-removal
+ * connectivity of the input (Section III), so the classes are those of the
+ * certificate without its bridges (found by Algorithm 1 on the host).
+ *   h_label  host int32 [V]: the smallest vertex id of each vertex's class.
+ *   *n_classes number of classes (= number of bridges + number of components).
+ * Synchronous; errors as for br_bridges_find.
+ */
+int br_two_edge_components(br_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t V, int32_t M, int32_t* h_label,
+                           int64_t* n_classes, void* stream);
+
+/*
  * br_certificate_bridges -- the final step alone, on the host: Algorithm 1's
  * depth-first search (Section IV-A) on a certificate S = F u F' given as two
  * host edge lists, then canonical order.  Any edge lists are accepted (the
@@ -210,6 +224,8 @@ int br_submit_device(br_server* srv, const int32_t* d_edges, int64_t E, int32_t 
 int br_poll(br_server* srv, uint64_t ticket, int32_t* h_out, int64_t cap, int64_t* n, int* done);
 int br_wait(br_server* srv, uint64_t ticket, int32_t* h_out, int64_t cap, int64_t* n);
 int br_server_stats(br_server* srv, br_server_stats_t* out, int reset);
+/* Final step of the requests admitted from now on (see br_set_final_step). */
+int br_server_set_final_step(br_server* srv, int mode);
 int br_server_destroy(br_server* srv);
 
 #ifdef __cplusplus

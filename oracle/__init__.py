@@ -119,6 +119,57 @@ def phase_tree(edges, V: int, M: int):
     return x0[:n1.value].copy(), x0[n1.value:n1.value + n2.value].copy(), sizes
 
 
+def two_edge_labels(edges, V: int) -> np.ndarray:
+    """2-edge-connected classes: the components of G without its bridges
+    (Section I's bridges from the oracle above); label = smallest vertex of
+    the class.  Plain sequential union-find."""
+    e = _as_edges(edges)
+    b = bridges(e, V)
+    bset = set(map(tuple, b.tolist()))
+    par = np.arange(V, dtype=np.int64)
+
+    def find(x):
+        r = x
+        while par[r] != r:
+            r = par[r]
+        while par[x] != r:
+            par[x], x = r, par[x]
+        return r
+
+    for u, v in e.tolist():
+        if u == v or (min(u, v), max(u, v)) in bset:
+            continue
+        a, c = find(u), find(v)
+        if a != c:
+            par[max(a, c)] = min(a, c)
+    return np.array([find(x) for x in range(V)], dtype=np.int32)
+
+
+def brute_two_edge_labels(edges, V: int) -> np.ndarray:
+    """The definition for tiny graphs: u and v share a class iff they stay
+    connected after removing any single edge."""
+    e = [(int(a), int(b)) for a, b in _as_edges(edges)]
+
+    def comp(pairs):
+        par = list(range(V))
+
+        def f(x):
+            while par[x] != x:
+                x = par[x]
+            return x
+        for a, b in pairs:
+            ra, rb = f(a), f(b)
+            if ra != rb:
+                par[ra] = rb
+        return [f(x) for x in range(V)]
+
+    cs = [comp(e)] + [comp(e[:i] + e[i + 1:]) for i in range(len(e))]
+    lab = []
+    for v in range(V):
+        lab.append(min(u for u in range(V) if all(c[u] == c[v] for c in cs)))
+    return np.array(lab, dtype=np.int32)
+
+
 # ---- definitions written out for tiny graphs ---------------------------------
 
 def _count_components_py(V: int, pairs) -> int:

@@ -19,10 +19,10 @@ SO_PATH = os.path.join(_DIR, "libbridges.so")
 BR_OK, BR_EINVAL, BR_ERANGE, BR_ENOMEM, BR_EHIP, BR_EBUSY, BR_ECAP, BR_EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
 
 EXPORTS = ["br_last_error", "br_create", "br_destroy", "br_cert_build", "br_cert_merge", "br_bridges_find",
-           "br_certificate_bridges",
+           "br_certificate_bridges", "br_two_edge_components",
            "br_bridges_find_batched", "br_batched_max_v", "br_set_profiling", "br_set_final_step", "br_get_profile",
            "br_server_create", "br_submit", "br_submit_device", "br_poll", "br_wait", "br_server_stats",
-           "br_server_destroy"]
+           "br_server_set_final_step", "br_server_destroy"]
 
 
 class BridgeError(RuntimeError):
@@ -63,6 +63,7 @@ def load():
     lib.br_cert_build.argtypes = [vp, vp, i64, i32, i32, vp, i64, vp, vp]
     lib.br_cert_merge.argtypes = [vp, vp, i64, vp, i64, i32, vp, i64, vp, vp]
     lib.br_bridges_find.argtypes = [vp, vp, i64, i32, i32, vp, i64, p64, vp]
+    lib.br_two_edge_components.argtypes = [vp, vp, i64, i32, i32, vp, p64, vp]
     lib.br_certificate_bridges.argtypes = [vp, i64, vp, i64, i32, vp, i64, p64]
     lib.br_bridges_find_batched.argtypes = [vp, vp, vp, vp, i32, i32, vp, i64, vp, vp]
     lib.br_batched_max_v.restype = i32
@@ -75,6 +76,7 @@ def load():
     lib.br_poll.argtypes = [vp, ctypes.c_uint64, vp, i64, p64, ctypes.POINTER(ctypes.c_int)]
     lib.br_wait.argtypes = [vp, ctypes.c_uint64, vp, i64, p64]
     lib.br_server_stats.argtypes = [vp, ctypes.POINTER(_ServerStats), ctypes.c_int]
+    lib.br_server_set_final_step.argtypes = [vp, ctypes.c_int]
     lib.br_server_destroy.argtypes = [vp]
     _lib = lib
     return lib
@@ -144,6 +146,15 @@ class Context:
         _check(self._lib.br_bridges_find(self._h, ptr, E, int(V), int(M), out.ctypes.data, cap, ctypes.byref(n),
                                          _stream(stream)))
         return out[:n.value].copy()
+
+    def two_edge_components(self, edges, V: int, M: int = 1, stream=None):
+        """(labels int32 [V] = smallest vertex of each 2-edge-connected class, number of classes)."""
+        ptr, E = _edges_arg(edges)
+        lab = np.empty(max(int(V), 1), dtype=np.int32)
+        n = ctypes.c_int64(0)
+        _check(self._lib.br_two_edge_components(self._h, ptr, E, int(V), int(M), lab.ctypes.data, ctypes.byref(n),
+                                                _stream(stream)))
+        return lab[:int(V)].copy(), n.value
 
     def _cert_result(self, out, counts):
         import torch
@@ -227,6 +238,9 @@ class Server:
         n = ctypes.c_int64(0)
         _check(self._lib.br_wait(self._h, ticket, out.ctypes.data, cap, ctypes.byref(n)))
         return out[:n.value].copy()
+
+    def set_final_step(self, mode: int):
+        _check(self._lib.br_server_set_final_step(self._h, int(mode)))
 
     def stats(self, reset: bool = False) -> dict:
         st = _ServerStats()

@@ -391,6 +391,63 @@ int br_bridges_find(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int
     return BR_OK;
 }
 
+int br_two_edge_components(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int32_t M, int32_t* h_label,
+                           int64_t* n_classes, void* stream) {
+    if (!c || !h_label || !n_classes) return fail(BR_EINVAL, "br_two_edge_components: null argument");
+    int rc = check_common(d_edges, E, V);
+    if (rc) return rc;
+    if (M < 1) return fail(BR_EINVAL, "M = %d < 1", M);
+    if (V > (1 << 29)) return fail(BR_EINVAL, "V = %d above the host search limit 2^29", V);
+    BR_HIP(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    BR_HIP(hipEventSynchronize(c->ev[7]));
+    const int saved = c->final_step;
+    c->final_step = 0;
+    Plan P;
+    DevBufs B;
+    rc = run_certificate(c, d_edges, E, nullptr, 0, V, M, s, P, B);
+    c->final_step = saved;
+    if (rc) return rc;
+    const int64_t cap0 = P.cap[0];
+    rc = ensure_pinned(c, sizeof(int2) * (size_t)std::max<int64_t>(cap0, 1) + 64);
+    if (rc) return rc;
+    char* h = static_cast<char*>(c->pinned);
+    uint32_t* hc = reinterpret_cast<uint32_t*>(h);
+    int2* hx = reinterpret_cast<int2*>(h + 64);
+    BR_HIP(hipMemcpyAsync(hc, B.cnt, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    BR_HIP(hipMemcpyAsync(hc + 2, B.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    if (cap0 > 0) BR_HIP(hipMemcpyAsync(hx, B.cert + P.off[0], sizeof(int2) * cap0, hipMemcpyDeviceToHost, s));
+    BR_HIP(hipStreamSynchronize(s));
+    const uint32_t n1 = hc[0], n2 = hc[1], err = hc[2];
+    if (err & 1u) return fail(BR_ERANGE, "br_two_edge_components: an edge has a vertex id outside [0, %d)", V);
+    if (err != 0 || (int64_t)n1 + n2 > cap0) return fail(BR_EINTERNAL, "br_two_edge_components: region overflow");
+    c->keys.clear();
+    certificate_bridges(hx, n1, hx + cap0 - n2, n2, V, c->dfs, c->keys);
+    canonical_sort(c->keys);
+    // union of the certificate's non-bridge edges (a bridge has no parallel copy)
+    std::vector<int32_t> par((size_t)V);
+    for (int32_t v = 0; v < V; v++) par[v] = v;
+    auto find = [&](int32_t x) {
+        while (par[x] != x) { par[x] = par[par[x]]; x = par[x]; }
+        return x;
+    };
+    int64_t classes = V;
+    auto join = [&](const int2& e) {
+        const uint64_t k = (uint64_t)(uint32_t)std::min(e.x, e.y) << 32 | (uint32_t)std::max(e.x, e.y);
+        if (std::binary_search(c->keys.begin(), c->keys.end(), k)) return;
+        int32_t a = find(e.x), b = find(e.y);
+        if (a == b) return;
+        if (a < b) std::swap(a, b);
+        par[a] = b;     // the smaller id stays the root: the label is the class minimum
+        classes--;
+    };
+    for (uint32_t k = 0; k < n1; k++) join(hx[k]);
+    for (uint32_t k = 0; k < n2; k++) join(hx[cap0 - n2 + k]);
+    for (int32_t v = 0; v < V; v++) h_label[v] = find(v);
+    *n_classes = classes;
+    return BR_OK;
+}
+
 int br_certificate_bridges(const int32_t* h_f1, int64_t n1, const int32_t* h_f2, int64_t n2, int32_t V,
                            int32_t* h_bridges, int64_t cap, int64_t* n_bridges) {
     if (!n_bridges || n1 < 0 || n2 < 0 || (n1 > 0 && !h_f1) || (n2 > 0 && !h_f2) || cap < 0 || (cap > 0 && !h_bridges))

@@ -98,10 +98,22 @@ struct BatchPlan {
     int2* h_area0 = nullptr;
     uint32_t* h_cnt0 = nullptr;
     uint32_t* h_err = nullptr;
+    // final step on the device: the certificates of all small graphs as one
+    // certificate of their disjoint union (vertex ids shifted by vbase)
+    std::vector<int64_t> vbase;      // [S+1]
+    int64_t vtot = 0;
+    int32_t *n1x = nullptr, *n2x = nullptr, *scan_scr = nullptr, *bws = nullptr;
+    int2 *f1c = nullptr, *f2c = nullptr;
+    uint32_t* cnt2 = nullptr;
+    uint64_t* d_keys = nullptr;
+    uint32_t* d_nkeys = nullptr;
+    uint32_t* h_nkeys = nullptr;
+    uint64_t* h_keys = nullptr;
     // captured launch
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     const void* graph_edges = nullptr;
+    int graph_mode = -1;
     int blocks = 0;
     ~BatchPlan() {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -118,6 +130,8 @@ struct BatchState {
     std::map<std::string, int32_t> tuned;               // batch shape -> chunk_edges
     std::vector<DfsScratch> scratch;
     std::vector<std::vector<uint64_t>> keys;
+    std::unique_ptr<uint64_t[]> outk;           // per-graph bridge slots (reused, never zero-filled)
+    size_t outk_n = 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipEvent_t k0 = nullptr, k1 = nullptr;   // around the replayed graph (counter clear + persistent kernel)
 };
@@ -203,6 +217,20 @@ int build_plan(BatchPlan& P, const int64_t* eoff, const int32_t* V, int32_t G, i
     const size_t o_ncap = o; o = a256(o + 8 * (size_t)P.nodes);
     const size_t o_items = o; o = a256(o + 8 * std::max<size_t>(P.items.size(), 1));
     const size_t o_cert = o; o = a256(o + 8 * (size_t)std::max<int64_t>(P.cert_pairs, 1));
+    P.vbase.assign((size_t)S + 1, 0);
+    for (int32_t s = 0; s < S; s++) P.vbase[s + 1] = P.vbase[s] + V[P.small[s]];
+    P.vtot = P.vbase[S];
+    if (P.vtot >= (int64_t(1) << 30)) return fail(BR_EINVAL, "batched: %lld vertices in one batch", (long long)P.vtot);
+    const int64_t fcap = std::max<int64_t>(1, P.vtot - S);   // sum of (V_s - 1): room for every F and every F'
+    const size_t o_vb = o; o = a256(o + 8 * (size_t)(S + 1));
+    const size_t o_root = o; o = a256(o + 4 * (size_t)std::max<int64_t>(P.vtot, 1));
+    const size_t o_n1x = o; o = a256(o + 4 * (size_t)(S + 1));
+    const size_t o_n2x = o; o = a256(o + 4 * (size_t)(S + 1));
+    const size_t o_f1c = o; o = a256(o + 8 * (size_t)fcap);
+    const size_t o_f2c = o; o = a256(o + 8 * (size_t)fcap);
+    const size_t o_cnt2 = o; o = a256(o + 16);
+    const size_t o_sscr = o; o = a256(o + 4 * (size_t)scan_scratch_words(S + 1));
+    const size_t o_bws = o; o = a256(o + 4 * (size_t)device_bridges_words((int32_t)std::max<int64_t>(P.vtot, 2)));
     BR_HIP(hipMalloc(&P.dmem, o));
     char* d = static_cast<char*>(P.dmem);
     std::vector<int32_t> sV(S);
@@ -222,6 +250,14 @@ int build_plan(BatchPlan& P, const int64_t* eoff, const int32_t* V, int32_t G, i
         BR_HIP(hipMemcpy(d + o_ncap, P.ncap.data(), 8 * (size_t)P.nodes, hipMemcpyHostToDevice));
         BR_HIP(hipMemcpy(d + o_items, P.items.data(), 8 * P.items.size(), hipMemcpyHostToDevice));
     }
+    if (S) BR_HIP(hipMemcpy(d + o_vb, P.vbase.data(), 8 * (size_t)S, hipMemcpyHostToDevice));
+    P.n1x = reinterpret_cast<int32_t*>(d + o_n1x);
+    P.n2x = reinterpret_cast<int32_t*>(d + o_n2x);
+    P.f1c = reinterpret_cast<int2*>(d + o_f1c);
+    P.f2c = reinterpret_cast<int2*>(d + o_f2c);
+    P.cnt2 = reinterpret_cast<uint32_t*>(d + o_cnt2);
+    P.scan_scr = reinterpret_cast<int32_t*>(d + o_sscr);
+    P.bws = reinterpret_cast<int32_t*>(d + o_bws);
     uint32_t* clr = reinterpret_cast<uint32_t*>(d + o_clear);
     P.dev.eoff = reinterpret_cast<const int64_t*>(d + o_eoff);
     P.dev.V = reinterpret_cast<const int32_t*>(d + o_V);
@@ -237,44 +273,68 @@ int build_plan(BatchPlan& P, const int64_t* eoff, const int32_t* V, int32_t G, i
     P.dev.arrive = clr + 2 * P.nodes;
     P.dev.queue = clr + 2 * P.nodes + P.counters;
     P.dev.err = P.dev.queue + 1;
+    P.dev.vbase = reinterpret_cast<const int64_t*>(d + o_vb);
+    P.dev.rootw = reinterpret_cast<uint32_t*>(d + o_root);
     // pinned host staging
-    const size_t hbytes = a256(8 * (size_t)std::max<int64_t>(P.area0, 1)) + a256(8 * (size_t)std::max(S, 1)) + 256;
+    const size_t hbytes = a256(8 * (size_t)std::max<int64_t>(P.area0, 1)) + a256(8 * (size_t)std::max(S, 1)) + 256 +
+                          a256(8 * (size_t)std::max<int64_t>(P.vtot, 1)) + 256;
     BR_HIP(hipHostMalloc(&P.hmem, hbytes, hipHostMallocDefault));
     char* h = static_cast<char*>(P.hmem);
     P.h_area0 = reinterpret_cast<int2*>(h);
     P.h_cnt0 = reinterpret_cast<uint32_t*>(h + a256(8 * (size_t)std::max<int64_t>(P.area0, 1)));
     P.h_err = P.h_cnt0 + 2 * (size_t)std::max(S, 1);
+    P.h_nkeys = P.h_err + 4;
+    P.h_keys = reinterpret_cast<uint64_t*>(h + a256(8 * (size_t)std::max<int64_t>(P.area0, 1)) +
+                                           a256(8 * (size_t)std::max(S, 1)) + 256);
     P.blocks = std::max(1, cus * batched_blocks_per_cu());
     return BR_OK;
 }
 
 // enqueue clear -> kernel -> copies on s (captured into P.graph on first use)
-// the captured part: clear the counters, then the persistent kernel
-int enqueue(BatchPlan& P, const int32_t* d_edges, hipStream_t s) {
+// the captured part: clear the counters, the persistent kernel, and with the
+// final step on the device the combined certificate and its bridge step
+int enqueue(BatchPlan& P, const int32_t* d_edges, hipStream_t s, int mode) {
     P.dev.edges = reinterpret_cast<const int2*>(d_edges);
     launch_fill_u32(P.dev.ncnt, (int64_t)P.clear_words, 0u, s);
     BR_HIP(hipGetLastError());
     if (P.dev.n_items) launch_batched(P.dev, P.blocks, s);
     BR_HIP(hipGetLastError());
+    if (mode == 1 && !P.small.empty()) {
+        const int32_t S = (int32_t)P.small.size();
+        launch_combine(P.dev, S, P.n1x, P.n2x, P.f1c, P.f2c, P.cnt2, P.scan_scr, s);
+        BR_HIP(hipGetLastError());
+        int32_t maxv = 2;
+        for (int32_t g : P.small) maxv = std::max(maxv, P.V[g]);
+        int rc = device_bridges_cert(P.f1c, P.f2c, 1, P.cnt2, P.dev.rootw, 1, (int32_t)std::max<int64_t>(P.vtot, 2),
+                                     maxv, P.bws, &P.d_keys, &P.d_nkeys, s);
+        if (rc) return rc;
+        BR_HIP(hipGetLastError());
+    }
     return BR_OK;
 }
 
-// node-0 certificates, their counters and the error word to the host
-int copy_back(BatchPlan& P, hipStream_t s) {
+// node-0 certificates (or, with the final step on the device, the number of
+// bridges), their counters and the error word to the host
+int copy_back(BatchPlan& P, hipStream_t s, int mode) {
     const int32_t S = (int32_t)P.small.size();
+    if (mode == 1) {
+        if (S) BR_HIP(hipMemcpyAsync(P.h_nkeys, P.d_nkeys, 4, hipMemcpyDeviceToHost, s));
+        BR_HIP(hipMemcpyAsync(P.h_err, P.dev.err, 4, hipMemcpyDeviceToHost, s));
+        return BR_OK;
+    }
     if (P.area0) BR_HIP(hipMemcpyAsync(P.h_area0, P.dev.cert, 8 * (size_t)P.area0, hipMemcpyDeviceToHost, s));
     if (S) BR_HIP(hipMemcpyAsync(P.h_cnt0, P.dev.ncnt, 8 * (size_t)S, hipMemcpyDeviceToHost, s));
     BR_HIP(hipMemcpyAsync(P.h_err, P.dev.err, 4, hipMemcpyDeviceToHost, s));
     return BR_OK;
 }
 
-int run_device(BatchState& st, BatchPlan& P, const int32_t* d_edges) {
+int run_device(BatchState& st, BatchPlan& P, const int32_t* d_edges, int mode) {
     hipStream_t s = st.stream;
-    if (P.exec && P.graph_edges == d_edges) {
+    if (P.exec && P.graph_edges == d_edges && P.graph_mode == mode) {
         BR_HIP(hipEventRecord(st.k0, s));
         BR_HIP(hipGraphLaunch(P.exec, s));
         BR_HIP(hipEventRecord(st.k1, s));
-        return copy_back(P, s);
+        return copy_back(P, s, mode);
     }
     if (P.exec) {
         (void)hipGraphExecDestroy(P.exec);
@@ -285,7 +345,7 @@ int run_device(BatchState& st, BatchPlan& P, const int32_t* d_edges) {
         P.graph = nullptr;
     }
     BR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue(P, d_edges, s);
+    int rc = enqueue(P, d_edges, s, mode);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(s, &g);
     if (rc) {
@@ -296,10 +356,11 @@ int run_device(BatchState& st, BatchPlan& P, const int32_t* d_edges) {
     P.graph = g;
     BR_HIP(hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0));
     P.graph_edges = d_edges;
+    P.graph_mode = mode;
     BR_HIP(hipEventRecord(st.k0, s));
     BR_HIP(hipGraphLaunch(P.exec, s));
     BR_HIP(hipEventRecord(st.k1, s));
-    return copy_back(P, s);
+    return copy_back(P, s, mode);
 }
 
 std::string shape_key(const int64_t* eoff, const int32_t* V, int32_t G) {
@@ -409,7 +470,7 @@ int br_bridges_find_batched(br_ctx* c, const int32_t* d_edges, const int64_t* h_
                 float ms = 0.f;
                 for (int rep = 0; rep < 2; rep++) {
                     BR_HIP(hipEventRecord(st.e0, st.stream));
-                    rc = run_device(st, *P, d_edges);
+                    rc = run_device(st, *P, d_edges, 0);
                     if (rc) return rc;
                     BR_HIP(hipEventRecord(st.e1, st.stream));
                     BR_HIP(hipEventSynchronize(st.e1));
@@ -427,8 +488,9 @@ int br_bridges_find_batched(br_ctx* c, const int32_t* d_edges, const int64_t* h_
     BatchPlan* P = nullptr;
     int rc = get_plan(c, st, h_edge_off, h_V, G, C, &P);
     if (rc) return rc;
+    const int mode = c->final_step;
     if (c->profiling) BR_HIP(hipEventRecord(st.e0, st.stream));
-    rc = run_device(st, *P, d_edges);
+    rc = run_device(st, *P, d_edges, mode);
     if (rc) return rc;
     if (c->profiling) BR_HIP(hipEventRecord(st.e1, st.stream));
     BR_HIP(hipStreamSynchronize(st.stream));
@@ -436,35 +498,61 @@ int br_bridges_find_batched(br_ctx* c, const int32_t* d_edges, const int64_t* h_
     if (*P->h_err & 1u) return fail(BR_ERANGE, "batched: an edge has a vertex id outside its graph's [0, V)");
     if (*P->h_err) return fail(BR_EINTERNAL, "batched: certificate region overflow");
 
-    // final search per small graph, on the host pool; bridges of graph g go to
-    // a slot of V_g - 1 pairs, compacted afterwards
+    // final search per small graph; bridges of graph g go to a slot of V_g - 1
+    // pairs, compacted afterwards
     const int32_t S = (int32_t)P->small.size();
     std::vector<int64_t> slot(S + 1, 0), nb(G, 0);
     for (int32_t s = 0; s < S; s++) slot[s + 1] = slot[s] + std::max(P->V[P->small[s]] - 1, 0);
-    std::vector<uint64_t> outk((size_t)std::max<int64_t>(slot[S], 1));
-    std::atomic<int32_t> next{0};
-    std::atomic<int> bad{0};
-    st.pool->run([&](int w) {
-        DfsScratch& sc = st.scratch[w];
-        std::vector<uint64_t>& keys = st.keys[w];
-        for (;;) {
-            const int32_t s = next.fetch_add(1);
-            if (s >= S) break;
-            const int32_t g = P->small[s];
-            const uint32_t n1 = P->h_cnt0[2 * s], n2 = P->h_cnt0[2 * s + 1];
-            const int64_t off = P->noff[s], capg = P->ncap[s];
-            if ((int64_t)n1 + n2 > capg) {
-                bad = 1;
-                continue;
-            }
-            keys.clear();
-            certificate_bridges(P->h_area0 + off, n1, P->h_area0 + off + capg - n2, n2, P->V[g], sc, keys);
-            canonical_sort(keys);
-            std::copy(keys.begin(), keys.end(), outk.begin() + slot[s]);
-            nb[g] = (int64_t)keys.size();
+    if (st.outk_n < (size_t)std::max<int64_t>(slot[S], 1)) {
+        st.outk_n = (size_t)std::max<int64_t>(slot[S], 1);
+        st.outk.reset(new uint64_t[st.outk_n]);
+    }
+    uint64_t* outk = st.outk.get();
+    if (mode == 1) {
+        // bridges of the combined certificate, regrouped by graph
+        const uint32_t nk = S ? std::min<uint32_t>(*P->h_nkeys, (uint32_t)std::max<int64_t>(P->vtot, 1)) : 0;
+        if (nk) {
+            BR_HIP(hipMemcpyAsync(P->h_keys, P->d_keys, 8 * (size_t)nk, hipMemcpyDeviceToHost, st.stream));
+            BR_HIP(hipStreamSynchronize(st.stream));
         }
-    });
-    if (bad) return fail(BR_EINTERNAL, "batched: certificate counts exceed their region");
+        std::vector<int64_t> fillp(slot.begin(), slot.end() - 1);
+        for (uint32_t i = 0; i < nk; i++) {
+            const int64_t a = (int64_t)(P->h_keys[i] >> 32), b = (int64_t)(P->h_keys[i] & 0xffffffffu);
+            const int32_t s = (int32_t)(std::upper_bound(P->vbase.begin(), P->vbase.end(), a) - P->vbase.begin()) - 1;
+            if (s < 0 || s >= S || b >= P->vbase[s + 1] || fillp[s] >= slot[s + 1])
+                return fail(BR_EINTERNAL, "batched: bridge (%lld, %lld) outside its graph", (long long)a, (long long)b);
+            const uint64_t vb = (uint64_t)P->vbase[s];
+            outk[fillp[s]++] = ((uint64_t)(a - vb) << 32) | (uint64_t)(b - vb);
+        }
+        for (int32_t s = 0; s < S; s++) {
+            std::sort(outk + slot[s], outk + fillp[s]);
+            nb[P->small[s]] = fillp[s] - slot[s];
+        }
+    } else {
+        std::atomic<int32_t> next{0};
+        std::atomic<int> bad{0};
+        st.pool->run([&](int w) {
+            DfsScratch& sc = st.scratch[w];
+            std::vector<uint64_t>& keys = st.keys[w];
+            for (;;) {
+                const int32_t s = next.fetch_add(1);
+                if (s >= S) break;
+                const int32_t g = P->small[s];
+                const uint32_t n1 = P->h_cnt0[2 * s], n2 = P->h_cnt0[2 * s + 1];
+                const int64_t off = P->noff[s], capg = P->ncap[s];
+                if ((int64_t)n1 + n2 > capg) {
+                    bad = 1;
+                    continue;
+                }
+                keys.clear();
+                certificate_bridges(P->h_area0 + off, n1, P->h_area0 + off + capg - n2, n2, P->V[g], sc, keys);
+                canonical_sort(keys);
+                std::copy(keys.begin(), keys.end(), outk + slot[s]);
+                nb[g] = (int64_t)keys.size();
+            }
+        });
+        if (bad) return fail(BR_EINTERNAL, "batched: certificate counts exceed their region");
+    }
     auto t2 = std::chrono::steady_clock::now();
     // graphs above the LDS limit: the plain path, with the same chunk size
     std::vector<std::vector<int32_t>> large_out(P->large.size());

@@ -82,9 +82,31 @@ __device__ __forceinline__ bool lunite(uint32_t* q, uint32_t u, uint32_t v) {
     }
 }
 
+// Offer (u,v) to F, then to F'.  Both parents come from one 32-bit word per
+// endpoint: when the endpoints already share a parent in a forest (the usual
+// case once the state is compressed) that forest rejects without a search.
 __device__ __forceinline__ void loffer(uint32_t* q, uint32_t u, uint32_t v, bool& a1, bool& a2) {
-    a1 = lunite<0>(q, u, v);
-    a2 = !a1 && lunite<1>(q, u, v);
+    const uint32_t wu = q[u], wv = q[v];
+    const uint32_t p1u = u - (wu & 0xffffu), p1v = v - (wv & 0xffffu);
+    a1 = (p1u != p1v) && lunite<0>(q, p1u, p1v);
+    a2 = false;
+    if (!a1) {
+        const uint32_t p2u = u - (wu >> 16), p2v = v - (wv >> 16);
+        a2 = (p2u != p2v) && lunite<1>(q, p2u, p2v);
+    }
+}
+
+// Full path compression of the LDS state (no concurrent hooks: called between
+// barriers), so that later edges inside a component hit the shared-parent test.
+__device__ void lcompress(uint32_t* q, uint32_t V) {
+    for (uint32_t x = threadIdx.x; x < V; x += blockDim.x) {
+        const uint32_t w = q[x];
+        uint32_t r1 = x - (w & 0xffffu), r2 = x - (w >> 16);
+        for (uint32_t d = q[r1] & 0xffffu; d; d = q[r1] & 0xffffu) r1 -= d;
+        for (uint32_t d = q[r2] >> 16; d; d = q[r2] >> 16) r2 -= d;
+        const uint32_t nw = (x - r1) | ((x - r2) << 16);
+        if (nw != w) atomicCAS(&q[x], w, nw);
+    }
 }
 
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
@@ -116,7 +138,16 @@ __device__ void certify_chunk(LdsState& S, const BatchDev& B, int64_t t0, int64_
     for (uint32_t x = threadIdx.x; x < V; x += kBB) S.q[x] = 0;
     if (threadIdx.x == 0) { S.n1 = 0; S.n2 = 0; }
     __syncthreads();
+    // compress after the first 2V and 8V edges (dense chunks are then mostly
+    // rejected by the shared-parent test)
+    int64_t next_cmp = t0 + 2 * (int64_t)V;
     for (int64_t base = t0; base < t1; base += kBB) {
+        if (base >= next_cmp) {
+            __syncthreads();
+            lcompress(S.q, V);
+            __syncthreads();
+            next_cmp = next_cmp == t0 + 2 * (int64_t)V ? t0 + 8 * (int64_t)V : INT64_MAX;
+        }
         const int64_t i = base + threadIdx.x;
         bool a1 = false, a2 = false;
         int2 e = make_int2(0, 0);
@@ -186,7 +217,12 @@ __global__ void __launch_bounds__(kBB) k_batched(BatchDev B) {
                 B.ncnt[2 * nidx(node)] = n1;
                 B.ncnt[2 * nidx(node) + 1] = n2;
             }
-            if (step >= Mg) break;                          // node 0 holds the graph's certificate
+            if (step >= Mg) {                               // node 0 holds the graph's certificate
+                // the LDS state encodes its F: publish the roots of F's trees
+                const int64_t vb = B.vbase[g];
+                for (uint32_t x = threadIdx.x; x < V; x += kBB) B.rootw[vb + x] = (S.q[x] & 0xffffu) ? 1u : 0u;
+                break;
+            }
             const int64_t i = node & ~(2 * step - 1);       // left node of this round's pair
             const int64_t j = i + step;
             if (j >= Mg) {                                  // no partner: pass through
@@ -238,6 +274,52 @@ __global__ void __launch_bounds__(kBB) k_batched(BatchDev B) {
         }
         __syncthreads();
     }
+}
+
+namespace {
+
+__global__ void k_counts(const BatchDev B, int32_t S, int32_t* n1x, int32_t* n2x) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s <= S; s += (int64_t)gridDim.x * blockDim.x) {
+        if (s < S) {
+            const uint32_t cap = (uint32_t)B.ncap[s];
+            const uint32_t a = min(B.ncnt[2 * s], cap);
+            n1x[s] = (int32_t)a;
+            n2x[s] = (int32_t)min(B.ncnt[2 * s + 1], cap - a);
+        } else {
+            n1x[s] = 0;
+            n2x[s] = 0;
+        }
+    }
+}
+
+// one workgroup per graph: copy its F and F' with ids shifted by vbase
+__global__ void k_combine(const BatchDev B, int32_t S, const int32_t* o1, const int32_t* o2, int2* f1c, int2* f2c,
+                          uint32_t* cnt2) {
+    for (int64_t s = blockIdx.x; s < S; s += gridDim.x) {
+        const int64_t off = B.noff[s], cap = B.ncap[s], vb = B.vbase[s];
+        const int32_t n1 = o1[s + 1] - o1[s], n2 = o2[s + 1] - o2[s];
+        for (int32_t k = threadIdx.x; k < n1 + n2; k += blockDim.x) {
+            const int2 e = k < n1 ? B.cert[off + k] : B.cert[off + cap - n2 + (k - n1)];
+            const int2 o = make_int2((int32_t)(e.x + vb), (int32_t)(e.y + vb));
+            if (k < n1) f1c[o1[s] + k] = o;
+            else f2c[o2[s] + (k - n1)] = o;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        cnt2[0] = (uint32_t)o1[S];
+        cnt2[1] = (uint32_t)o2[S];
+    }
+}
+
+}  // namespace
+
+void launch_combine(const BatchDev& B, int32_t S, int32_t* n1x, int32_t* n2x, int2* f1c, int2* f2c, uint32_t* cnt2,
+                    int32_t* scan_scratch, hipStream_t s) {
+    hipLaunchKernelGGL(k_counts, dim3((unsigned)std::max(1, (S + 256) / 256)), dim3(256), 0, s, B, S, n1x, n2x);
+    device_scan(n1x, (int64_t)S + 1, scan_scratch, s);
+    device_scan(n2x, (int64_t)S + 1, scan_scratch, s);
+    hipLaunchKernelGGL(k_combine, dim3((unsigned)std::max(1, std::min(S, 65536))), dim3(256), 0, s, B, S, n1x, n2x, f1c,
+                       f2c, cnt2);
 }
 
 void launch_batched(const BatchDev& B, int blocks, hipStream_t s) {

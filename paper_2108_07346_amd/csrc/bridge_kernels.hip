@@ -98,7 +98,7 @@ __global__ void k_fill_adj(const int2* f1, const uint32_t* cnt, const int32_t* h
 
 // successor in the Euler tour; tours cut open at union-find roots of F
 __global__ void k_succ(const int2* f1, const uint32_t* cnt, const int32_t* head, const int32_t* adj,
-                       const int32_t* posof, const uint32_t* q, int32_t* nxt, int32_t* rank, int32_t* tail) {
+                       const int32_t* posof, const uint32_t* q, int32_t qs, int32_t* nxt, int32_t* rank, int32_t* tail) {
     const int64_t A = 2 * (int64_t)cnt[0];
     GRID_LOOP(a, A) {
         const int32_t y = arc_dst(f1, (int32_t)a);
@@ -106,7 +106,7 @@ __global__ void k_succ(const int2* f1, const uint32_t* cnt, const int32_t* head,
         const int32_t nx = (p + 1 < head[y + 1]) ? p + 1 : head[y];
         int32_t s = adj[nx];
         // arc (c -> r) closing the tour of root r: r's last listed arc is (r -> c)
-        if (q[2 * (size_t)y] == 0 && p == head[y + 1] - 1) s = -1;
+        if (q[qs * (size_t)y] == 0 && p == head[y + 1] - 1) s = -1;
         nxt[a] = s;
         rank[a] = s < 0 ? 0 : 1;
         tail[a] = s < 0 ? (int32_t)a : s;
@@ -132,12 +132,11 @@ __global__ void k_jump(const uint32_t* cnt, const int32_t* nxt, const int32_t* r
 }
 
 // per root: tour length (arcs) and vertex count; written at the root's slot
-__global__ void k_root_sizes(const int2* f1, const uint32_t* cnt, const int32_t* head, const int32_t* adj,
-                             const int32_t* rank, const uint32_t* q, int32_t V, int32_t* tour_len, int32_t* tree_n) {
-    (void)cnt;
+__global__ void k_root_sizes(const int32_t* head, const int32_t* adj, const int32_t* rank, const uint32_t* q, int32_t qs,
+                             int32_t V, int32_t* tour_len, int32_t* tree_n) {
     GRID_LOOP(r, (int64_t)V) {
         int32_t L = 0, nv = 0;
-        if (q[2 * (size_t)r] == 0 && head[r + 1] > head[r]) {
+        if (q[qs * (size_t)r] == 0 && head[r + 1] > head[r]) {
             L = rank[adj[head[r]]] + 1;
             nv = L / 2 + 1;
         }
@@ -173,14 +172,14 @@ __global__ void k_down(const int2* f1, const uint32_t* cnt, const int32_t* tail,
 }
 
 // preorder numbers; lo = hi = own preorder to start
-__global__ void k_preorder(const int2* f1, const uint32_t* q, const int32_t* head, const int32_t* in_arc,
+__global__ void k_preorder(const int2* f1, const uint32_t* q, int32_t qs, const int32_t* head, const int32_t* in_arc,
                            const int32_t* tail, const int32_t* pos, const int32_t* tour_base, const int32_t* down_ex,
                            const int32_t* vbase, const int32_t* tree_n, int32_t V, int32_t* pre, int32_t* sub, int32_t* lo,
                            int32_t* hi) {
     GRID_LOOP(v, (int64_t)V) {
         int32_t pv = -1;
         if (head[v + 1] > head[v]) {
-            if (q[2 * (size_t)v] == 0) {         // root of its tree
+            if (q[qs * (size_t)v] == 0) {        // root of its tree
                 pv = vbase[v];
                 sub[v] = tree_n[v];
             } else {
@@ -196,10 +195,10 @@ __global__ void k_preorder(const int2* f1, const uint32_t* q, const int32_t* hea
 }
 
 // F' edges pull each endpoint's lo/hi toward the other endpoint's preorder
-__global__ void k_nontree(const int2* f2, const uint32_t* cnt, const int32_t* pre, int32_t* lo, int32_t* hi) {
+__global__ void k_nontree(const int2* f2, int32_t dir, const uint32_t* cnt, const int32_t* pre, int32_t* lo, int32_t* hi) {
     const int64_t n2 = cnt[1];
     GRID_LOOP(k, n2) {
-        const int2 e = f2[-k];
+        const int2 e = f2[dir * k];
         const int32_t px = pre[e.x], py = pre[e.y];
         atomicMin(&lo[e.x], py);
         atomicMax(&hi[e.x], py);
@@ -227,13 +226,13 @@ __global__ void k_sparse_level(const int32_t* pmin, const int32_t* pmax, int32_t
 
 __device__ __forceinline__ int floor_log2(uint32_t x) { return 31 - __clz(x); }
 
-__global__ void k_bridges(const int2* f1, const uint32_t* q, const int32_t* head, const int32_t* in_arc,
+__global__ void k_bridges(const int2* f1, const uint32_t* q, int32_t qs, const int32_t* head, const int32_t* in_arc,
                           const int32_t* pre, const int32_t* sub, const int32_t* tmin, const int32_t* tmax, int64_t nt,
                           int32_t V, uint64_t* out, uint32_t* nout) {
     GRID_LOOP(v, (int64_t)V) {
         bool br = false;
         uint64_t key = 0;
-        if (head[v + 1] > head[v] && q[2 * (size_t)v] != 0) {
+        if (head[v + 1] > head[v] && q[qs * (size_t)v] != 0) {
             const int32_t l = pre[v], r = pre[v] + sub[v] - 1;
             const int j = floor_log2((uint32_t)(r - l + 1));
             const int64_t lev = (int64_t)j * nt;
@@ -265,7 +264,9 @@ int grid_for(int64_t n) {
 }  // namespace
 
 // scratch words needed by device_scan for n elements
-static int64_t scan_scratch(int64_t n) {
+int64_t scan_scratch_words(int64_t n);
+static int64_t scan_scratch(int64_t n) { return scan_scratch_words(n); }
+int64_t scan_scratch_words(int64_t n) {
     int64_t s = 0;
     while (n > kSB) {
         n = (n + kSB - 1) / kSB;
@@ -274,7 +275,7 @@ static int64_t scan_scratch(int64_t n) {
     return s + 64;
 }
 
-static void device_scan(int32_t* a, int64_t n, int32_t* scratch, hipStream_t s) {
+void device_scan(int32_t* a, int64_t n, int32_t* scratch, hipStream_t s) {
     if (n <= 0) return;
     const int64_t blocks = (n + kSB - 1) / kSB;
     if (blocks == 1) {
@@ -287,55 +288,73 @@ static void device_scan(int32_t* a, int64_t n, int32_t* scratch, hipStream_t s) 
     hipLaunchKernelGGL(k_scan_add, dim3((unsigned)blocks), dim3(kT), 0, s, a, n, (const int32_t*)sums);
 }
 
-int64_t device_bridges_words(int32_t V) {
+// Scratch layout of the bridge step, shared by the size query and the launch
+// sequence so that the two cannot disagree.
+struct BridgeWs {
+    int32_t *head, *cur, *adj, *posof, *nxt, *rank, *tail, *nxt2, *rank2, *tail2, *tour_len, *tree_n, *tour_base,
+        *vbase, *pos, *flag, *in_arc, *sub, *pre, *lo, *hi, *tmin, *tmax, *misc, *scr;
+    uint64_t* keys;
+    int64_t words;
+};
+
+static BridgeWs carve(int32_t* base, int32_t V) {
     const int64_t A = 2 * (int64_t)std::max(V - 1, 1);
     int J = 1;
     while ((int64_t(1) << J) < V) J++;
-    // head(V+1) cur deg.. adj posof nxt rank tail x2, tour_len tree_n tour_base vbase, pos flag,
-    // in_arc sub pre lo hi, sparse tables 2*(J+1)*V, out keys 2V, scan scratch
-    return (int64_t)(V + 2) * 12 + A * 9 + 2 * (int64_t)(J + 1) * V + 2 * (int64_t)V + scan_scratch(std::max<int64_t>(A, V) + 1) + 4096;
+    BridgeWs w{};
+    int64_t o = 0;
+    auto take = [&](int64_t n) { int32_t* p = base ? base + o : nullptr; o += (n + 63) & ~int64_t(63); return p; };
+    w.head = take(V + 2);
+    w.cur = take(V + 1);
+    w.adj = take(A);
+    w.posof = take(A);
+    w.nxt = take(A);
+    w.rank = take(A);
+    w.tail = take(A);
+    w.nxt2 = take(A);
+    w.rank2 = take(A);
+    w.tail2 = take(A);
+    w.tour_len = take(V);
+    w.tree_n = take(V);
+    w.tour_base = take(V + 1);
+    w.vbase = take(V + 1);
+    w.pos = take(A);
+    w.flag = take(A + 1);
+    w.in_arc = take(V);
+    w.sub = take(V);
+    w.pre = take(V);
+    w.lo = take(V);
+    w.hi = take(V);
+    w.tmin = take((int64_t)(J + 1) * V);
+    w.tmax = take((int64_t)(J + 1) * V);
+    w.keys = reinterpret_cast<uint64_t*>(take(2 * (int64_t)V + 2));
+    w.misc = take(64);   // [0] changed flag, [1] key count
+    w.scr = take(scan_scratch(std::max<int64_t>(A, V) + 1));
+    w.words = o;
+    return w;
 }
 
-// Bridges of node 0's certificate (regions at B, counts on the device).
-// Writes up to V keys at *d_keys and their number at *d_n.
-int device_bridges(const Plan& P, const DevBufs& B, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s) {
-    const int32_t V = P.V;
-    const int64_t A = 2 * (int64_t)std::max(V - 1, 1);
-    int J = 1;
-    while ((int64_t(1) << J) < V) J++;
-    int32_t* w = ws;
-    auto take = [&](int64_t n) { int32_t* p = w; w += (n + 63) & ~int64_t(63); return p; };
-    int32_t* head = take(V + 2);
-    int32_t* cur = take(V + 1);
-    int32_t* adj = take(A);
-    int32_t* posof = take(A);
-    int32_t* nxt = take(A);
-    int32_t* rank = take(A);
-    int32_t* tail = take(A);
-    int32_t* nxt2 = take(A);
-    int32_t* rank2 = take(A);
-    int32_t* tail2 = take(A);
-    int32_t* tour_len = take(V);
-    int32_t* tree_n = take(V);
-    int32_t* tour_base = take(V + 1);
-    int32_t* vbase = take(V + 1);
-    int32_t* pos = take(A);
-    int32_t* flag = take(A + 1);
-    int32_t* in_arc = take(V);
-    int32_t* sub = take(V);
-    int32_t* pre = take(V);
-    int32_t* lo = take(V);
-    int32_t* hi = take(V);
-    int32_t* tmin = take((int64_t)(J + 1) * V);
-    int32_t* tmax = take((int64_t)(J + 1) * V);
-    uint64_t* keys = reinterpret_cast<uint64_t*>(take(2 * (int64_t)V + 2));
-    int32_t* misc = take(64);   // [0] changed flag, [1] key count
-    int32_t* scr = take(scan_scratch(std::max<int64_t>(A, V) + 1));
-    const int2* f1 = B.cert + P.off[0];
-    const int2* f2 = B.cert + P.off[0] + P.cap[0] - 1;   // F' stored backwards from the region's end
-    const uint32_t* q = B.state;                           // node 0's state
-    const uint32_t* cnt = B.cnt;
+int64_t device_bridges_words(int32_t V) { return carve(nullptr, V).words; }
 
+// Bridges of a certificate held on the device: F = f1[0..cnt[0]), F' =
+// f2[dir*k] for k < cnt[1] (counts read on the device), vertex v is the root of
+// its tree of F iff q[qs*v] == 0.  Writes up to V keys at *d_keys and their
+// number at *d_n.
+int device_bridges_cert(const int2* f1, const int2* f2, int32_t dir, const uint32_t* cnt, const uint32_t* q, int32_t qs,
+                        int32_t V, int32_t max_tree, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s) {
+    const int64_t A = 2 * (int64_t)std::max(V - 1, 1);
+    // list ranking and the subtree range tables only need the largest tree:
+    // tours have at most 2(max_tree - 1) arcs, subtrees at most max_tree vertices
+    max_tree = std::max(2, std::min(max_tree, V));
+    int J = 1;
+    while ((int64_t(1) << J) < max_tree) J++;
+    const BridgeWs W = carve(ws, V);
+    int32_t *head = W.head, *cur = W.cur, *adj = W.adj, *posof = W.posof, *nxt = W.nxt, *rank = W.rank,
+            *tail = W.tail, *nxt2 = W.nxt2, *rank2 = W.rank2, *tail2 = W.tail2, *tour_len = W.tour_len,
+            *tree_n = W.tree_n, *tour_base = W.tour_base, *vbase = W.vbase, *pos = W.pos, *flag = W.flag,
+            *in_arc = W.in_arc, *sub = W.sub, *pre = W.pre, *lo = W.lo, *hi = W.hi, *tmin = W.tmin, *tmax = W.tmax,
+            *misc = W.misc, *scr = W.scr;
+    uint64_t* keys = W.keys;
     hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(V + 2)), dim3(kT), 0, s, head, (int64_t)V + 2);
     hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(V + 1)), dim3(kT), 0, s, cur, (int64_t)V + 1);
     hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(A + 1)), dim3(kT), 0, s, flag, A + 1);
@@ -343,16 +362,16 @@ int device_bridges(const Plan& P, const DevBufs& B, int32_t* ws, uint64_t** d_ke
     hipLaunchKernelGGL(k_degree, dim3(grid_for(V)), dim3(kT), 0, s, f1, cnt, head);
     device_scan(head, V + 1, scr, s);
     hipLaunchKernelGGL(k_fill_adj, dim3(grid_for(A)), dim3(kT), 0, s, f1, cnt, head, cur, adj, posof);
-    hipLaunchKernelGGL(k_succ, dim3(grid_for(A)), dim3(kT), 0, s, f1, cnt, head, adj, posof, q, nxt, rank, tail);
+    hipLaunchKernelGGL(k_succ, dim3(grid_for(A)), dim3(kT), 0, s, f1, cnt, head, adj, posof, q, qs, nxt, rank, tail);
     int rounds = 0;
-    while ((int64_t(1) << rounds) < A) rounds++;
+    while ((int64_t(1) << rounds) < 2 * (int64_t)max_tree) rounds++;
     for (int i = 0; i < rounds; i++) {
         hipLaunchKernelGGL(k_jump, dim3(grid_for(A)), dim3(kT), 0, s, cnt, nxt, rank, tail, nxt2, rank2, tail2, misc);
         std::swap(nxt, nxt2);
         std::swap(rank, rank2);
         std::swap(tail, tail2);
     }
-    hipLaunchKernelGGL(k_root_sizes, dim3(grid_for(V)), dim3(kT), 0, s, f1, cnt, head, adj, rank, q, V, tour_len, tree_n);
+    hipLaunchKernelGGL(k_root_sizes, dim3(grid_for(V)), dim3(kT), 0, s, head, adj, rank, q, qs, V, tour_len, tree_n);
     BR_HIP(hipMemcpyAsync(tour_base, tour_len, sizeof(int32_t) * V, hipMemcpyDeviceToDevice, s));
     BR_HIP(hipMemcpyAsync(vbase, tree_n, sizeof(int32_t) * V, hipMemcpyDeviceToDevice, s));
     device_scan(tour_base, V, scr, s);
@@ -360,19 +379,27 @@ int device_bridges(const Plan& P, const DevBufs& B, int32_t* ws, uint64_t** d_ke
     hipLaunchKernelGGL(k_positions, dim3(grid_for(A)), dim3(kT), 0, s, f1, cnt, rank, tail, tour_len, tour_base, pos, flag);
     hipLaunchKernelGGL(k_down, dim3(grid_for(A)), dim3(kT), 0, s, f1, cnt, tail, pos, tour_base, flag, in_arc, sub);
     device_scan(flag, A + 1, scr, s);
-    hipLaunchKernelGGL(k_preorder, dim3(grid_for(V)), dim3(kT), 0, s, f1, q, head, in_arc, tail, pos, tour_base, flag,
+    hipLaunchKernelGGL(k_preorder, dim3(grid_for(V)), dim3(kT), 0, s, f1, q, qs, head, in_arc, tail, pos, tour_base, flag,
                        vbase, tree_n, V, pre, sub, lo, hi);
-    hipLaunchKernelGGL(k_nontree, dim3(grid_for(V)), dim3(kT), 0, s, f2, cnt, pre, lo, hi);
+    hipLaunchKernelGGL(k_nontree, dim3(grid_for(V)), dim3(kT), 0, s, f2, dir, cnt, pre, lo, hi);
     hipLaunchKernelGGL(k_to_preorder, dim3(grid_for(V)), dim3(kT), 0, s, pre, lo, hi, V, tmin, tmax);
     for (int j = 1; j <= J; j++)
         hipLaunchKernelGGL(k_sparse_level, dim3(grid_for(V)), dim3(kT), 0, s, tmin + (int64_t)(j - 1) * V,
                            tmax + (int64_t)(j - 1) * V, tmin + (int64_t)j * V, tmax + (int64_t)j * V, (int64_t)V,
                            (int64_t)1 << (j - 1));
-    hipLaunchKernelGGL(k_bridges, dim3(grid_for(V)), dim3(kT), 0, s, f1, q, head, in_arc, pre, sub, tmin, tmax, (int64_t)V,
+    hipLaunchKernelGGL(k_bridges, dim3(grid_for(V)), dim3(kT), 0, s, f1, q, qs, head, in_arc, pre, sub, tmin, tmax, (int64_t)V,
                        V, keys, reinterpret_cast<uint32_t*>(misc + 1));
     *d_keys = keys;
     *d_n = reinterpret_cast<uint32_t*>(misc + 1);
     return BR_OK;
+}
+
+// Bridges of node 0's certificate of the plain path (F' stored backwards from
+// the end of the region; roots read from node 0's carried union-find state).
+int device_bridges(const Plan& P, const DevBufs& B, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s) {
+    const int2* f1 = B.cert + P.off[0];
+    const int2* f2 = B.cert + P.off[0] + P.cap[0] - 1;
+    return device_bridges_cert(f1, f2, -1, B.cnt, B.state, 2, P.V, P.V, ws, d_keys, d_n, s);
 }
 
 }  // namespace br

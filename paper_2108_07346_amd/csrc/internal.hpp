@@ -70,8 +70,16 @@ struct BatchDev {
     uint32_t* arrive;         // merge arrival counters
     uint32_t* queue;          // [1] next item
     uint32_t* err;            // bit 0: id out of range; bit 1: region overflow
+    const int64_t* vbase;     // [S] first vertex of graph s in the combined numbering
+    uint32_t* rootw;          // [sum V] 0 at each root of F of the graph's final certificate, else 1
 };
 void launch_batched(const BatchDev& B, int blocks, hipStream_t s);
+// Gather the node-0 certificates of all graphs into one certificate of their
+// disjoint union (vertex ids offset by vbase); counts of F and F' at cnt2[0..1].
+void launch_combine(const BatchDev& B, int32_t S, int32_t* n1x, int32_t* n2x, int2* f1c, int2* f2c, uint32_t* cnt2,
+                    int32_t* scan_scratch, hipStream_t s);
+void device_scan(int32_t* a, int64_t n, int32_t* scratch, hipStream_t s);
+int64_t scan_scratch_words(int64_t n);
 int32_t batched_max_v_dev();
 int32_t batched_blocks_per_cu();
 
@@ -88,6 +96,8 @@ Plan make_plan(int64_t E, int32_t V, int32_t M);
 // *d_keys (count at *d_n) on the device.
 int64_t device_bridges_words(int32_t V);
 int device_bridges(const Plan& P, const DevBufs& B, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s);
+int device_bridges_cert(const int2* f1, const int2* f2, int32_t dir, const uint32_t* cnt, const uint32_t* q, int32_t qs,
+                        int32_t V, int32_t max_tree, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s);
 
 // ---- host side of the path --------------------------------------------------
 // Algorithm 1 (iterative) on the certificate; appends canonical keys (min<<32|max).

@@ -326,6 +326,13 @@ int br_server_stats(br_server* S, br_server_stats_t* out, int reset) {
     return BR_OK;
 }
 
+int br_server_set_final_step(br_server* S, int mode) {
+    if (!S || mode < 0 || mode > 1) return fail(BR_EINVAL, "br_server_set_final_step: bad argument");
+    std::lock_guard<std::mutex> g(S->mu);
+    for (auto& sl : S->slots) br_set_final_step(sl->ctx, mode);
+    return BR_OK;
+}
+
 int br_server_destroy(br_server* S) {
     if (!S) return BR_OK;
     {

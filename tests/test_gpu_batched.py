@@ -101,3 +101,28 @@ def test_out_of_range_id_reported(ctx):
     e, off, Vs = pack([(np.array([[0, 1], [1, 2]], np.int32), 3)])
     pairs, boff = ctx.find_batched(torch.from_numpy(e).cuda(), off, Vs, 64)
     assert np.array_equal(pairs, [[0, 1], [1, 2]])
+
+
+def test_batched_device_final_step(ctx):
+    # final step on the GPU: all certificates as one disjoint union, one bridge step
+    ctx.set_final_step(1)
+    try:
+        b = graphgen.batched(0, n_graphs=192)
+        for chunk in (4096, 65536):
+            say("batched device final step chunk=%d" % chunk)
+            check_all(ctx, b.edges, b.offsets, b.V, chunk)
+        rng = np.random.default_rng(32)
+        graphs = [(rng.integers(0, V, size=(int(rng.integers(0, 4 * V)), 2)).astype(np.int32), V)
+                  for V in rng.integers(1, 200, size=30).tolist()]
+        graphs.append((np.zeros((0, 2), np.int32), 1))
+        graphs.append((np.array([[0, 0]], np.int32), 1))
+        big = graphgen.planted(6, k=3, vc=5000, p=0.05, n_pend=4)
+        graphs.append((big.edges, big.V))
+        e, off, Vs = pack(graphs)
+        say("batched device final step mixed")
+        check_all(ctx, e, off, Vs, 128)
+        full = graphgen.batched(0, n_graphs=4096)
+        say("batched device final step full")
+        check_all(ctx, full.edges, full.offsets, full.V, 0)
+    finally:
+        ctx.set_final_step(0)

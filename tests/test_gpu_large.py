@@ -45,13 +45,17 @@ def test_large_workload_bit_exact():
         pytest.skip("no GPU")
     import paper_2108_07346_amd as br
     head, want = read_golden()
+    import time
+    t0 = time.time()
     say("large: generating")
     g = graphgen.config("large")
+    say("large: generated in %.1f s" % (time.time() - t0))
     assert ("V %d E %d" % (g.V, g.E)) in head
     h = hashlib.sha256()
     for i in range(0, g.E, 1 << 24):
         h.update(g.edges[i:i + (1 << 24)].tobytes())
     assert h.hexdigest() in head, "generated edges differ from the ones the golden file was written for"
+    say("large: edge digest matches (%.1f s)" % (time.time() - t0))
     pend = np.sort(np.stack([g.pend.min(1), g.pend.max(1)], 1).astype(np.int64) @ np.array([1 << 32, 1]))
     keys = want.astype(np.int64) @ np.array([1 << 32, 1])
     assert np.array_equal(np.sort(keys), pend)          # planted: exactly the pendant edges

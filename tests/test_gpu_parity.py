@@ -190,3 +190,19 @@ def test_device_final_step_bit_exact(ctx, small, dense):
         assert ctx.find(dev([[0, 0]]), 1, 1).shape[0] == 0
     finally:
         ctx.set_final_step(0)
+
+
+def test_two_edge_connected_classes(ctx, small, dense):
+    # 2-edge-connected classes through the certificate path equal the oracle's
+    g, _, d = dense
+    for M in (1, 16):
+        say("2ecc dense M=%d" % M)
+        lab, n = ctx.two_edge_components(d, g.V, M)
+        want = oracle.two_edge_labels(g.edges, g.V)
+        assert np.array_equal(lab, want) and n == np.unique(want).shape[0]
+    rng = np.random.default_rng(25)
+    for t in range(40):
+        V = int(rng.integers(1, 200))
+        e = rng.integers(0, V, size=(int(rng.integers(0, 4 * V)), 2)).astype(np.int32)
+        lab, n = ctx.two_edge_components(dev(e), V, int(rng.choice([1, 3, 16])))
+        assert np.array_equal(lab, oracle.two_edge_labels(e, V)), (V, e.shape[0])

@@ -231,3 +231,20 @@ def test_small_workload_contains_planted_and_extras_are_real():
         if (u, v) in gs:
             continue
         assert oracle.components(np.delete(g.edges, i, axis=0), g.V) == c
+
+
+# ---- 2-edge-connected classes (oracle side) ---------------------------------
+
+def test_two_edge_labels_brute_force_and_invariants():
+    rng = np.random.default_rng(41)
+    for _ in range(150):
+        V = int(rng.integers(1, 10))
+        e = rng.integers(0, V, size=(int(rng.integers(0, 3 * V + 1)), 2)).astype(np.int32)
+        lab = oracle.two_edge_labels(e, V)
+        assert np.array_equal(lab, oracle.brute_two_edge_labels(e, V)), (V, e.tolist())
+        assert np.unique(lab).shape[0] == oracle.bridges(e, V).shape[0] + oracle.components(e, V)
+    # closed forms: a cycle is one class; a tree has V singleton classes
+    cyc = np.stack([np.arange(6), (np.arange(6) + 1) % 6], 1)
+    assert np.all(oracle.two_edge_labels(cyc, 6) == 0)
+    tree = np.array([[0, 1], [1, 2], [1, 3]])
+    assert np.array_equal(oracle.two_edge_labels(tree, 4), [0, 1, 2, 3])
