@@ -1,9 +1,11 @@
 """Benchmark of the bridge path on one MI355X.
 
 One step = one br_bridges_find call: per-chunk certificates (phase 0), the
-merge rounds, the certificate copy to the host, the depth-first search on it
-and the canonical sort -- every step of the path, on input already resident
-in HBM.  Prints one JSON line (rank 0, N = 1).
+merge rounds, the bridges of the merged certificate (the library's default
+bridge step on the GPU), the copy of the bridges to the host and the
+canonical sort -- every step of the path, on input already resident in HBM.
+The same steps with Algorithm 1's depth-first search on the host as the final
+step are reported under "detail".  Prints one JSON line (rank 0, N = 1).
 
 Default workload: the dense configuration (V = 66,536 as 256 clusters of
 256 vertices with p = 0.5, cluster tree, 5 extra cross edges, 1,000 pendant
@@ -106,26 +108,27 @@ def bench_batched(args):
     chunk = int(ctx.profile()["rounds"])
     phases = {k: v / args.steps for k, v in acc.items()}
     ms_step = 1000 * dt / args.steps
-    # the same batch with the final step on the GPU (one bridge step over all certificates)
-    ctx.set_final_step(1)
+    # the same batch with Algorithm 1's search per graph on the host instead of
+    # the default bridge step on the GPU (one launch sequence over all certificates)
+    ctx.set_final_step(0)
     ctx.set_profiling(True)
     ctx.find_batched(d, b.offsets, b.V, args.chunk, stream)
-    accd = {"ms_phase0": 0.0, "ms_cert": 0.0, "ms_dfs": 0.0}
+    acch = {"ms_phase0": 0.0, "ms_cert": 0.0, "ms_dfs": 0.0}
     torch.cuda.synchronize()
-    td = time.perf_counter()
+    th = time.perf_counter()
     for _ in range(args.steps):
-        pd, bd = ctx.find_batched(d, b.offsets, b.V, args.chunk, stream)
+        ph_, bh_ = ctx.find_batched(d, b.offsets, b.V, args.chunk, stream)
         p = ctx.profile()
-        for k in accd:
-            accd[k] += p[k]
+        for k in acch:
+            acch[k] += p[k]
     torch.cuda.synchronize()
-    dtd = time.perf_counter() - td
-    ctx.set_final_step(0)
-    assert np.array_equal(pd, pairs) and np.array_equal(bd, boff)
-    gpu_final = {"edges_per_s": E * args.steps / dtd, "ms_per_step": 1000 * dtd / args.steps,
-                 "ms_device": round(accd["ms_phase0"] / args.steps, 4)}
-    print("bench: batched, final step on GPU %s" % json.dumps(gpu_final), file=sys.stderr, flush=True)
-    # baseline: the plain path, one call (certificate kernels + host search) per graph
+    dth = time.perf_counter() - th
+    ctx.set_final_step(1)
+    assert np.array_equal(ph_, pairs) and np.array_equal(bh_, boff)
+    host_search = {"edges_per_s": E * args.steps / dth, "ms_per_step": 1000 * dth / args.steps,
+                   "ms_host_search": round(acch["ms_dfs"] / args.steps, 4)}
+    print("bench: batched, host search %s" % json.dumps(host_search), file=sys.stderr, flush=True)
+    # baseline: the plain path, one call (certificate kernels + bridge step) per graph
     ctx.set_profiling(False)
     views = [d[b.offsets[g]:b.offsets[g + 1]] for g in range(b.G)]
     torch.cuda.synchronize()
@@ -161,7 +164,7 @@ def bench_batched(args):
         "detail": {"phases_ms": {k: round(v, 4) for k, v in phases.items()},
                    "one_call_per_graph": {"ms": 1000 * t_base, "edges_per_s": E / t_base,
                                           "speedup_of_batched": t_base / (dt / args.steps)},
-                   "final_step_on_gpu": gpu_final,
+                   "host_search": host_search,
                    "bridges": int(boff[-1])},
     }
     print(json.dumps(line), flush=True)
@@ -209,7 +212,7 @@ def bench_figures(args):
                 ms = 1000 * (time.perf_counter() - t) / reps
                 row["ms_host_search" if mode == 0 else "ms_gpu_final_step"] = round(ms, 4)
                 row.update({k: round(v, 4) for k, v in ph.items()})
-            ctx.set_final_step(0)
+            ctx.set_final_step(1)
             rows.append(row)
             print("bench: %s %s" % (fig, json.dumps(row)), file=sys.stderr, flush=True)
         out[fig] = rows
@@ -312,7 +315,7 @@ def main():
     ap.add_argument("--pool", type=int, default=32, help="served: distinct requests generated")
     ap.add_argument("--slots", type=int, default=8, help="served: device slots")
     ap.add_argument("--resident", action="store_true", help="served: also run with edges resident on the GPU")
-    ap.add_argument("--final-step", type=int, default=0, help="served: 0 host search, 1 bridge step on the GPU")
+    ap.add_argument("--final-step", type=int, default=1, help="served: 1 bridge step on the GPU (default), 0 host search")
     ap.add_argument("--graphs", type=int, default=4096, help="batched: number of graphs")
     ap.add_argument("--chunk", type=int, default=0, help="batched: chunk_edges (0 = tuned)")
     ap.add_argument("--M", type=int, default=None)
@@ -391,24 +394,26 @@ def main():
     detail = {"phases_ms": {k: round(v, 5) for k, v in phases.items()}, "bridges": int(out.shape[0]),
               "certificate_edges": int(prof["cert_f1"] + prof["cert_f2"]), "merge_rounds": int(prof["rounds"]),
               "complexity_claim": "O(E/M + V log M) on M machines (paper, Section V)"}
-    # the same step with the final step on the GPU (bridges of the certificate by
-    # Euler-tour rooting and the subtree low/high test) instead of the host search
-    ctx.set_final_step(1)
-    run_steps(M, 2, False)
-    ddt, dph, dout = run_steps(M, args.steps, True)
+    # the same step with Algorithm 1's depth-first search on the host (after
+    # copying the certificate) instead of the default bridge step on the GPU
     ctx.set_final_step(0)
-    assert dout.shape == out.shape and (dout == out).all()
-    detail["final_step_on_gpu"] = {"edges_per_s": g.E * args.steps / ddt, "ms_per_step": 1000 * ddt / args.steps,
-                                   "ms_bridge_step": round(dph["ms_bridge_dev"], 5)}
-    print("bench: final step on GPU %s" % json.dumps(detail["final_step_on_gpu"]), file=sys.stderr, flush=True)
-    if args.workload == "dense" and not args.no_sweep:
+    run_steps(M, 2, False)
+    hdt, hph, hout = run_steps(M, args.steps, True)
+    ctx.set_final_step(1)
+    assert hout.shape == out.shape and (hout == out).all()
+    detail["host_search"] = {"edges_per_s": g.E * args.steps / hdt, "ms_per_step": 1000 * hdt / args.steps,
+                             "ms_d2h": round(hph["ms_d2h"], 5), "ms_dfs": round(hph["ms_dfs"], 5)}
+    print("bench: host search %s" % json.dumps(detail["host_search"]), file=sys.stderr, flush=True)
+    sweep_ms = {"dense": (1, 16, 256, 1024), "large": (64, 256, 1024, 4096)}.get(args.workload)
+    if sweep_ms and not args.no_sweep:
         sweep = {}
-        for Mx in (1, 16, 256, 1024):
-            run_steps(Mx, 2, False)
-            sdt, sph, _ = run_steps(Mx, 10, True)
-            sweep[str(Mx)] = {"edges_per_s": g.E * 10 / sdt, "ms_per_step": 1000 * sdt / 10,
+        reps = 10 if args.workload == "dense" else 2
+        for Mx in sweep_ms:
+            run_steps(Mx, 1, False)
+            sdt, sph, _ = run_steps(Mx, reps, True)
+            sweep[str(Mx)] = {"edges_per_s": g.E * reps / sdt, "ms_per_step": 1000 * sdt / reps,
                               "ms_phase0": round(sph["ms_phase0"], 5), "ms_merge": round(sph["ms_merge"], 5),
-                              "ms_dfs": round(sph["ms_dfs"], 5),
+                              "ms_bridge_step": round(sph["ms_bridge_dev"], 5),
                               "phase0_frac_hbm": (8.0 * g.E / (sph["ms_phase0"] / 1000) / 1e9) / PEAK_GBS
                               if sph["ms_phase0"] > 0 else None}
             print("bench: sweep M=%d %s" % (Mx, json.dumps(sweep[str(Mx)])), file=sys.stderr, flush=True)

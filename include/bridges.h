@@ -11,8 +11,11 @@
  *     (Algorithm 2, Section IV-B), at most 2(V-1) edges (Lemma 1, Section III);
  *   - the M certificates are merged pairwise in ceil(log2 M) rounds, each merge
  *     being the certificate of the union of two certificates (Section III);
- *   - the bridges of the final certificate, found by a depth-first search
- *     (Algorithm 1, Section IV-A), are the bridges of the input.
+ *   - the bridges of the final certificate are the bridges of the input; they
+ *     are found on the GPU by rooting the certificate's forest and testing
+ *     every tree edge's subtree (the low-link test of Algorithm 1, Section
+ *     IV-A, made parallel as Section VII suggests), or by Algorithm 1's
+ *     depth-first search itself on the host (br_set_final_step).
  *
  * Conventions for every entry point
  *   - Vertex ids are int32 in [0, V) with 1 <= V <= 2^31 - 1.
@@ -89,8 +92,9 @@ int br_cert_merge(br_ctx* ctx, const int32_t* d_a, int64_t Ea, const int32_t* d_
 
 /*
  * br_bridges_find -- the whole path: certificate over M chunks (as
- * br_cert_build), then Algorithm 1's depth-first search on the final
- * certificate (on the host, in this library), then canonical order.
+ * br_cert_build), then the bridges of the final certificate (by default on the
+ * GPU; Algorithm 1's depth-first search on the host with br_set_final_step
+ * mode 0), then canonical order.
  *   h_bridges host int32 [cap][2]; cap >= V-1 always suffices.
  *   *n_bridges number of bridges; if it exceeds cap the call returns BR_ECAP
  *              and writes no pairs.
@@ -170,10 +174,10 @@ int br_set_profiling(br_ctx* ctx, int on);
 
 /*
  * Final step used by br_bridges_find on this context:
- *   0 (default) -- Algorithm 1's depth-first search (Section IV-A) on the
+ *   0           -- Algorithm 1's depth-first search (Section IV-A) on the
  *                  certificate, in the library's host code, after copying the
  *                  certificate (at most 2(V-1) edges) to the host;
- *   1           -- the same bridge set computed on the GPU: F of the
+ *   1 (default) -- the same bridge set computed on the GPU: F of the
  *                  certificate rooted by Euler tours, preorder numbers and
  *                  subtree sizes by list ranking, and a tree edge kept as a
  *                  bridge iff no certificate edge leaves the child's subtree

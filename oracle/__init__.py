@@ -22,6 +22,14 @@ Contents
     to judge certificates that are correct but not unique.
 ``components(edges, V)``
     Number of connected components (scipy's graph routine).
+``articulation_points(edges, V)`` / ``brute_articulation_points(edges, V)``
+    The abstract's "failure points": vertices whose removal increases the
+    number of components -- by the low-link search (``articulation.c``) and
+    by the definition written out for tiny graphs.
+``scan_first_certificate(edges, V)``
+    Two scan-first (breadth-first) forests, the second on the vertex pairs the
+    first does not use: the certificate form under which articulation points
+    survive (checked against the definition in the tests).
 """
 from __future__ import annotations
 
@@ -40,7 +48,8 @@ def build() -> str:
     """Compile the C oracle into liboracle.so (host C, gcc, no GPU code)."""
     tmp = _SO + ".tmp%d" % os.getpid()
     subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-Wall",
-                           os.path.join(_DIR, "tarjan.c"), os.path.join(_DIR, "certificate.c"), "-o", tmp])
+                           os.path.join(_DIR, "tarjan.c"), os.path.join(_DIR, "certificate.c"),
+                           os.path.join(_DIR, "articulation.c"), "-o", tmp])
     os.replace(tmp, _SO)
     return _SO
 
@@ -59,6 +68,8 @@ def _load():
     lib.oracle_certificate.argtypes = [vp, i64, i64, vp, ctypes.POINTER(i64), vp, ctypes.POINTER(i64)]
     lib.oracle_phase_tree.restype = ctypes.c_int
     lib.oracle_phase_tree.argtypes = [vp, i64, i64, i64, vp, ctypes.POINTER(i64), ctypes.POINTER(i64), vp]
+    lib.oracle_articulation_points.restype = ctypes.c_int
+    lib.oracle_articulation_points.argtypes = [vp, i64, i64, vp, i64, ctypes.POINTER(i64)]
     _lib = lib
     return lib
 
@@ -266,3 +277,71 @@ def check_certificate(f1, f2, edges, V: int, check_bridges: bool = True) -> list
     if check_bridges and not np.array_equal(bridges(s, V), bridges(e, V)):
         bad.append("bridges(S) != bridges(G)")
     return bad
+
+
+# ---- articulation points ("failure points" of the abstract) -------------------
+
+def articulation_points(edges, V: int) -> np.ndarray:
+    """Articulation points of (V, edges): int32 vertex ids ascending."""
+    e = _as_edges(edges)
+    lib = _load()
+    n = ctypes.c_int64(0)
+    out = np.empty(max(int(V), 1), dtype=np.int32)
+    rc = lib.oracle_articulation_points(e.ctypes.data, e.shape[0], int(V), out.ctypes.data, out.shape[0],
+                                        ctypes.byref(n))
+    if rc:
+        raise ValueError("oracle_articulation_points: " + _ERR.get(rc, str(rc)))
+    return out[:n.value].copy()
+
+
+def brute_articulation_points(edges, V: int) -> np.ndarray:
+    """The definition for tiny graphs: v is an articulation point iff the
+    graph without v (and its edges) has more components than the graph."""
+    e = [(int(a), int(b)) for a, b in _as_edges(edges)]
+    base = _count_components_py(V, e)
+    out = []
+    for v in range(V):
+        rest = [(a if a < v else a - 1, b if b < v else b - 1) for a, b in e if a != v and b != v]
+        if _count_components_py(V - 1, rest) > base:
+            out.append(v)
+    return np.array(out, dtype=np.int32)
+
+
+def scan_first_certificate(edges, V: int):
+    """Two scan-first search forests (F, F'): F by breadth-first search from
+    the smallest vertex of each component, a vertex's parent being its
+    smallest-id neighbour one level up (scanning each level's vertices in id
+    order makes this a scan-first search); F' the same on the edges whose
+    vertex pair is not a pair of F (parallel copies of F's pairs excluded).
+    Returns int32 [n, 2] arrays of the chosen edges (as listed in the input)."""
+    e = _as_edges(edges)
+    forests = []
+    banned = set()
+    for _ in range(2):
+        adj = [[] for _ in range(int(V))]
+        for i, (a, b) in enumerate(e.tolist()):
+            if a == b or (min(a, b), max(a, b)) in banned:
+                continue
+            adj[a].append((b, i))
+            adj[b].append((a, i))
+        level = [-1] * int(V)
+        chosen = []
+        for r in range(int(V)):
+            if level[r] != -1:
+                continue
+            level[r] = 0
+            front = [r]
+            while front:
+                cand = {}
+                for u in sorted(front):
+                    for w, i in adj[u]:
+                        if level[w] == -1 and (w not in cand or (u, i) < cand[w]):
+                            cand[w] = (u, i)
+                for w, (u, i) in cand.items():
+                    level[w] = level[u] + 1
+                    chosen.append(i)
+                front = list(cand)
+        f = e[np.array(sorted(chosen), dtype=np.int64)] if chosen else np.zeros((0, 2), np.int32)
+        forests.append(f)
+        banned = {(min(a, b), max(a, b)) for a, b in f.tolist()}
+    return forests[0], forests[1]

@@ -324,20 +324,22 @@ int br_bridges_find(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int
         if (rc) return rc;
         BR_HIP(hipGetLastError());
         ev_record(c, 5, s);
-        rc = ensure_pinned(c, 64 + 8 * (size_t)V);
+        // counters, error word and the first keys in one copy (the status block
+        // precedes the keys); more keys than last time take a second copy
+        rc = ensure_pinned(c, 256 + 8 * (size_t)V);
         if (rc) return rc;
         uint32_t* hc = static_cast<uint32_t*>(c->pinned);
-        BR_HIP(hipMemcpyAsync(hc, B.cnt, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        BR_HIP(hipMemcpyAsync(hc + 2, B.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        BR_HIP(hipMemcpyAsync(hc + 3, d_n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        uint64_t* hk = reinterpret_cast<uint64_t*>(static_cast<char*>(c->pinned) + 256);
+        const size_t guess = std::min<size_t>(std::max<size_t>(c->keys_hint, 1024), (size_t)V);
+        BR_HIP(hipMemcpyAsync(hc, d_n - 1, 256 + 8 * guess, hipMemcpyDeviceToHost, s));
         BR_HIP(hipStreamSynchronize(s));
-        n1 = hc[0]; n2 = hc[1]; err = hc[2];
-        const uint32_t nk = std::min<uint32_t>(hc[3], (uint32_t)std::max(V - 1, 0));
-        uint64_t* hk = reinterpret_cast<uint64_t*>(static_cast<char*>(c->pinned) + 64);
-        if (nk) {
-            BR_HIP(hipMemcpyAsync(hk, d_keys, 8 * (size_t)nk, hipMemcpyDeviceToHost, s));
+        n1 = hc[2]; n2 = hc[3]; err = hc[4];
+        const uint32_t nk = std::min<uint32_t>(hc[1], (uint32_t)std::max(V - 1, 0));
+        if (nk > guess) {
+            BR_HIP(hipMemcpyAsync(hk + guess, d_keys + guess, 8 * (size_t)(nk - guess), hipMemcpyDeviceToHost, s));
             BR_HIP(hipStreamSynchronize(s));
         }
+        c->keys_hint = nk;
         ev_record(c, 4, s);
         t1 = std::chrono::steady_clock::now();
         if (err & 1u) return fail(BR_ERANGE, "br_bridges_find: an edge has a vertex id outside [0, %d)", V);
@@ -364,6 +366,8 @@ int br_bridges_find(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int
         if (err != 0 || (int64_t)n1 + n2 > cap0)
             return fail(BR_EINTERNAL, "br_bridges_find: certificate region overflow (|F|=%u |F'|=%u cap=%lld)", n1,
                         n2, (long long)cap0);
+        // adjacency with F's arcs first in every list (measured faster to walk
+        // than a device-built adjacency in arbitrary order)
         certificate_bridges(hx, n1, hx + cap0 - n2, n2, V, c->dfs, c->keys);
         t2 = std::chrono::steady_clock::now();
     }

@@ -109,15 +109,20 @@ struct BatchPlan {
     uint32_t* d_nkeys = nullptr;
     uint32_t* h_nkeys = nullptr;
     uint64_t* h_keys = nullptr;
-    // captured launch
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    uint32_t* h_blk = nullptr;       // status block of the bridge step, followed by h_keys
+    size_t keys_hint = 0;            // bridges of the previous call (size of the first copy)
+    // captured launches: the persistent kernel, then (final step on the device)
+    // the combined certificate and its bridge step, with an event in between
+    hipGraph_t graph = nullptr, graph2 = nullptr;
+    hipGraphExec_t exec = nullptr, exec2 = nullptr;
     const void* graph_edges = nullptr;
     int graph_mode = -1;
     int blocks = 0;
     ~BatchPlan() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+        if (exec2) (void)hipGraphExecDestroy(exec2);
+        if (graph2) (void)hipGraphDestroy(graph2);
         if (dmem) (void)hipFree(dmem);
         if (hmem) (void)hipHostFree(hmem);
     }
@@ -133,7 +138,8 @@ struct BatchState {
     std::unique_ptr<uint64_t[]> outk;           // per-graph bridge slots (reused, never zero-filled)
     size_t outk_n = 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipEvent_t k0 = nullptr, k1 = nullptr;   // around the replayed graph (counter clear + persistent kernel)
+    hipEvent_t k0 = nullptr, k1 = nullptr;   // around the persistent kernel's graph (counter clear + kernel)
+    hipEvent_t k2 = nullptr;                 // after the bridge step's graph
 };
 
 BatchState* state_of(br_ctx* c) {
@@ -276,16 +282,17 @@ int build_plan(BatchPlan& P, const int64_t* eoff, const int32_t* V, int32_t G, i
     P.dev.vbase = reinterpret_cast<const int64_t*>(d + o_vb);
     P.dev.rootw = reinterpret_cast<uint32_t*>(d + o_root);
     // pinned host staging
-    const size_t hbytes = a256(8 * (size_t)std::max<int64_t>(P.area0, 1)) + a256(8 * (size_t)std::max(S, 1)) + 256 +
-                          a256(8 * (size_t)std::max<int64_t>(P.vtot, 1)) + 256;
+    const size_t hbytes = a256(8 * (size_t)std::max<int64_t>(P.area0, 1)) + a256(8 * (size_t)std::max(S, 1)) + 512 +
+                          a256(8 * (size_t)std::max<int64_t>(P.vtot, 2)) + 256;
     BR_HIP(hipHostMalloc(&P.hmem, hbytes, hipHostMallocDefault));
     char* h = static_cast<char*>(P.hmem);
     P.h_area0 = reinterpret_cast<int2*>(h);
     P.h_cnt0 = reinterpret_cast<uint32_t*>(h + a256(8 * (size_t)std::max<int64_t>(P.area0, 1)));
     P.h_err = P.h_cnt0 + 2 * (size_t)std::max(S, 1);
     P.h_nkeys = P.h_err + 4;
-    P.h_keys = reinterpret_cast<uint64_t*>(h + a256(8 * (size_t)std::max<int64_t>(P.area0, 1)) +
-                                           a256(8 * (size_t)std::max(S, 1)) + 256);
+    P.h_blk = reinterpret_cast<uint32_t*>(h + a256(8 * (size_t)std::max<int64_t>(P.area0, 1)) +
+                                          a256(8 * (size_t)std::max(S, 1)) + 256);
+    P.h_keys = reinterpret_cast<uint64_t*>(P.h_blk + 64);
     P.blocks = std::max(1, cus * batched_blocks_per_cu());
     return BR_OK;
 }
@@ -293,12 +300,15 @@ int build_plan(BatchPlan& P, const int64_t* eoff, const int32_t* V, int32_t G, i
 // enqueue clear -> kernel -> copies on s (captured into P.graph on first use)
 // the captured part: clear the counters, the persistent kernel, and with the
 // final step on the device the combined certificate and its bridge step
-int enqueue(BatchPlan& P, const int32_t* d_edges, hipStream_t s, int mode) {
+int enqueue(BatchPlan& P, const int32_t* d_edges, hipStream_t s, int mode, int part) {
     P.dev.edges = reinterpret_cast<const int2*>(d_edges);
-    launch_fill_u32(P.dev.ncnt, (int64_t)P.clear_words, 0u, s);
-    BR_HIP(hipGetLastError());
-    if (P.dev.n_items) launch_batched(P.dev, P.blocks, s);
-    BR_HIP(hipGetLastError());
+    if (part == 0) {
+        launch_fill_u32(P.dev.ncnt, (int64_t)P.clear_words, 0u, s);
+        BR_HIP(hipGetLastError());
+        if (P.dev.n_items) launch_batched(P.dev, P.blocks, s);
+        BR_HIP(hipGetLastError());
+        return BR_OK;
+    }
     if (mode == 1 && !P.small.empty()) {
         const int32_t S = (int32_t)P.small.size();
         launch_combine(P.dev, S, P.n1x, P.n2x, P.f1c, P.f2c, P.cnt2, P.scan_scr, s);
@@ -308,6 +318,7 @@ int enqueue(BatchPlan& P, const int32_t* d_edges, hipStream_t s, int mode) {
         int rc = device_bridges_cert(P.f1c, P.f2c, 1, P.cnt2, P.dev.rootw, 1, (int32_t)std::max<int64_t>(P.vtot, 2),
                                      maxv, P.bws, &P.d_keys, &P.d_nkeys, s);
         if (rc) return rc;
+        launch_bridge_status(P.cnt2, P.dev.err, P.d_nkeys, s);
         BR_HIP(hipGetLastError());
     }
     return BR_OK;
@@ -318,8 +329,13 @@ int enqueue(BatchPlan& P, const int32_t* d_edges, hipStream_t s, int mode) {
 int copy_back(BatchPlan& P, hipStream_t s, int mode) {
     const int32_t S = (int32_t)P.small.size();
     if (mode == 1) {
-        if (S) BR_HIP(hipMemcpyAsync(P.h_nkeys, P.d_nkeys, 4, hipMemcpyDeviceToHost, s));
-        BR_HIP(hipMemcpyAsync(P.h_err, P.dev.err, 4, hipMemcpyDeviceToHost, s));
+        if (S) {
+            // status block (counts, error word) and the first keys in one copy
+            const size_t guess = std::min<size_t>(std::max<size_t>(P.keys_hint, 1024), (size_t)std::max<int64_t>(P.vtot, 2));
+            BR_HIP(hipMemcpyAsync(P.h_blk, P.d_nkeys - 1, 256 + 8 * guess, hipMemcpyDeviceToHost, s));
+        } else {
+            BR_HIP(hipMemcpyAsync(P.h_err, P.dev.err, 4, hipMemcpyDeviceToHost, s));
+        }
         return BR_OK;
     }
     if (P.area0) BR_HIP(hipMemcpyAsync(P.h_area0, P.dev.cert, 8 * (size_t)P.area0, hipMemcpyDeviceToHost, s));
@@ -328,24 +344,10 @@ int copy_back(BatchPlan& P, hipStream_t s, int mode) {
     return BR_OK;
 }
 
-int run_device(BatchState& st, BatchPlan& P, const int32_t* d_edges, int mode) {
-    hipStream_t s = st.stream;
-    if (P.exec && P.graph_edges == d_edges && P.graph_mode == mode) {
-        BR_HIP(hipEventRecord(st.k0, s));
-        BR_HIP(hipGraphLaunch(P.exec, s));
-        BR_HIP(hipEventRecord(st.k1, s));
-        return copy_back(P, s, mode);
-    }
-    if (P.exec) {
-        (void)hipGraphExecDestroy(P.exec);
-        P.exec = nullptr;
-    }
-    if (P.graph) {
-        (void)hipGraphDestroy(P.graph);
-        P.graph = nullptr;
-    }
+static int capture(BatchPlan& P, const int32_t* d_edges, hipStream_t s, int mode, int part, hipGraph_t* graph,
+                   hipGraphExec_t* exec) {
     BR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue(P, d_edges, s, mode);
+    int rc = enqueue(P, d_edges, s, mode, part);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(s, &g);
     if (rc) {
@@ -353,13 +355,34 @@ int run_device(BatchState& st, BatchPlan& P, const int32_t* d_edges, int mode) {
         return rc;
     }
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-    P.graph = g;
-    BR_HIP(hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0));
-    P.graph_edges = d_edges;
-    P.graph_mode = mode;
+    *graph = g;
+    BR_HIP(hipGraphInstantiate(exec, g, nullptr, nullptr, 0));
+    return BR_OK;
+}
+
+int run_device(BatchState& st, BatchPlan& P, const int32_t* d_edges, int mode) {
+    hipStream_t s = st.stream;
+    const bool two = mode == 1 && !P.small.empty();
+    if (!(P.exec && P.graph_edges == d_edges && P.graph_mode == mode)) {
+        for (hipGraphExec_t* x : {&P.exec, &P.exec2})
+            if (*x) { (void)hipGraphExecDestroy(*x); *x = nullptr; }
+        for (hipGraph_t* g : {&P.graph, &P.graph2})
+            if (*g) { (void)hipGraphDestroy(*g); *g = nullptr; }
+        P.graph_edges = nullptr;
+        int rc = capture(P, d_edges, s, mode, 0, &P.graph, &P.exec);
+        if (rc) return rc;
+        if (two) {
+            rc = capture(P, d_edges, s, mode, 1, &P.graph2, &P.exec2);
+            if (rc) return rc;
+        }
+        P.graph_edges = d_edges;
+        P.graph_mode = mode;
+    }
     BR_HIP(hipEventRecord(st.k0, s));
     BR_HIP(hipGraphLaunch(P.exec, s));
     BR_HIP(hipEventRecord(st.k1, s));
+    if (two) BR_HIP(hipGraphLaunch(P.exec2, s));
+    BR_HIP(hipEventRecord(st.k2, s));
     return copy_back(P, s, mode);
 }
 
@@ -389,6 +412,7 @@ void batched_release(br_ctx* c) {
     if (st->e1) (void)hipEventDestroy(st->e1);
     if (st->k0) (void)hipEventDestroy(st->k0);
     if (st->k1) (void)hipEventDestroy(st->k1);
+    if (st->k2) (void)hipEventDestroy(st->k2);
     if (st->stream) (void)hipStreamDestroy(st->stream);
     delete st;
     c->batched = nullptr;
@@ -442,6 +466,7 @@ int br_bridges_find_batched(br_ctx* c, const int32_t* d_edges, const int64_t* h_
         BR_HIP(hipEventCreate(&st.e1));
         BR_HIP(hipEventCreate(&st.k0));
         BR_HIP(hipEventCreate(&st.k1));
+        BR_HIP(hipEventCreate(&st.k2));
     }
     if (!st.pool) {
         int n = (int)std::thread::hardware_concurrency();
@@ -495,6 +520,7 @@ int br_bridges_find_batched(br_ctx* c, const int32_t* d_edges, const int64_t* h_
     if (c->profiling) BR_HIP(hipEventRecord(st.e1, st.stream));
     BR_HIP(hipStreamSynchronize(st.stream));
     auto t1 = std::chrono::steady_clock::now();
+    if (mode == 1 && !P->small.empty()) *P->h_err = P->h_blk[4];
     if (*P->h_err & 1u) return fail(BR_ERANGE, "batched: an edge has a vertex id outside its graph's [0, V)");
     if (*P->h_err) return fail(BR_EINTERNAL, "batched: certificate region overflow");
 
@@ -509,12 +535,16 @@ int br_bridges_find_batched(br_ctx* c, const int32_t* d_edges, const int64_t* h_
     }
     uint64_t* outk = st.outk.get();
     if (mode == 1) {
-        // bridges of the combined certificate, regrouped by graph
-        const uint32_t nk = S ? std::min<uint32_t>(*P->h_nkeys, (uint32_t)std::max<int64_t>(P->vtot, 1)) : 0;
-        if (nk) {
-            BR_HIP(hipMemcpyAsync(P->h_keys, P->d_keys, 8 * (size_t)nk, hipMemcpyDeviceToHost, st.stream));
+        // bridges of the combined certificate, regrouped by graph (the first
+        // keys came with the status block; any beyond the guess follow now)
+        const size_t guess = std::min<size_t>(std::max<size_t>(P->keys_hint, 1024), (size_t)std::max<int64_t>(P->vtot, 2));
+        const uint32_t nk = S ? std::min<uint32_t>(P->h_blk[1], (uint32_t)std::max<int64_t>(P->vtot, 1)) : 0;
+        if (nk > guess) {
+            BR_HIP(hipMemcpyAsync(P->h_keys + guess, P->d_keys + guess, 8 * (size_t)(nk - guess), hipMemcpyDeviceToHost,
+                                  st.stream));
             BR_HIP(hipStreamSynchronize(st.stream));
         }
+        P->keys_hint = nk;
         std::vector<int64_t> fillp(slot.begin(), slot.end() - 1);
         for (uint32_t i = 0; i < nk; i++) {
             const int64_t a = (int64_t)(P->h_keys[i] >> 32), b = (int64_t)(P->h_keys[i] & 0xffffffffu);
@@ -591,6 +621,8 @@ int br_bridges_find_batched(br_ctx* c, const int32_t* d_edges, const int64_t* h_
         c->prof.ms_cert = ms;
         if (hipEventElapsedTime(&ms, st.k0, st.k1) != hipSuccess) ms = 0.f;   // clear + persistent kernel
         c->prof.ms_phase0 = ms;
+        if (hipEventElapsedTime(&ms, st.k1, st.k2) != hipSuccess) ms = 0.f;   // combined bridge step (if any)
+        c->prof.ms_bridge_dev = mode == 1 ? ms : 0.0;
         (void)hipGetLastError();
         c->prof.ms_merge = 0;
         c->prof.ms_d2h = 0;

@@ -133,6 +133,18 @@ namespace {
 
 // Certify edges [t0, t1) of graph g (ids < V) into an empty LDS state and write
 // the accepted edges to node region (off, cap).  Counts go to S.n1, S.n2.
+// Each thread takes kU edges per step and the next step's edges are loaded
+// before the current ones are offered, so that enough loads are in flight to
+// cover HBM latency while the LDS work proceeds.
+constexpr int kU = 4;
+
+__device__ __forceinline__ void load_step(const BatchDev& B, int64_t base, int64_t t1, int2 (&e)[kU]) {
+    for (int j = 0; j < kU; j++) {
+        const int64_t i = base + j * kBB + threadIdx.x;
+        e[j] = i < t1 ? B.edges[i] : make_int2(-1, -1);
+    }
+}
+
 __device__ void certify_chunk(LdsState& S, const BatchDev& B, int64_t t0, int64_t t1, uint32_t V, int64_t off,
                               int64_t cap) {
     for (uint32_t x = threadIdx.x; x < V; x += kBB) S.q[x] = 0;
@@ -141,26 +153,32 @@ __device__ void certify_chunk(LdsState& S, const BatchDev& B, int64_t t0, int64_
     // compress after the first 2V and 8V edges (dense chunks are then mostly
     // rejected by the shared-parent test)
     int64_t next_cmp = t0 + 2 * (int64_t)V;
-    for (int64_t base = t0; base < t1; base += kBB) {
+    constexpr int64_t kStep = (int64_t)kBB * kU;
+    int2 cur[kU], nxt[kU];
+    if (t0 < t1) load_step(B, t0, t1, cur);
+    for (int64_t base = t0; base < t1; base += kStep) {
         if (base >= next_cmp) {
             __syncthreads();
             lcompress(S.q, V);
             __syncthreads();
             next_cmp = next_cmp == t0 + 2 * (int64_t)V ? t0 + 8 * (int64_t)V : INT64_MAX;
         }
-        const int64_t i = base + threadIdx.x;
-        bool a1 = false, a2 = false;
-        int2 e = make_int2(0, 0);
-        if (i < t1) {
-            e = B.edges[i];
-            if ((uint32_t)e.x < V && (uint32_t)e.y < V) loffer(S.q, (uint32_t)e.x, (uint32_t)e.y, a1, a2);
-            else atomicOr(B.err, 1u);
+        if (base + kStep < t1) load_step(B, base + kStep, t1, nxt);
+        for (int j = 0; j < kU; j++) {
+            const int2 e = cur[j];
+            const bool live = base + j * kBB + threadIdx.x < t1;
+            bool a1 = false, a2 = false;
+            if (live) {
+                if ((uint32_t)e.x < V && (uint32_t)e.y < V) loffer(S.q, (uint32_t)e.x, (uint32_t)e.y, a1, a2);
+                else atomicOr(B.err, 1u);
+            }
+            uint64_t m;
+            const uint32_t p1 = reserve(&S.n1, a1, m);
+            if (a1) { if (p1 < cap) B.cert[off + p1] = e; else atomicOr(B.err, 2u); }
+            const uint32_t p2 = reserve(&S.n2, a2, m);
+            if (a2) { if (p2 < cap) B.cert[off + cap - 1 - p2] = e; else atomicOr(B.err, 2u); }
         }
-        uint64_t m;
-        const uint32_t p1 = reserve(&S.n1, a1, m);
-        if (a1) { if (p1 < cap) B.cert[off + p1] = e; else atomicOr(B.err, 2u); }
-        const uint32_t p2 = reserve(&S.n2, a2, m);
-        if (a2) { if (p2 < cap) B.cert[off + cap - 1 - p2] = e; else atomicOr(B.err, 2u); }
+        for (int j = 0; j < kU; j++) cur[j] = nxt[j];
     }
     __syncthreads();
 }
@@ -231,17 +249,18 @@ __global__ void __launch_bounds__(kBB) k_batched(BatchDev B) {
                 level++;
                 continue;
             }
-            // publish this node's certificate: every thread releases its own
-            // stores, then one arrival per workgroup on the pair's counter
-            __threadfence();
+            // publish this node's certificate: the barrier orders every
+            // thread's stores before thread 0's device-scope release (which
+            // writes the XCD's L2 back), then one arrival per workgroup
             __syncthreads();
             if (threadIdx.x == 0) {
+                __threadfence();
                 const uint32_t prev = atomicAdd(&B.arrive[cb + level * ((Mg + 1) / 2) + (i >> (level + 1))], 1u);
                 S.last = prev == 1u;
+                if (S.last) __threadfence();                // acquire the partner's certificate
             }
             __syncthreads();
             if (!S.last) break;                             // the partner will merge
-            __threadfence();                                // acquire the partner's certificate
             // merge: Certificate(X_i u X_j), staged in LDS, written back to node i
             for (uint32_t x = threadIdx.x; x < V; x += kBB) S.q[x] = 0;
             if (threadIdx.x == 0) { S.n1 = 0; S.n2 = 0; }

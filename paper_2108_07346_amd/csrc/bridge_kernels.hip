@@ -31,17 +31,6 @@ __device__ __forceinline__ int32_t arc_dst(const int2* f1, int32_t a) { const in
 
 #define GRID_LOOP(i, n) for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
-__global__ void k_zero_i32(int32_t* p, int64_t n) { GRID_LOOP(i, n) p[i] = 0; }
-
-__global__ void k_degree(const int2* f1, const uint32_t* cnt, int32_t* deg) {
-    const int64_t n1 = cnt[0];
-    GRID_LOOP(k, n1) {
-        const int2 e = f1[k];
-        atomicAdd(&deg[e.x], 1);
-        atomicAdd(&deg[e.y], 1);
-    }
-}
-
 // ---- exclusive scan (int32), reduce-then-scan in blocks of kT*4 -------------
 constexpr int kSB = kT * 4;
 
@@ -84,7 +73,104 @@ __global__ void k_scan_add(int32_t* a, int64_t n, const int32_t* sums) {
     for (int j = 0; j < 4; j++) if (base + j < n) a[base + j] += add;
 }
 
+// ---- one-pass exclusive scans (decoupled look-back) ----------------------------
+//
+// Each block takes a ticket (its order of arrival), scans its kSB elements,
+// publishes its aggregate, then adds the prefixes published by the blocks
+// before it.  A block only waits on blocks with smaller tickets, which are
+// already running, so the waits end.  Two 30-bit sums travel in one 64-bit
+// status word together with a 2-bit state (0 none, 1 aggregate, 2 inclusive).
+constexpr uint64_t kLoMask = (uint64_t(1) << 30) - 1;
+
+__device__ __forceinline__ uint64_t st_load(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_store(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// exclusive scan of one packed value per thread across the block; the block's
+// total goes to `total`.  Packed sums never carry between the two halves.
+__device__ __forceinline__ uint64_t block_exclusive64(uint64_t v, uint64_t* sh, uint64_t& total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint64_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) sh[w] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t s = 0;
+        for (int i = 0; i < kT / 64; i++) { const uint64_t t = sh[i]; sh[i] = s; s += t; }
+        sh[kT / 64] = s;
+    }
+    __syncthreads();
+    total = sh[kT / 64];
+    const uint64_t r = x - v + sh[w];
+    __syncthreads();
+    return r;
+}
+
+// prefix of everything before this block: thread 0 publishes the aggregate,
+// then wavefront 0 inspects 64 predecessors per round trip, summing back to the
+// nearest one that already holds its inclusive prefix
+__device__ __forceinline__ uint64_t look_back(uint64_t* status, uint32_t ticket, uint64_t total, uint64_t* sh) {
+    constexpr uint64_t kVal = ~(uint64_t(3) << 62);
+    if (threadIdx.x == 0) st_store(status + ticket, (uint64_t(ticket == 0 ? 2 : 1) << 62) | total);
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        uint64_t prefix = 0;
+        for (int64_t j = (int64_t)ticket - 1; j >= 0; j -= 64) {
+            const int64_t idx = j - lane;
+            uint64_t w = uint64_t(2) << 62;                   // before block 0: inclusive, zero
+            if (idx >= 0)
+                do { w = st_load(status + idx); } while ((w >> 62) == 0);
+            const uint64_t incl = __ballot((w >> 62) == 2);
+            const int stop = incl ? __ffsll((unsigned long long)incl) - 1 : 63;
+            uint64_t v = lane <= stop ? (w & kVal) : 0;
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            prefix += v;
+            if (incl) break;
+        }
+        if (lane == 0) {
+            if (ticket != 0) st_store(status + ticket, (uint64_t(2) << 62) | (prefix + total));
+            sh[kT / 64 + 1] = prefix;
+        }
+    }
+    __syncthreads();
+    return sh[kT / 64 + 1];
+}
+
+// in-place exclusive scan of a[0..n); status[] and *ticket zeroed beforehand
+__global__ void __launch_bounds__(kT) k_scan1(int32_t* a, int64_t n, uint64_t* status, uint32_t* ticket) {
+    __shared__ uint64_t sh[kT / 64 + 2];
+    __shared__ uint32_t tk;
+    if (threadIdx.x == 0) tk = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const uint32_t t = tk;
+    const int64_t base = (int64_t)t * kSB + threadIdx.x * 4;
+    int32_t v[4];
+    uint64_t sum = 0;
+    for (int j = 0; j < 4; j++) { v[j] = base + j < n ? a[base + j] : 0; sum += (uint32_t)v[j]; }
+    uint64_t total;
+    uint64_t ex = block_exclusive64(sum, sh, total);
+    ex += look_back(status, t, total, sh);
+    for (int j = 0; j < 4; j++) { if (base + j < n) a[base + j] = (int32_t)ex; ex += (uint32_t)v[j]; }
+}
+
 // ---- adjacency of F -----------------------------------------------------------
+__global__ void k_zero_i32(int32_t* p, int64_t n) { GRID_LOOP(i, n) p[i] = 0; }
+
+__global__ void k_degree(const int2* f1, const uint32_t* cnt, int32_t* deg) {
+    const int64_t n1 = cnt[0];
+    GRID_LOOP(k, n1) {
+        const int2 e = f1[k];
+        atomicAdd(&deg[e.x], 1);
+        atomicAdd(&deg[e.y], 1);
+    }
+}
+
 __global__ void k_fill_adj(const int2* f1, const uint32_t* cnt, const int32_t* head, int32_t* cur, int32_t* adj,
                            int32_t* posof) {
     const int64_t A = 2 * (int64_t)cnt[0];
@@ -96,9 +182,17 @@ __global__ void k_fill_adj(const int2* f1, const uint32_t* cnt, const int32_t* h
     }
 }
 
+// ---- list ranking of the Euler tours -------------------------------------------
+//
+// link[a] = (next, dist, far): while next >= 0, next == far is the arc `dist`
+// steps after a; once the tour's end is reached next = -1 and far is the
+// tour's last arc, `dist` steps after a.  A round follows kHop links of the
+// previous round, so spans grow kHop-fold per launch.
+constexpr int kHop = 8;
+
 // successor in the Euler tour; tours cut open at union-find roots of F
 __global__ void k_succ(const int2* f1, const uint32_t* cnt, const int32_t* head, const int32_t* adj,
-                       const int32_t* posof, const uint32_t* q, int32_t qs, int32_t* nxt, int32_t* rank, int32_t* tail) {
+                       const int32_t* posof, const uint32_t* q, int32_t qs, int4* link) {
     const int64_t A = 2 * (int64_t)cnt[0];
     GRID_LOOP(a, A) {
         const int32_t y = arc_dst(f1, (int32_t)a);
@@ -107,63 +201,83 @@ __global__ void k_succ(const int2* f1, const uint32_t* cnt, const int32_t* head,
         int32_t s = adj[nx];
         // arc (c -> r) closing the tour of root r: r's last listed arc is (r -> c)
         if (q[qs * (size_t)y] == 0 && p == head[y + 1] - 1) s = -1;
-        nxt[a] = s;
-        rank[a] = s < 0 ? 0 : 1;
-        tail[a] = s < 0 ? (int32_t)a : s;
+        link[a] = s < 0 ? make_int4(-1, 0, (int32_t)a, 0) : make_int4(s, 1, s, 0);
     }
 }
 
-__global__ void k_jump(const uint32_t* cnt, const int32_t* nxt, const int32_t* rank, const int32_t* tail, int32_t* nxt2,
-                       int32_t* rank2, int32_t* tail2, int32_t* changed) {
+__global__ void k_jump(const uint32_t* cnt, const int4* link, int4* out) {
     const int64_t A = 2 * (int64_t)cnt[0];
     GRID_LOOP(a, A) {
-        const int32_t s = nxt[a];
-        if (s >= 0) {
-            rank2[a] = rank[a] + rank[s];
-            tail2[a] = tail[s];
-            nxt2[a] = nxt[s];
-            if (nxt[s] >= 0) *changed = 1;
-        } else {
-            rank2[a] = rank[a];
-            tail2[a] = tail[a];
-            nxt2[a] = -1;
+        int4 x = link[a];
+#pragma unroll
+        for (int j = 1; j < kHop; j++) {
+            if (x.x < 0) break;
+            const int4 y = link[x.x];
+            x = make_int4(y.x, x.y + y.y, y.z, 0);
         }
+        out[a] = x;
     }
 }
 
-// per root: tour length (arcs) and vertex count; written at the root's slot
-__global__ void k_root_sizes(const int32_t* head, const int32_t* adj, const int32_t* rank, const uint32_t* q, int32_t qs,
-                             int32_t V, int32_t* tour_len, int32_t* tree_n) {
-    GRID_LOOP(r, (int64_t)V) {
-        int32_t L = 0, nv = 0;
-        if (q[qs * (size_t)r] == 0 && head[r + 1] > head[r]) {
-            L = rank[adj[head[r]]] + 1;
-            nv = L / 2 + 1;
+// per vertex r: the arcs and vertices of its tree if r is a root (else 0),
+// and their exclusive prefix sums over r -- one pass, two sums per status word
+__global__ void __launch_bounds__(kT) k_tours(const int32_t* head, const int32_t* adj, const int4* link,
+                                              const uint32_t* q, int32_t qs, int32_t V, int32_t* tour_len,
+                                              int32_t* tree_n, int32_t* tour_base, int32_t* vbase, uint64_t* status,
+                                              uint32_t* ticket) {
+    __shared__ uint64_t sh[kT / 64 + 2];
+    __shared__ uint32_t tk;
+    if (threadIdx.x == 0) tk = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const uint32_t t = tk;
+    const int64_t base = (int64_t)t * kSB + threadIdx.x * 4;
+    int32_t L[4], N[4];
+    uint64_t sum = 0;
+    for (int j = 0; j < 4; j++) {
+        const int64_t r = base + j;
+        L[j] = 0;
+        N[j] = 0;
+        if (r < V && q[qs * (size_t)r] == 0 && head[r + 1] > head[r]) {
+            L[j] = link[adj[head[r]]].y + 1;
+            N[j] = L[j] / 2 + 1;
         }
-        tour_len[r] = L;
-        tree_n[r] = nv;
+        sum += (uint64_t)(uint32_t)L[j] | ((uint64_t)(uint32_t)N[j] << 30);
+    }
+    uint64_t total;
+    uint64_t ex = block_exclusive64(sum, sh, total);
+    ex += look_back(status, t, total, sh);
+    for (int j = 0; j < 4; j++) {
+        const int64_t r = base + j;
+        if (r < V) {
+            tour_len[r] = L[j];
+            tree_n[r] = N[j];
+            tour_base[r] = (int32_t)(ex & kLoMask);
+            vbase[r] = (int32_t)(ex >> 30);
+        }
+        ex += (uint64_t)(uint32_t)L[j] | ((uint64_t)(uint32_t)N[j] << 30);
     }
 }
 
-// tour position of every arc; downward arcs give parent, subtree size and a flag in tour order
-__global__ void k_positions(const int2* f1, const uint32_t* cnt, const int32_t* rank, const int32_t* tail,
-                            const int32_t* tour_len, const int32_t* tour_base, int32_t* pos, int32_t* flag) {
-    const int64_t A = 2 * (int64_t)cnt[0];
-    GRID_LOOP(a, A) {
-        const int32_t r = arc_dst(f1, tail[a]);
-        const int32_t p = tour_len[r] - 1 - rank[a];
-        pos[a] = p;
-    }
+__device__ __forceinline__ int32_t tour_pos(const int2* f1, const int4* link, const int32_t* tour_len, int32_t a,
+                                            int32_t* root) {
+    const int4 l = link[a];
+    const int32_t r = arc_dst(f1, l.z);
+    *root = r;
+    return tour_len[r] - 1 - l.y;
 }
 
-__global__ void k_down(const int2* f1, const uint32_t* cnt, const int32_t* tail, const int32_t* pos,
+// downward arcs (first entry into a vertex): parent arc, subtree size and a
+// flag at the arc's place in the concatenated tours
+__global__ void k_down(const int2* f1, const uint32_t* cnt, const int4* link, const int32_t* tour_len,
                        const int32_t* tour_base, int32_t* flag, int32_t* in_arc, int32_t* sub) {
     const int64_t A = 2 * (int64_t)cnt[0];
     GRID_LOOP(a, A) {
-        const int32_t p = pos[a], pr = pos[a ^ 1];
+        int32_t r;
+        const int32_t p = tour_pos(f1, link, tour_len, (int32_t)a, &r);
+        const int32_t L = tour_len[r], pr = L - 1 - link[a ^ 1].y;
+        if (p < 0 || pr >= L) continue;   // only an inconsistent forest gets here
         if (p < pr) {   // a = (x -> y) enters y for the first time
             const int32_t y = arc_dst(f1, (int32_t)a);
-            const int32_t r = arc_dst(f1, tail[a]);
             flag[tour_base[r] + p] = 1;
             in_arc[y] = (int32_t)a;
             sub[y] = (pr - p + 1) / 2;
@@ -171,11 +285,11 @@ __global__ void k_down(const int2* f1, const uint32_t* cnt, const int32_t* tail,
     }
 }
 
-// preorder numbers; lo = hi = own preorder to start
+// preorder numbers; the range tables start with every vertex's own number
 __global__ void k_preorder(const int2* f1, const uint32_t* q, int32_t qs, const int32_t* head, const int32_t* in_arc,
-                           const int32_t* tail, const int32_t* pos, const int32_t* tour_base, const int32_t* down_ex,
-                           const int32_t* vbase, const int32_t* tree_n, int32_t V, int32_t* pre, int32_t* sub, int32_t* lo,
-                           int32_t* hi) {
+                           const int4* link, const int32_t* tour_len, const int32_t* tour_base, const int32_t* down_ex,
+                           const int32_t* vbase, const int32_t* tree_n, int32_t V, int32_t* pre, int32_t* sub,
+                           int32_t* tmin, int32_t* tmax) {
     GRID_LOOP(v, (int64_t)V) {
         int32_t pv = -1;
         if (head[v + 1] > head[v]) {
@@ -183,64 +297,168 @@ __global__ void k_preorder(const int2* f1, const uint32_t* q, int32_t qs, const 
                 pv = vbase[v];
                 sub[v] = tree_n[v];
             } else {
-                const int32_t a = in_arc[v];
-                const int32_t r = arc_dst(f1, tail[a]);
-                pv = vbase[r] + 1 + (down_ex[tour_base[r] + pos[a]] - down_ex[tour_base[r]]);
+                int32_t r;
+                const int32_t p = tour_pos(f1, link, tour_len, in_arc[v], &r);
+                if (p >= 0 && p < tour_len[r]) pv = vbase[r] + 1 + (down_ex[tour_base[r] + p] - down_ex[tour_base[r]]);
+            }
+            if (pv >= 0 && pv < V) {
+                tmin[pv] = pv;
+                tmax[pv] = pv;
             }
         }
         pre[v] = pv;
-        lo[v] = pv;
-        hi[v] = pv;
     }
 }
 
-// F' edges pull each endpoint's lo/hi toward the other endpoint's preorder
-__global__ void k_nontree(const int2* f2, int32_t dir, const uint32_t* cnt, const int32_t* pre, int32_t* lo, int32_t* hi) {
+// F' edges pull each endpoint's range toward the other endpoint's number
+// (both endpoints of an F' edge lie in one tree of F, so both are numbered)
+__global__ void k_nontree(const int2* f2, int32_t dir, const uint32_t* cnt, const int32_t* pre, int32_t* tmin,
+                          int32_t* tmax) {
     const int64_t n2 = cnt[1];
     GRID_LOOP(k, n2) {
         const int2 e = f2[dir * k];
         const int32_t px = pre[e.x], py = pre[e.y];
-        atomicMin(&lo[e.x], py);
-        atomicMax(&hi[e.x], py);
-        atomicMin(&lo[e.y], px);
-        atomicMax(&hi[e.y], px);
+        if (px < 0 || py < 0) continue;   // only an inconsistent certificate gets here
+        atomicMin(&tmin[px], py);
+        atomicMax(&tmax[px], py);
+        atomicMin(&tmin[py], px);
+        atomicMax(&tmax[py], px);
     }
 }
 
-__global__ void k_to_preorder(const int32_t* pre, const int32_t* lo, const int32_t* hi, int32_t V, int32_t* tmin,
-                              int32_t* tmax) {
-    GRID_LOOP(v, (int64_t)V) {
-        const int32_t p = pre[v];
-        if (p >= 0) { tmin[p] = lo[v]; tmax[p] = hi[v]; }
-    }
-}
-
-__global__ void k_sparse_level(const int32_t* pmin, const int32_t* pmax, int32_t* cmin, int32_t* cmax, int64_t n,
-                               int64_t half) {
-    GRID_LOOP(i, n) {
-        const int64_t j = i + half < n ? i + half : n - 1;
-        cmin[i] = min(pmin[i], pmin[j]);
-        cmax[i] = max(pmax[i], pmax[j]);
-    }
-}
+// ---- range minimum / maximum over preorder intervals ---------------------------
+//
+// Blocks of 64 numbers (one wavefront each).  Inside a block, level j (1..5)
+// holds the min/max of the 2^j numbers starting at each position (clipped at
+// the block's end), so any range inside one block takes two lookups; a sparse
+// table over the blocks' own min/max answers a run of whole blocks.  The
+// workgroup that finishes last builds that table in LDS when it is small.
+constexpr int kRB = 64;
+constexpr int kInLev = 5;              // in-block levels 1..5 (level 6 = the block value)
+constexpr int kLdsBlocks = 4096;       // block tables up to this size are built in LDS
 
 __device__ __forceinline__ int floor_log2(uint32_t x) { return 31 - __clz(x); }
 
+__device__ void build_block_table(int32_t* tmn, int32_t* tmx, int64_t nb, int32_t levels, int32_t* smn, int32_t* smx) {
+    for (int64_t i = threadIdx.x; i < nb; i += blockDim.x) { smn[i] = tmn[i]; smx[i] = tmx[i]; }
+    __syncthreads();
+    constexpr int kPer = kLdsBlocks / kT;
+    for (int32_t j = 1; j < levels; j++) {
+        const int64_t half = int64_t(1) << (j - 1);
+        int32_t a[kPer], b[kPer];
+        for (int k = 0; k < kPer; k++) {
+            const int64_t i = threadIdx.x + (int64_t)k * kT;
+            if (i < nb) {
+                const int64_t q = i + half < nb ? i + half : nb - 1;
+                a[k] = min(smn[i], smn[q]);
+                b[k] = max(smx[i], smx[q]);
+            }
+        }
+        __syncthreads();
+        for (int k = 0; k < kPer; k++) {
+            const int64_t i = threadIdx.x + (int64_t)k * kT;
+            if (i < nb) {
+                smn[i] = a[k];
+                smx[i] = b[k];
+                tmn[j * nb + i] = a[k];
+                tmx[j * nb + i] = b[k];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// per block: in-block levels and the block's min/max (level 0 of the block table)
+__global__ void __launch_bounds__(kT) k_rmq_blocks(const int32_t* tmin, const int32_t* tmax, int64_t n, int32_t* lmin,
+                                                   int32_t* lmax, int32_t* tmn, int32_t* tmx, int64_t nb) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    int32_t a = i < n ? tmin[i] : INT32_MAX, b = i < n ? tmax[i] : INT32_MIN;
+    for (int j = 1; j <= kInLev + 1; j++) {
+        const int o = 1 << (j - 1);
+        const int32_t da = __shfl_down(a, o), db = __shfl_down(b, o);
+        if (lane + o < 64) { a = min(a, da); b = max(b, db); }
+        if (j <= kInLev) {
+            if (i < n) { lmin[(int64_t)(j - 1) * n + i] = a; lmax[(int64_t)(j - 1) * n + i] = b; }
+        } else if (lane == 0 && (i >> 6) < nb) {
+            tmn[i >> 6] = a;
+            tmx[i >> 6] = b;
+        }
+    }
+}
+
+// the block table in one workgroup, in LDS (nb <= kLdsBlocks)
+__global__ void __launch_bounds__(kT) k_rmq_table(int32_t* tmn, int32_t* tmx, int64_t nb, int32_t levels) {
+    __shared__ int32_t smn[kLdsBlocks], smx[kLdsBlocks];
+    build_block_table(tmn, tmx, nb, levels, smn, smx);
+}
+
+// sparse table level j (j >= 1) over nb block values, levels stored nb apart
+__global__ void k_rmq_level(int32_t* tmn, int32_t* tmx, int64_t nb, int32_t j) {
+    const int64_t half = int64_t(1) << (j - 1);
+    int32_t *pmn = tmn + (j - 1) * nb, *pmx = tmx + (j - 1) * nb, *cmn = tmn + j * nb, *cmx = tmx + j * nb;
+    GRID_LOOP(i, nb) {
+        const int64_t k = i + half < nb ? i + half : nb - 1;
+        cmn[i] = min(pmn[i], pmn[k]);
+        cmx[i] = max(pmx[i], pmx[k]);
+    }
+}
+
+struct Rmq {
+    const int32_t *t, *u, *lmin, *lmax, *tmn, *tmx;
+    int64_t n, nb;
+};
+
+// min/max over [a, b] inside one block
+__device__ __forceinline__ void in_block(const Rmq& R, int32_t a, int32_t b, int32_t& mn, int32_t& mx) {
+    const int j = floor_log2((uint32_t)(b - a + 1));
+    if (j == 0) {
+        mn = R.t[a];
+        mx = R.u[a];
+    } else if (j <= kInLev) {
+        const int64_t o = (int64_t)(j - 1) * R.n;
+        const int32_t c = b - (1 << j) + 1;
+        mn = min(R.lmin[o + a], R.lmin[o + c]);
+        mx = max(R.lmax[o + a], R.lmax[o + c]);
+    } else {   // the whole block
+        mn = R.tmn[a >> 6];
+        mx = R.tmx[a >> 6];
+    }
+}
+
+__device__ __forceinline__ void range_minmax(const Rmq& R, int32_t l, int32_t r, int32_t& mn, int32_t& mx) {
+    const int32_t bl = l >> 6, br = r >> 6;
+    if (bl == br) {
+        in_block(R, l, r, mn, mx);
+        return;
+    }
+    int32_t m2, x2;
+    in_block(R, l, bl * 64 + 63, mn, mx);
+    in_block(R, br * 64, r, m2, x2);
+    mn = min(mn, m2);
+    mx = max(mx, x2);
+    if (br - bl > 1) {
+        const int32_t a = bl + 1, b = br - 1;
+        const int j = floor_log2((uint32_t)(b - a + 1));
+        const int64_t lev = (int64_t)j * R.nb;
+        mn = min(mn, min(R.tmn[lev + a], R.tmn[lev + b - (1 << j) + 1]));
+        mx = max(mx, max(R.tmx[lev + a], R.tmx[lev + b - (1 << j) + 1]));
+    }
+}
+
 __global__ void k_bridges(const int2* f1, const uint32_t* q, int32_t qs, const int32_t* head, const int32_t* in_arc,
-                          const int32_t* pre, const int32_t* sub, const int32_t* tmin, const int32_t* tmax, int64_t nt,
-                          int32_t V, uint64_t* out, uint32_t* nout) {
+                          const int32_t* pre, const int32_t* sub, Rmq R, int32_t V, int64_t A, uint64_t* out,
+                          uint32_t* nout) {
     GRID_LOOP(v, (int64_t)V) {
         bool br = false;
         uint64_t key = 0;
         if (head[v + 1] > head[v] && q[qs * (size_t)v] != 0) {
-            const int32_t l = pre[v], r = pre[v] + sub[v] - 1;
-            const int j = floor_log2((uint32_t)(r - l + 1));
-            const int64_t lev = (int64_t)j * nt;
-            const int32_t mn = min(tmin[lev + l], tmin[lev + r - (1 << j) + 1]);
-            const int32_t mx = max(tmax[lev + l], tmax[lev + r - (1 << j) + 1]);
+            const int32_t l = pre[v], r = pre[v] + sub[v] - 1, a = in_arc[v];
+            int32_t mn = -1, mx = V;
+            if (l >= 0 && r >= l && r < V && a >= 0 && a < A) range_minmax(R, l, r, mn, mx);
             if (mn >= l && mx <= r) {
                 br = true;
-                const int2 e = f1[in_arc[v] >> 1];
+                const int2 e = f1[a >> 1];
                 const uint32_t a = (uint32_t)min(e.x, e.y), b = (uint32_t)max(e.x, e.y);
                 key = (uint64_t)a << 32 | b;
             }
@@ -253,6 +471,15 @@ __global__ void k_bridges(const int2* f1, const uint32_t* q, int32_t qs, const i
             base = __shfl(base, leader);
             if (br) out[base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = key;
         }
+    }
+}
+
+// counters of the certificate and the result next to the keys, for one copy
+__global__ void k_status(const uint32_t* cnt, const uint32_t* err, uint32_t* misc) {
+    if (threadIdx.x == 0) {
+        misc[2] = cnt[0];
+        misc[3] = cnt[1];
+        misc[4] = err ? *err : 0u;
     }
 }
 
@@ -289,47 +516,56 @@ void device_scan(int32_t* a, int64_t n, int32_t* scratch, hipStream_t s) {
 }
 
 // Scratch layout of the bridge step, shared by the size query and the launch
-// sequence so that the two cannot disagree.
+// sequence so that the two cannot disagree.  Everything from `head` up to the
+// end of `misc` is cleared by one kernel at the start; the keys follow `misc`
+// directly, so that the counters and the keys leave in one copy.
 struct BridgeWs {
-    int32_t *head, *cur, *adj, *posof, *nxt, *rank, *tail, *nxt2, *rank2, *tail2, *tour_len, *tree_n, *tour_base,
-        *vbase, *pos, *flag, *in_arc, *sub, *pre, *lo, *hi, *tmin, *tmax, *misc, *scr;
-    uint64_t* keys;
+    int32_t *head, *cur, *flag, *tickets, *misc, *adj, *posof, *tour_len, *tree_n, *tour_base, *vbase, *in_arc, *sub,
+        *pre, *tmin, *tmax, *lmin, *lmax, *tmn, *tmx;
+    uint64_t *st_head, *st_tours, *st_flag, *keys;
+    int4 *link, *link2;
+    int64_t zero_words, nb;
+    int32_t levels;
     int64_t words;
 };
 
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
 static BridgeWs carve(int32_t* base, int32_t V) {
     const int64_t A = 2 * (int64_t)std::max(V - 1, 1);
-    int J = 1;
-    while ((int64_t(1) << J) < V) J++;
     BridgeWs w{};
     int64_t o = 0;
     auto take = [&](int64_t n) { int32_t* p = base ? base + o : nullptr; o += (n + 63) & ~int64_t(63); return p; };
     w.head = take(V + 2);
     w.cur = take(V + 1);
-    w.adj = take(A);
-    w.posof = take(A);
-    w.nxt = take(A);
-    w.rank = take(A);
-    w.tail = take(A);
-    w.nxt2 = take(A);
-    w.rank2 = take(A);
-    w.tail2 = take(A);
-    w.tour_len = take(V);
-    w.tree_n = take(V);
-    w.tour_base = take(V + 1);
-    w.vbase = take(V + 1);
-    w.pos = take(A);
     w.flag = take(A + 1);
+    w.tickets = take(64);   // [0..2] scan tickets
+    w.st_head = reinterpret_cast<uint64_t*>(take(2 * cdiv(V + 1, kSB)));
+    w.st_tours = reinterpret_cast<uint64_t*>(take(2 * cdiv(V, kSB)));
+    w.st_flag = reinterpret_cast<uint64_t*>(take(2 * cdiv(A + 1, kSB)));
     w.in_arc = take(V);
     w.sub = take(V);
-    w.pre = take(V);
-    w.lo = take(V);
-    w.hi = take(V);
-    w.tmin = take((int64_t)(J + 1) * V);
-    w.tmax = take((int64_t)(J + 1) * V);
+    w.misc = take(64);   // [1] key count, [2..4] |F|, |F'|, error word
+    w.zero_words = o;
     w.keys = reinterpret_cast<uint64_t*>(take(2 * (int64_t)V + 2));
-    w.misc = take(64);   // [0] changed flag, [1] key count
-    w.scr = take(scan_scratch(std::max<int64_t>(A, V) + 1));
+    w.adj = take(A);
+    w.posof = take(A);
+    w.link = reinterpret_cast<int4*>(take(4 * A));
+    w.link2 = reinterpret_cast<int4*>(take(4 * A));
+    w.tour_len = take(V);
+    w.tree_n = take(V);
+    w.tour_base = take(V);
+    w.vbase = take(V);
+    w.pre = take(V);
+    w.tmin = take(V);
+    w.tmax = take(V);
+    w.lmin = take((int64_t)kInLev * V);
+    w.lmax = take((int64_t)kInLev * V);
+    w.nb = cdiv(V, kRB);
+    w.levels = 1;
+    while ((int64_t(1) << w.levels) <= w.nb) w.levels++;
+    w.tmn = take(w.levels * w.nb);
+    w.tmx = take(w.levels * w.nb);
     w.words = o;
     return w;
 }
@@ -339,58 +575,49 @@ int64_t device_bridges_words(int32_t V) { return carve(nullptr, V).words; }
 // Bridges of a certificate held on the device: F = f1[0..cnt[0]), F' =
 // f2[dir*k] for k < cnt[1] (counts read on the device), vertex v is the root of
 // its tree of F iff q[qs*v] == 0.  Writes up to V keys at *d_keys and their
-// number at *d_n.
+// number at *d_n; *d_n sits 4 bytes into a 256-byte status block that the keys
+// follow directly.
 int device_bridges_cert(const int2* f1, const int2* f2, int32_t dir, const uint32_t* cnt, const uint32_t* q, int32_t qs,
                         int32_t V, int32_t max_tree, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s) {
     const int64_t A = 2 * (int64_t)std::max(V - 1, 1);
-    // list ranking and the subtree range tables only need the largest tree:
-    // tours have at most 2(max_tree - 1) arcs, subtrees at most max_tree vertices
+    // list ranking only needs the longest tour: at most 2(max_tree - 1) arcs
     max_tree = std::max(2, std::min(max_tree, V));
-    int J = 1;
-    while ((int64_t(1) << J) < max_tree) J++;
     const BridgeWs W = carve(ws, V);
-    int32_t *head = W.head, *cur = W.cur, *adj = W.adj, *posof = W.posof, *nxt = W.nxt, *rank = W.rank,
-            *tail = W.tail, *nxt2 = W.nxt2, *rank2 = W.rank2, *tail2 = W.tail2, *tour_len = W.tour_len,
-            *tree_n = W.tree_n, *tour_base = W.tour_base, *vbase = W.vbase, *pos = W.pos, *flag = W.flag,
-            *in_arc = W.in_arc, *sub = W.sub, *pre = W.pre, *lo = W.lo, *hi = W.hi, *tmin = W.tmin, *tmax = W.tmax,
-            *misc = W.misc, *scr = W.scr;
-    uint64_t* keys = W.keys;
-    hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(V + 2)), dim3(kT), 0, s, head, (int64_t)V + 2);
-    hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(V + 1)), dim3(kT), 0, s, cur, (int64_t)V + 1);
-    hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(A + 1)), dim3(kT), 0, s, flag, A + 1);
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(kT), 0, s, misc, (int64_t)64);
-    hipLaunchKernelGGL(k_degree, dim3(grid_for(V)), dim3(kT), 0, s, f1, cnt, head);
-    device_scan(head, V + 1, scr, s);
-    hipLaunchKernelGGL(k_fill_adj, dim3(grid_for(A)), dim3(kT), 0, s, f1, cnt, head, cur, adj, posof);
-    hipLaunchKernelGGL(k_succ, dim3(grid_for(A)), dim3(kT), 0, s, f1, cnt, head, adj, posof, q, qs, nxt, rank, tail);
-    int rounds = 0;
-    while ((int64_t(1) << rounds) < 2 * (int64_t)max_tree) rounds++;
-    for (int i = 0; i < rounds; i++) {
-        hipLaunchKernelGGL(k_jump, dim3(grid_for(A)), dim3(kT), 0, s, cnt, nxt, rank, tail, nxt2, rank2, tail2, misc);
-        std::swap(nxt, nxt2);
-        std::swap(rank, rank2);
-        std::swap(tail, tail2);
+    hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(W.zero_words)), dim3(kT), 0, s, W.head, W.zero_words);
+    hipLaunchKernelGGL(k_degree, dim3(grid_for(V)), dim3(kT), 0, s, f1, cnt, W.head);
+    hipLaunchKernelGGL(k_scan1, dim3((unsigned)cdiv(V + 1, kSB)), dim3(kT), 0, s, W.head, (int64_t)V + 1, W.st_head,
+                       reinterpret_cast<uint32_t*>(W.tickets));
+    hipLaunchKernelGGL(k_fill_adj, dim3(grid_for(A)), dim3(kT), 0, s, f1, cnt, W.head, W.cur, W.adj, W.posof);
+    int4 *link = W.link, *link2 = W.link2;
+    hipLaunchKernelGGL(k_succ, dim3(grid_for(A)), dim3(kT), 0, s, f1, cnt, W.head, W.adj, W.posof, q, qs, link);
+    const int64_t longest = 2 * ((int64_t)max_tree - 1);
+    for (int64_t span = 1; span < longest; span *= kHop) {
+        hipLaunchKernelGGL(k_jump, dim3(grid_for(A)), dim3(kT), 0, s, cnt, (const int4*)link, link2);
+        std::swap(link, link2);
     }
-    hipLaunchKernelGGL(k_root_sizes, dim3(grid_for(V)), dim3(kT), 0, s, head, adj, rank, q, qs, V, tour_len, tree_n);
-    BR_HIP(hipMemcpyAsync(tour_base, tour_len, sizeof(int32_t) * V, hipMemcpyDeviceToDevice, s));
-    BR_HIP(hipMemcpyAsync(vbase, tree_n, sizeof(int32_t) * V, hipMemcpyDeviceToDevice, s));
-    device_scan(tour_base, V, scr, s);
-    device_scan(vbase, V, scr, s);
-    hipLaunchKernelGGL(k_positions, dim3(grid_for(A)), dim3(kT), 0, s, f1, cnt, rank, tail, tour_len, tour_base, pos, flag);
-    hipLaunchKernelGGL(k_down, dim3(grid_for(A)), dim3(kT), 0, s, f1, cnt, tail, pos, tour_base, flag, in_arc, sub);
-    device_scan(flag, A + 1, scr, s);
-    hipLaunchKernelGGL(k_preorder, dim3(grid_for(V)), dim3(kT), 0, s, f1, q, qs, head, in_arc, tail, pos, tour_base, flag,
-                       vbase, tree_n, V, pre, sub, lo, hi);
-    hipLaunchKernelGGL(k_nontree, dim3(grid_for(V)), dim3(kT), 0, s, f2, dir, cnt, pre, lo, hi);
-    hipLaunchKernelGGL(k_to_preorder, dim3(grid_for(V)), dim3(kT), 0, s, pre, lo, hi, V, tmin, tmax);
-    for (int j = 1; j <= J; j++)
-        hipLaunchKernelGGL(k_sparse_level, dim3(grid_for(V)), dim3(kT), 0, s, tmin + (int64_t)(j - 1) * V,
-                           tmax + (int64_t)(j - 1) * V, tmin + (int64_t)j * V, tmax + (int64_t)j * V, (int64_t)V,
-                           (int64_t)1 << (j - 1));
-    hipLaunchKernelGGL(k_bridges, dim3(grid_for(V)), dim3(kT), 0, s, f1, q, qs, head, in_arc, pre, sub, tmin, tmax, (int64_t)V,
-                       V, keys, reinterpret_cast<uint32_t*>(misc + 1));
-    *d_keys = keys;
-    *d_n = reinterpret_cast<uint32_t*>(misc + 1);
+    hipLaunchKernelGGL(k_tours, dim3((unsigned)cdiv(V, kSB)), dim3(kT), 0, s, W.head, W.adj, (const int4*)link, q, qs, V,
+                       W.tour_len, W.tree_n, W.tour_base, W.vbase, W.st_tours, reinterpret_cast<uint32_t*>(W.tickets) + 1);
+    hipLaunchKernelGGL(k_down, dim3(grid_for(A)), dim3(kT), 0, s, f1, cnt, (const int4*)link, W.tour_len, W.tour_base,
+                       W.flag, W.in_arc, W.sub);
+    hipLaunchKernelGGL(k_scan1, dim3((unsigned)cdiv(A + 1, kSB)), dim3(kT), 0, s, W.flag, A + 1, W.st_flag,
+                       reinterpret_cast<uint32_t*>(W.tickets) + 2);
+    hipLaunchKernelGGL(k_preorder, dim3(grid_for(V)), dim3(kT), 0, s, f1, q, qs, W.head, W.in_arc, (const int4*)link,
+                       W.tour_len, W.tour_base, W.flag, W.vbase, W.tree_n, V, W.pre, W.sub, W.tmin, W.tmax);
+    hipLaunchKernelGGL(k_nontree, dim3(grid_for(V)), dim3(kT), 0, s, f2, dir, cnt, W.pre, W.tmin, W.tmax);
+    const int64_t rblocks = cdiv(W.nb * kRB, kT);
+    hipLaunchKernelGGL(k_rmq_blocks, dim3((unsigned)rblocks), dim3(kT), 0, s, W.tmin, W.tmax, (int64_t)V, W.lmin,
+                       W.lmax, W.tmn, W.tmx, W.nb);
+    if (W.nb <= kLdsBlocks) {
+        hipLaunchKernelGGL(k_rmq_table, dim3(1), dim3(kT), 0, s, W.tmn, W.tmx, W.nb, W.levels);
+    } else {
+        for (int32_t j = 1; j < W.levels; j++)
+            hipLaunchKernelGGL(k_rmq_level, dim3(grid_for(W.nb)), dim3(kT), 0, s, W.tmn, W.tmx, W.nb, j);
+    }
+    const Rmq R{W.tmin, W.tmax, W.lmin, W.lmax, W.tmn, W.tmx, (int64_t)V, W.nb};
+    hipLaunchKernelGGL(k_bridges, dim3(grid_for(V)), dim3(kT), 0, s, f1, q, qs, W.head, W.in_arc, W.pre, W.sub, R, V,
+                       A, W.keys, reinterpret_cast<uint32_t*>(W.misc + 1));
+    *d_keys = W.keys;
+    *d_n = reinterpret_cast<uint32_t*>(W.misc + 1);
     return BR_OK;
 }
 
@@ -399,7 +626,15 @@ int device_bridges_cert(const int2* f1, const int2* f2, int32_t dir, const uint3
 int device_bridges(const Plan& P, const DevBufs& B, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s) {
     const int2* f1 = B.cert + P.off[0];
     const int2* f2 = B.cert + P.off[0] + P.cap[0] - 1;
-    return device_bridges_cert(f1, f2, -1, B.cnt, B.state, 2, P.V, P.V, ws, d_keys, d_n, s);
+    const int rc = device_bridges_cert(f1, f2, -1, B.cnt, B.state, 2, P.V, P.V, ws, d_keys, d_n, s);
+    if (rc) return rc;
+    launch_bridge_status(B.cnt, B.err, *d_n, s);
+    return BR_OK;
+}
+
+// |F|, |F'| and the error word into the status block that holds the key count
+void launch_bridge_status(const uint32_t* cnt, const uint32_t* err, uint32_t* d_n, hipStream_t s) {
+    hipLaunchKernelGGL(k_status, dim3(1), dim3(64), 0, s, cnt, err, d_n - 1);
 }
 
 }  // namespace br

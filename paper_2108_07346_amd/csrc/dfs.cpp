@@ -20,6 +20,8 @@
 
 namespace br {
 
+void walk(const int32_t* head, const int2* arc, int32_t V, DfsScratch& S, std::vector<uint64_t>& keys);
+
 void certificate_bridges(const int2* f1, int64_t n1, const int2* f2, int64_t n2, int32_t V, DfsScratch& S,
                          std::vector<uint64_t>& keys) {
     const int64_t m = n1 + n2;
@@ -42,19 +44,20 @@ void certificate_bridges(const int2* f1, int64_t n1, const int2* f2, int64_t n2,
         S.arc[S.fill[e.x]++] = make_int2(e.y, (int32_t)k);
         S.arc[S.fill[e.y]++] = make_int2(e.x, (int32_t)k);
     }
+    walk(S.head.data(), S.arc.data(), V, S, keys);
+}
+
+// The search proper over an adjacency grouped by source.  Roots are taken in
+// id order (vertices without arcs carry no bridge).
+void walk(const int32_t* head, const int2* arc, int32_t V, DfsScratch& S, std::vector<uint64_t>& keys) {
     S.dl.assign((size_t)V, make_int2(0, 0));    // disc 0 = not reached; times start at 1
     S.st_v.resize((size_t)V);
     S.st_pe.resize((size_t)V);
     S.st_it.resize((size_t)V);
-    const int2* arc = S.arc.data();
-    const int32_t* head = S.head.data();
     int2* dl = S.dl.data();
     int32_t clock = 0;
-    // roots: endpoints in certificate order (vertices without certificate
-    // edges are isolated in the certificate and carry no bridge)
-    for (int64_t k = 0; k < m; k++) {
-        const int32_t r = edge(k).x;
-        if (dl[r].x) continue;
+    for (int32_t r = 0; r < V; r++) {
+        if (dl[r].x || head[r + 1] == head[r]) continue;
         int32_t top = 0;
         S.st_v[0] = r;
         S.st_pe[0] = -1;

@@ -95,6 +95,9 @@ Plan make_plan(int64_t E, int32_t V, int32_t M);
 // the launch sequence over node 0's certificate; the bridges' keys land at
 // *d_keys (count at *d_n) on the device.
 int64_t device_bridges_words(int32_t V);
+// copies |F|, |F'| (cnt[0..1]) and *err into the 256-byte status block whose
+// word 1 is the key count d_n of a bridge step (the keys follow the block)
+void launch_bridge_status(const uint32_t* cnt, const uint32_t* err, uint32_t* d_n, hipStream_t s);
 int device_bridges(const Plan& P, const DevBufs& B, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s);
 int device_bridges_cert(const int2* f1, const int2* f2, int32_t dir, const uint32_t* cnt, const uint32_t* q, int32_t qs,
                         int32_t V, int32_t max_tree, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s);
@@ -108,6 +111,7 @@ struct DfsScratch {
 };
 void certificate_bridges(const int2* f1, int64_t n1, const int2* f2, int64_t n2, int32_t V, DfsScratch& S,
                          std::vector<uint64_t>& keys);
+
 void canonical_sort(std::vector<uint64_t>& keys);
 
 // ---- context ------------------------------------------------------------------
@@ -128,7 +132,8 @@ struct br_ctx {
     br::DfsScratch dfs;
     std::vector<uint64_t> keys;
     int profiling = 0;
-    int final_step = 0;            // 0: host search (Algorithm 1), 1: device bridge step
+    size_t keys_hint = 0;          // bridges found by the previous call (first copy size)
+    int final_step = 1;            // 0: host search (Algorithm 1), 1: device bridge step
     int32_t* bws = nullptr;        // device bridge-step scratch inside the workspace
     br_profile prof{};
     hipEvent_t ev[8] = {};

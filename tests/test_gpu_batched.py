@@ -103,13 +103,15 @@ def test_out_of_range_id_reported(ctx):
     assert np.array_equal(pairs, [[0, 1], [1, 2]])
 
 
-def test_batched_device_final_step(ctx):
-    # final step on the GPU: all certificates as one disjoint union, one bridge step
-    ctx.set_final_step(1)
+def test_batched_host_search(ctx):
+    # the other tests use the default final step (one bridge step on the GPU
+    # over all certificates as a disjoint union); this one runs Algorithm 1's
+    # search per graph on the host
+    ctx.set_final_step(0)
     try:
         b = graphgen.batched(0, n_graphs=192)
         for chunk in (4096, 65536):
-            say("batched device final step chunk=%d" % chunk)
+            say("batched host search chunk=%d" % chunk)
             check_all(ctx, b.edges, b.offsets, b.V, chunk)
         rng = np.random.default_rng(32)
         graphs = [(rng.integers(0, V, size=(int(rng.integers(0, 4 * V)), 2)).astype(np.int32), V)
@@ -119,10 +121,10 @@ def test_batched_device_final_step(ctx):
         big = graphgen.planted(6, k=3, vc=5000, p=0.05, n_pend=4)
         graphs.append((big.edges, big.V))
         e, off, Vs = pack(graphs)
-        say("batched device final step mixed")
+        say("batched host search mixed")
         check_all(ctx, e, off, Vs, 128)
         full = graphgen.batched(0, n_graphs=4096)
-        say("batched device final step full")
+        say("batched host search full")
         check_all(ctx, full.edges, full.offsets, full.V, 0)
     finally:
-        ctx.set_final_step(0)
+        ctx.set_final_step(1)

@@ -21,12 +21,16 @@ def say(*a):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def ctx():
+@pytest.fixture(scope="module", params=[1, 0], ids=["gpu_final_step", "host_search"])
+def ctx(request):
+    # every test runs with both final steps: the GPU bridge step (the
+    # library's default) and Algorithm 1's search on the host
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import paper_2108_07346_amd as br
     c = br.Context(0)
+    c.set_final_step(request.param)
+    say("final step %d" % request.param)
     yield c
     c.close()
 
@@ -163,33 +167,49 @@ def test_concurrency_stress_same_bridges(ctx, dense):
     say("distinct certificates over runs: %d" % len(hashes))
 
 
-def test_device_final_step_bit_exact(ctx, small, dense):
-    # the final step on the GPU (Euler-tour rooting + subtree low/high test)
+def test_deep_trees_paths_and_random(ctx, small, dense):
+    # long tours (list ranking), deep subtrees (range tables), random multigraphs
     g, want, d = dense
-    ctx.set_final_step(1)
-    try:
-        for M in (1, 16, 1024):
-            say("device final step dense M=%d" % M)
-            assert np.array_equal(ctx.find(d, g.V, M), want)
-        assert np.array_equal(ctx.find(dev(small.edges), small.V, 4), oracle.bridges(small.edges, small.V))
-        rng = np.random.default_rng(24)
-        for t in range(80):
-            V = int(rng.integers(1, 300))
-            e = rng.integers(0, V, size=(int(rng.integers(0, 5 * V)), 2)).astype(np.int32)
-            M = int(rng.choice([1, 2, 5, 33]))
-            say("device final step random t=%d V=%d E=%d M=%d" % (t, V, e.shape[0], M))
-            assert np.array_equal(ctx.find(dev(e), V, M), oracle.bridges(e, V)), (V, M)
-        Vt = 3000
-        par = np.array([rng.integers(max(0, i - 3), i) for i in range(1, Vt)])      # deep tree
-        tree = np.stack([par, np.arange(1, Vt)], 1).astype(np.int32)
-        assert np.array_equal(ctx.find(dev(tree), Vt, 3), oracle.bridges(tree, Vt))
-        path = np.stack([np.arange(Vt - 1), np.arange(1, Vt)], 1).astype(np.int32)
-        assert np.array_equal(ctx.find(dev(path[::-1].copy()), Vt, 1), oracle.bridges(path, Vt))
-        empty = torch.zeros((0, 2), dtype=torch.int32, device="cuda")
-        assert ctx.find(empty, 5, 1).shape[0] == 0
-        assert ctx.find(dev([[0, 0]]), 1, 1).shape[0] == 0
-    finally:
-        ctx.set_final_step(0)
+    for M in (1, 16, 1024):
+        say("dense M=%d" % M)
+        assert np.array_equal(ctx.find(d, g.V, M), want)
+    assert np.array_equal(ctx.find(dev(small.edges), small.V, 4), oracle.bridges(small.edges, small.V))
+    rng = np.random.default_rng(24)
+    for t in range(80):
+        V = int(rng.integers(1, 300))
+        e = rng.integers(0, V, size=(int(rng.integers(0, 5 * V)), 2)).astype(np.int32)
+        M = int(rng.choice([1, 2, 5, 33]))
+        say("random t=%d V=%d E=%d M=%d" % (t, V, e.shape[0], M))
+        assert np.array_equal(ctx.find(dev(e), V, M), oracle.bridges(e, V)), (V, M)
+    Vt = 3000
+    par = np.array([rng.integers(max(0, i - 3), i) for i in range(1, Vt)])      # deep tree
+    tree = np.stack([par, np.arange(1, Vt)], 1).astype(np.int32)
+    assert np.array_equal(ctx.find(dev(tree), Vt, 3), oracle.bridges(tree, Vt))
+    path = np.stack([np.arange(Vt - 1), np.arange(1, Vt)], 1).astype(np.int32)
+    assert np.array_equal(ctx.find(dev(path[::-1].copy()), Vt, 1), oracle.bridges(path, Vt))
+    empty = torch.zeros((0, 2), dtype=torch.int32, device="cuda")
+    assert ctx.find(empty, 5, 1).shape[0] == 0
+    assert ctx.find(dev([[0, 0]]), 1, 1).shape[0] == 0
+
+
+def test_two_million_vertex_path_and_cycle(ctx):
+    # a path of 2.2M vertices (one tour of 4.4M arcs, range tables of more than
+    # 32768 blocks), relabelled at random, with a few chords and a detached cycle
+    rng = np.random.default_rng(25)
+    V = 2_200_000
+    perm = rng.permutation(V).astype(np.int32)
+    path = np.stack([perm[:-1], perm[1:]], 1)
+    chords = np.stack([perm[[10, 500_000, 1_700_000]], perm[[20, 900_000, 1_700_003]]], 1)
+    ring = np.arange(V, V + 1000)
+    cyc = np.stack([ring, np.roll(ring, -1)], 1)
+    e = np.concatenate([path, chords, cyc]).astype(np.int32)
+    e = e[rng.permutation(e.shape[0])]
+    Vall = V + 1000
+    want = oracle.bridges(e, Vall)
+    assert want.shape[0] == (V - 1) - (10 + 400_000 + 3)
+    for M in (1, 8):
+        say("long path M=%d" % M)
+        assert np.array_equal(ctx.find(dev(e), Vall, M), want)
 
 
 def test_two_edge_connected_classes(ctx, small, dense):

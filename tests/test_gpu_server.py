@@ -61,10 +61,12 @@ def test_mix_equals_oracle_and_alone(br):
     ctx.close()
 
 
-def test_reordered_arrivals_threads_and_device_submission(br):
+@pytest.mark.parametrize("final_step", [1, 0], ids=["gpu_final_step", "host_search"])
+def test_reordered_arrivals_threads_and_device_submission(br, final_step):
     reqs = request_mix(24, seed=3)
     want = [oracle.bridges(e, V) for e, V in reqs]
     srv = br.Server(0, mem_budget=8 << 30, max_slots=4)
+    srv.set_final_step(final_step)
     res = [None] * len(reqs)
     dev = [torch.from_numpy(e).cuda() for e, _ in reqs]
     order = np.random.default_rng(5).permutation(len(reqs))
