@@ -102,15 +102,14 @@ struct BatchPlan {
     // certificate of their disjoint union (vertex ids shifted by vbase)
     std::vector<int64_t> vbase;      // [S+1]
     int64_t vtot = 0;
-    int32_t *n1x = nullptr, *n2x = nullptr, *scan_scr = nullptr, *bws = nullptr;
-    int2 *f1c = nullptr, *f2c = nullptr;
-    uint32_t* cnt2 = nullptr;
-    uint64_t* d_keys = nullptr;
-    uint32_t* d_nkeys = nullptr;
-    uint32_t* h_nkeys = nullptr;
-    uint64_t* h_keys = nullptr;
-    uint32_t* h_blk = nullptr;       // status block of the bridge step, followed by h_keys
-    size_t keys_hint = 0;            // bridges of the previous call (size of the first copy)
+    // final step on the device: per graph bridge keys (u << 16 | v, sorted) in
+    // one array; header word 0 = number of keys, words 16 + 2s, 17 + 2s = base
+    // and count of small graph s; the keys follow the header directly
+    uint32_t* d_sb = nullptr;
+    uint32_t* h_sb = nullptr;
+    int64_t sb_hdr = 0;              // header words (16 + 2S)
+    int64_t sb_keys = 0;             // room for keys: sum of (V_s - 1)
+    size_t keys_hint = 0;            // keys of the previous call (size of the first copy)
     // captured launches: the persistent kernel, then (final step on the device)
     // the combined certificate and its bridge step, with an event in between
     hipGraph_t graph = nullptr, graph2 = nullptr;
@@ -227,16 +226,11 @@ int build_plan(BatchPlan& P, const int64_t* eoff, const int32_t* V, int32_t G, i
     for (int32_t s = 0; s < S; s++) P.vbase[s + 1] = P.vbase[s] + V[P.small[s]];
     P.vtot = P.vbase[S];
     if (P.vtot >= (int64_t(1) << 30)) return fail(BR_EINVAL, "batched: %lld vertices in one batch", (long long)P.vtot);
-    const int64_t fcap = std::max<int64_t>(1, P.vtot - S);   // sum of (V_s - 1): room for every F and every F'
+    P.sb_hdr = 16 + 2 * (int64_t)S;
+    P.sb_keys = std::max<int64_t>(1, P.vtot - S);   // sum of (V_s - 1): every bridge of every graph
     const size_t o_vb = o; o = a256(o + 8 * (size_t)(S + 1));
     const size_t o_root = o; o = a256(o + 4 * (size_t)std::max<int64_t>(P.vtot, 1));
-    const size_t o_n1x = o; o = a256(o + 4 * (size_t)(S + 1));
-    const size_t o_n2x = o; o = a256(o + 4 * (size_t)(S + 1));
-    const size_t o_f1c = o; o = a256(o + 8 * (size_t)fcap);
-    const size_t o_f2c = o; o = a256(o + 8 * (size_t)fcap);
-    const size_t o_cnt2 = o; o = a256(o + 16);
-    const size_t o_sscr = o; o = a256(o + 4 * (size_t)scan_scratch_words(S + 1));
-    const size_t o_bws = o; o = a256(o + 4 * (size_t)device_bridges_words((int32_t)std::max<int64_t>(P.vtot, 2)));
+    const size_t o_sb = o; o = a256(o + 4 * (size_t)(P.sb_hdr + P.sb_keys));
     BR_HIP(hipMalloc(&P.dmem, o));
     char* d = static_cast<char*>(P.dmem);
     std::vector<int32_t> sV(S);
@@ -257,13 +251,7 @@ int build_plan(BatchPlan& P, const int64_t* eoff, const int32_t* V, int32_t G, i
         BR_HIP(hipMemcpy(d + o_items, P.items.data(), 8 * P.items.size(), hipMemcpyHostToDevice));
     }
     if (S) BR_HIP(hipMemcpy(d + o_vb, P.vbase.data(), 8 * (size_t)S, hipMemcpyHostToDevice));
-    P.n1x = reinterpret_cast<int32_t*>(d + o_n1x);
-    P.n2x = reinterpret_cast<int32_t*>(d + o_n2x);
-    P.f1c = reinterpret_cast<int2*>(d + o_f1c);
-    P.f2c = reinterpret_cast<int2*>(d + o_f2c);
-    P.cnt2 = reinterpret_cast<uint32_t*>(d + o_cnt2);
-    P.scan_scr = reinterpret_cast<int32_t*>(d + o_sscr);
-    P.bws = reinterpret_cast<int32_t*>(d + o_bws);
+    P.d_sb = reinterpret_cast<uint32_t*>(d + o_sb);
     uint32_t* clr = reinterpret_cast<uint32_t*>(d + o_clear);
     P.dev.eoff = reinterpret_cast<const int64_t*>(d + o_eoff);
     P.dev.V = reinterpret_cast<const int32_t*>(d + o_V);
@@ -282,17 +270,15 @@ int build_plan(BatchPlan& P, const int64_t* eoff, const int32_t* V, int32_t G, i
     P.dev.vbase = reinterpret_cast<const int64_t*>(d + o_vb);
     P.dev.rootw = reinterpret_cast<uint32_t*>(d + o_root);
     // pinned host staging
-    const size_t hbytes = a256(8 * (size_t)std::max<int64_t>(P.area0, 1)) + a256(8 * (size_t)std::max(S, 1)) + 512 +
-                          a256(8 * (size_t)std::max<int64_t>(P.vtot, 2)) + 256;
+    const size_t hbytes = a256(8 * (size_t)std::max<int64_t>(P.area0, 1)) + a256(8 * (size_t)std::max(S, 1)) + 256 +
+                          a256(4 * (size_t)(P.sb_hdr + P.sb_keys));
     BR_HIP(hipHostMalloc(&P.hmem, hbytes, hipHostMallocDefault));
     char* h = static_cast<char*>(P.hmem);
     P.h_area0 = reinterpret_cast<int2*>(h);
     P.h_cnt0 = reinterpret_cast<uint32_t*>(h + a256(8 * (size_t)std::max<int64_t>(P.area0, 1)));
     P.h_err = P.h_cnt0 + 2 * (size_t)std::max(S, 1);
-    P.h_nkeys = P.h_err + 4;
-    P.h_blk = reinterpret_cast<uint32_t*>(h + a256(8 * (size_t)std::max<int64_t>(P.area0, 1)) +
-                                          a256(8 * (size_t)std::max(S, 1)) + 256);
-    P.h_keys = reinterpret_cast<uint64_t*>(P.h_blk + 64);
+    P.h_sb = reinterpret_cast<uint32_t*>(h + a256(8 * (size_t)std::max<int64_t>(P.area0, 1)) +
+                                         a256(8 * (size_t)std::max(S, 1)) + 256);
     P.blocks = std::max(1, cus * batched_blocks_per_cu());
     return BR_OK;
 }
@@ -311,14 +297,8 @@ int enqueue(BatchPlan& P, const int32_t* d_edges, hipStream_t s, int mode, int p
     }
     if (mode == 1 && !P.small.empty()) {
         const int32_t S = (int32_t)P.small.size();
-        launch_combine(P.dev, S, P.n1x, P.n2x, P.f1c, P.f2c, P.cnt2, P.scan_scr, s);
-        BR_HIP(hipGetLastError());
-        int32_t maxv = 2;
-        for (int32_t g : P.small) maxv = std::max(maxv, P.V[g]);
-        int rc = device_bridges_cert(P.f1c, P.f2c, 1, P.cnt2, P.dev.rootw, 1, (int32_t)std::max<int64_t>(P.vtot, 2),
-                                     maxv, P.bws, &P.d_keys, &P.d_nkeys, s);
-        if (rc) return rc;
-        launch_bridge_status(P.cnt2, P.dev.err, P.d_nkeys, s);
+        launch_fill_u32(P.d_sb, 16, 0u, s);
+        launch_small_bridges(P.dev, S, P.d_sb, P.d_sb + P.sb_hdr, std::min(S, 4 * std::max(1, P.blocks)), s);
         BR_HIP(hipGetLastError());
     }
     return BR_OK;
@@ -330,12 +310,11 @@ int copy_back(BatchPlan& P, hipStream_t s, int mode) {
     const int32_t S = (int32_t)P.small.size();
     if (mode == 1) {
         if (S) {
-            // status block (counts, error word) and the first keys in one copy
-            const size_t guess = std::min<size_t>(std::max<size_t>(P.keys_hint, 1024), (size_t)std::max<int64_t>(P.vtot, 2));
-            BR_HIP(hipMemcpyAsync(P.h_blk, P.d_nkeys - 1, 256 + 8 * guess, hipMemcpyDeviceToHost, s));
-        } else {
-            BR_HIP(hipMemcpyAsync(P.h_err, P.dev.err, 4, hipMemcpyDeviceToHost, s));
+            // header, per-graph table and the first keys in one copy
+            const size_t guess = std::min<size_t>(std::max<size_t>(P.keys_hint, 4096), (size_t)P.sb_keys);
+            BR_HIP(hipMemcpyAsync(P.h_sb, P.d_sb, 4 * ((size_t)P.sb_hdr + guess), hipMemcpyDeviceToHost, s));
         }
+        BR_HIP(hipMemcpyAsync(P.h_err, P.dev.err, 4, hipMemcpyDeviceToHost, s));
         return BR_OK;
     }
     if (P.area0) BR_HIP(hipMemcpyAsync(P.h_area0, P.dev.cert, 8 * (size_t)P.area0, hipMemcpyDeviceToHost, s));
@@ -467,6 +446,7 @@ int br_bridges_find_batched(br_ctx* c, const int32_t* d_edges, const int64_t* h_
         BR_HIP(hipEventCreate(&st.k0));
         BR_HIP(hipEventCreate(&st.k1));
         BR_HIP(hipEventCreate(&st.k2));
+        if (prepare_small_bridges() != 0) return fail(BR_EHIP, "batched: cannot raise the LDS limit of the bridge kernel");
     }
     if (!st.pool) {
         int n = (int)std::thread::hardware_concurrency();
@@ -520,7 +500,6 @@ int br_bridges_find_batched(br_ctx* c, const int32_t* d_edges, const int64_t* h_
     if (c->profiling) BR_HIP(hipEventRecord(st.e1, st.stream));
     BR_HIP(hipStreamSynchronize(st.stream));
     auto t1 = std::chrono::steady_clock::now();
-    if (mode == 1 && !P->small.empty()) *P->h_err = P->h_blk[4];
     if (*P->h_err & 1u) return fail(BR_ERANGE, "batched: an edge has a vertex id outside its graph's [0, V)");
     if (*P->h_err) return fail(BR_EINTERNAL, "batched: certificate region overflow");
 
@@ -535,28 +514,27 @@ int br_bridges_find_batched(br_ctx* c, const int32_t* d_edges, const int64_t* h_
     }
     uint64_t* outk = st.outk.get();
     if (mode == 1) {
-        // bridges of the combined certificate, regrouped by graph (the first
-        // keys came with the status block; any beyond the guess follow now)
-        const size_t guess = std::min<size_t>(std::max<size_t>(P->keys_hint, 1024), (size_t)std::max<int64_t>(P->vtot, 2));
-        const uint32_t nk = S ? std::min<uint32_t>(P->h_blk[1], (uint32_t)std::max<int64_t>(P->vtot, 1)) : 0;
+        // per graph: base and count in the key array, keys already sorted
+        const size_t guess = std::min<size_t>(std::max<size_t>(P->keys_hint, 4096), (size_t)P->sb_keys);
+        const uint32_t* hdr = P->h_sb;
+        const uint32_t* keys = P->h_sb + P->sb_hdr;
+        const uint32_t nk = S ? hdr[0] : 0;
+        if (nk > (uint32_t)P->sb_keys) return fail(BR_EINTERNAL, "batched: %u bridge keys for room %lld", nk, (long long)P->sb_keys);
         if (nk > guess) {
-            BR_HIP(hipMemcpyAsync(P->h_keys + guess, P->d_keys + guess, 8 * (size_t)(nk - guess), hipMemcpyDeviceToHost,
-                                  st.stream));
+            BR_HIP(hipMemcpyAsync(P->h_sb + P->sb_hdr + guess, P->d_sb + P->sb_hdr + guess, 4 * (size_t)(nk - guess),
+                                  hipMemcpyDeviceToHost, st.stream));
             BR_HIP(hipStreamSynchronize(st.stream));
         }
         P->keys_hint = nk;
-        std::vector<int64_t> fillp(slot.begin(), slot.end() - 1);
-        for (uint32_t i = 0; i < nk; i++) {
-            const int64_t a = (int64_t)(P->h_keys[i] >> 32), b = (int64_t)(P->h_keys[i] & 0xffffffffu);
-            const int32_t s = (int32_t)(std::upper_bound(P->vbase.begin(), P->vbase.end(), a) - P->vbase.begin()) - 1;
-            if (s < 0 || s >= S || b >= P->vbase[s + 1] || fillp[s] >= slot[s + 1])
-                return fail(BR_EINTERNAL, "batched: bridge (%lld, %lld) outside its graph", (long long)a, (long long)b);
-            const uint64_t vb = (uint64_t)P->vbase[s];
-            outk[fillp[s]++] = ((uint64_t)(a - vb) << 32) | (uint64_t)(b - vb);
-        }
         for (int32_t s = 0; s < S; s++) {
-            std::sort(outk + slot[s], outk + fillp[s]);
-            nb[P->small[s]] = fillp[s] - slot[s];
+            const uint32_t base = hdr[16 + 2 * s], cnt = hdr[17 + 2 * s];
+            if ((uint64_t)base + cnt > nk || (int64_t)cnt > slot[s + 1] - slot[s])
+                return fail(BR_EINTERNAL, "batched: graph %d reports %u bridges at %u", (int)P->small[s], cnt, base);
+            for (uint32_t i = 0; i < cnt; i++) {
+                const uint32_t k = keys[base + i];
+                outk[slot[s] + i] = ((uint64_t)(k >> 16) << 32) | (uint64_t)(k & 0xffffu);
+            }
+            nb[P->small[s]] = cnt;
         }
     } else {
         std::atomic<int32_t> next{0};

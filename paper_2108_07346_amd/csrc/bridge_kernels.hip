@@ -31,47 +31,7 @@ __device__ __forceinline__ int32_t arc_dst(const int2* f1, int32_t a) { const in
 
 #define GRID_LOOP(i, n) for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
-// ---- exclusive scan (int32), reduce-then-scan in blocks of kT*4 -------------
-constexpr int kSB = kT * 4;
-
-__device__ __forceinline__ int32_t block_exclusive(int32_t v, int32_t* sh, int32_t& total) {
-    // inclusive scan of one value per thread across the block
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int32_t x = v;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int32_t y = __shfl_up(x, o);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) sh[w] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int32_t s = 0;
-        for (int i = 0; i < kT / 64; i++) { const int32_t t = sh[i]; sh[i] = s; s += t; }
-        sh[kT / 64] = s;
-    }
-    __syncthreads();
-    total = sh[kT / 64];
-    const int32_t r = x - v + sh[w];
-    __syncthreads();
-    return r;
-}
-
-__global__ void k_scan_block(int32_t* a, int64_t n, int32_t* sums) {
-    __shared__ int32_t sh[kT / 64 + 1];
-    const int64_t base = blockIdx.x * (int64_t)kSB + threadIdx.x * 4;
-    int32_t v[4], s = 0;
-    for (int j = 0; j < 4; j++) { v[j] = base + j < n ? a[base + j] : 0; s += v[j]; }
-    int32_t total;
-    int32_t ex = block_exclusive(s, sh, total);
-    for (int j = 0; j < 4; j++) { if (base + j < n) a[base + j] = ex; ex += v[j]; }
-    if (threadIdx.x == 0 && sums) sums[blockIdx.x] = total;
-}
-
-__global__ void k_scan_add(int32_t* a, int64_t n, const int32_t* sums) {
-    const int32_t add = sums[blockIdx.x];
-    const int64_t base = blockIdx.x * (int64_t)kSB + threadIdx.x * 4;
-    for (int j = 0; j < 4; j++) if (base + j < n) a[base + j] += add;
-}
+constexpr int kSB = kT * 4;   // elements per block of the one-pass scans
 
 // ---- one-pass exclusive scans (decoupled look-back) ----------------------------
 //
@@ -489,31 +449,6 @@ int grid_for(int64_t n) {
 }
 
 }  // namespace
-
-// scratch words needed by device_scan for n elements
-int64_t scan_scratch_words(int64_t n);
-static int64_t scan_scratch(int64_t n) { return scan_scratch_words(n); }
-int64_t scan_scratch_words(int64_t n) {
-    int64_t s = 0;
-    while (n > kSB) {
-        n = (n + kSB - 1) / kSB;
-        s += n + 64;
-    }
-    return s + 64;
-}
-
-void device_scan(int32_t* a, int64_t n, int32_t* scratch, hipStream_t s) {
-    if (n <= 0) return;
-    const int64_t blocks = (n + kSB - 1) / kSB;
-    if (blocks == 1) {
-        hipLaunchKernelGGL(k_scan_block, dim3(1), dim3(kT), 0, s, a, n, (int32_t*)nullptr);
-        return;
-    }
-    int32_t* sums = scratch;
-    hipLaunchKernelGGL(k_scan_block, dim3((unsigned)blocks), dim3(kT), 0, s, a, n, sums);
-    device_scan(sums, blocks, scratch + blocks + 64, s);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)blocks), dim3(kT), 0, s, a, n, (const int32_t*)sums);
-}
 
 // Scratch layout of the bridge step, shared by the size query and the launch
 // sequence so that the two cannot disagree.  Everything from `head` up to the

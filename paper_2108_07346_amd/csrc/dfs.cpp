@@ -110,4 +110,5 @@ void walk(const int32_t* head, const int2* arc, int32_t V, DfsScratch& S, std::v
 
 void canonical_sort(std::vector<uint64_t>& keys) { std::sort(keys.begin(), keys.end()); }
 
+
 }  // namespace br

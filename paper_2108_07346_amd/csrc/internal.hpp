@@ -74,12 +74,13 @@ struct BatchDev {
     uint32_t* rootw;          // [sum V] 0 at each root of F of the graph's final certificate, else 1
 };
 void launch_batched(const BatchDev& B, int blocks, hipStream_t s);
-// Gather the node-0 certificates of all graphs into one certificate of their
-// disjoint union (vertex ids offset by vbase); counts of F and F' at cnt2[0..1].
-void launch_combine(const BatchDev& B, int32_t S, int32_t* n1x, int32_t* n2x, int2* f1c, int2* f2c, uint32_t* cnt2,
-                    int32_t* scan_scratch, hipStream_t s);
-void device_scan(int32_t* a, int64_t n, int32_t* scratch, hipStream_t s);
-int64_t scan_scratch_words(int64_t n);
+// Final step on the device for the batched path: one workgroup per small graph
+// finds the bridges of node 0's certificate in LDS; keys (u << 16 | v, sorted)
+// go to out_keys at a base taken from out_hdr[0]; out_hdr[16 + 2s] / [17 + 2s]
+// receive graph s's base and count.  out_hdr[0] must be zero at launch.
+void launch_small_bridges(const BatchDev& B, int32_t S, uint32_t* out_hdr, uint32_t* out_keys, int blocks, hipStream_t s);
+// Allows the kernel above its LDS size (once per process, before any launch or capture).
+int prepare_small_bridges();
 int32_t batched_max_v_dev();
 int32_t batched_blocks_per_cu();
 
