@@ -447,6 +447,7 @@ int br_bridges_find_batched(br_ctx* c, const int32_t* d_edges, const int64_t* h_
         BR_HIP(hipEventCreate(&st.k1));
         BR_HIP(hipEventCreate(&st.k2));
         if (prepare_small_bridges() != 0) return fail(BR_EHIP, "batched: cannot raise the LDS limit of the bridge kernel");
+        if (small_bridges_max_v() < batched_max_v_dev()) return fail(BR_EINTERNAL, "batched: bridge kernel limit below the LDS path's");
     }
     if (!st.pool) {
         int n = (int)std::thread::hardware_concurrency();

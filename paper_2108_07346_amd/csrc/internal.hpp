@@ -81,6 +81,7 @@ void launch_batched(const BatchDev& B, int blocks, hipStream_t s);
 void launch_small_bridges(const BatchDev& B, int32_t S, uint32_t* out_hdr, uint32_t* out_keys, int blocks, hipStream_t s);
 // Allows the kernel above its LDS size (once per process, before any launch or capture).
 int prepare_small_bridges();
+int32_t small_bridges_max_v();   // largest V the kernel above takes
 int32_t batched_max_v_dev();
 int32_t batched_blocks_per_cu();
 
