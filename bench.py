@@ -225,6 +225,55 @@ def bench_figures(args):
     ctx.close()
 
 
+def bench_articulation(args):
+    """Articulation points of the dense workload: the scan-first certificate on
+    the GPU, then the low-link search on the host; the oracle (the low-link
+    search on the whole graph) timed beside it."""
+    import numpy as np
+    import torch
+    import graphgen
+    import paper_2108_07346_amd as br
+    g = graphgen.config("dense")
+    d = torch.from_numpy(g.edges).cuda()
+    ctx = br.Context(0)
+    stream = torch.cuda.current_stream()
+    for _ in range(max(args.warmup, 1)):
+        out = ctx.articulation_points(d, g.V, stream)
+    acc = {"ms_cert": 0.0, "ms_dfs": 0.0}
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        out = ctx.articulation_points(d, g.V, stream)
+        p = ctx.profile()
+        for k in acc:
+            acc[k] += p[k] / args.steps
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        reps, tc = 0, time.perf_counter()
+        while True:
+            want = oracle.articulation_points(g.edges, g.V)
+            reps += 1
+            if time.perf_counter() - tc >= min(args.cpu_budget, 10.0):
+                break
+        dtc = time.perf_counter() - tc
+        assert np.array_equal(want, out)
+        cpu = {"value": g.E * reps / dtc, "unit": "edges/s", "cores": 1, "kind": "oracle",
+               "sample": "whole dense workload, %d repetition(s) in %.1f s, one host core" % (reps, dtc)}
+    line = {"metric": "articulation points: edges/s (scan-first certificate on the GPU + host low-link search)",
+            "value": g.E * args.steps / dt, "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": 1000 * dt / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "int32", "data": "synthetic (seeded planted-cluster generator)",
+            "config": {"workload": "dense", "V": g.V, "E": g.E, "parallelism": "single GPU"},
+            "roofline": None, "cpu_baseline": cpu,
+            "detail": {"phases_ms": {k: round(v, 4) for k, v in acc.items()}, "articulation_points": int(out.shape[0]),
+                       "certificate_edges": int(p["cert_f1"] + p["cert_f2"]), "bfs_levels": int(p["rounds"])}}
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def bench_served(args):
     """Served workload: open-loop Poisson arrivals at fixed QPS; latency from
     each request's scheduled arrival to the moment its answer is back on the
@@ -308,7 +357,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="dense", choices=["small", "dense", "large", "batched", "served", "figures"])
+    ap.add_argument("--workload", default="dense", choices=["small", "dense", "large", "batched", "served", "figures", "articulation"])
     ap.add_argument("--qps", default="100,200,500,1000,2000,5000", help="served: comma-separated QPS")
     ap.add_argument("--seconds", type=float, default=2.0, help="served: seconds per QPS point")
     ap.add_argument("--max-requests", type=int, default=600, help="served: cap per QPS point")
@@ -350,6 +399,8 @@ def main():
         return bench_served(args)
     if args.workload == "figures":
         return bench_figures(args)
+    if args.workload == "articulation":
+        return bench_articulation(args)
     M = args.M or {"small": 4, "dense": 16, "large": 4096}[args.workload]
     t0 = time.perf_counter()
     g = graphgen.config(args.workload)

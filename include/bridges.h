@@ -190,6 +190,28 @@ int br_set_final_step(br_ctx* ctx, int mode);
 int br_get_profile(br_ctx* ctx, br_profile* out);
 
 /*
+ * br_articulation_points -- the "failure points" of the abstract: vertices
+ * whose removal (with their edges) increases the number of connected
+ * components (Section I's bridge definition carried over to vertices).
+ * Path: a scan-first certificate of the whole edge list on the GPU -- F a
+ * breadth-first forest of G (each tree from the smallest vertex of its
+ * component; a newly reached vertex takes its smallest-id neighbour one level
+ * up as parent), F' a breadth-first forest of G without the vertex pairs of F
+ * (all parallel copies of them left out) -- then the low-link search on the
+ * host over F u F' (at most 2(V-1) edges): a non-root p is a cut vertex iff a
+ * child c has low[c] >= disc[p], a root iff it has two or more children.  The
+ * union-find forests of Algorithm 2 (Section IV-B) would not do: they keep
+ * edge connectivity but not vertex connectivity; search-ordered forests keep
+ * both (the certificate definition of Section III, for 2-vertex connectivity).
+ *   d_edges  device int32 [E][2], E <= 2^31 - 1; self-loops and parallel edges accepted.
+ *   h_out    host int32 [cap]: vertex ids ascending; cap >= V always suffices.
+ *   *n_out   number of articulation points; BR_ECAP (no ids written) if it exceeds cap.
+ * Synchronous with respect to `stream`.  BR_ERANGE if an id is out of range.
+ */
+int br_articulation_points(br_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t V, int32_t* h_out, int64_t cap,
+                           int64_t* n_out, void* stream);
+
+/*
  * Serving: continuous batching of bridge queries on one device.
  *   br_server_create  device, device-memory budget in bytes for resident
  *                     requests (edge lists, union-find state, certificates),

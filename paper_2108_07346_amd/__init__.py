@@ -19,7 +19,7 @@ SO_PATH = os.path.join(_DIR, "libbridges.so")
 BR_OK, BR_EINVAL, BR_ERANGE, BR_ENOMEM, BR_EHIP, BR_EBUSY, BR_ECAP, BR_EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
 
 EXPORTS = ["br_last_error", "br_create", "br_destroy", "br_cert_build", "br_cert_merge", "br_bridges_find",
-           "br_certificate_bridges", "br_two_edge_components",
+           "br_certificate_bridges", "br_two_edge_components", "br_articulation_points",
            "br_bridges_find_batched", "br_batched_max_v", "br_set_profiling", "br_set_final_step", "br_get_profile",
            "br_server_create", "br_submit", "br_submit_device", "br_poll", "br_wait", "br_server_stats",
            "br_server_set_final_step", "br_server_destroy"]
@@ -64,6 +64,7 @@ def load():
     lib.br_cert_merge.argtypes = [vp, vp, i64, vp, i64, i32, vp, i64, vp, vp]
     lib.br_bridges_find.argtypes = [vp, vp, i64, i32, i32, vp, i64, p64, vp]
     lib.br_two_edge_components.argtypes = [vp, vp, i64, i32, i32, vp, p64, vp]
+    lib.br_articulation_points.argtypes = [vp, vp, i64, i32, vp, i64, p64, vp]
     lib.br_certificate_bridges.argtypes = [vp, i64, vp, i64, i32, vp, i64, p64]
     lib.br_bridges_find_batched.argtypes = [vp, vp, vp, vp, i32, i32, vp, i64, vp, vp]
     lib.br_batched_max_v.restype = i32
@@ -155,6 +156,15 @@ class Context:
         _check(self._lib.br_two_edge_components(self._h, ptr, E, int(V), int(M), lab.ctypes.data, ctypes.byref(n),
                                                 _stream(stream)))
         return lab[:int(V)].copy(), n.value
+
+    def articulation_points(self, edges, V: int, stream=None) -> np.ndarray:
+        """Articulation points (int32 vertex ids ascending) through the scan-first certificate."""
+        ptr, E = _edges_arg(edges)
+        out = np.empty(max(int(V), 1), dtype=np.int32)
+        n = ctypes.c_int64(0)
+        _check(self._lib.br_articulation_points(self._h, ptr, E, int(V), out.ctypes.data, out.shape[0], ctypes.byref(n),
+                                                _stream(stream)))
+        return out[:n.value].copy()
 
     def _cert_result(self, out, counts):
         import torch

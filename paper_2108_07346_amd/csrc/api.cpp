@@ -452,6 +452,51 @@ int br_two_edge_components(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t
     return BR_OK;
 }
 
+int br_articulation_points(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int32_t* h_out, int64_t cap,
+                           int64_t* n_out, void* stream) {
+    if (!c || !n_out || (!h_out && cap > 0)) return fail(BR_EINVAL, "br_articulation_points: null argument");
+    int rc = check_common(d_edges, E, V);
+    if (rc) return rc;
+    if (cap < 0) return fail(BR_EINVAL, "cap < 0");
+    if (E > 2147483647LL) return fail(BR_EINVAL, "br_articulation_points: E = %lld above 2^31 - 1", (long long)E);
+    if (V > (1 << 29)) return fail(BR_EINVAL, "V = %d above the host search limit 2^29", V);
+    auto t0 = std::chrono::steady_clock::now();
+    BR_HIP(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    BR_HIP(hipEventSynchronize(c->ev[7]));
+    rc = ensure_workspace(c, 4 * (size_t)scan_first_words(E, V), s);
+    if (rc) return rc;
+    rc = ensure_pinned(c, 256 + 2 * sizeof(int2) * (size_t)std::max(V, 1));
+    if (rc) return rc;
+    char* h = static_cast<char*>(c->pinned);
+    uint32_t* hs = reinterpret_cast<uint32_t*>(h);
+    int2* hf1 = reinterpret_cast<int2*>(h + 256);
+    int2* hf2 = hf1 + std::max(V, 1);
+    uint32_t n1 = 0, n2 = 0;
+    int l1 = 0, l2 = 0;
+    ev_record(c, 0, s);
+    rc = scan_first_certificate(reinterpret_cast<const int2*>(d_edges), E, V, static_cast<char*>(c->ws.base), s, hs, hf1,
+                                hf2, &n1, &n2, &l1, &l2);
+    if (rc) return rc;
+    ev_record(c, 3, s);
+    auto t1 = std::chrono::steady_clock::now();
+    std::vector<int32_t> aps;
+    certificate_articulation(hf1, n1, hf2, n2, V, c->dfs, aps);
+    auto t2 = std::chrono::steady_clock::now();
+    *n_out = (int64_t)aps.size();
+    c->prof.cert_f1 = n1;
+    c->prof.cert_f2 = n2;
+    c->prof.rounds = l1 + l2;          // breadth-first levels of the two forests
+    c->prof.ms_cert = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    c->prof.ms_dfs = std::chrono::duration<double, std::milli>(t2 - t1).count();
+    c->prof.ms_total = c->prof.ms_cert + c->prof.ms_dfs;
+    if ((int64_t)aps.size() > cap)
+        return fail(BR_ECAP, "br_articulation_points: %lld articulation points, capacity %lld", (long long)aps.size(),
+                    (long long)cap);
+    std::copy(aps.begin(), aps.end(), h_out);
+    return BR_OK;
+}
+
 int br_certificate_bridges(const int32_t* h_f1, int64_t n1, const int32_t* h_f2, int64_t n2, int32_t V,
                            int32_t* h_bridges, int64_t cap, int64_t* n_bridges) {
     if (!n_bridges || n1 < 0 || n2 < 0 || (n1 > 0 && !h_f1) || (n2 > 0 && !h_f2) || cap < 0 || (cap > 0 && !h_bridges))

@@ -507,6 +507,11 @@ static BridgeWs carve(int32_t* base, int32_t V) {
 
 int64_t device_bridges_words(int32_t V) { return carve(nullptr, V).words; }
 
+void device_scan1(int32_t* a, int64_t n, uint64_t* status, uint32_t* ticket, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_scan1, dim3((unsigned)cdiv(n, kSB)), dim3(kT), 0, s, a, n, status, ticket);
+}
+
 // Bridges of a certificate held on the device: F = f1[0..cnt[0]), F' =
 // f2[dir*k] for k < cnt[1] (counts read on the device), vertex v is the root of
 // its tree of F iff q[qs*v] == 0.  Writes up to V keys at *d_keys and their

@@ -112,3 +112,77 @@ void canonical_sort(std::vector<uint64_t>& keys) { std::sort(keys.begin(), keys.
 
 
 }  // namespace br
+
+namespace br {
+
+// Articulation points of the certificate (V, F u F'): the same low-link
+// search, with the vertex test -- a non-root p separates iff some child c has
+// low[c] >= disc[p], a root iff it has two or more children.  Parallel copies
+// and the arriving edge need no special case here (a back edge into p only
+// lowers low[c] to disc[p]).
+void certificate_articulation(const int2* f1, int64_t n1, const int2* f2, int64_t n2, int32_t V, DfsScratch& S,
+                              std::vector<int32_t>& out) {
+    const int64_t m = n1 + n2;
+    auto edge = [&](int64_t k) -> const int2& { return k < n1 ? f1[k] : f2[k - n1]; };
+    S.head.assign((size_t)V + 1, 0);
+    for (int64_t k = 0; k < m; k++) {
+        const int2 e = edge(k);
+        if (e.x == e.y) continue;
+        S.head[e.x + 1]++;
+        S.head[e.y + 1]++;
+    }
+    for (int32_t v = 0; v < V; v++) S.head[v + 1] += S.head[v];
+    S.arc.resize((size_t)std::max<int32_t>(S.head[V], 1));
+    S.fill.assign(S.head.begin(), S.head.end() - 1);
+    for (int64_t k = 0; k < m; k++) {
+        const int2 e = edge(k);
+        if (e.x == e.y) continue;
+        S.arc[S.fill[e.x]++] = make_int2(e.y, (int32_t)k);
+        S.arc[S.fill[e.y]++] = make_int2(e.x, (int32_t)k);
+    }
+    S.dl.assign((size_t)V, make_int2(0, 0));    // (disc, low); disc 0 = not reached
+    S.st_v.resize((size_t)V);
+    S.st_it.resize((size_t)V);
+    std::vector<uint8_t> cut((size_t)V, 0);
+    int2* dl = S.dl.data();
+    const int32_t* head = S.head.data();
+    const int2* arc = S.arc.data();
+    int32_t clock = 0;
+    for (int32_t r = 0; r < V; r++) {
+        if (dl[r].x || head[r + 1] == head[r]) continue;
+        int32_t sp = 0, children = 0;
+        S.st_v[0] = r;
+        S.st_it[0] = head[r];
+        ++clock;
+        dl[r] = make_int2(clock, clock);
+        while (sp >= 0) {
+            const int32_t x = S.st_v[sp];
+            if (S.st_it[sp] < head[x + 1]) {
+                const int32_t y = arc[S.st_it[sp]++].x;
+                if (!dl[y].x) {
+                    ++clock;
+                    dl[y] = make_int2(clock, clock);
+                    if (sp == 0) children++;
+                    ++sp;
+                    S.st_v[sp] = y;
+                    S.st_it[sp] = head[y];
+                } else if (dl[y].x < dl[x].y) {
+                    dl[x].y = dl[y].x;
+                }
+            } else {
+                --sp;
+                if (sp >= 0) {
+                    const int32_t p = S.st_v[sp];
+                    if (dl[x].y < dl[p].y) dl[p].y = dl[x].y;
+                    if (sp > 0 && dl[x].y >= dl[p].x) cut[p] = 1;
+                }
+            }
+        }
+        if (children >= 2) cut[r] = 1;
+    }
+    out.clear();
+    for (int32_t v = 0; v < V; v++)
+        if (cut[v]) out.push_back(v);
+}
+
+}  // namespace br

@@ -97,6 +97,15 @@ Plan make_plan(int64_t E, int32_t V, int32_t M);
 // the launch sequence over node 0's certificate; the bridges' keys land at
 // *d_keys (count at *d_n) on the device.
 int64_t device_bridges_words(int32_t V);
+// In-place exclusive scan of a[0..n) in one launch; status[ceil(n / 1024)] and
+// *ticket must be zero at launch.
+void device_scan1(int32_t* a, int64_t n, uint64_t* status, uint32_t* ticket, hipStream_t s);
+// Scan-first certificate (two breadth-first forests, the second avoiding the
+// first's vertex pairs) of an edge list on the device; workspace in 4-byte
+// words, and the call that fills h_f1 / h_f2 (V pairs each) and the counts.
+int64_t scan_first_words(int64_t E, int32_t V);
+int scan_first_certificate(const int2* edges, int64_t E, int32_t V, char* ws, hipStream_t s, uint32_t* h_small,
+                           int2* h_f1, int2* h_f2, uint32_t* n1, uint32_t* n2, int* levels1, int* levels2);
 // copies |F|, |F'| (cnt[0..1]) and *err into the 256-byte status block whose
 // word 1 is the key count d_n of a bridge step (the keys follow the block)
 void launch_bridge_status(const uint32_t* cnt, const uint32_t* err, uint32_t* d_n, hipStream_t s);
@@ -115,6 +124,10 @@ void certificate_bridges(const int2* f1, int64_t n1, const int2* f2, int64_t n2,
                          std::vector<uint64_t>& keys);
 
 void canonical_sort(std::vector<uint64_t>& keys);
+// Articulation points of the graph (V, F u F') by a low-link depth-first
+// search on the host: vertex ids ascending in out.
+void certificate_articulation(const int2* f1, int64_t n1, const int2* f2, int64_t n2, int32_t V, DfsScratch& S,
+                              std::vector<int32_t>& out);
 
 // ---- context ------------------------------------------------------------------
 struct Arena {
