@@ -12,11 +12,14 @@
 // in id order), which is the rule applied here; each tree starts at the
 // smallest vertex of its component.
 //
-// Pieces: a union-find pass for the components (roots are the smallest ids,
-// as in cert_kernels.hip), an adjacency array of the edge list, and per BFS
-// level an expand kernel (one wavefront per frontier vertex, candidate parents
-// by 64-bit atomic min of (parent, edge id)) and a settle kernel (new levels,
-// the next frontier, the chosen tree edges).
+// Pieces: a union-find pass for the components (in stages with full path
+// compression between them, as in phase 0; roots are the smallest ids), an
+// adjacency array of the edge list, and one launch per breadth-first level.
+// A vertex's candidate word holds (level of the parent) << 32 | parent, so an
+// atomic minimum keeps the shallowest, then smallest-id parent; the wavefront
+// that handles a vertex of level d emits its tree edge (its candidate is final:
+// only level d - 1 could set it) and offers (d << 32 | itself) to its
+// neighbours, and the first touch of a neighbour appends it to level d + 1.
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"
@@ -55,23 +58,62 @@ __device__ __forceinline__ uint32_t cc_find(uint32_t* q, uint32_t x) {
     return x;
 }
 
-__global__ void k_cc(const int2* edges, int64_t E, int32_t V, const int32_t* par1, uint32_t* q, uint32_t* err) {
-    GRID_LOOP(i, E) {
-        const int2 e = edges[i];
-        if ((uint32_t)e.x >= (uint32_t)V || (uint32_t)e.y >= (uint32_t)V) { atomicOr(err, 1u); continue; }
-        if (e.x == e.y || excluded(par1, e.x, e.y)) continue;
-        uint32_t u = (uint32_t)e.x, v = (uint32_t)e.y;
-        for (;;) {
-            u = cc_find(q, u);
-            v = cc_find(q, v);
-            if (u == v) break;
-            if (u < v) { const uint32_t t = u; u = v; v = t; }
-            uint32_t expect = 0;
-            if (__hip_atomic_compare_exchange_strong(q + u, &expect, u - v, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT))
-                break;
-            u = u - expect;
+__device__ __forceinline__ void cc_unite(uint32_t* q, uint32_t u, uint32_t v) {
+    for (;;) {
+        u = cc_find(q, u);
+        v = cc_find(q, v);
+        if (u == v) return;
+        if (u < v) { const uint32_t t = u; u = v; v = t; }
+        uint32_t expect = 0;
+        if (__hip_atomic_compare_exchange_strong(q + u, &expect, u - v, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            return;
+        u = u - expect;
+    }
+}
+
+// edges [lo, hi), kCcU per thread with their loads issued together; an edge
+// whose endpoints already have the same parent is done after two loads (after
+// a full compression that parent is the root)
+constexpr int kCcU = 4;
+
+__global__ void k_cc(const int2* edges, int64_t lo, int64_t hi, int32_t V, const int32_t* par1, uint32_t* q,
+                     uint32_t* err) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i0 < hi; i0 += kCcU * stride) {
+        int2 e[kCcU];
+        bool ok[kCcU];
+#pragma unroll
+        for (int j = 0; j < kCcU; j++) {
+            const int64_t i = i0 + j * stride;
+            e[j] = i < hi ? edges[i] : make_int2(0, 0);
+            ok[j] = i < hi;
+            if (ok[j] && ((uint32_t)e[j].x >= (uint32_t)V || (uint32_t)e[j].y >= (uint32_t)V)) {
+                atomicOr(err, 1u);
+                ok[j] = false;
+            }
+            if (ok[j] && (e[j].x == e[j].y || excluded(par1, e[j].x, e[j].y))) ok[j] = false;
         }
+        uint32_t pu[kCcU], pv[kCcU];
+#pragma unroll
+        for (int j = 0; j < kCcU; j++) {
+            pu[j] = ok[j] ? (uint32_t)e[j].x - __hip_atomic_load(q + e[j].x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) : 0u;
+            pv[j] = ok[j] ? (uint32_t)e[j].y - __hip_atomic_load(q + e[j].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kCcU; j++)
+            if (ok[j] && pu[j] != pv[j]) cc_unite(q, pu[j], pv[j]);
+    }
+}
+
+// every vertex straight under its root (no hook runs concurrently)
+__global__ void k_cc_compress(uint32_t* q, int32_t V) {
+    GRID_LOOP(x, (int64_t)V) {
+        const uint32_t d = q[x];
+        if (d == 0) continue;
+        uint32_t r = (uint32_t)x - d;
+        for (uint32_t e = q[r]; e != 0; e = q[r]) r -= e;
+        if (r != (uint32_t)x - d) q[x] = (uint32_t)x - r;
     }
 }
 
@@ -95,76 +137,76 @@ __global__ void k_adj_fill(const int2* edges, int64_t E, int32_t V, const int32_
 }
 
 // search start: the root of every component is level 0 and the first frontier
-__global__ void k_bfs_start(const uint32_t* q, int32_t V, int32_t* level, int32_t* par, uint64_t* cand,
-                            int32_t* frontier, uint32_t* fcount) {
+__global__ void k_bfs_start(const uint32_t* q, int32_t V, int32_t* par, uint64_t* cand, int32_t* frontier,
+                            uint32_t* fcount) {
     GRID_LOOP(v, (int64_t)V) {
         const bool root = q[v] == 0;
-        level[v] = root ? 0 : -1;
         par[v] = -1;
-        cand[v] = kNoCand;
+        cand[v] = root ? 0 : kNoCand;
         if (root) frontier[atomicAdd(fcount, 1u)] = (int32_t)v;
     }
 }
 
-// one wavefront per frontier vertex u: every unreached neighbour w gets u as a
-// candidate parent (smallest (u, edge id) wins)
-__global__ void k_bfs_expand(const int32_t* frontier, const uint32_t* fcount, const int32_t* head, const int2* adj,
-                             const int32_t* level, const int32_t* par1, uint64_t* cand) {
-    const uint32_t n = *fcount;
+// level d: one wavefront per vertex w of the level -- its tree edge (parent
+// from the candidate word) goes to slot base_d + (w's place in the level),
+// base_d being the number of tree edges of the earlier levels (kept in
+// base[d & 1]; block 0 writes base[(d + 1) & 1]); then its offers to the
+// neighbours, newly reached ones appended with one reservation per wavefront
+__global__ void k_bfs_level(const int32_t* level_list, const uint32_t* count, uint32_t* count_after_next, int32_t d,
+                            uint32_t* base, const int32_t* head, const int2* adj, const int32_t* par1, uint64_t* cand,
+                            int32_t* par, int32_t* next_list, uint32_t* next_count, int2* out, int64_t cap,
+                            uint32_t* err) {
+    const uint32_t n = *count;
+    const uint32_t b0 = base[d & 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *count_after_next = 0;                       // the count level d + 2 will use
+        base[(d + 1) & 1] = b0 + (d > 0 ? n : 0u);
+    }
     const int lane = threadIdx.x & 63;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t f = wave; f < n; f += waves) {
-        const int32_t u = frontier[f];
-        for (int32_t k = head[u] + lane; k < head[u + 1]; k += 64) {
-            const int2 a = adj[k];
-            const int32_t w = a.x;
-            if (level[w] != -1 || excluded(par1, u, w)) continue;
-            const uint64_t key = ((uint64_t)(uint32_t)u << 32) | (uint32_t)a.y;
-            if (key < cand[w]) atomicMin(reinterpret_cast<unsigned long long*>(cand + w), (unsigned long long)key);
+        const int32_t w = level_list[f];
+        if (d > 0 && lane == 0) {
+            const int32_t p = (int32_t)(cand[w] & 0xffffffffu);
+            par[w] = p;
+            const int64_t pos = (int64_t)b0 + f;
+            if (pos < cap) out[pos] = make_int2(p, w);
+            else atomicOr(err, 2u);
         }
-    }
-}
-
-// vertices reached in this level: level, parent, next frontier, tree edge out
-__global__ void k_bfs_settle(int32_t V, int32_t d, const int2* edges, int32_t* level, int32_t* par, uint64_t* cand,
-                             int32_t* next, uint32_t* ncount, int2* out, uint32_t* nout, int64_t cap, uint32_t* err) {
-    GRID_LOOP(v, (int64_t)V) {
-        bool got = false;
-        int2 e = make_int2(0, 0);
-        if (level[v] == -1) {
-            const uint64_t c = cand[v];
-            if (c != kNoCand) {
-                got = true;
-                level[v] = d + 1;
-                par[v] = (int32_t)(c >> 32);
-                e = edges[c & 0xffffffffu];
-                next[atomicAdd(ncount, 1u)] = (int32_t)v;
+        const uint64_t mine = ((uint64_t)(uint32_t)d << 32) | (uint32_t)w;
+        const int32_t h0 = head[w], h1 = head[w + 1];
+        for (int32_t kb = h0; kb < h1; kb += 64) {
+            const int32_t k = kb + lane;
+            bool got = false;
+            int32_t x = 0;
+            if (k < h1) {
+                x = adj[k].x;
+                if (!excluded(par1, w, x) && cand[x] > mine)
+                    got = atomicMin(reinterpret_cast<unsigned long long*>(cand + x), (unsigned long long)mine) ==
+                          (unsigned long long)kNoCand;
             }
-        }
-        const uint64_t m = __ballot(got);
-        if (m) {
-            const int leader = __ffsll((unsigned long long)m) - 1;
-            uint32_t base = 0;
-            if (__lane_id() == leader) base = atomicAdd(nout, (uint32_t)__popcll(m));
-            base = __shfl(base, leader);
-            if (got) {
-                const uint32_t pos = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                if (pos < cap) out[pos] = e;
-                else atomicOr(err, 2u);
+            const uint64_t m = __ballot(got);
+            if (m) {
+                const int leader = __ffsll((unsigned long long)m) - 1;
+                uint32_t at = 0;
+                if (lane == leader) at = atomicAdd(next_count, (uint32_t)__popcll(m));
+                at = __shfl(at, leader);
+                if (got) next_list[at + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = x;
             }
         }
     }
 }
 
 __global__ void k_zero_u32(uint32_t* p, int64_t n) { GRID_LOOP(i, n) p[i] = 0; }
+__global__ void k_copy_u32(const uint32_t* a, uint32_t* b) { if (threadIdx.x == 0) *b = *a; }
 
 }  // namespace
 
 // Workspace words (4-byte) for the scan-first certificate of E edges on V vertices.
 struct ApWs {
     uint32_t *q, *fcount, *err, *nout;
-    int32_t *head, *cur, *level, *par1, *par2, *fa, *fb;
+    int32_t *head, *cur, *par1, *par2, *fa, *fb;
     uint64_t *cand, *scan_status;
     int2 *adj, *f1, *f2;
     int64_t zero_words, words;
@@ -183,7 +225,6 @@ static ApWs ap_carve(char* base, int64_t E, int32_t V) {
     w.scan_status = reinterpret_cast<uint64_t*>(take(8 * (((int64_t)V + 1 + 1023) / 1024)));
     w.zero_words = o / 4;
     w.nout = w.err + 1;
-    w.level = reinterpret_cast<int32_t*>(take(4 * (int64_t)V));
     w.par1 = reinterpret_cast<int32_t*>(take(4 * (int64_t)V));
     w.par2 = reinterpret_cast<int32_t*>(take(4 * (int64_t)V));
     w.fa = reinterpret_cast<int32_t*>(take(4 * (int64_t)V));
@@ -199,33 +240,48 @@ static ApWs ap_carve(char* base, int64_t E, int32_t V) {
 int64_t scan_first_words(int64_t E, int32_t V) { return ap_carve(nullptr, E, V).words; }
 
 // One breadth-first forest: levels are run in groups; a group ends early on
-// the device (an empty frontier makes every later launch return at once), and
-// the host only checks the frontier count between groups.
-static int bfs_forest(const ApWs& W, const int2* edges, int32_t V, const int32_t* par1, int32_t* par, int2* out,
-                      uint32_t* nout, hipStream_t s, uint32_t* h_count, int* levels) {
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kT), 0, s, W.fcount, (int64_t)128);
-    hipLaunchKernelGGL(k_bfs_start, dim3(grid_for(V)), dim3(kT), 0, s, W.q, V, W.level, par, W.cand, W.fa, W.fcount);
-    int32_t *cur_f = W.fa, *nxt_f = W.fb;
+// the device (an empty level makes every later launch return at once), and
+// the host only checks the level size between groups.
+static int bfs_forest(const ApWs& W, int32_t V, const int32_t* par1, int32_t* par, int2* out, uint32_t* nout,
+                      hipStream_t s, uint32_t* h_count, int* levels) {
+    // fcount[0..127]: level sizes (ring), fcount[128..129]: tree edges before the level (ping-pong)
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kT), 0, s, W.fcount, (int64_t)130);
+    hipLaunchKernelGGL(k_bfs_start, dim3(grid_for(V)), dim3(kT), 0, s, W.q, V, par, W.cand, W.fa, W.fcount);
+    int32_t *cur_l = W.fa, *nxt_l = W.fb;
     int d = 0;
     constexpr int kGroup = 16;
     for (;;) {
         for (int k = 0; k < kGroup && d < V; k++, d++) {
-            uint32_t* fc = W.fcount + (d % 128);
-            uint32_t* nc = W.fcount + ((d + 1) % 128);
-            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, nc, (int64_t)1);
-            hipLaunchKernelGGL(k_bfs_expand, dim3(2048), dim3(kT), 0, s, (const int32_t*)cur_f, (const uint32_t*)fc,
-                               (const int32_t*)W.head, (const int2*)W.adj, (const int32_t*)W.level, par1, W.cand);
-            hipLaunchKernelGGL(k_bfs_settle, dim3(grid_for(V)), dim3(kT), 0, s, V, d, edges, W.level, par, W.cand, nxt_f,
-                               nc, out, nout, (int64_t)V, W.err);
-            std::swap(cur_f, nxt_f);
+            hipLaunchKernelGGL(k_bfs_level, dim3(2048), dim3(kT), 0, s, (const int32_t*)cur_l,
+                               (const uint32_t*)(W.fcount + d % 128), W.fcount + (d + 2) % 128, d, W.fcount + 128,
+                               (const int32_t*)W.head, (const int2*)W.adj, par1, W.cand, par, nxt_l,
+                               W.fcount + (d + 1) % 128, out, (int64_t)V, W.err);
+            std::swap(cur_l, nxt_l);
         }
         BR_HIP(hipGetLastError());
-        BR_HIP(hipMemcpyAsync(h_count, W.fcount + (d % 128), 4, hipMemcpyDeviceToHost, s));
+        BR_HIP(hipMemcpyAsync(h_count, W.fcount + d % 128, 4, hipMemcpyDeviceToHost, s));
         BR_HIP(hipStreamSynchronize(s));
         if (*h_count == 0 || d >= V) break;
     }
+    // tree edges emitted = base after the last level that had vertices
+    hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(64), 0, s, W.fcount + 128 + (d & 1), nout);
     *levels = d;
     return BR_OK;
+}
+
+// components of the edges (minus the pairs of par1 when given): union-find in
+// stages with full compression between them; afterwards q[v] == 0 exactly at
+// the smallest vertex of each component
+static void components(const ApWs& W, const int2* edges, int64_t E, int32_t V, const int32_t* par1, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(V)), dim3(kT), 0, s, W.q, (int64_t)V);
+    const int64_t cuts[4] = {0, std::min<int64_t>(E, 2 * (int64_t)V), std::min<int64_t>(E, 8 * (int64_t)V), E};
+    for (int k = 0; k < 3; k++) {
+        if (cuts[k + 1] <= cuts[k]) continue;
+        if (k > 0) hipLaunchKernelGGL(k_cc_compress, dim3(grid_for(V)), dim3(kT), 0, s, W.q, V);
+        hipLaunchKernelGGL(k_cc, dim3(grid_for((cuts[k + 1] - cuts[k] + kCcU - 1) / kCcU)), dim3(kT), 0, s, edges, cuts[k],
+                           cuts[k + 1], V, par1, W.q, W.err);
+    }
+    hipLaunchKernelGGL(k_cc_compress, dim3(grid_for(V)), dim3(kT), 0, s, W.q, V);
 }
 
 // The scan-first certificate (F, F') of d_edges on the device; on return the
@@ -236,18 +292,17 @@ int scan_first_certificate(const int2* edges, int64_t E, int32_t V, char* ws, hi
     hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(W.zero_words)), dim3(kT), 0, s, reinterpret_cast<uint32_t*>(ws),
                        W.zero_words);
     // components and adjacency
-    hipLaunchKernelGGL(k_cc, dim3(grid_for(E)), dim3(kT), 0, s, edges, E, V, (const int32_t*)nullptr, W.q, W.err);
+    components(W, edges, E, V, nullptr, s);
     hipLaunchKernelGGL(k_adj_degree, dim3(grid_for(E)), dim3(kT), 0, s, edges, E, V, W.head);
     device_scan1(W.head, (int64_t)V + 1, W.scan_status, W.fcount + 255, s);
     hipLaunchKernelGGL(k_adj_fill, dim3(grid_for(E)), dim3(kT), 0, s, edges, E, V, (const int32_t*)W.head, W.cur, W.adj);
     BR_HIP(hipGetLastError());
     // F: breadth-first forest of G
-    int rc = bfs_forest(W, edges, V, nullptr, W.par1, W.f1, W.nout, s, h_small, levels1);
+    int rc = bfs_forest(W, V, nullptr, W.par1, W.f1, W.nout, s, h_small, levels1);
     if (rc) return rc;
     // F': breadth-first forest of G without F's vertex pairs (own components)
-    hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(V)), dim3(kT), 0, s, W.q, (int64_t)V);
-    hipLaunchKernelGGL(k_cc, dim3(grid_for(E)), dim3(kT), 0, s, edges, E, V, (const int32_t*)W.par1, W.q, W.err);
-    rc = bfs_forest(W, edges, V, W.par1, W.par2, W.f2, W.nout + 1, s, h_small, levels2);
+    components(W, edges, E, V, W.par1, s);
+    rc = bfs_forest(W, V, W.par1, W.par2, W.f2, W.nout + 1, s, h_small, levels2);
     if (rc) return rc;
     BR_HIP(hipMemcpyAsync(h_small, W.err, 16, hipMemcpyDeviceToHost, s));
     BR_HIP(hipStreamSynchronize(s));

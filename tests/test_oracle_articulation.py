@@ -214,3 +214,29 @@ def test_pins_reject_mutant(name):
             e = rng.integers(0, V, size=(int(rng.integers(0, 3 * V + 1)), 2)).astype(np.int32)
             caught = not np.array_equal(run(e, V), oracle.brute_articulation_points(e, V))
         assert caught, "mutant %s survived the pins" % name
+
+
+def test_scan_first_certificates_through_the_phase_tree():
+    # the merge rule of Section III (certificate of the union of two
+    # certificates, pairwise in ceil(log2 M) rounds) with scan-first
+    # certificates keeps the articulation points for any split
+    rng = np.random.default_rng(57)
+
+    def cert(e, V):
+        f1, f2 = oracle.scan_first_certificate(e, V)
+        return np.concatenate([f1, f2]).astype(np.int32).reshape(-1, 2)
+
+    for t in range(200):
+        V = int(rng.integers(2, 30))
+        e = rng.integers(0, V, size=(int(rng.integers(0, 5 * V)), 2)).astype(np.int32)
+        M = int(rng.integers(1, 9))
+        E = e.shape[0]
+        X = [cert(e[(i * E) // M:((i + 1) * E) // M], V) for i in range(M)]
+        step = 1
+        while step < M:
+            for i in range(0, M, 2 * step):
+                if i + step < M:
+                    X[i] = cert(np.concatenate([X[i], X[i + step]]), V)
+            step *= 2
+        assert X[0].shape[0] <= 2 * (V - 1)
+        assert np.array_equal(oracle.articulation_points(X[0], V), oracle.articulation_points(e, V)), (V, M, e.tolist())
