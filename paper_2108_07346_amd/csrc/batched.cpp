@@ -28,56 +28,7 @@ namespace br {
 namespace {
 
 // simple fixed pool of host threads for the final search
-class Pool {
-  public:
-    explicit Pool(int n) {
-        for (int i = 0; i < n; i++) th_.emplace_back([this, i] { loop(i); });
-    }
-    ~Pool() {
-        {
-            std::lock_guard<std::mutex> g(mu_);
-            stop_ = true;
-        }
-        cv_.notify_all();
-        for (auto& t : th_) t.join();
-    }
-    int size() const { return (int)th_.size(); }
-    // run fn(worker) on every worker and wait
-    void run(const std::function<void(int)>& fn) {
-        std::unique_lock<std::mutex> g(mu_);
-        fn_ = &fn;
-        pending_ = (int)th_.size();
-        gen_++;
-        cv_.notify_all();
-        done_.wait(g, [this] { return pending_ == 0; });
-        fn_ = nullptr;
-    }
 
-  private:
-    void loop(int i) {
-        uint64_t seen = 0;
-        for (;;) {
-            const std::function<void(int)>* f;
-            {
-                std::unique_lock<std::mutex> g(mu_);
-                cv_.wait(g, [&] { return stop_ || gen_ != seen; });
-                if (stop_) return;
-                seen = gen_;
-                f = fn_;
-            }
-            (*f)(i);
-            std::lock_guard<std::mutex> g(mu_);
-            if (--pending_ == 0) done_.notify_one();
-        }
-    }
-    std::vector<std::thread> th_;
-    std::mutex mu_;
-    std::condition_variable cv_, done_;
-    const std::function<void(int)>* fn_ = nullptr;
-    int pending_ = 0;
-    uint64_t gen_ = 0;
-    bool stop_ = false;
-};
 
 struct BatchPlan {
     // key

@@ -3,8 +3,12 @@
 
 #include <hip/hip_runtime.h>
 
+#include <condition_variable>
 #include <cstdint>
+#include <functional>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/bridges.h"
@@ -19,6 +23,58 @@ int hip_fail(hipError_t e, const char* what);      // BR_EHIP (or BR_ENOMEM) wit
         hipError_t e_ = (call);                           \
         if (e_ != hipSuccess) return br::hip_fail(e_, #call); \
     } while (0)
+
+// ---- host worker pool: run(fn) calls fn(i) on every worker i and waits ----------
+class Pool {
+  public:
+    explicit Pool(int n) {
+        for (int i = 0; i < n; i++) th_.emplace_back([this, i] { loop(i); });
+    }
+    ~Pool() {
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto& t : th_) t.join();
+    }
+    int size() const { return (int)th_.size(); }
+    // run fn(worker) on every worker and wait
+    void run(const std::function<void(int)>& fn) {
+        std::unique_lock<std::mutex> g(mu_);
+        fn_ = &fn;
+        pending_ = (int)th_.size();
+        gen_++;
+        cv_.notify_all();
+        done_.wait(g, [this] { return pending_ == 0; });
+        fn_ = nullptr;
+    }
+
+  private:
+    void loop(int i) {
+        uint64_t seen = 0;
+        for (;;) {
+            const std::function<void(int)>* f;
+            {
+                std::unique_lock<std::mutex> g(mu_);
+                cv_.wait(g, [&] { return stop_ || gen_ != seen; });
+                if (stop_) return;
+                seen = gen_;
+                f = fn_;
+            }
+            (*f)(i);
+            std::lock_guard<std::mutex> g(mu_);
+            if (--pending_ == 0) done_.notify_one();
+        }
+    }
+    std::vector<std::thread> th_;
+    std::mutex mu_;
+    std::condition_variable cv_, done_;
+    const std::function<void(int)>* fn_ = nullptr;
+    int pending_ = 0;
+    uint64_t gen_ = 0;
+    bool stop_ = false;
+};
 
 // ---- device geometry shared with the kernels ---------------------------------
 // Chunk i of the phase tree is edges [lo(i), lo(i+1)) with lo(i) = floor(iE/M).

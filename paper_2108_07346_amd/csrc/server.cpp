@@ -27,7 +27,9 @@ using Clock = std::chrono::steady_clock;
 
 struct Request {
     uint64_t ticket = 0;
-    std::vector<int32_t> h_edges;      // owned copy (host submissions)
+    void* pin = nullptr;               // owned copy in pinned staging memory (host submissions) ...
+    size_t pin_cap = 0;
+    std::vector<int32_t> h_edges;      // ... or in pageable memory when the pinned pool is full
     const int32_t* d_edges = nullptr;  // caller's device buffer (device submissions)
     int64_t E = 0;
     int32_t V = 0;
@@ -73,6 +75,11 @@ struct br_server {
     int64_t inflight = 0, peak_inflight = 0;
     br::Clock::time_point busy_start;
     double busy_ms = 0;
+    // pinned staging for host submissions: free buffers, bytes held, cap
+    std::vector<std::pair<void*, size_t>> pin_free;
+    int64_t pin_total = 0, pin_limit = 0;
+    std::unique_ptr<br::Pool> copier;    // parallel copy of submitted edge lists
+    std::mutex copy_mu;
 };
 
 namespace br {
@@ -84,6 +91,53 @@ int64_t charge(int64_t E, int32_t V, int32_t M, bool host_edges) {
     int64_t b = 8 * (int64_t)V * M + 8 * P.cert_pairs + 64 * (int64_t)M + (1 << 20);
     if (host_edges) b += 8 * E;
     return b;
+}
+
+// a pinned buffer of at least `bytes` (best fit among the free ones, else a new
+// one while the pool stays under its cap); {nullptr, 0} when none
+std::pair<void*, size_t> acquire_pinned(br_server* S, size_t bytes) {
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        size_t best = SIZE_MAX;
+        int at = -1;
+        for (size_t i = 0; i < S->pin_free.size(); i++)
+            if (S->pin_free[i].second >= bytes && S->pin_free[i].second < best) {
+                best = S->pin_free[i].second;
+                at = (int)i;
+            }
+        if (at >= 0) {
+            auto b = S->pin_free[at];
+            S->pin_free.erase(S->pin_free.begin() + at);
+            return b;
+        }
+        size_t cap = (size_t)1 << 20;
+        while (cap < bytes) cap <<= 1;
+        if (S->pin_total + (int64_t)cap > S->pin_limit) return {nullptr, 0};
+        S->pin_total += (int64_t)cap;
+        bytes = cap;
+    }
+    void* p = nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocPortable) != hipSuccess) {
+        (void)hipGetLastError();
+        std::lock_guard<std::mutex> g(S->mu);
+        S->pin_total -= (int64_t)bytes;
+        return {nullptr, 0};
+    }
+    return {p, bytes};
+}
+
+// copy with every worker of the server's copy pool (one copy at a time)
+void parallel_copy(br_server* S, void* dst, const void* src, size_t bytes) {
+    if (bytes < ((size_t)4 << 20)) {
+        std::memcpy(dst, src, bytes);
+        return;
+    }
+    std::lock_guard<std::mutex> g(S->copy_mu);
+    const int n = S->copier->size();
+    S->copier->run([&](int w) {
+        const size_t lo = bytes * (size_t)w / n, hi = bytes * (size_t)(w + 1) / n;
+        std::memcpy(static_cast<char*>(dst) + lo, static_cast<const char*>(src) + lo, hi - lo);
+    });
 }
 
 // chunk count per request: keep chunks several times larger than V (so phase 0
@@ -109,9 +163,10 @@ void run_request(br_server* S, Slot& sl, Request& r) {
             }
             sl.d_cap = bytes;
         }
-        // one asynchronous upload from the request's own copy (the runtime
-        // pipelines pageable transfers through its staging buffers)
-        if (hipMemcpyAsync(sl.d_buf, r.h_edges.data(), bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess) {
+        // one asynchronous upload from the request's own copy (a DMA from the
+        // pinned staging buffer; pageable copies go through the runtime's staging)
+        const void* src = r.pin ? r.pin : static_cast<const void*>(r.h_edges.data());
+        if (hipMemcpyAsync(sl.d_buf, src, bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess) {
             (void)hipGetLastError();
             r.status = BR_EHIP;
             r.msg = "server: upload failed";
@@ -147,6 +202,10 @@ void slot_loop(br_server* S, Slot* sl) {
             r->done = true;
             r->h_edges.clear();
             r->h_edges.shrink_to_fit();
+            if (r->pin) {                      // the stream was synchronised by the bridge search
+                S->pin_free.emplace_back(r->pin, r->pin_cap);
+                r->pin = nullptr;
+            }
             S->in_use -= r->bytes;
             S->inflight--;
             if (S->inflight == 0) S->busy_ms += std::chrono::duration<double, std::milli>(Clock::now() - S->busy_start).count();
@@ -238,6 +297,8 @@ int br_server_create(br_server** out, int device, int64_t mem_budget, int32_t ma
     auto S = std::make_unique<br_server>();
     S->device = device;
     S->budget = mem_budget;
+    S->pin_limit = std::min<int64_t>(mem_budget / 4, (int64_t)8 << 30);
+    S->copier = std::make_unique<Pool>(8);
     for (int32_t i = 0; i < max_slots; i++) {
         auto sl = std::make_unique<Slot>();
         int rc = br_create(&sl->ctx, device);
@@ -273,8 +334,22 @@ int br_submit(br_server* S, const int32_t* h_edges, int64_t E, int32_t V, uint64
     auto r = std::make_shared<Request>();
     r->E = E;
     r->V = V;
-    r->h_edges.assign(h_edges, h_edges + 2 * E);
-    return submit_common(S, std::move(r), ticket, true);
+    const size_t bytes = 8 * (size_t)E;
+    auto pb = E > 0 ? acquire_pinned(S, bytes) : std::pair<void*, size_t>{nullptr, 0};
+    if (pb.first) {
+        parallel_copy(S, pb.first, h_edges, bytes);
+        r->pin = pb.first;
+        r->pin_cap = pb.second;
+    } else {
+        r->h_edges.assign(h_edges, h_edges + 2 * E);
+    }
+    const int rc = submit_common(S, r, ticket, true);
+    if (rc != BR_OK && r->pin) {                // not queued: the buffer goes back to the pool
+        std::lock_guard<std::mutex> g(S->mu);
+        S->pin_free.emplace_back(r->pin, r->pin_cap);
+        r->pin = nullptr;
+    }
+    return rc;
 }
 
 int br_submit_device(br_server* S, const int32_t* d_edges, int64_t E, int32_t V, uint64_t* ticket) {
@@ -350,6 +425,7 @@ int br_server_destroy(br_server* S) {
         if (sl->d_buf) (void)hipFree(sl->d_buf);
         br_destroy(sl->ctx);
     }
+    for (auto& b : S->pin_free) (void)hipHostFree(b.first);
     delete S;
     return BR_OK;
 }
