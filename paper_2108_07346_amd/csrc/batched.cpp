@@ -58,6 +58,9 @@ struct BatchPlan {
     // and count of small graph s; the keys follow the header directly
     uint32_t* d_sb = nullptr;
     uint32_t* h_sb = nullptr;
+    int32_t* d_lists = nullptr;      // small graphs by size class: [na] then [nb]
+    int32_t na = 0, nb = 0;
+    int cus = 1;
     int64_t sb_hdr = 0;              // header words (16 + 2S)
     int64_t sb_keys = 0;             // room for keys: sum of (V_s - 1)
     size_t keys_hint = 0;            // keys of the previous call (size of the first copy)
@@ -182,6 +185,7 @@ int build_plan(BatchPlan& P, const int64_t* eoff, const int32_t* V, int32_t G, i
     const size_t o_vb = o; o = a256(o + 8 * (size_t)(S + 1));
     const size_t o_root = o; o = a256(o + 4 * (size_t)std::max<int64_t>(P.vtot, 1));
     const size_t o_sb = o; o = a256(o + 4 * (size_t)(P.sb_hdr + P.sb_keys));
+    const size_t o_lists = o; o = a256(o + 4 * (size_t)std::max(S, 1));
     BR_HIP(hipMalloc(&P.dmem, o));
     char* d = static_cast<char*>(P.dmem);
     std::vector<int32_t> sV(S);
@@ -203,6 +207,16 @@ int build_plan(BatchPlan& P, const int64_t* eoff, const int32_t* V, int32_t G, i
     }
     if (S) BR_HIP(hipMemcpy(d + o_vb, P.vbase.data(), 8 * (size_t)S, hipMemcpyHostToDevice));
     P.d_sb = reinterpret_cast<uint32_t*>(d + o_sb);
+    P.d_lists = reinterpret_cast<int32_t*>(d + o_lists);
+    {
+        std::vector<int32_t> la, lb;
+        for (int32_t s = 0; s < S; s++) (V[P.small[s]] <= small_bridges_split_v() ? la : lb).push_back(s);
+        P.na = (int32_t)la.size();
+        P.nb = (int32_t)lb.size();
+        la.insert(la.end(), lb.begin(), lb.end());
+        if (S) BR_HIP(hipMemcpy(P.d_lists, la.data(), 4 * (size_t)S, hipMemcpyHostToDevice));
+    }
+    P.cus = std::max(1, cus);
     uint32_t* clr = reinterpret_cast<uint32_t*>(d + o_clear);
     P.dev.eoff = reinterpret_cast<const int64_t*>(d + o_eoff);
     P.dev.V = reinterpret_cast<const int32_t*>(d + o_V);
@@ -247,9 +261,8 @@ int enqueue(BatchPlan& P, const int32_t* d_edges, hipStream_t s, int mode, int p
         return BR_OK;
     }
     if (mode == 1 && !P.small.empty()) {
-        const int32_t S = (int32_t)P.small.size();
         launch_fill_u32(P.d_sb, 16, 0u, s);
-        launch_small_bridges(P.dev, S, P.d_sb, P.d_sb + P.sb_hdr, std::min(S, 4 * std::max(1, P.blocks)), s);
+        launch_small_bridges(P.dev, P.d_lists, P.na, P.d_lists + P.na, P.nb, P.d_sb, P.d_sb + P.sb_hdr, P.cus, s);
         BR_HIP(hipGetLastError());
     }
     return BR_OK;

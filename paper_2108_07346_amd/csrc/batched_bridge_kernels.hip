@@ -13,7 +13,8 @@ namespace br {
 
 namespace {
 
-constexpr int kMaxV = 4096;                   // vertices per small graph (the batched kernel's LDS limit)
+constexpr int kLimitV = 4096;                 // vertices per small graph (the batched kernel's LDS limit)
+constexpr int kSplitV = 1024;                 // graphs up to this size run in smaller workgroups, several per CU
 
 // ---- bridge step of one small graph, entirely in LDS --------------------------
 //
@@ -25,13 +26,14 @@ constexpr int kMaxV = 4096;                   // vertices per small graph (the b
 // itself, and a tree edge (parent(c), c) kept as a bridge iff the subtree of c
 // reaches nothing outside its own preorder interval (the low-link test of
 // Algorithm 1 applied to an arbitrary rooted spanning tree).  One workgroup
-// per graph; buffers are reused from phase to phase.
-constexpr int kST = 1024;                     // threads of the small-graph bridge step
-constexpr int kMaxA = 2 * (kMaxV - 1);        // arcs of a spanning forest of kMaxV vertices
+// per graph; buffers are reused from phase to phase.  Two instances: graphs of
+// up to kSplitV vertices in 256-thread workgroups with ~39 KB of LDS (several
+// per CU), larger ones in 1024-thread workgroups with ~155 KB.
 constexpr uint32_t kEnd = 0xffffu;
-constexpr int kPerT = (kMaxA + kST - 1) / kST;   // arcs per thread
 
+template <int kMaxV, int kST>
 struct SmallLds {
+    static constexpr int kMaxA = 2 * (kMaxV - 1);   // arcs of a spanning forest of kMaxV vertices
     uint32_t e1[kMaxV];           // F edges, u | v << 16
     uint32_t head[kMaxV + 4];     // degrees, then adjacency starts
     uint32_t cur[kMaxV];          // fill cursors; tour base | tree base << 16 per root; then the keys
@@ -47,6 +49,7 @@ struct SmallLds {
 };
 
 // exclusive scan of one value per thread over the workgroup; total to *tot
+template <int kST>
 __device__ __forceinline__ uint32_t wg_exclusive(uint32_t v, uint32_t* wsum, uint32_t* tot) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t x = v;
@@ -68,11 +71,12 @@ __device__ __forceinline__ uint32_t wg_exclusive(uint32_t v, uint32_t* wsum, uin
 }
 
 // in-place exclusive scan of n <= 8 * kST 16-bit values
+template <int kST>
 __device__ void scan_u16(uint16_t* a, int n, uint32_t* wsum, uint32_t* tot) {
     const int b = threadIdx.x * 8;
     uint32_t v[8], s = 0;
     for (int j = 0; j < 8; j++) { v[j] = b + j < n ? a[b + j] : 0u; s += v[j]; }
-    uint32_t ex = wg_exclusive(s, wsum, tot);
+    uint32_t ex = wg_exclusive<kST>(s, wsum, tot);
     for (int j = 0; j < 8; j++) { if (b + j < n) a[b + j] = (uint16_t)ex; ex += v[j]; }
     __syncthreads();
 }
@@ -86,11 +90,17 @@ __device__ __forceinline__ uint32_t e_dst(const uint32_t* e1, uint32_t a) {
     return (a & 1) ? (e & 0xffffu) : (e >> 16);
 }
 
-__global__ void __launch_bounds__(kST) k_small_bridges(const BatchDev B, int32_t S, uint32_t* out_hdr, uint32_t* out_keys) {
+template <int kMaxV, int kST>
+__global__ void __launch_bounds__(kST) k_small_bridges(const BatchDev B, const int32_t* list, int32_t nlist,
+                                                       uint32_t* out_hdr, uint32_t* out_keys) {
+    static_assert(4 * kST >= kMaxV && 8 * kST >= 2 * kMaxV, "per-thread scan widths must cover the arrays");
+    constexpr int kMaxA = 2 * (kMaxV - 1);
+    constexpr int kPerT = (kMaxA + kST - 1) / kST;   // arcs per thread
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    SmallLds& L = *reinterpret_cast<SmallLds*>(lds_raw);
+    SmallLds<kMaxV, kST>& L = *reinterpret_cast<SmallLds<kMaxV, kST>*>(lds_raw);
     const int tid = threadIdx.x;
-    for (int64_t g = blockIdx.x; g < S; g += gridDim.x) {
+    for (int64_t it = blockIdx.x; it < nlist; it += gridDim.x) {
+        const int64_t g = list[it];
         const uint32_t V = (uint32_t)B.V[g];
         const int64_t off = B.noff[g], cap = B.ncap[g], vb = B.vbase[g];
         const uint32_t c1 = min((int64_t)B.ncnt[2 * g], cap);
@@ -126,7 +136,7 @@ __global__ void __launch_bounds__(kST) k_small_bridges(const BatchDev B, int32_t
             const int b = tid * 8;
             uint32_t v[8], sm = 0;
             for (int j = 0; j < 8; j++) { v[j] = b + j <= (int)V ? L.head[b + j] : 0u; sm += v[j]; }
-            uint32_t ex = wg_exclusive(sm, L.wsum, &L.total);
+            uint32_t ex = wg_exclusive<kST>(sm, L.wsum, &L.total);
             for (int j = 0; j < 8; j++) { if (b + j <= (int)V) L.head[b + j] = ex; ex += v[j]; }
             __syncthreads();
         }
@@ -185,7 +195,7 @@ __global__ void __launch_bounds__(kST) k_small_bridges(const BatchDev B, int32_t
                 v[j] = Lr | ((Lr ? Lr / 2 + 1 : 0u) << 16);
                 sm += v[j];
             }
-            uint32_t ex = wg_exclusive(sm, L.wsum, &L.total);
+            uint32_t ex = wg_exclusive<kST>(sm, L.wsum, &L.total);
             for (int j = 0; j < 4; j++) {
                 const uint32_t r = b + j;
                 if (r < V) { L.cur[r] = ex; L.posof[r] = (uint16_t)(v[j] & 0xffffu); }
@@ -225,7 +235,7 @@ __global__ void __launch_bounds__(kST) k_small_bridges(const BatchDev B, int32_t
             }
             __syncthreads();
         }
-        scan_u16(L.adj, (int)A + 1, L.wsum, &L.total);
+        scan_u16<kST>(L.adj, (int)A + 1, L.wsum, &L.total);
         // ---- preorder numbers; lo = hi = own number
         uint32_t* lo = L.link;
         uint32_t* hi = L.link + kMaxV;
@@ -325,16 +335,25 @@ __global__ void __launch_bounds__(kST) k_small_bridges(const BatchDev B, int32_t
 
 }  // namespace
 
-int32_t small_bridges_max_v() { return kMaxV; }
+int32_t small_bridges_max_v() { return kLimitV; }
+int32_t small_bridges_split_v() { return kSplitV; }
 
-void launch_small_bridges(const BatchDev& B, int32_t S, uint32_t* out_hdr, uint32_t* out_keys, int blocks,
-                          hipStream_t s) {
-    hipLaunchKernelGGL(k_small_bridges, dim3(blocks), dim3(kST), sizeof(SmallLds), s, B, S, out_hdr, out_keys);
+void launch_small_bridges(const BatchDev& B, const int32_t* list_a, int32_t na, const int32_t* list_b, int32_t nb,
+                          uint32_t* out_hdr, uint32_t* out_keys, int cus, hipStream_t s) {
+    if (na > 0)
+        hipLaunchKernelGGL((k_small_bridges<kSplitV, 256>), dim3((unsigned)std::min(na, 16 * cus)), dim3(256),
+                           sizeof(SmallLds<kSplitV, 256>), s, B, list_a, na, out_hdr, out_keys);
+    if (nb > 0)
+        hipLaunchKernelGGL((k_small_bridges<kLimitV, 1024>), dim3((unsigned)std::min(nb, 4 * cus)), dim3(1024),
+                           sizeof(SmallLds<kLimitV, 1024>), s, B, list_b, nb, out_hdr, out_keys);
 }
 
 int prepare_small_bridges() {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small_bridges),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(SmallLds));
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small_bridges<kLimitV, 1024>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(SmallLds<kLimitV, 1024>));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small_bridges<kSplitV, 256>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(SmallLds<kSplitV, 256>));
     return e == hipSuccess ? 0 : -1;
 }
 

@@ -134,9 +134,12 @@ void launch_batched(const BatchDev& B, int blocks, hipStream_t s);
 // finds the bridges of node 0's certificate in LDS; keys (u << 16 | v, sorted)
 // go to out_keys at a base taken from out_hdr[0]; out_hdr[16 + 2s] / [17 + 2s]
 // receive graph s's base and count.  out_hdr[0] must be zero at launch.
-void launch_small_bridges(const BatchDev& B, int32_t S, uint32_t* out_hdr, uint32_t* out_keys, int blocks, hipStream_t s);
-// Allows the kernel above its LDS size (once per process, before any launch or capture).
+// list_a holds the graphs with V <= small_bridges_split_v(), list_b the rest.
+void launch_small_bridges(const BatchDev& B, const int32_t* list_a, int32_t na, const int32_t* list_b, int32_t nb,
+                          uint32_t* out_hdr, uint32_t* out_keys, int cus, hipStream_t s);
+// Allows the kernels above their LDS sizes (once per process, before any launch or capture).
 int prepare_small_bridges();
+int32_t small_bridges_split_v();
 int32_t small_bridges_max_v();   // largest V the kernel above takes
 int32_t batched_max_v_dev();
 int32_t batched_blocks_per_cu();
