@@ -84,6 +84,8 @@ struct BatchPlan {
 struct BatchState {
     std::unique_ptr<Pool> pool;
     hipStream_t stream = nullptr;
+    hipStream_t stream2 = nullptr;           // second branch of the captured final step (default priority)
+    hipEvent_t fork = nullptr, join = nullptr;
     std::vector<std::unique_ptr<BatchPlan>> plans;      // small LRU
     std::map<std::string, int32_t> tuned;               // batch shape -> chunk_edges
     std::vector<DfsScratch> scratch;
@@ -251,7 +253,7 @@ int build_plan(BatchPlan& P, const int64_t* eoff, const int32_t* V, int32_t G, i
 // enqueue clear -> kernel -> copies on s (captured into P.graph on first use)
 // the captured part: clear the counters, the persistent kernel, and with the
 // final step on the device the combined certificate and its bridge step
-int enqueue(BatchPlan& P, const int32_t* d_edges, hipStream_t s, int mode, int part) {
+int enqueue(BatchPlan& P, const int32_t* d_edges, hipStream_t s, int mode, int part, BatchState* st) {
     P.dev.edges = reinterpret_cast<const int2*>(d_edges);
     if (part == 0) {
         launch_fill_u32(P.dev.ncnt, (int64_t)P.clear_words, 0u, s);
@@ -262,8 +264,14 @@ int enqueue(BatchPlan& P, const int32_t* d_edges, hipStream_t s, int mode, int p
     }
     if (mode == 1 && !P.small.empty()) {
         launch_fill_u32(P.d_sb, 16, 0u, s);
-        launch_small_bridges(P.dev, P.d_lists, P.na, P.d_lists + P.na, P.nb, P.d_sb, P.d_sb + P.sb_hdr, P.cus, s);
+        // fork: the two size classes run side by side, then join back on s
+        BR_HIP(hipEventRecord(st->fork, s));
+        BR_HIP(hipStreamWaitEvent(st->stream2, st->fork, 0));
+        launch_small_bridges(P.dev, P.d_lists, P.na, P.d_lists + P.na, P.nb, P.d_sb, P.d_sb + P.sb_hdr, P.cus, s,
+                             st->stream2);
         BR_HIP(hipGetLastError());
+        BR_HIP(hipEventRecord(st->join, st->stream2));
+        BR_HIP(hipStreamWaitEvent(s, st->join, 0));
     }
     return BR_OK;
 }
@@ -288,9 +296,9 @@ int copy_back(BatchPlan& P, hipStream_t s, int mode) {
 }
 
 static int capture(BatchPlan& P, const int32_t* d_edges, hipStream_t s, int mode, int part, hipGraph_t* graph,
-                   hipGraphExec_t* exec) {
+                   hipGraphExec_t* exec, BatchState* st) {
     BR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue(P, d_edges, s, mode, part);
+    int rc = enqueue(P, d_edges, s, mode, part, st);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(s, &g);
     if (rc) {
@@ -312,10 +320,10 @@ int run_device(BatchState& st, BatchPlan& P, const int32_t* d_edges, int mode) {
         for (hipGraph_t* g : {&P.graph, &P.graph2})
             if (*g) { (void)hipGraphDestroy(*g); *g = nullptr; }
         P.graph_edges = nullptr;
-        int rc = capture(P, d_edges, s, mode, 0, &P.graph, &P.exec);
+        int rc = capture(P, d_edges, s, mode, 0, &P.graph, &P.exec, &st);
         if (rc) return rc;
         if (two) {
-            rc = capture(P, d_edges, s, mode, 1, &P.graph2, &P.exec2);
+            rc = capture(P, d_edges, s, mode, 1, &P.graph2, &P.exec2, &st);
             if (rc) return rc;
         }
         P.graph_edges = d_edges;
@@ -356,6 +364,9 @@ void batched_release(br_ctx* c) {
     if (st->k0) (void)hipEventDestroy(st->k0);
     if (st->k1) (void)hipEventDestroy(st->k1);
     if (st->k2) (void)hipEventDestroy(st->k2);
+    if (st->fork) (void)hipEventDestroy(st->fork);
+    if (st->join) (void)hipEventDestroy(st->join);
+    if (st->stream2) (void)hipStreamDestroy(st->stream2);
     if (st->stream) (void)hipStreamDestroy(st->stream);
     delete st;
     c->batched = nullptr;
@@ -410,6 +421,9 @@ int br_bridges_find_batched(br_ctx* c, const int32_t* d_edges, const int64_t* h_
         BR_HIP(hipEventCreate(&st.k0));
         BR_HIP(hipEventCreate(&st.k1));
         BR_HIP(hipEventCreate(&st.k2));
+        BR_HIP(hipStreamCreateWithFlags(&st.stream2, hipStreamNonBlocking));
+        BR_HIP(hipEventCreateWithFlags(&st.fork, hipEventDisableTiming));
+        BR_HIP(hipEventCreateWithFlags(&st.join, hipEventDisableTiming));
         if (prepare_small_bridges() != 0) return fail(BR_EHIP, "batched: cannot raise the LDS limit of the bridge kernel");
         if (small_bridges_max_v() < batched_max_v_dev()) return fail(BR_EINTERNAL, "batched: bridge kernel limit below the LDS path's");
     }

@@ -339,13 +339,13 @@ int32_t small_bridges_max_v() { return kLimitV; }
 int32_t small_bridges_split_v() { return kSplitV; }
 
 void launch_small_bridges(const BatchDev& B, const int32_t* list_a, int32_t na, const int32_t* list_b, int32_t nb,
-                          uint32_t* out_hdr, uint32_t* out_keys, int cus, hipStream_t s) {
+                          uint32_t* out_hdr, uint32_t* out_keys, int cus, hipStream_t s, hipStream_t s_b) {
+    if (nb > 0)
+        hipLaunchKernelGGL((k_small_bridges<kLimitV, 1024>), dim3((unsigned)std::min(nb, 4 * cus)), dim3(1024),
+                           sizeof(SmallLds<kLimitV, 1024>), s_b, B, list_b, nb, out_hdr, out_keys);
     if (na > 0)
         hipLaunchKernelGGL((k_small_bridges<kSplitV, 256>), dim3((unsigned)std::min(na, 16 * cus)), dim3(256),
                            sizeof(SmallLds<kSplitV, 256>), s, B, list_a, na, out_hdr, out_keys);
-    if (nb > 0)
-        hipLaunchKernelGGL((k_small_bridges<kLimitV, 1024>), dim3((unsigned)std::min(nb, 4 * cus)), dim3(1024),
-                           sizeof(SmallLds<kLimitV, 1024>), s, B, list_b, nb, out_hdr, out_keys);
 }
 
 int prepare_small_bridges() {

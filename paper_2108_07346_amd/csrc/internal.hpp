@@ -135,8 +135,10 @@ void launch_batched(const BatchDev& B, int blocks, hipStream_t s);
 // go to out_keys at a base taken from out_hdr[0]; out_hdr[16 + 2s] / [17 + 2s]
 // receive graph s's base and count.  out_hdr[0] must be zero at launch.
 // list_a holds the graphs with V <= small_bridges_split_v(), list_b the rest.
+// The two size classes go to streams s (small) and s_b (large) so that they
+// can overlap; the caller orders s_b after earlier work on s and joins it back.
 void launch_small_bridges(const BatchDev& B, const int32_t* list_a, int32_t na, const int32_t* list_b, int32_t nb,
-                          uint32_t* out_hdr, uint32_t* out_keys, int cus, hipStream_t s);
+                          uint32_t* out_hdr, uint32_t* out_keys, int cus, hipStream_t s, hipStream_t s_b);
 // Allows the kernels above their LDS sizes (once per process, before any launch or capture).
 int prepare_small_bridges();
 int32_t small_bridges_split_v();

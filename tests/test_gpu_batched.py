@@ -66,6 +66,10 @@ def test_mixed_sizes_and_edge_cases(ctx):
     graphs.append((np.zeros((0, 2), np.int32), 1))                      # empty, V = 1
     graphs.append((np.array([[0, 0], [0, 0]], np.int32), 1))            # loops only
     graphs.append((np.array([[3, 1]], np.int32), 4096))                 # at the LDS limit
+    for Vb in (1023, 1024, 1025):                                        # both sides of the final step's size split
+        path = np.stack([np.arange(Vb - 1), np.arange(1, Vb)], 1).astype(np.int32)
+        chords = rng.integers(0, Vb, size=(Vb // 3, 2)).astype(np.int32)
+        graphs.append((np.concatenate([path, chords])[rng.permutation(Vb - 1 + Vb // 3)], Vb))
     big = graphgen.planted(5, k=4, vc=6000, p=0.05, n_extra=1, n_pend=7)    # above the LDS limit
     graphs.append((big.edges, big.V))
     tree = np.stack([np.arange(4095), np.arange(1, 4096)], 1).astype(np.int32)
