@@ -197,9 +197,16 @@ int br_get_profile(br_ctx* ctx, br_profile* out);
  * breadth-first forest of G (each tree from the smallest vertex of its
  * component; a newly reached vertex takes its smallest-id neighbour one level
  * up as parent), F' a breadth-first forest of G without the vertex pairs of F
- * (all parallel copies of them left out) -- then the low-link search on the
- * host over F u F' (at most 2(V-1) edges): a non-root p is a cut vertex iff a
- * child c has low[c] >= disc[p], a root iff it has two or more children.  The
+ * (all parallel copies of them left out) -- then the cut-vertex test on
+ * F u F' (at most 2(V-1) edges).  With the default final step (see
+ * br_set_final_step) the test runs on the GPU: F rooted by its Euler tours,
+ * tree edges grouped into blocks (an edge of F' between unrelated vertices
+ * joins their parent edges; a child's parent edge joins its parent's when the
+ * child's subtree reaches outside the parent's), a vertex cut iff its child
+ * edges are not all in its own parent edge's block (a root: in two or more
+ * blocks).  Final step 0 runs the low-link search on the host instead: a
+ * non-root p cuts iff a child c has low[c] >= disc[p], a root iff it has two
+ * or more children.  The
  * union-find forests of Algorithm 2 (Section IV-B) would not do: they keep
  * edge connectivity but not vertex connectivity; search-ordered forests keep
  * both (the certificate definition of Section III, for 2-vertex connectivity).

@@ -199,6 +199,8 @@ __global__ void k_bfs_level(const int32_t* level_list, const uint32_t* count, ui
 }
 
 __global__ void k_zero_u32(uint32_t* p, int64_t n) { GRID_LOOP(i, n) p[i] = 0; }
+// roots of F (no BFS parent) flagged 0, every other vertex 1
+__global__ void k_root_flags(const int32_t* par1, int32_t V, uint32_t* flag) { GRID_LOOP(v, (int64_t)V) flag[v] = par1[v] < 0 ? 0u : 1u; }
 __global__ void k_copy_u32(const uint32_t* a, uint32_t* b) { if (threadIdx.x == 0) *b = *a; }
 
 }  // namespace
@@ -284,10 +286,11 @@ static void components(const ApWs& W, const int2* edges, int64_t E, int32_t V, c
     hipLaunchKernelGGL(k_cc_compress, dim3(grid_for(V)), dim3(kT), 0, s, W.q, V);
 }
 
-// The scan-first certificate (F, F') of d_edges on the device; on return the
-// host holds |F|, |F'| and both edge lists (pinned buffers of the context).
-int scan_first_certificate(const int2* edges, int64_t E, int32_t V, char* ws, hipStream_t s, uint32_t* h_small,
-                           int2* h_f1, int2* h_f2, uint32_t* n1, uint32_t* n2, int* levels1, int* levels2) {
+// The scan-first certificate (F, F') of d_edges, left on the device: F at
+// *d_f1, F' at *d_f2, |F| and |F'| at (*d_cnt)[0..1], the error word at
+// *d_err, and per vertex 0 at the roots of F, 1 elsewhere, at *d_roots.
+int scan_first_device(const int2* edges, int64_t E, int32_t V, char* ws, hipStream_t s, uint32_t* h_small, int* levels1,
+                      int* levels2, int2** d_f1, int2** d_f2, uint32_t** d_cnt, uint32_t** d_err, uint32_t** d_roots) {
     const ApWs W = ap_carve(ws, E, V);
     hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(W.zero_words)), dim3(kT), 0, s, reinterpret_cast<uint32_t*>(ws),
                        W.zero_words);
@@ -304,15 +307,32 @@ int scan_first_certificate(const int2* edges, int64_t E, int32_t V, char* ws, hi
     components(W, edges, E, V, W.par1, s);
     rc = bfs_forest(W, V, W.par1, W.par2, W.f2, W.nout + 1, s, h_small, levels2);
     if (rc) return rc;
-    BR_HIP(hipMemcpyAsync(h_small, W.err, 16, hipMemcpyDeviceToHost, s));
+    hipLaunchKernelGGL(k_root_flags, dim3(grid_for(V)), dim3(kT), 0, s, (const int32_t*)W.par1, V, W.q);
+    BR_HIP(hipGetLastError());
+    *d_f1 = W.f1;
+    *d_f2 = W.f2;
+    *d_cnt = W.nout;
+    *d_err = W.err;
+    *d_roots = W.q;
+    return BR_OK;
+}
+
+// The same certificate copied to the host (pinned h_f1 / h_f2, V pairs each).
+int scan_first_certificate(const int2* edges, int64_t E, int32_t V, char* ws, hipStream_t s, uint32_t* h_small,
+                           int2* h_f1, int2* h_f2, uint32_t* n1, uint32_t* n2, int* levels1, int* levels2) {
+    int2 *f1 = nullptr, *f2 = nullptr;
+    uint32_t *cnt = nullptr, *err = nullptr, *roots = nullptr;
+    int rc = scan_first_device(edges, E, V, ws, s, h_small, levels1, levels2, &f1, &f2, &cnt, &err, &roots);
+    if (rc) return rc;
+    BR_HIP(hipMemcpyAsync(h_small, err, 16, hipMemcpyDeviceToHost, s));
     BR_HIP(hipStreamSynchronize(s));
-    const uint32_t err = h_small[0];
+    const uint32_t e = h_small[0];
     *n1 = std::min<uint32_t>(h_small[1], (uint32_t)V);
     *n2 = std::min<uint32_t>(h_small[2], (uint32_t)V);
-    if (err & 1u) return fail(BR_ERANGE, "scan-first certificate: an edge has a vertex id outside [0, %d)", V);
-    if (err) return fail(BR_EINTERNAL, "scan-first certificate: forest larger than V - 1");
-    if (*n1) BR_HIP(hipMemcpyAsync(h_f1, W.f1, 8 * (size_t)*n1, hipMemcpyDeviceToHost, s));
-    if (*n2) BR_HIP(hipMemcpyAsync(h_f2, W.f2, 8 * (size_t)*n2, hipMemcpyDeviceToHost, s));
+    if (e & 1u) return fail(BR_ERANGE, "scan-first certificate: an edge has a vertex id outside [0, %d)", V);
+    if (e) return fail(BR_EINTERNAL, "scan-first certificate: forest larger than V - 1");
+    if (*n1) BR_HIP(hipMemcpyAsync(h_f1, f1, 8 * (size_t)*n1, hipMemcpyDeviceToHost, s));
+    if (*n2) BR_HIP(hipMemcpyAsync(h_f2, f2, 8 * (size_t)*n2, hipMemcpyDeviceToHost, s));
     BR_HIP(hipStreamSynchronize(s));
     return BR_OK;
 }

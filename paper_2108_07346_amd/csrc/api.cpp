@@ -464,24 +464,60 @@ int br_articulation_points(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t
     BR_HIP(hipSetDevice(c->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     BR_HIP(hipEventSynchronize(c->ev[7]));
-    rc = ensure_workspace(c, 4 * (size_t)scan_first_words(E, V), s);
+    const size_t ws_cert = 4 * (size_t)scan_first_words(E, V);
+    const size_t ws_test = c->final_step == 1 ? 4 * (size_t)device_bridges_words(V) : 0;
+    rc = ensure_workspace(c, ws_cert + ws_test + 256, s);
     if (rc) return rc;
     rc = ensure_pinned(c, 256 + 2 * sizeof(int2) * (size_t)std::max(V, 1));
     if (rc) return rc;
     char* h = static_cast<char*>(c->pinned);
     uint32_t* hs = reinterpret_cast<uint32_t*>(h);
-    int2* hf1 = reinterpret_cast<int2*>(h + 256);
-    int2* hf2 = hf1 + std::max(V, 1);
     uint32_t n1 = 0, n2 = 0;
     int l1 = 0, l2 = 0;
-    ev_record(c, 0, s);
-    rc = scan_first_certificate(reinterpret_cast<const int2*>(d_edges), E, V, static_cast<char*>(c->ws.base), s, hs, hf1,
-                                hf2, &n1, &n2, &l1, &l2);
-    if (rc) return rc;
-    ev_record(c, 3, s);
-    auto t1 = std::chrono::steady_clock::now();
     std::vector<int32_t> aps;
-    certificate_articulation(hf1, n1, hf2, n2, V, c->dfs, aps);
+    std::chrono::steady_clock::time_point t1;
+    char* wsb = static_cast<char*>(c->ws.base);
+    if (c->final_step == 1) {
+        // test on the device: only the articulation points come back
+        int2 *f1 = nullptr, *f2 = nullptr;
+        uint32_t *cnt = nullptr, *err = nullptr, *roots = nullptr;
+        rc = scan_first_device(reinterpret_cast<const int2*>(d_edges), E, V, wsb, s, hs, &l1, &l2, &f1, &f2, &cnt, &err,
+                               &roots);
+        if (rc) return rc;
+        int32_t* tws = reinterpret_cast<int32_t*>(wsb + ((ws_cert + 255) & ~size_t(255)));
+        uint64_t* d_keys = nullptr;
+        uint32_t* d_n = nullptr;
+        rc = device_articulation_cert(f1, f2, 1, cnt, roots, 1, V, tws, &d_keys, &d_n, s);
+        if (rc) return rc;
+        launch_bridge_status(cnt, err, d_n, s);
+        BR_HIP(hipGetLastError());
+        uint64_t* hk = reinterpret_cast<uint64_t*>(h + 256);
+        const size_t guess = std::min<size_t>(std::max<size_t>(c->keys_hint, 1024), (size_t)std::max(V, 1));
+        BR_HIP(hipMemcpyAsync(hs, d_n - 1, 256 + 8 * guess, hipMemcpyDeviceToHost, s));
+        BR_HIP(hipStreamSynchronize(s));
+        n1 = hs[2]; n2 = hs[3];
+        const uint32_t e = hs[4], nk = std::min<uint32_t>(hs[1], (uint32_t)std::max(V, 1));
+        if (e & 1u) return fail(BR_ERANGE, "br_articulation_points: an edge has a vertex id outside [0, %d)", V);
+        if (e) return fail(BR_EINTERNAL, "br_articulation_points: forest larger than V - 1");
+        if (nk > guess) {
+            BR_HIP(hipMemcpyAsync(hk + guess, d_keys + guess, 8 * (size_t)(nk - guess), hipMemcpyDeviceToHost, s));
+            BR_HIP(hipStreamSynchronize(s));
+        }
+        c->keys_hint = nk;
+        t1 = std::chrono::steady_clock::now();
+        aps.resize(nk);
+        for (uint32_t i = 0; i < nk; i++) aps[i] = (int32_t)hk[i];
+        std::sort(aps.begin(), aps.end());
+    } else {
+        // Algorithm 1's search (vertex test) on the host over the copied certificate
+        int2* hf1 = reinterpret_cast<int2*>(h + 256);
+        int2* hf2 = hf1 + std::max(V, 1);
+        rc = scan_first_certificate(reinterpret_cast<const int2*>(d_edges), E, V, wsb, s, hs, hf1, hf2, &n1, &n2, &l1,
+                                    &l2);
+        if (rc) return rc;
+        t1 = std::chrono::steady_clock::now();
+        certificate_articulation(hf1, n1, hf2, n2, V, c->dfs, aps);
+    }
     auto t2 = std::chrono::steady_clock::now();
     *n_out = (int64_t)aps.size();
     c->prof.cert_f1 = n1;

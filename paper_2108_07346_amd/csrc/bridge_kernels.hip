@@ -434,6 +434,126 @@ __global__ void k_bridges(const int2* f1, const uint32_t* q, int32_t qs, const i
     }
 }
 
+// ---- articulation points of the certificate ------------------------------------
+//
+// The test of Tarjan and Vishkin on the rooted spanning tree F (any spanning
+// tree will do, breadth-first included).  Tree edges are named by their child
+// c and grouped by a union-find: an edge of F' between two unrelated vertices
+// (neither in the other's subtree) joins their parent edges, and the parent
+// edge of c joins that of its parent p (p not a root) when c's subtree reaches
+// a vertex outside p's subtree.  The groups are the blocks; a vertex is an
+// articulation point iff the edges to its children do not all lie in the block
+// of its own parent edge -- for a root, iff they lie in at least two blocks.
+__device__ __forceinline__ uint32_t tv_find(uint32_t* g, uint32_t x) {
+    uint32_t d = g[x];
+    while (d != 0) {
+        const uint32_t p = x - d, dp = g[p];
+        if (dp == 0) return p;
+        g[x] = d + dp;
+        x = p - dp;
+        d = g[x];
+    }
+    return x;
+}
+
+__device__ __forceinline__ void tv_unite(uint32_t* g, uint32_t a, uint32_t b) {
+    for (;;) {
+        a = tv_find(g, a);
+        b = tv_find(g, b);
+        if (a == b) return;
+        if (a < b) { const uint32_t t = a; a = b; b = t; }
+        uint32_t expect = 0;
+        if (__hip_atomic_compare_exchange_strong(g + a, &expect, a - b, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            return;
+        a -= expect;
+    }
+}
+
+__global__ void k_tv_init(int32_t V, uint32_t* g, int32_t* rmin, int32_t* rmax, int32_t* apf) {
+    GRID_LOOP(v, (int64_t)V) {
+        g[v] = 0;
+        rmin[v] = INT32_MAX;
+        rmax[v] = -1;
+        apf[v] = 0;
+    }
+}
+
+// tree edge (w, v), w not a root: joins (parent(w), w) when v's subtree escapes w's
+__global__ void k_tv_tree(const int2* f1, const uint32_t* q, int32_t qs, const int32_t* head, const int32_t* in_arc,
+                          const int32_t* pre, const int32_t* sub, Rmq R, int32_t V, int64_t A, uint32_t* g) {
+    GRID_LOOP(v, (int64_t)V) {
+        if (head[v + 1] == head[v] || q[qs * (size_t)v] == 0) continue;
+        const int32_t a = in_arc[v];
+        if (a < 0 || a >= A) continue;
+        const int32_t w = arc_src(f1, a);
+        if (q[qs * (size_t)w] == 0) continue;
+        const int32_t l = pre[v], r = pre[v] + sub[v] - 1, pw = pre[w];
+        if (l < 0 || r < l || r >= V || pw < 0) continue;
+        int32_t mn, mx;
+        range_minmax(R, l, r, mn, mx);
+        if (mn < pw || mx >= pw + sub[w]) tv_unite(g, (uint32_t)v, (uint32_t)w);
+    }
+}
+
+// edge of F' between unrelated vertices: joins their parent edges
+__global__ void k_tv_cross(const int2* f2, int32_t dir, const uint32_t* cnt, const int32_t* pre, const int32_t* sub,
+                           uint32_t* g) {
+    const int64_t n2 = cnt[1];
+    GRID_LOOP(k, n2) {
+        const int2 e = f2[dir * k];
+        const int32_t px = pre[e.x], py = pre[e.y];
+        if (px < 0 || py < 0 || e.x == e.y) continue;
+        const bool related = (px <= py && py < px + sub[e.x]) || (py <= px && px < py + sub[e.y]);
+        if (!related) tv_unite(g, (uint32_t)e.x, (uint32_t)e.y);
+    }
+}
+
+__global__ void k_tv_compress(uint32_t* g, int32_t V) {
+    GRID_LOOP(x, (int64_t)V) {
+        const uint32_t d = g[x];
+        if (d == 0) continue;
+        uint32_t r = (uint32_t)x - d;
+        for (uint32_t e = g[r]; e != 0; e = g[r]) r -= e;
+        g[x] = (uint32_t)x - r;
+    }
+}
+
+// per tree edge (w, v): compare v's block with the block of w's own parent edge
+__global__ void k_tv_mark(const int2* f1, const uint32_t* q, int32_t qs, const int32_t* head, const int32_t* in_arc,
+                          int32_t V, int64_t A, const uint32_t* g, int32_t* rmin, int32_t* rmax, int32_t* apf) {
+    GRID_LOOP(v, (int64_t)V) {
+        if (head[v + 1] == head[v] || q[qs * (size_t)v] == 0) continue;
+        const int32_t a = in_arc[v];
+        if (a < 0 || a >= A) continue;
+        const int32_t w = arc_src(f1, a);
+        const int32_t cv = (int32_t)((uint32_t)v - g[v]);
+        if (q[qs * (size_t)w] == 0) {
+            atomicMin(&rmin[w], cv);
+            atomicMax(&rmax[w], cv);
+        } else if (cv != (int32_t)((uint32_t)w - g[w])) {
+            apf[w] = 1;
+        }
+    }
+}
+
+__global__ void k_tv_list(const uint32_t* q, int32_t qs, const int32_t* head, int32_t V, const int32_t* rmin,
+                          const int32_t* rmax, const int32_t* apf, uint64_t* out, uint32_t* nout) {
+    GRID_LOOP(v, (int64_t)V) {
+        bool cut = false;
+        if (head[v + 1] > head[v])
+            cut = q[qs * (size_t)v] == 0 ? (rmax[v] >= 0 && rmin[v] != rmax[v]) : apf[v] != 0;
+        const uint64_t m = __ballot(cut);
+        if (m) {
+            const int leader = __ffsll((unsigned long long)m) - 1;
+            uint32_t base = 0;
+            if (__lane_id() == leader) base = atomicAdd(nout, (uint32_t)__popcll(m));
+            base = __shfl(base, leader);
+            if (cut) out[base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = (uint64_t)v;
+        }
+    }
+}
+
 // counters of the certificate and the result next to the keys, for one copy
 __global__ void k_status(const uint32_t* cnt, const uint32_t* err, uint32_t* misc) {
     if (threadIdx.x == 0) {
@@ -517,8 +637,11 @@ void device_scan1(int32_t* a, int64_t n, uint64_t* status, uint32_t* ticket, hip
 // its tree of F iff q[qs*v] == 0.  Writes up to V keys at *d_keys and their
 // number at *d_n; *d_n sits 4 bytes into a 256-byte status block that the keys
 // follow directly.
-int device_bridges_cert(const int2* f1, const int2* f2, int32_t dir, const uint32_t* cnt, const uint32_t* q, int32_t qs,
-                        int32_t V, int32_t max_tree, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s) {
+// The part shared by the bridge and articulation-point tests: adjacency of F,
+// Euler tours ranked, preorder numbers, subtree sizes, min/max preorder numbers
+// reached through F' and their range tables.
+static BridgeWs number_tree(const int2* f1, const int2* f2, int32_t dir, const uint32_t* cnt, const uint32_t* q,
+                            int32_t qs, int32_t V, int32_t max_tree, int32_t* ws, hipStream_t s, Rmq* R) {
     const int64_t A = 2 * (int64_t)std::max(V - 1, 1);
     // list ranking only needs the longest tour: at most 2(max_tree - 1) arcs
     max_tree = std::max(2, std::min(max_tree, V));
@@ -553,9 +676,41 @@ int device_bridges_cert(const int2* f1, const int2* f2, int32_t dir, const uint3
         for (int32_t j = 1; j < W.levels; j++)
             hipLaunchKernelGGL(k_rmq_level, dim3(grid_for(W.nb)), dim3(kT), 0, s, W.tmn, W.tmx, W.nb, j);
     }
-    const Rmq R{W.tmin, W.tmax, W.lmin, W.lmax, W.tmn, W.tmx, (int64_t)V, W.nb};
+    *R = Rmq{W.tmin, W.tmax, W.lmin, W.lmax, W.tmn, W.tmx, (int64_t)V, W.nb};
+    return W;
+}
+
+int device_bridges_cert(const int2* f1, const int2* f2, int32_t dir, const uint32_t* cnt, const uint32_t* q, int32_t qs,
+                        int32_t V, int32_t max_tree, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s) {
+    const int64_t A = 2 * (int64_t)std::max(V - 1, 1);
+    Rmq R;
+    const BridgeWs W = number_tree(f1, f2, dir, cnt, q, qs, V, max_tree, ws, s, &R);
     hipLaunchKernelGGL(k_bridges, dim3(grid_for(V)), dim3(kT), 0, s, f1, q, qs, W.head, W.in_arc, W.pre, W.sub, R, V,
                        A, W.keys, reinterpret_cast<uint32_t*>(W.misc + 1));
+    *d_keys = W.keys;
+    *d_n = reinterpret_cast<uint32_t*>(W.misc + 1);
+    return BR_OK;
+}
+
+// Articulation points of a certificate held on the device (same arguments as
+// device_bridges_cert); F must be the spanning forest of the certificate.
+// Writes the vertex ids (as 64-bit keys, unordered) at *d_keys and their number
+// at *d_n, in the same status-block layout.  Scratch reused from the numbering:
+// cur (blocks), tour_len / tree_n (roots' min / max child block), posof (flags).
+int device_articulation_cert(const int2* f1, const int2* f2, int32_t dir, const uint32_t* cnt, const uint32_t* q,
+                             int32_t qs, int32_t V, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s) {
+    const int64_t A = 2 * (int64_t)std::max(V - 1, 1);
+    Rmq R;
+    const BridgeWs W = number_tree(f1, f2, dir, cnt, q, qs, V, V, ws, s, &R);
+    uint32_t* g = reinterpret_cast<uint32_t*>(W.cur);
+    hipLaunchKernelGGL(k_tv_init, dim3(grid_for(V)), dim3(kT), 0, s, V, g, W.tour_len, W.tree_n, W.posof);
+    hipLaunchKernelGGL(k_tv_tree, dim3(grid_for(V)), dim3(kT), 0, s, f1, q, qs, W.head, W.in_arc, W.pre, W.sub, R, V, A, g);
+    hipLaunchKernelGGL(k_tv_cross, dim3(grid_for(V)), dim3(kT), 0, s, f2, dir, cnt, W.pre, W.sub, g);
+    hipLaunchKernelGGL(k_tv_compress, dim3(grid_for(V)), dim3(kT), 0, s, g, V);
+    hipLaunchKernelGGL(k_tv_mark, dim3(grid_for(V)), dim3(kT), 0, s, f1, q, qs, W.head, W.in_arc, V, A, (const uint32_t*)g,
+                       W.tour_len, W.tree_n, W.posof);
+    hipLaunchKernelGGL(k_tv_list, dim3(grid_for(V)), dim3(kT), 0, s, q, qs, W.head, V, W.tour_len, W.tree_n, W.posof,
+                       W.keys, reinterpret_cast<uint32_t*>(W.misc + 1));
     *d_keys = W.keys;
     *d_n = reinterpret_cast<uint32_t*>(W.misc + 1);
     return BR_OK;

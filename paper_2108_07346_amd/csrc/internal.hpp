@@ -167,6 +167,13 @@ void device_scan1(int32_t* a, int64_t n, uint64_t* status, uint32_t* ticket, hip
 int64_t scan_first_words(int64_t E, int32_t V);
 int scan_first_certificate(const int2* edges, int64_t E, int32_t V, char* ws, hipStream_t s, uint32_t* h_small,
                            int2* h_f1, int2* h_f2, uint32_t* n1, uint32_t* n2, int* levels1, int* levels2);
+int scan_first_device(const int2* edges, int64_t E, int32_t V, char* ws, hipStream_t s, uint32_t* h_small, int* levels1,
+                      int* levels2, int2** d_f1, int2** d_f2, uint32_t** d_cnt, uint32_t** d_err, uint32_t** d_roots);
+// Articulation points of a certificate on the device (F spanning forest, roots
+// flagged 0 in q[qs * v]); ids as 64-bit keys at *d_keys, their number at *d_n
+// (the bridge step's status-block layout).
+int device_articulation_cert(const int2* f1, const int2* f2, int32_t dir, const uint32_t* cnt, const uint32_t* q,
+                             int32_t qs, int32_t V, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s);
 // copies |F|, |F'| (cnt[0..1]) and *err into the 256-byte status block whose
 // word 1 is the key count d_n of a bridge step (the keys follow the block)
 void launch_bridge_status(const uint32_t* cnt, const uint32_t* err, uint32_t* d_n, hipStream_t s);

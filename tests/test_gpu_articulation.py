@@ -1,6 +1,7 @@
 """GPU parity of the articulation points ("failure points" of the abstract):
-the scan-first certificate built on the GPU, then the low-link search on it,
-against the CPU oracle (low-link search on the whole graph), bit-exact."""
+the scan-first certificate built on the GPU, then the cut-vertex test on it
+(on the GPU by default, or the low-link search on the host), against the CPU
+oracle (low-link search on the whole graph), bit-exact."""
 import itertools
 import sys
 
@@ -19,12 +20,16 @@ def say(*a):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def ctx():
+@pytest.fixture(scope="module", params=[1, 0], ids=["gpu_test", "host_search"])
+def ctx(request):
+    # both final steps: the block test on the GPU (default) and the low-link
+    # search on the host over the copied certificate
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import paper_2108_07346_amd as br
     c = br.Context(0)
+    c.set_final_step(request.param)
+    say("final step %d" % request.param)
     yield c
     c.close()
 
