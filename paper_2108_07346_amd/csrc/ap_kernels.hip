@@ -117,22 +117,149 @@ __global__ void k_cc_compress(uint32_t* q, int32_t V) {
     }
 }
 
-// adjacency: degrees, then (after a scan of head) each arc at its place
-__global__ void k_adj_degree(const int2* edges, int64_t E, int32_t V, int32_t* head) {
-    GRID_LOOP(i, E) {
+// ---- adjacency (neighbour ids, grouped by vertex) ------------------------------
+//
+// By a counting sort in two levels.  Buckets of 2^sh consecutive vertices
+// (nb <= kMaxBuckets of them): every block counts the arcs of its tile of the
+// edge list per bucket in LDS and adds the counts to the bucket totals; after a
+// scan of the totals each block reserves one run per bucket and writes its arcs
+// (source, target) there; then one block per bucket counts its arcs per source
+// in LDS, scans the counts into the vertex heads and places every target.  Only
+// nb global atomics per block are left of the 4E a direct build would make
+// (a degree count and a slot reservation per arc end).  Graphs with more
+// vertices than the bucket limit allows use the direct build.
+constexpr int kMaxBuckets = 4096;
+constexpr int kMaxBucketShift = 13;     // 2^13 counters = 32 KB of LDS per block
+constexpr int kBktBlocks = 512;
+
+__device__ __forceinline__ bool arc_edge(int2 e, int32_t V) {
+    return (uint32_t)e.x < (uint32_t)V && (uint32_t)e.y < (uint32_t)V && e.x != e.y;
+}
+
+// in-place exclusive scan of v[0..n) (n <= 256 * per) by one block; returns the total
+__device__ uint32_t block_scan_lds(uint32_t* v, int n, uint32_t* part) {
+    const int per = (n + kT - 1) / kT;
+    const int l0 = threadIdx.x * per;
+    uint32_t s = 0;
+    for (int j = 0; j < per; j++)
+        if (l0 + j < n) s += v[l0 + j];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < kT; off <<= 1) {
+        const uint32_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    uint32_t ex = part[threadIdx.x] - s;
+    for (int j = 0; j < per; j++)
+        if (l0 + j < n) { const uint32_t c = v[l0 + j]; v[l0 + j] = ex; ex += c; }
+    const uint32_t total = part[kT - 1];
+    __syncthreads();
+    return total;
+}
+
+__device__ __forceinline__ void tile_of(int64_t E, int64_t& lo, int64_t& hi) {
+    lo = E * blockIdx.x / gridDim.x;
+    hi = E * (blockIdx.x + 1) / gridDim.x;
+}
+
+__device__ void count_tile(const int2* edges, int64_t lo, int64_t hi, int32_t V, int sh, uint32_t* h) {
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kT) {
         const int2 e = edges[i];
-        if ((uint32_t)e.x >= (uint32_t)V || (uint32_t)e.y >= (uint32_t)V || e.x == e.y) continue;
-        atomicAdd(&head[e.x], 1);
-        atomicAdd(&head[e.y], 1);
+        if (!arc_edge(e, V)) continue;
+        atomicAdd(&h[(uint32_t)e.x >> sh], 1u);
+        atomicAdd(&h[(uint32_t)e.y >> sh], 1u);
     }
 }
 
-__global__ void k_adj_fill(const int2* edges, int64_t E, int32_t V, const int32_t* head, int32_t* cur, int2* adj) {
+__global__ void __launch_bounds__(kT) k_bkt_count(const int2* edges, int64_t E, int32_t V, int sh, int nb,
+                                                  uint32_t* total) {
+    __shared__ uint32_t h[kMaxBuckets];
+    for (int b = threadIdx.x; b < nb; b += kT) h[b] = 0;
+    __syncthreads();
+    int64_t lo, hi;
+    tile_of(E, lo, hi);
+    count_tile(edges, lo, hi, V, sh, h);
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += kT)
+        if (h[b]) atomicAdd(&total[b], h[b]);
+}
+
+// total[0..nb) -> base[0..nb] (exclusive, base[nb] = all arcs) and cur = base
+__global__ void __launch_bounds__(kT) k_bkt_scan(const uint32_t* total, int nb, uint32_t* base, uint32_t* cur) {
+    __shared__ uint32_t v[kMaxBuckets];
+    __shared__ uint32_t part[kT];
+    for (int b = threadIdx.x; b < nb; b += kT) v[b] = total[b];
+    __syncthreads();
+    const uint32_t all = block_scan_lds(v, nb, part);
+    for (int b = threadIdx.x; b < nb; b += kT) { base[b] = v[b]; cur[b] = v[b]; }
+    if (threadIdx.x == 0) base[nb] = all;
+}
+
+__global__ void __launch_bounds__(kT) k_bkt_scatter(const int2* edges, int64_t E, int32_t V, int sh, int nb,
+                                                    uint32_t* cur, int2* arcs) {
+    __shared__ uint32_t h[kMaxBuckets];
+    for (int b = threadIdx.x; b < nb; b += kT) h[b] = 0;
+    __syncthreads();
+    int64_t lo, hi;
+    tile_of(E, lo, hi);
+    count_tile(edges, lo, hi, V, sh, h);
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += kT)
+        if (h[b]) h[b] = atomicAdd(&cur[b], h[b]);     // this block's run in bucket b
+    __syncthreads();
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kT) {
+        const int2 e = edges[i];
+        if (!arc_edge(e, V)) continue;
+        arcs[atomicAdd(&h[(uint32_t)e.x >> sh], 1u)] = e;
+        arcs[atomicAdd(&h[(uint32_t)e.y >> sh], 1u)] = make_int2(e.y, e.x);
+    }
+}
+
+// block b: the arcs of bucket b -> head[] of its vertices and adj[] (targets)
+__global__ void __launch_bounds__(kT) k_bkt_csr(const int2* arcs, const uint32_t* base, int32_t V, int sh,
+                                                uint32_t* head, int32_t* adj) {
+    __shared__ uint32_t c[1 << kMaxBucketShift];
+    __shared__ uint32_t part[kT];
+    const int n = 1 << sh;
+    const uint32_t mask = (uint32_t)n - 1;
+    const int64_t lo = base[blockIdx.x], hi = base[blockIdx.x + 1];
+    for (int l = threadIdx.x; l < n; l += kT) c[l] = 0;
+    __syncthreads();
+    for (int64_t k = lo + threadIdx.x; k < hi; k += kT) atomicAdd(&c[(uint32_t)arcs[k].x & mask], 1u);
+    __syncthreads();
+    block_scan_lds(c, n, part);
+    const int64_t v0 = (int64_t)blockIdx.x << sh;
+    for (int l = threadIdx.x; l < n; l += kT) {
+        c[l] += (uint32_t)lo;
+        if (v0 + l < V) head[v0 + l] = c[l];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) head[V] = (uint32_t)hi;
+    __syncthreads();
+    for (int64_t k = lo + threadIdx.x; k < hi; k += kT) {
+        const int2 a = arcs[k];
+        adj[atomicAdd(&c[(uint32_t)a.x & mask], 1u)] = a.y;
+    }
+}
+
+// direct build (graphs past the bucket limit): degrees, then (after a scan of
+// head) each arc at its place
+__global__ void k_adj_degree(const int2* edges, int64_t E, int32_t V, uint32_t* head) {
     GRID_LOOP(i, E) {
         const int2 e = edges[i];
-        if ((uint32_t)e.x >= (uint32_t)V || (uint32_t)e.y >= (uint32_t)V || e.x == e.y) continue;
-        adj[head[e.x] + atomicAdd(&cur[e.x], 1)] = make_int2(e.y, (int32_t)i);
-        adj[head[e.y] + atomicAdd(&cur[e.y], 1)] = make_int2(e.x, (int32_t)i);
+        if (!arc_edge(e, V)) continue;
+        atomicAdd(&head[e.x], 1u);
+        atomicAdd(&head[e.y], 1u);
+    }
+}
+
+__global__ void k_adj_fill(const int2* edges, int64_t E, int32_t V, const uint32_t* head, uint32_t* cur, int32_t* adj) {
+    GRID_LOOP(i, E) {
+        const int2 e = edges[i];
+        if (!arc_edge(e, V)) continue;
+        adj[head[e.x] + atomicAdd(&cur[e.x], 1u)] = e.y;
+        adj[head[e.y] + atomicAdd(&cur[e.y], 1u)] = e.x;
     }
 }
 
@@ -153,7 +280,7 @@ __global__ void k_bfs_start(const uint32_t* q, int32_t V, int32_t* par, uint64_t
 // base[d & 1]; block 0 writes base[(d + 1) & 1]); then its offers to the
 // neighbours, newly reached ones appended with one reservation per wavefront
 __global__ void k_bfs_level(const int32_t* level_list, const uint32_t* count, uint32_t* count_after_next, int32_t d,
-                            uint32_t* base, const int32_t* head, const int2* adj, const int32_t* par1, uint64_t* cand,
+                            uint32_t* base, const uint32_t* head, const int32_t* adj, const int32_t* par1, uint64_t* cand,
                             int32_t* par, int32_t* next_list, uint32_t* next_count, int2* out, int64_t cap,
                             uint32_t* err) {
     const uint32_t n = *count;
@@ -175,13 +302,13 @@ __global__ void k_bfs_level(const int32_t* level_list, const uint32_t* count, ui
             else atomicOr(err, 2u);
         }
         const uint64_t mine = ((uint64_t)(uint32_t)d << 32) | (uint32_t)w;
-        const int32_t h0 = head[w], h1 = head[w + 1];
-        for (int32_t kb = h0; kb < h1; kb += 64) {
-            const int32_t k = kb + lane;
+        const int64_t h0 = head[w], h1 = head[w + 1];
+        for (int64_t kb = h0; kb < h1; kb += 64) {
+            const int64_t k = kb + lane;
             bool got = false;
             int32_t x = 0;
             if (k < h1) {
-                x = adj[k].x;
+                x = adj[k];
                 if (!excluded(par1, w, x) && cand[x] > mine)
                     got = atomicMin(reinterpret_cast<unsigned long long*>(cand + x), (unsigned long long)mine) ==
                           (unsigned long long)kNoCand;
@@ -205,28 +332,45 @@ __global__ void k_copy_u32(const uint32_t* a, uint32_t* b) { if (threadIdx.x == 
 
 }  // namespace
 
+// bucket size 2^sh: about 1,000 to 2,000 buckets (at least 64 vertices each)
+struct BktPlan {
+    int sh, nb;
+    bool on;
+};
+
+static BktPlan bucket_plan(int32_t V) {
+    int sh = 6;
+    while (sh < kMaxBucketShift && ((int64_t)V >> sh) >= 2048) sh++;
+    const int64_t nb = ((int64_t)V + (int64_t(1) << sh) - 1) >> sh;
+    return {sh, (int)std::min<int64_t>(nb, kMaxBuckets + 1), nb <= kMaxBuckets};
+}
+
 // Workspace words (4-byte) for the scan-first certificate of E edges on V vertices.
 struct ApWs {
-    uint32_t *q, *fcount, *err, *nout;
-    int32_t *head, *cur, *par1, *par2, *fa, *fb;
+    uint32_t *q, *fcount, *err, *nout, *head, *cur, *btot, *bbase, *bcur;
+    int32_t *par1, *par2, *fa, *fb, *adj;
     uint64_t *cand, *scan_status;
-    int2 *adj, *f1, *f2;
+    int2 *arcs, *f1, *f2;
     int64_t zero_words, words;
 };
 
 static ApWs ap_carve(char* base, int64_t E, int32_t V) {
     ApWs w{};
+    const BktPlan P = bucket_plan(V);
     int64_t o = 0;
     auto take = [&](int64_t bytes) { char* p = base ? base + o : nullptr; o += (bytes + 255) & ~int64_t(255); return p; };
     // cleared together at the start
     w.q = reinterpret_cast<uint32_t*>(take(4 * (int64_t)V));
-    w.head = reinterpret_cast<int32_t*>(take(4 * ((int64_t)V + 1)));
-    w.cur = reinterpret_cast<int32_t*>(take(4 * (int64_t)V));
+    w.head = reinterpret_cast<uint32_t*>(take(4 * ((int64_t)V + 1)));
+    w.cur = reinterpret_cast<uint32_t*>(take(P.on ? 4 : 4 * (int64_t)V));
+    w.btot = reinterpret_cast<uint32_t*>(take(4 * (int64_t)kMaxBuckets));
     w.fcount = reinterpret_cast<uint32_t*>(take(4 * 256));   // per-level frontier counts, then scan ticket
     w.err = reinterpret_cast<uint32_t*>(take(256));           // [0] error, [1..2] |F|, |F'|
     w.scan_status = reinterpret_cast<uint64_t*>(take(8 * (((int64_t)V + 1 + 1023) / 1024)));
     w.zero_words = o / 4;
     w.nout = w.err + 1;
+    w.bbase = reinterpret_cast<uint32_t*>(take(4 * ((int64_t)kMaxBuckets + 1)));
+    w.bcur = reinterpret_cast<uint32_t*>(take(4 * (int64_t)kMaxBuckets));
     w.par1 = reinterpret_cast<int32_t*>(take(4 * (int64_t)V));
     w.par2 = reinterpret_cast<int32_t*>(take(4 * (int64_t)V));
     w.fa = reinterpret_cast<int32_t*>(take(4 * (int64_t)V));
@@ -234,7 +378,8 @@ static ApWs ap_carve(char* base, int64_t E, int32_t V) {
     w.cand = reinterpret_cast<uint64_t*>(take(8 * (int64_t)V));
     w.f1 = reinterpret_cast<int2*>(take(8 * (int64_t)std::max(V, 1)));
     w.f2 = reinterpret_cast<int2*>(take(8 * (int64_t)std::max(V, 1)));
-    w.adj = reinterpret_cast<int2*>(take(16 * std::max<int64_t>(E, 1)));
+    w.adj = reinterpret_cast<int32_t*>(take(8 * std::max<int64_t>(E, 1)));
+    w.arcs = reinterpret_cast<int2*>(take(P.on ? 16 * std::max<int64_t>(E, 1) : 8));
     w.words = o / 4;
     return w;
 }
@@ -256,7 +401,7 @@ static int bfs_forest(const ApWs& W, int32_t V, const int32_t* par1, int32_t* pa
         for (int k = 0; k < kGroup && d < V; k++, d++) {
             hipLaunchKernelGGL(k_bfs_level, dim3(2048), dim3(kT), 0, s, (const int32_t*)cur_l,
                                (const uint32_t*)(W.fcount + d % 128), W.fcount + (d + 2) % 128, d, W.fcount + 128,
-                               (const int32_t*)W.head, (const int2*)W.adj, par1, W.cand, par, nxt_l,
+                               (const uint32_t*)W.head, (const int32_t*)W.adj, par1, W.cand, par, nxt_l,
                                W.fcount + (d + 1) % 128, out, (int64_t)V, W.err);
             std::swap(cur_l, nxt_l);
         }
@@ -296,9 +441,20 @@ int scan_first_device(const int2* edges, int64_t E, int32_t V, char* ws, hipStre
                        W.zero_words);
     // components and adjacency
     components(W, edges, E, V, nullptr, s);
-    hipLaunchKernelGGL(k_adj_degree, dim3(grid_for(E)), dim3(kT), 0, s, edges, E, V, W.head);
-    device_scan1(W.head, (int64_t)V + 1, W.scan_status, W.fcount + 255, s);
-    hipLaunchKernelGGL(k_adj_fill, dim3(grid_for(E)), dim3(kT), 0, s, edges, E, V, (const int32_t*)W.head, W.cur, W.adj);
+    const BktPlan P = bucket_plan(V);
+    if (P.on) {
+        const int g = (int)std::max<int64_t>(1, std::min<int64_t>(kBktBlocks, (E + 1023) / 1024));
+        hipLaunchKernelGGL(k_bkt_count, dim3(g), dim3(kT), 0, s, edges, E, V, P.sh, P.nb, W.btot);
+        hipLaunchKernelGGL(k_bkt_scan, dim3(1), dim3(kT), 0, s, (const uint32_t*)W.btot, P.nb, W.bbase, W.bcur);
+        hipLaunchKernelGGL(k_bkt_scatter, dim3(g), dim3(kT), 0, s, edges, E, V, P.sh, P.nb, W.bcur, W.arcs);
+        hipLaunchKernelGGL(k_bkt_csr, dim3(P.nb), dim3(kT), 0, s, (const int2*)W.arcs, (const uint32_t*)W.bbase, V, P.sh,
+                           W.head, W.adj);
+    } else {
+        hipLaunchKernelGGL(k_adj_degree, dim3(grid_for(E)), dim3(kT), 0, s, edges, E, V, W.head);
+        device_scan1(reinterpret_cast<int32_t*>(W.head), (int64_t)V + 1, W.scan_status, W.fcount + 255, s);
+        hipLaunchKernelGGL(k_adj_fill, dim3(grid_for(E)), dim3(kT), 0, s, edges, E, V, (const uint32_t*)W.head, W.cur,
+                           W.adj);
+    }
     BR_HIP(hipGetLastError());
     // F: breadth-first forest of G
     int rc = bfs_forest(W, V, nullptr, W.par1, W.f1, W.nout, s, h_small, levels1);

@@ -110,3 +110,19 @@ def test_same_answer_on_permuted_inputs(ctx):
         relabel = rng.permutation(g.V).astype(np.int32)
         got = ctx.articulation_points(dev(relabel[e]), g.V)
         assert np.array_equal(np.sort(got), np.sort(relabel[want]))
+
+
+@pytest.mark.parametrize("V", [1 << 25, (1 << 25) + 4096], ids=["bucketed_limit", "direct_build"])
+def test_random_recursive_tree_at_the_bucket_limit(ctx, V):
+    # 2^25 vertices is the most the bucketed adjacency build takes (4,096
+    # buckets of 8,192); past it the direct build runs.  A random recursive
+    # tree, relabelled: its cut vertices are exactly its vertices of degree >= 2.
+    rng = np.random.default_rng(64)
+    i = np.arange(1, V, dtype=np.int64)
+    par = (rng.random(V - 1) * i).astype(np.int64)
+    relabel = rng.permutation(V).astype(np.int32)
+    e = np.stack([relabel[par], relabel[i]], 1)
+    deg = np.bincount(e.ravel(), minlength=V)
+    say("articulation random recursive tree V=%d" % V)
+    got = ctx.articulation_points(dev(e), V)
+    assert np.array_equal(got, np.flatnonzero(deg >= 2))
