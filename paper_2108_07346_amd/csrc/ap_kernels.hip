@@ -263,14 +263,17 @@ __global__ void k_adj_fill(const int2* edges, int64_t E, int32_t V, const uint32
     }
 }
 
+// A level list holds one int4 per vertex: (vertex, first arc, end of its arcs, 0),
+// so that a level's wavefront goes from its list entry straight to the arcs.
+
 // search start: the root of every component is level 0 and the first frontier
-__global__ void k_bfs_start(const uint32_t* q, int32_t V, int32_t* par, uint64_t* cand, int32_t* frontier,
-                            uint32_t* fcount) {
+__global__ void k_bfs_start(const uint32_t* q, int32_t V, const uint32_t* head, int32_t* par, uint64_t* cand,
+                            int4* frontier, uint32_t* fcount) {
     GRID_LOOP(v, (int64_t)V) {
         const bool root = q[v] == 0;
         par[v] = -1;
         cand[v] = root ? 0 : kNoCand;
-        if (root) frontier[atomicAdd(fcount, 1u)] = (int32_t)v;
+        if (root) frontier[atomicAdd(fcount, 1u)] = make_int4((int32_t)v, (int32_t)head[v], (int32_t)head[v + 1], 0);
     }
 }
 
@@ -278,22 +281,28 @@ __global__ void k_bfs_start(const uint32_t* q, int32_t V, int32_t* par, uint64_t
 // from the candidate word) goes to slot base_d + (w's place in the level),
 // base_d being the number of tree edges of the earlier levels (kept in
 // base[d & 1]; block 0 writes base[(d + 1) & 1]); then its offers to the
-// neighbours, newly reached ones appended with one reservation per wavefront
-__global__ void k_bfs_level(const int32_t* level_list, const uint32_t* count, uint32_t* count_after_next, int32_t d,
-                            uint32_t* base, const uint32_t* head, const int32_t* adj, const int32_t* par1, uint64_t* cand,
-                            int32_t* par, int32_t* next_list, uint32_t* next_count, int2* out, int64_t cap,
-                            uint32_t* err) {
+// neighbours, newly reached ones appended with one reservation per wavefront.
+// A wavefront's first list entry is loaded together with the level size (the
+// list has room for V entries; entries past the level are stale and unused),
+// and a neighbour's arc range is loaded together with the offer, so a level
+// costs one dependent load fewer per step.
+__global__ void k_bfs_level(const int4* level_list, const uint32_t* count, uint32_t* count_after_next, int32_t d,
+                            int32_t V, uint32_t* base, const uint32_t* head, const int32_t* adj, const int32_t* par1,
+                            uint64_t* cand, int32_t* par, int4* next_list, uint32_t* next_count, int2* out,
+                            int64_t cap, uint32_t* err) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int4 first = wave < V ? level_list[wave] : make_int4(0, 0, 0, 0);
     const uint32_t n = *count;
     const uint32_t b0 = base[d & 1];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         *count_after_next = 0;                       // the count level d + 2 will use
         base[(d + 1) & 1] = b0 + (d > 0 ? n : 0u);
     }
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t f = wave; f < n; f += waves) {
-        const int32_t w = level_list[f];
+        const int4 it = f == wave ? first : level_list[f];
+        const int32_t w = it.x;
         if (d > 0 && lane == 0) {
             const int32_t p = (int32_t)(cand[w] & 0xffffffffu);
             par[w] = p;
@@ -302,16 +311,20 @@ __global__ void k_bfs_level(const int32_t* level_list, const uint32_t* count, ui
             else atomicOr(err, 2u);
         }
         const uint64_t mine = ((uint64_t)(uint32_t)d << 32) | (uint32_t)w;
-        const int64_t h0 = head[w], h1 = head[w + 1];
+        const int64_t h0 = (uint32_t)it.y, h1 = (uint32_t)it.z;
         for (int64_t kb = h0; kb < h1; kb += 64) {
             const int64_t k = kb + lane;
             bool got = false;
             int32_t x = 0;
+            uint32_t x0 = 0, x1 = 0;
             if (k < h1) {
                 x = adj[k];
-                if (!excluded(par1, w, x) && cand[x] > mine)
+                if (!excluded(par1, w, x) && cand[x] > mine) {
+                    x0 = head[x];
+                    x1 = head[x + 1];
                     got = atomicMin(reinterpret_cast<unsigned long long*>(cand + x), (unsigned long long)mine) ==
                           (unsigned long long)kNoCand;
+                }
             }
             const uint64_t m = __ballot(got);
             if (m) {
@@ -319,7 +332,9 @@ __global__ void k_bfs_level(const int32_t* level_list, const uint32_t* count, ui
                 uint32_t at = 0;
                 if (lane == leader) at = atomicAdd(next_count, (uint32_t)__popcll(m));
                 at = __shfl(at, leader);
-                if (got) next_list[at + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = x;
+                if (got)
+                    next_list[at + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
+                        make_int4(x, (int32_t)x0, (int32_t)x1, 0);
             }
         }
     }
@@ -348,7 +363,8 @@ static BktPlan bucket_plan(int32_t V) {
 // Workspace words (4-byte) for the scan-first certificate of E edges on V vertices.
 struct ApWs {
     uint32_t *q, *fcount, *err, *nout, *head, *cur, *btot, *bbase, *bcur;
-    int32_t *par1, *par2, *fa, *fb, *adj;
+    int32_t *par1, *par2, *adj;
+    int4 *fa, *fb;
     uint64_t *cand, *scan_status;
     int2 *arcs, *f1, *f2;
     int64_t zero_words, words;
@@ -373,8 +389,8 @@ static ApWs ap_carve(char* base, int64_t E, int32_t V) {
     w.bcur = reinterpret_cast<uint32_t*>(take(4 * (int64_t)kMaxBuckets));
     w.par1 = reinterpret_cast<int32_t*>(take(4 * (int64_t)V));
     w.par2 = reinterpret_cast<int32_t*>(take(4 * (int64_t)V));
-    w.fa = reinterpret_cast<int32_t*>(take(4 * (int64_t)V));
-    w.fb = reinterpret_cast<int32_t*>(take(4 * (int64_t)V));
+    w.fa = reinterpret_cast<int4*>(take(16 * (int64_t)V));
+    w.fb = reinterpret_cast<int4*>(take(16 * (int64_t)V));
     w.cand = reinterpret_cast<uint64_t*>(take(8 * (int64_t)V));
     w.f1 = reinterpret_cast<int2*>(take(8 * (int64_t)std::max(V, 1)));
     w.f2 = reinterpret_cast<int2*>(take(8 * (int64_t)std::max(V, 1)));
@@ -393,14 +409,15 @@ static int bfs_forest(const ApWs& W, int32_t V, const int32_t* par1, int32_t* pa
                       hipStream_t s, uint32_t* h_count, int* levels) {
     // fcount[0..127]: level sizes (ring), fcount[128..129]: tree edges before the level (ping-pong)
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kT), 0, s, W.fcount, (int64_t)130);
-    hipLaunchKernelGGL(k_bfs_start, dim3(grid_for(V)), dim3(kT), 0, s, W.q, V, par, W.cand, W.fa, W.fcount);
-    int32_t *cur_l = W.fa, *nxt_l = W.fb;
+    hipLaunchKernelGGL(k_bfs_start, dim3(grid_for(V)), dim3(kT), 0, s, W.q, V, (const uint32_t*)W.head, par, W.cand, W.fa,
+                       W.fcount);
+    int4 *cur_l = W.fa, *nxt_l = W.fb;
     int d = 0;
     constexpr int kGroup = 16;
     for (;;) {
         for (int k = 0; k < kGroup && d < V; k++, d++) {
-            hipLaunchKernelGGL(k_bfs_level, dim3(2048), dim3(kT), 0, s, (const int32_t*)cur_l,
-                               (const uint32_t*)(W.fcount + d % 128), W.fcount + (d + 2) % 128, d, W.fcount + 128,
+            hipLaunchKernelGGL(k_bfs_level, dim3(2048), dim3(kT), 0, s, (const int4*)cur_l,
+                               (const uint32_t*)(W.fcount + d % 128), W.fcount + (d + 2) % 128, d, V, W.fcount + 128,
                                (const uint32_t*)W.head, (const int32_t*)W.adj, par1, W.cand, par, nxt_l,
                                W.fcount + (d + 1) % 128, out, (int64_t)V, W.err);
             std::swap(cur_l, nxt_l);
