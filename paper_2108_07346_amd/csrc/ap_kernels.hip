@@ -22,6 +22,8 @@
 // neighbours, and the first touch of a neighbour appends it to level d + 1.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+
 #include "internal.hpp"
 
 namespace br {
@@ -186,7 +188,7 @@ __global__ void __launch_bounds__(kT) k_bkt_count(const int2* edges, int64_t E, 
         if (h[b]) atomicAdd(&total[b], h[b]);
 }
 
-// total[0..nb) -> base[0..nb] (exclusive, base[nb] = all arcs) and cur = base
+// totals -> base[0..nb] (exclusive, base[nb] = all arcs) and the cursors = base
 __global__ void __launch_bounds__(kT) k_bkt_scan(const uint32_t* total, int nb, uint32_t* base, uint32_t* cur) {
     __shared__ uint32_t v[kMaxBuckets];
     __shared__ uint32_t part[kT];
@@ -265,85 +267,249 @@ __global__ void k_adj_fill(const int2* edges, int64_t E, int32_t V, const uint32
 
 // A level list holds one int4 per vertex: (vertex, first arc, end of its arcs, 0),
 // so that a level's wavefront goes from its list entry straight to the arcs.
+// Level counters are 64-bit words (arcs << 30 | vertices): the vertices of a
+// level and the sum of their degrees, the latter choosing how the next level
+// is found.  V <= 2^29 keeps the vertex count below bit 30 and 2E < 2^32 keeps
+// the arc sum below bit 62.
+constexpr int kCountBits = 30;
+constexpr uint64_t kCountMask = (uint64_t(1) << kCountBits) - 1;
+constexpr int kUpG = 16;    // lanes per vertex in a bottom-up level
+constexpr int kUpU = 8;     // arcs per lane loaded together in a bottom-up level
 
-// search start: the root of every component is level 0 and the first frontier
-__global__ void k_bfs_start(const uint32_t* q, int32_t V, const uint32_t* head, int32_t* par, uint64_t* cand,
-                            int4* frontier, uint32_t* fcount) {
-    GRID_LOOP(v, (int64_t)V) {
-        const bool root = q[v] == 0;
-        par[v] = -1;
-        cand[v] = root ? 0 : kNoCand;
-        if (root) frontier[atomicAdd(fcount, 1u)] = make_int4((int32_t)v, (int32_t)head[v], (int32_t)head[v + 1], 0);
+// Returning atomics to one address are serialised at the memory side (about
+// 12 ns each on MI355X, measured), so a level appends its newly reached
+// vertices with one reservation per block, not per wavefront: a block of
+// kLvT threads stages them in LDS and reserves its run once at its end; only
+// a block whose LDS run is full reserves per wavefront for the rest.
+constexpr int kLvT = 1024;
+constexpr int kLvBlocks = 256;
+constexpr int kLvBuf = 2048;
+
+struct LevelLds {
+    int4 buf[kLvBuf];
+    uint32_t n, fail, arcs;
+    uint32_t base;
+};
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t lane_rank(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ void lds_begin(LevelLds& L) {
+    if (threadIdx.x == 0) {
+        L.n = 0;
+        L.fail = kLvBuf;
+        L.arcs = 0;
+    }
+    __syncthreads();
+}
+
+// one wavefront step (whole wavefront active, m = ballot(add) != 0): the lanes
+// with `add` stage (item, degree deg)
+__device__ __forceinline__ void lds_stage(LevelLds& L, bool add, int4 item, uint32_t deg, uint64_t m,
+                                          unsigned long long* ring, int4* list) {
+    const uint32_t sum = wave_sum(add ? deg : 0u);
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    const uint32_t cnt = (uint32_t)__popcll(m);
+    uint32_t at = 0;
+    if (lane == leader) at = atomicAdd(&L.n, cnt);
+    at = __shfl(at, leader);
+    if (at + cnt <= (uint32_t)kLvBuf) {
+        if (lane == leader) atomicAdd(&L.arcs, sum);
+        if (add) L.buf[at + lane_rank(m)] = item;
+    } else {
+        // LDS run full: this and every later step of the block reserve on their own
+        uint32_t g = 0;
+        if (lane == leader) {
+            atomicMin(&L.fail, at);
+            g = (uint32_t)(atomicAdd(ring, ((unsigned long long)sum << kCountBits) | (unsigned long long)cnt) & kCountMask);
+        }
+        g = __shfl(g, leader);
+        if (add) list[g + lane_rank(m)] = item;
     }
 }
 
-// level d: one wavefront per vertex w of the level -- its tree edge (parent
-// from the candidate word) goes to slot base_d + (w's place in the level),
-// base_d being the number of tree edges of the earlier levels (kept in
-// base[d & 1]; block 0 writes base[(d + 1) & 1]); then its offers to the
-// neighbours, newly reached ones appended with one reservation per wavefront.
-// A wavefront's first list entry is loaded together with the level size (the
-// list has room for V entries; entries past the level are stale and unused),
-// and a neighbour's arc range is loaded together with the offer, so a level
-// costs one dependent load fewer per step.
-__global__ void k_bfs_level(const int4* level_list, const uint32_t* count, uint32_t* count_after_next, int32_t d,
-                            int32_t V, uint32_t* base, const uint32_t* head, const int32_t* adj, const int32_t* par1,
-                            uint64_t* cand, int32_t* par, int4* next_list, uint32_t* next_count, int2* out,
-                            int64_t cap, uint32_t* err) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const int4 first = wave < V ? level_list[wave] : make_int4(0, 0, 0, 0);
-    const uint32_t n = *count;
-    const uint32_t b0 = base[d & 1];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        *count_after_next = 0;                       // the count level d + 2 will use
-        base[(d + 1) & 1] = b0 + (d > 0 ? n : 0u);
-    }
-    for (int64_t f = wave; f < n; f += waves) {
-        const int4 it = f == wave ? first : level_list[f];
-        const int32_t w = it.x;
-        if (d > 0 && lane == 0) {
-            const int32_t p = (int32_t)(cand[w] & 0xffffffffu);
-            par[w] = p;
-            const int64_t pos = (int64_t)b0 + f;
-            if (pos < cap) out[pos] = make_int2(p, w);
-            else atomicOr(err, 2u);
+// every thread of the block: LDS entries [0, min(n, fail)) are all written
+// (steps succeed in order until the first that does not fit); one reservation
+__device__ __forceinline__ void lds_flush(LevelLds& L, unsigned long long* ring, int4* list) {
+    __syncthreads();
+    const uint32_t stored = min(L.n, L.fail);
+    if (threadIdx.x == 0 && stored)
+        L.base = (uint32_t)(atomicAdd(ring, ((unsigned long long)L.arcs << kCountBits) | (unsigned long long)stored) &
+                            kCountMask);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < stored; i += blockDim.x) list[L.base + i] = L.buf[i];
+}
+
+// search start: the root of every component is level 0 and the first frontier;
+// block b takes the vertices [V b / G, V (b + 1) / G)
+__global__ void __launch_bounds__(kLvT) k_bfs_start(const uint32_t* q, int32_t V, const uint32_t* head, int32_t* par,
+                                                    uint64_t* cand, int32_t* lvl, int4* frontier,
+                                                    unsigned long long* ring) {
+    __shared__ LevelLds L;
+    lds_begin(L);
+    const int64_t lo = (int64_t)V * blockIdx.x / gridDim.x, hi = (int64_t)V * (blockIdx.x + 1) / gridDim.x;
+    // whole wavefronts run the loop (staging is a wavefront operation)
+    const int64_t end = lo + ((hi - lo + 63) & ~int64_t(63));
+    for (int64_t v = lo + threadIdx.x; v < end; v += kLvT) {
+        const bool in = v < hi;
+        const bool root = in && q[v] == 0;
+        uint32_t h0 = 0, h1 = 0;
+        if (in) {
+            par[v] = -1;
+            cand[v] = root ? 0 : kNoCand;
+            lvl[v] = root ? 0 : -1;
         }
-        const uint64_t mine = ((uint64_t)(uint32_t)d << 32) | (uint32_t)w;
-        const int64_t h0 = (uint32_t)it.y, h1 = (uint32_t)it.z;
-        for (int64_t kb = h0; kb < h1; kb += 64) {
-            const int64_t k = kb + lane;
-            bool got = false;
-            int32_t x = 0;
-            uint32_t x0 = 0, x1 = 0;
-            if (k < h1) {
-                x = adj[k];
-                if (!excluded(par1, w, x) && cand[x] > mine) {
-                    x0 = head[x];
-                    x1 = head[x + 1];
-                    got = atomicMin(reinterpret_cast<unsigned long long*>(cand + x), (unsigned long long)mine) ==
-                          (unsigned long long)kNoCand;
+        if (root) {
+            h0 = head[v];
+            h1 = head[v + 1];
+        }
+        const uint64_t m = __ballot(root);
+        if (m) lds_stage(L, root, make_int4((int32_t)v, (int32_t)h0, (int32_t)h1, 0), h1 - h0, m, ring, frontier);
+    }
+    lds_flush(L, ring, frontier);
+}
+
+// Level d finds level d + 1 top-down or bottom-up, whichever costs less: the
+// top-down pass scans the level's arcs (mf), often with a 64-bit atomic each,
+// the bottom-up pass the arcs of the unvisited vertices (mu) with two loads
+// each, after one look at every vertex; bottom-up is taken when
+// mu + V/4 < 4 mf.  acc[0..1] (ping-pong by d) hold the tree edges emitted
+// before level d, acc[2..3] the arcs of the levels before d; block 0 writes
+// the values for d + 1 and clears the counter level d + 2 will use.
+//
+// Top-down: one wavefront per vertex w of the level -- its tree edge (parent
+// from the candidate word) goes to slot base_d + (w's place in the level);
+// then its offers to the neighbours by 64-bit atomic minimum of
+// (d << 32 | w), the first touch of a neighbour reaching it.  A wavefront's
+// first list entry is loaded together with the level counter (the list has
+// room for V entries; entries past the level are stale and unused), and a
+// neighbour's arc range together with the offer.
+//
+// Bottom-up: the level's tree edges are emitted one per thread; then kUpG
+// lanes per unvisited vertex x scan its arcs for neighbours of level d (F's
+// vertex pairs excluded in F'), kUpU arcs per lane loaded together, and the
+// smallest one becomes x's parent -- the same choice the atomic minimum makes.
+// Only x's own lanes write x's words.
+__global__ void __launch_bounds__(kLvT) k_bfs_level(const int4* level_list, unsigned long long* ring, int32_t d,
+                                                    int32_t V, uint64_t* acc, const uint32_t* head, const int32_t* adj,
+                                                    const int32_t* par1, uint64_t* cand, int32_t* lvl, int32_t* par,
+                                                    int4* next_list, int2* out, int64_t cap, uint32_t* err) {
+    __shared__ LevelLds L;
+    const int lane = threadIdx.x & 63;
+    const int64_t gtid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t threads = (int64_t)gridDim.x * blockDim.x;
+    const int64_t wave = gtid >> 6;
+    const int64_t waves = threads >> 6;
+    const int4 first = wave < V ? level_list[wave] : make_int4(0, 0, 0, 0);
+    const uint64_t cw = ring[d % 128];
+    const uint32_t n = (uint32_t)(cw & kCountMask);
+    const uint64_t mf = cw >> kCountBits;
+    const uint64_t b0 = acc[d & 1], seen = acc[2 + (d & 1)];
+    const uint64_t mu = (uint64_t)head[V] - seen - mf;      // arcs of the vertices in no level up to d
+    unsigned long long* next = ring + (d + 1) % 128;
+    if (gtid == 0) {
+        ring[(d + 2) % 128] = 0;
+        acc[(d + 1) & 1] = b0 + (d > 0 ? n : 0u);
+        acc[2 + ((d + 1) & 1)] = seen + mf;
+    }
+    if (n == 0) return;         // the same for every thread
+    lds_begin(L);
+    if (mu + ((uint64_t)V >> 2) >= 4 * mf) {
+        // ---- top-down
+        for (int64_t f = wave; f < n; f += waves) {
+            const int4 it = f == wave ? first : level_list[f];
+            const int32_t w = it.x;
+            if (d > 0 && lane == 0) {
+                const int32_t p = (int32_t)(cand[w] & 0xffffffffu);
+                par[w] = p;
+                const int64_t pos = (int64_t)b0 + f;
+                if (pos < cap) out[pos] = make_int2(p, w);
+                else atomicOr(err, 2u);
+            }
+            const uint64_t mine = ((uint64_t)(uint32_t)d << 32) | (uint32_t)w;
+            const int64_t h0 = (uint32_t)it.y, h1 = (uint32_t)it.z;
+            for (int64_t kb = h0; kb < h1; kb += 64) {
+                const int64_t k = kb + lane;
+                bool got = false;
+                int32_t x = 0;
+                uint32_t x0 = 0, x1 = 0;
+                if (k < h1) {
+                    x = adj[k];
+                    if (!excluded(par1, w, x) && cand[x] > mine) {
+                        x0 = head[x];
+                        x1 = head[x + 1];
+                        got = atomicMin(reinterpret_cast<unsigned long long*>(cand + x), (unsigned long long)mine) ==
+                              (unsigned long long)kNoCand;
+                    }
+                }
+                const uint64_t m = __ballot(got);
+                if (m) {
+                    if (got) lvl[x] = d + 1;
+                    lds_stage(L, got, make_int4(x, (int32_t)x0, (int32_t)x1, 0), x1 - x0, m, next, next_list);
                 }
             }
-            const uint64_t m = __ballot(got);
-            if (m) {
-                const int leader = __ffsll((unsigned long long)m) - 1;
-                uint32_t at = 0;
-                if (lane == leader) at = atomicAdd(next_count, (uint32_t)__popcll(m));
-                at = __shfl(at, leader);
-                if (got)
-                    next_list[at + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
-                        make_int4(x, (int32_t)x0, (int32_t)x1, 0);
+        }
+    } else {
+        // ---- bottom-up
+        if (d > 0) {
+            for (int64_t f = gtid; f < n; f += threads) {
+                const int32_t w = level_list[f].x;
+                const int32_t p = (int32_t)(cand[w] & 0xffffffffu);
+                par[w] = p;
+                const int64_t pos = (int64_t)b0 + f;
+                if (pos < cap) out[pos] = make_int2(p, w);
+                else atomicOr(err, 2u);
             }
         }
+        const int sub = lane & (kUpG - 1);
+        // whole wavefronts run the loop: groups past V idle through the last turn
+        const int64_t groups = threads / kUpG;
+        const int64_t end = ((int64_t)V + 64 / kUpG - 1) / (64 / kUpG) * (64 / kUpG);
+        for (int64_t x = gtid / kUpG; x < end; x += groups) {
+            uint32_t best = 0xffffffffu, h0 = 0, h1 = 0;
+            if (x < V && lvl[x] < 0) {
+                h0 = head[x];
+                h1 = head[x + 1];
+                const int32_t px = par1 ? par1[x] : -1;
+                // kUpU arcs per lane at a time: their loads, then their neighbours' words, issued together
+                for (int64_t kb = (int64_t)h0 + sub; kb < h1; kb += kUpG * kUpU) {
+                    int32_t y[kUpU], l[kUpU], py[kUpU];
+#pragma unroll
+                    for (int j = 0; j < kUpU; j++) y[j] = kb + j * kUpG < h1 ? adj[kb + j * kUpG] : -1;
+#pragma unroll
+                    for (int j = 0; j < kUpU; j++) {
+                        l[j] = y[j] >= 0 ? lvl[y[j]] : -1;
+                        py[j] = par1 && y[j] >= 0 ? par1[y[j]] : -1;
+                    }
+#pragma unroll
+                    for (int j = 0; j < kUpU; j++)
+                        if (l[j] == d && px != y[j] && py[j] != (int32_t)x && (uint32_t)y[j] < best) best = (uint32_t)y[j];
+                }
+            }
+            for (int o = 1; o < kUpG; o <<= 1) best = min(best, (uint32_t)__shfl_xor(best, o));
+            const bool found = sub == 0 && best != 0xffffffffu;
+            if (found) {
+                cand[x] = ((uint64_t)(uint32_t)d << 32) | best;
+                lvl[x] = d + 1;
+            }
+            const uint64_t m = __ballot(found);
+            if (m) lds_stage(L, found, make_int4((int32_t)x, (int32_t)h0, (int32_t)h1, 0), h1 - h0, m, next, next_list);
+        }
     }
+    lds_flush(L, next, next_list);
 }
 
 __global__ void k_zero_u32(uint32_t* p, int64_t n) { GRID_LOOP(i, n) p[i] = 0; }
 // roots of F (no BFS parent) flagged 0, every other vertex 1
 __global__ void k_root_flags(const int32_t* par1, int32_t V, uint32_t* flag) { GRID_LOOP(v, (int64_t)V) flag[v] = par1[v] < 0 ? 0u : 1u; }
-__global__ void k_copy_u32(const uint32_t* a, uint32_t* b) { if (threadIdx.x == 0) *b = *a; }
+__global__ void k_copy_lo(const uint64_t* a, uint32_t* b) { if (threadIdx.x == 0) *b = (uint32_t)*a; }
 
 }  // namespace
 
@@ -362,8 +528,9 @@ static BktPlan bucket_plan(int32_t V) {
 
 // Workspace words (4-byte) for the scan-first certificate of E edges on V vertices.
 struct ApWs {
-    uint32_t *q, *fcount, *err, *nout, *head, *cur, *btot, *bbase, *bcur;
-    int32_t *par1, *par2, *adj;
+    uint32_t *q, *ticket, *err, *nout, *head, *cur, *btot, *bbase, *bcur;
+    uint64_t* ring;
+    int32_t *par1, *par2, *adj, *lvl;
     int4 *fa, *fb;
     uint64_t *cand, *scan_status;
     int2 *arcs, *f1, *f2;
@@ -380,7 +547,8 @@ static ApWs ap_carve(char* base, int64_t E, int32_t V) {
     w.head = reinterpret_cast<uint32_t*>(take(4 * ((int64_t)V + 1)));
     w.cur = reinterpret_cast<uint32_t*>(take(P.on ? 4 : 4 * (int64_t)V));
     w.btot = reinterpret_cast<uint32_t*>(take(4 * (int64_t)kMaxBuckets));
-    w.fcount = reinterpret_cast<uint32_t*>(take(4 * 256));   // per-level frontier counts, then scan ticket
+    w.ring = reinterpret_cast<uint64_t*>(take(8 * 256));     // level counters (ring of 128), acc[4]
+    w.ticket = reinterpret_cast<uint32_t*>(take(4));          // ticket of the direct build's scan
     w.err = reinterpret_cast<uint32_t*>(take(256));           // [0] error, [1..2] |F|, |F'|
     w.scan_status = reinterpret_cast<uint64_t*>(take(8 * (((int64_t)V + 1 + 1023) / 1024)));
     w.zero_words = o / 4;
@@ -389,6 +557,7 @@ static ApWs ap_carve(char* base, int64_t E, int32_t V) {
     w.bcur = reinterpret_cast<uint32_t*>(take(4 * (int64_t)kMaxBuckets));
     w.par1 = reinterpret_cast<int32_t*>(take(4 * (int64_t)V));
     w.par2 = reinterpret_cast<int32_t*>(take(4 * (int64_t)V));
+    w.lvl = reinterpret_cast<int32_t*>(take(4 * (int64_t)V));
     w.fa = reinterpret_cast<int4*>(take(16 * (int64_t)V));
     w.fb = reinterpret_cast<int4*>(take(16 * (int64_t)V));
     w.cand = reinterpret_cast<uint64_t*>(take(8 * (int64_t)V));
@@ -407,28 +576,30 @@ int64_t scan_first_words(int64_t E, int32_t V) { return ap_carve(nullptr, E, V).
 // the host only checks the level size between groups.
 static int bfs_forest(const ApWs& W, int32_t V, const int32_t* par1, int32_t* par, int2* out, uint32_t* nout,
                       hipStream_t s, uint32_t* h_count, int* levels) {
-    // fcount[0..127]: level sizes (ring), fcount[128..129]: tree edges before the level (ping-pong)
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kT), 0, s, W.fcount, (int64_t)130);
-    hipLaunchKernelGGL(k_bfs_start, dim3(grid_for(V)), dim3(kT), 0, s, W.q, V, (const uint32_t*)W.head, par, W.cand, W.fa,
-                       W.fcount);
+    // ring[0..127]: level counters, ring[128..131]: acc (tree edges and arcs before the level, ping-pong)
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kT), 0, s, reinterpret_cast<uint32_t*>(W.ring), (int64_t)2 * 132);
+    const int gs = (int)std::max<int64_t>(1, std::min<int64_t>(kLvBlocks, ((int64_t)V + kLvT - 1) / kLvT));
+    hipLaunchKernelGGL(k_bfs_start, dim3(gs), dim3(kLvT), 0, s, W.q, V, (const uint32_t*)W.head, par, W.cand, W.lvl, W.fa,
+                       reinterpret_cast<unsigned long long*>(W.ring));
     int4 *cur_l = W.fa, *nxt_l = W.fb;
     int d = 0;
     constexpr int kGroup = 16;
     for (;;) {
         for (int k = 0; k < kGroup && d < V; k++, d++) {
-            hipLaunchKernelGGL(k_bfs_level, dim3(2048), dim3(kT), 0, s, (const int4*)cur_l,
-                               (const uint32_t*)(W.fcount + d % 128), W.fcount + (d + 2) % 128, d, V, W.fcount + 128,
-                               (const uint32_t*)W.head, (const int32_t*)W.adj, par1, W.cand, par, nxt_l,
-                               W.fcount + (d + 1) % 128, out, (int64_t)V, W.err);
+            hipLaunchKernelGGL(k_bfs_level, dim3(kLvBlocks), dim3(kLvT), 0, s, (const int4*)cur_l,
+                               reinterpret_cast<unsigned long long*>(W.ring), d, V, W.ring + 128, (const uint32_t*)W.head,
+                               (const int32_t*)W.adj, par1, W.cand, W.lvl, par, nxt_l, out, (int64_t)V, W.err);
             std::swap(cur_l, nxt_l);
         }
         BR_HIP(hipGetLastError());
-        BR_HIP(hipMemcpyAsync(h_count, W.fcount + d % 128, 4, hipMemcpyDeviceToHost, s));
+        BR_HIP(hipMemcpyAsync(h_count, W.ring + d % 128, 8, hipMemcpyDeviceToHost, s));
         BR_HIP(hipStreamSynchronize(s));
-        if (*h_count == 0 || d >= V) break;
+        uint64_t c = 0;
+        std::memcpy(&c, h_count, 8);
+        if ((c & kCountMask) == 0 || d >= V) break;
     }
-    // tree edges emitted = base after the last level that had vertices
-    hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(64), 0, s, W.fcount + 128 + (d & 1), nout);
+    // tree edges emitted = acc after the last level that had vertices
+    hipLaunchKernelGGL(k_copy_lo, dim3(1), dim3(64), 0, s, (const uint64_t*)(W.ring + 128 + (d & 1)), nout);
     *levels = d;
     return BR_OK;
 }
@@ -468,7 +639,7 @@ int scan_first_device(const int2* edges, int64_t E, int32_t V, char* ws, hipStre
                            W.head, W.adj);
     } else {
         hipLaunchKernelGGL(k_adj_degree, dim3(grid_for(E)), dim3(kT), 0, s, edges, E, V, W.head);
-        device_scan1(reinterpret_cast<int32_t*>(W.head), (int64_t)V + 1, W.scan_status, W.fcount + 255, s);
+        device_scan1(reinterpret_cast<int32_t*>(W.head), (int64_t)V + 1, W.scan_status, W.ticket, s);
         hipLaunchKernelGGL(k_adj_fill, dim3(grid_for(E)), dim3(kT), 0, s, edges, E, V, (const uint32_t*)W.head, W.cur,
                            W.adj);
     }

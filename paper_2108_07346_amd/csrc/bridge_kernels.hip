@@ -406,9 +406,62 @@ __device__ __forceinline__ void range_minmax(const Rmq& R, int32_t l, int32_t r,
     }
 }
 
+// Result keys leave a block through LDS with one reservation on *nout per
+// block: returning atomics to one address are serialised at the memory side
+// (about 12 ns each on MI355X, measured), so one per wavefront would cost more
+// than the test itself.  A block whose LDS run is full reserves per wavefront
+// for the rest.  Launched with at most kOutBlocks blocks.
+constexpr int kOutBuf = 2048;
+constexpr int kOutBlocks = 1024;
+
+struct OutLds {
+    uint64_t buf[kOutBuf];
+    uint32_t n, fail, base;
+};
+
+__device__ __forceinline__ void out_begin(OutLds& L) {
+    if (threadIdx.x == 0) {
+        L.n = 0;
+        L.fail = kOutBuf;
+    }
+    __syncthreads();
+}
+
+// the active lanes of a wavefront; m = ballot(add) != 0
+__device__ __forceinline__ void out_put(OutLds& L, bool add, uint64_t key, uint64_t m, uint64_t* out, uint32_t* nout) {
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    const uint32_t cnt = (uint32_t)__popcll(m);
+    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    uint32_t at = 0;
+    if (__lane_id() == leader) at = atomicAdd(&L.n, cnt);
+    at = __shfl(at, leader);
+    if (at + cnt <= (uint32_t)kOutBuf) {
+        if (add) L.buf[at + rank] = key;
+    } else {
+        uint32_t g = 0;
+        if (__lane_id() == leader) {
+            atomicMin(&L.fail, at);
+            g = atomicAdd(nout, cnt);
+        }
+        g = __shfl(g, leader);
+        if (add) out[g + rank] = key;
+    }
+}
+
+// every thread of the block: entries [0, min(n, fail)) are all written
+__device__ __forceinline__ void out_end(OutLds& L, uint64_t* out, uint32_t* nout) {
+    __syncthreads();
+    const uint32_t stored = min(L.n, L.fail);
+    if (threadIdx.x == 0 && stored) L.base = atomicAdd(nout, stored);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < stored; i += blockDim.x) out[L.base + i] = L.buf[i];
+}
+
 __global__ void k_bridges(const int2* f1, const uint32_t* q, int32_t qs, const int32_t* head, const int32_t* in_arc,
                           const int32_t* pre, const int32_t* sub, Rmq R, int32_t V, int64_t A, uint64_t* out,
                           uint32_t* nout) {
+    __shared__ OutLds L;
+    out_begin(L);
     GRID_LOOP(v, (int64_t)V) {
         bool br = false;
         uint64_t key = 0;
@@ -424,14 +477,9 @@ __global__ void k_bridges(const int2* f1, const uint32_t* q, int32_t qs, const i
             }
         }
         const uint64_t m = __ballot(br);
-        if (m) {
-            const int leader = __ffsll((unsigned long long)m) - 1;
-            uint32_t base = 0;
-            if (__lane_id() == leader) base = atomicAdd(nout, (uint32_t)__popcll(m));
-            base = __shfl(base, leader);
-            if (br) out[base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = key;
-        }
+        if (m) out_put(L, br, key, m, out, nout);
     }
+    out_end(L, out, nout);
 }
 
 // ---- articulation points of the certificate ------------------------------------
@@ -539,19 +587,16 @@ __global__ void k_tv_mark(const int2* f1, const uint32_t* q, int32_t qs, const i
 
 __global__ void k_tv_list(const uint32_t* q, int32_t qs, const int32_t* head, int32_t V, const int32_t* rmin,
                           const int32_t* rmax, const int32_t* apf, uint64_t* out, uint32_t* nout) {
+    __shared__ OutLds L;
+    out_begin(L);
     GRID_LOOP(v, (int64_t)V) {
         bool cut = false;
         if (head[v + 1] > head[v])
             cut = q[qs * (size_t)v] == 0 ? (rmax[v] >= 0 && rmin[v] != rmax[v]) : apf[v] != 0;
         const uint64_t m = __ballot(cut);
-        if (m) {
-            const int leader = __ffsll((unsigned long long)m) - 1;
-            uint32_t base = 0;
-            if (__lane_id() == leader) base = atomicAdd(nout, (uint32_t)__popcll(m));
-            base = __shfl(base, leader);
-            if (cut) out[base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = (uint64_t)v;
-        }
+        if (m) out_put(L, cut, (uint64_t)v, m, out, nout);
     }
+    out_end(L, out, nout);
 }
 
 // counters of the certificate and the result next to the keys, for one copy
@@ -685,7 +730,7 @@ int device_bridges_cert(const int2* f1, const int2* f2, int32_t dir, const uint3
     const int64_t A = 2 * (int64_t)std::max(V - 1, 1);
     Rmq R;
     const BridgeWs W = number_tree(f1, f2, dir, cnt, q, qs, V, max_tree, ws, s, &R);
-    hipLaunchKernelGGL(k_bridges, dim3(grid_for(V)), dim3(kT), 0, s, f1, q, qs, W.head, W.in_arc, W.pre, W.sub, R, V,
+    hipLaunchKernelGGL(k_bridges, dim3(std::min(grid_for(V), kOutBlocks)), dim3(kT), 0, s, f1, q, qs, W.head, W.in_arc, W.pre, W.sub, R, V,
                        A, W.keys, reinterpret_cast<uint32_t*>(W.misc + 1));
     *d_keys = W.keys;
     *d_n = reinterpret_cast<uint32_t*>(W.misc + 1);
@@ -709,7 +754,7 @@ int device_articulation_cert(const int2* f1, const int2* f2, int32_t dir, const 
     hipLaunchKernelGGL(k_tv_compress, dim3(grid_for(V)), dim3(kT), 0, s, g, V);
     hipLaunchKernelGGL(k_tv_mark, dim3(grid_for(V)), dim3(kT), 0, s, f1, q, qs, W.head, W.in_arc, V, A, (const uint32_t*)g,
                        W.tour_len, W.tree_n, W.posof);
-    hipLaunchKernelGGL(k_tv_list, dim3(grid_for(V)), dim3(kT), 0, s, q, qs, W.head, V, W.tour_len, W.tree_n, W.posof,
+    hipLaunchKernelGGL(k_tv_list, dim3(std::min(grid_for(V), kOutBlocks)), dim3(kT), 0, s, q, qs, W.head, V, W.tour_len, W.tree_n, W.posof,
                        W.keys, reinterpret_cast<uint32_t*>(W.misc + 1));
     *d_keys = W.keys;
     *d_n = reinterpret_cast<uint32_t*>(W.misc + 1);
