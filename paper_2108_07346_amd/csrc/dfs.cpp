@@ -108,7 +108,42 @@ void walk(const int32_t* head, const int2* arc, int32_t V, DfsScratch& S, std::v
     }
 }
 
-void canonical_sort(std::vector<uint64_t>& keys) { std::sort(keys.begin(), keys.end()); }
+// Keys are (a << 32 | b) with a < b < 2^31.  Packed into 2w bits (w = bits of
+// the largest field) and sorted least-significant digit first, digits of about
+// log2(n) bits; a handful of keys go through std::sort.
+void canonical_sort(std::vector<uint64_t>& keys) {
+    const size_t n = keys.size();
+    if (n < 64) {
+        std::sort(keys.begin(), keys.end());
+        return;
+    }
+    uint32_t all = 0;
+    for (const uint64_t k : keys) all |= (uint32_t)(k >> 32) | (uint32_t)k;
+    const int w = all ? 32 - __builtin_clz(all) : 1;
+    const uint64_t lo_mask = (uint64_t(1) << w) - 1;
+    int dbits = 6;
+    while (dbits < 11 && (size_t(1) << (dbits + 1)) <= n) dbits++;
+    const uint32_t dmask = (1u << dbits) - 1;
+    thread_local std::vector<uint64_t> tmp;
+    thread_local std::vector<uint32_t> cnt;
+    tmp.resize(n);
+    cnt.resize(size_t(1) << dbits);
+    for (size_t i = 0; i < n; i++) keys[i] = (keys[i] >> 32) << w | (keys[i] & 0xffffffffu);
+    uint64_t *src = keys.data(), *dst = tmp.data();
+    for (int sh = 0; sh < 2 * w; sh += dbits) {
+        std::fill(cnt.begin(), cnt.end(), 0u);
+        for (size_t i = 0; i < n; i++) cnt[(src[i] >> sh) & dmask]++;
+        uint32_t run = 0;
+        for (uint32_t& c : cnt) {
+            const uint32_t t = c;
+            c = run;
+            run += t;
+        }
+        for (size_t i = 0; i < n; i++) dst[cnt[(src[i] >> sh) & dmask]++] = src[i];
+        std::swap(src, dst);
+    }
+    for (size_t i = 0; i < n; i++) keys[i] = (src[i] >> w) << 32 | (src[i] & lo_mask);
+}
 
 
 }  // namespace br

@@ -80,3 +80,23 @@ def test_certificate_bridges_host_entry_matches_oracle():
         assert np.array_equal(br.certificate_bridges(e[:k], e[k:], V), oracle.bridges(e, V))
     with pytest.raises(br.BridgeError):
         br.certificate_bridges(np.array([[0, 3]]), np.zeros((0, 2)), 3)
+
+
+def test_certificate_bridges_many_keys():
+    # relabelled random recursive trees: every edge is a bridge, so the
+    # canonical ordering of many keys (the radix path) is checked against
+    # numpy's lexicographic sort; a chord per tree makes some edges non-bridges
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(1)
+    for V in (65, 1000, 70000, 300000):
+        i = np.arange(1, V, dtype=np.int64)
+        par = (rng.random(V - 1) * i).astype(np.int64)
+        relabel = rng.permutation(V).astype(np.int32)
+        e = relabel[np.stack([par, i], 1)]
+        s = np.sort(e, 1)
+        want = s[np.lexsort((s[:, 1], s[:, 0]))]
+        assert np.array_equal(br.certificate_bridges(e, np.zeros((0, 2), np.int32), V), want)
+        chord = np.array([[relabel[0], relabel[V - 1]]], dtype=np.int32)
+        if V <= 70000:
+            assert np.array_equal(br.certificate_bridges(e, chord, V), oracle.bridges(np.concatenate([e, chord]), V))
