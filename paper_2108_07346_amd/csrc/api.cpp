@@ -50,6 +50,10 @@ Plan make_plan(int64_t E, int32_t V, int32_t M) {
     for (int64_t b : {2 * (int64_t)V, 8 * (int64_t)V})
         if (b < per) P.stages.push_back(b);
     P.stages.push_back(per);
+    // state layout: one vertex per 32 bytes while all M states stay within
+    // 64 MB (measured faster at M = 1 and 16 on the dense workload), packed
+    // 8 bytes per vertex otherwise (more chunks: capacity wins)
+    P.qs = (int64_t)M * V * 32 <= (int64_t(64) << 20) ? 8 : 2;
     auto lo = [&](int64_t i) { return i * (E / M) + (i * (E % M)) / M; };
     const int64_t bound = 2 * (int64_t(V) - 1);
     P.off.resize(M);
@@ -109,7 +113,7 @@ static Layout layout(const Plan& P, bool device_final) {
     size_t o = 0;
     L.err = o; o += 256;
     L.cnt = o; o = align256(o + sizeof(uint32_t) * 2 * (size_t)P.M);
-    L.state = o; o = align256(o + sizeof(uint32_t) * 2 * (size_t)P.V * (size_t)P.M);
+    L.state = o; o = align256(o + sizeof(uint32_t) * (size_t)P.qs * (size_t)P.V * (size_t)P.M);
     L.cert = o; o = align256(o + sizeof(int2) * (size_t)std::max<int64_t>(P.cert_pairs, 1));
     L.off = o; o = align256(o + sizeof(int64_t) * (size_t)P.M);
     L.cap = o; o = align256(o + sizeof(int64_t) * (size_t)P.M);
@@ -146,6 +150,7 @@ int run_certificate(br_ctx* c, const int32_t* d_a, int64_t Ea, const int32_t* d_
     B.err = reinterpret_cast<uint32_t*>(base + L.err);
     B.cnt = reinterpret_cast<uint32_t*>(base + L.cnt);
     B.state = reinterpret_cast<uint32_t*>(base + L.state);
+    B.qs = P.qs;
     B.cert = reinterpret_cast<int2*>(base + L.cert);
     B.off = reinterpret_cast<const int64_t*>(base + L.off);
     B.cap = reinterpret_cast<const int64_t*>(base + L.cap);

@@ -766,7 +766,7 @@ int device_articulation_cert(const int2* f1, const int2* f2, int32_t dir, const 
 int device_bridges(const Plan& P, const DevBufs& B, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s) {
     const int2* f1 = B.cert + P.off[0];
     const int2* f2 = B.cert + P.off[0] + P.cap[0] - 1;
-    const int rc = device_bridges_cert(f1, f2, -1, B.cnt, B.state, 2, P.V, P.V, ws, d_keys, d_n, s);
+    const int rc = device_bridges_cert(f1, f2, -1, B.cnt, B.state, (int32_t)B.qs, P.V, P.V, ws, d_keys, d_n, s);
     if (rc) return rc;
     launch_bridge_status(B.cnt, B.err, *d_n, s);
     return BR_OK;

@@ -2,8 +2,11 @@
 // pairwise merge rounds of the phase tree (paper, Section III; Algorithm 2).
 //
 // Union-find state.  For every vertex x and forest f (0 = F, 1 = F') one
-// 32-bit word q[2x+f] holds x - parent(x); 0 marks a root, so a zero-filled
-// buffer is the all-singletons state.  Parents always have smaller ids than
+// 32-bit word q[qs*x+f] holds x - parent(x); 0 marks a root, so a zero-filled
+// buffer is the all-singletons state.  qs = 2 packs 16 vertices into a
+// 128-byte line; qs = 8 gives each vertex 32 bytes, so that a hook (a swap
+// performed at the memory side, which takes the line out of L2) disturbs the
+// words of fewer other vertices -- faster where the whole state stays small.  Parents always have smaller ids than
 // their children (a root is hooked under the smaller root), which makes
 // every pointer chain strictly decreasing and the structure acyclic.
 //
@@ -48,29 +51,29 @@ __device__ __forceinline__ uint64_t ld2(const uint32_t* p) {
 
 // representative of x in forest F (path halving on the way)
 template <int F>
-__device__ __forceinline__ uint32_t uf_find(uint32_t* q, uint32_t x) {
-    uint32_t d = ld(q + 2 * (size_t)x + F);
+__device__ __forceinline__ uint32_t uf_find(uint32_t* q, int64_t qs, uint32_t x) {
+    uint32_t d = ld(q + qs * (int64_t)x + F);
     while (d != 0) {
         const uint32_t p = x - d;
-        const uint32_t dp = ld(q + 2 * (size_t)p + F);
+        const uint32_t dp = ld(q + qs * (int64_t)p + F);
         if (dp == 0) return p;
-        st(q + 2 * (size_t)x + F, d + dp);   // x now points at its grandparent
+        st(q + qs * (int64_t)x + F, d + dp);   // x now points at its grandparent
         x = p - dp;
-        d = ld(q + 2 * (size_t)x + F);
+        d = ld(q + qs * (int64_t)x + F);
     }
     return x;
 }
 
 // true iff this call merged the components of u and v in forest F
 template <int F>
-__device__ __forceinline__ bool uf_unite(uint32_t* q, uint32_t u, uint32_t v) {
+__device__ __forceinline__ bool uf_unite(uint32_t* q, int64_t qs, uint32_t u, uint32_t v) {
     for (;;) {
-        u = uf_find<F>(q, u);
-        v = uf_find<F>(q, v);
+        u = uf_find<F>(q, qs, u);
+        v = uf_find<F>(q, qs, v);
         if (u == v) return false;
         if (u < v) { const uint32_t t = u; u = v; v = t; }
         uint32_t expect = 0;
-        if (__hip_atomic_compare_exchange_strong(q + 2 * (size_t)u + F, &expect, u - v, __ATOMIC_RELAXED,
+        if (__hip_atomic_compare_exchange_strong(q + qs * (int64_t)u + F, &expect, u - v, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             return true;
         u = u - expect;   // u was hooked meanwhile: continue from its parent
@@ -79,14 +82,14 @@ __device__ __forceinline__ bool uf_unite(uint32_t* q, uint32_t u, uint32_t v) {
 
 // Offer edge (u,v) to F, then (if rejected) to F'.  s1u.. are the endpoints'
 // parent words loaded together (one 8-byte load per endpoint).
-__device__ __forceinline__ void offer(uint32_t* q, uint32_t u, uint32_t v, bool& a1, bool& a2) {
-    const uint64_t su = ld2(q + 2 * (size_t)u), sv = ld2(q + 2 * (size_t)v);
+__device__ __forceinline__ void offer(uint32_t* q, int64_t qs, uint32_t u, uint32_t v, bool& a1, bool& a2) {
+    const uint64_t su = ld2(q + qs * (int64_t)u), sv = ld2(q + qs * (int64_t)v);
     const uint32_t p1u = u - (uint32_t)su, p1v = v - (uint32_t)sv;
-    a1 = (p1u != p1v) && uf_unite<0>(q, p1u, p1v);
+    a1 = (p1u != p1v) && uf_unite<0>(q, qs, p1u, p1v);
     a2 = false;
     if (!a1) {
         const uint32_t p2u = u - (uint32_t)(su >> 32), p2v = v - (uint32_t)(sv >> 32);
-        a2 = (p2u != p2v) && uf_unite<1>(q, p2u, p2v);
+        a2 = (p2u != p2v) && uf_unite<1>(q, qs, p2u, p2v);
     }
 }
 
@@ -174,14 +177,14 @@ __global__ void __launch_bounds__(kBlock) k_phase0(DevBufs B, int64_t E, int32_t
     if (t0 >= t1) return;
     __shared__ Stage S;
     stage_reset(S);
-    uint32_t* q = B.state + (size_t)c * 2 * (size_t)V;
+    uint32_t* q = B.state + (size_t)c * (size_t)B.qs * (size_t)V;
     for (int64_t base = t0; base < t1; base += kBlock) {
         const int64_t i = base + threadIdx.x;
         bool a1 = false, a2 = false;
         int2 e = make_int2(0, 0);
         if (i < t1) {
             e = i < B.split ? B.edges[i] : B.edges2[i - B.split];
-            if ((uint32_t)e.x < (uint32_t)V && (uint32_t)e.y < (uint32_t)V) offer(q, (uint32_t)e.x, (uint32_t)e.y, a1, a2);
+            if ((uint32_t)e.x < (uint32_t)V && (uint32_t)e.y < (uint32_t)V) offer(q, B.qs, (uint32_t)e.x, (uint32_t)e.y, a1, a2);
             else atomicOr(B.err, 1u);
         }
         stage_put(S, a1, a2, e);
@@ -208,14 +211,14 @@ __global__ void __launch_bounds__(kBlock) k_merge(DevBufs B, int32_t V, int32_t 
     if (t0 >= t1) return;
     __shared__ Stage S;
     stage_reset(S);
-    uint32_t* q = B.state + (size_t)i * 2 * (size_t)V;
+    uint32_t* q = B.state + (size_t)i * (size_t)B.qs * (size_t)V;
     for (int64_t base = t0; base < t1; base += kBlock) {
         const int64_t k = base + threadIdx.x;
         bool a1 = false, a2 = false;
         int2 e = make_int2(0, 0);
         if (k < t1) {
             e = B.cert[k < n1 ? offj + k : offj + capj - n2 + (k - n1)];
-            offer(q, (uint32_t)e.x, (uint32_t)e.y, a1, a2);
+            offer(q, B.qs, (uint32_t)e.x, (uint32_t)e.y, a1, a2);
         }
         stage_put(S, a1, a2, e);
     }
@@ -241,17 +244,17 @@ __global__ void k_copy_out(DevBufs B, int2* out, int64_t out_cap, int64_t* count
 // vertex points straight at its representative, so that later edges inside a
 // component are rejected by the two-load test in offer() without any search.
 // No hook runs concurrently, so plain stores are safe.
-__global__ void k_compress(uint32_t* state, int32_t V, int64_t slots) {
+__global__ void k_compress(uint32_t* state, int64_t qs, int32_t V, int64_t slots) {
     const int64_t n = (int64_t)V * slots;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t* q = state + (size_t)(k / V) * 2 * (size_t)V;
+        uint32_t* q = state + (size_t)(k / V) * (size_t)qs * (size_t)V;
         const uint32_t x = (uint32_t)(k % V);
         for (int f = 0; f < 2; f++) {
-            const uint32_t d = q[2 * (size_t)x + f];
+            const uint32_t d = q[qs * (int64_t)x + f];
             if (d == 0) continue;
             uint32_t r = x - d;
-            for (uint32_t e = q[2 * (size_t)r + f]; e != 0; e = q[2 * (size_t)r + f]) r -= e;
-            if (r != x - d) q[2 * (size_t)x + f] = x - r;
+            for (uint32_t e = q[qs * (int64_t)r + f]; e != 0; e = q[qs * (int64_t)r + f]) r -= e;
+            if (r != x - d) q[qs * (int64_t)x + f] = x - r;
         }
     }
 }
@@ -280,7 +283,7 @@ void launch_phase0(const Plan& P, const DevBufs& B, hipStream_t s) {
         if (k > 0) {
             const int64_t n = (int64_t)P.V * P.M;
             hipLaunchKernelGGL(k_compress, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536))),
-                               dim3(256), 0, s, B.state, P.V, (int64_t)P.M);
+                               dim3(256), 0, s, B.state, B.qs, P.V, (int64_t)P.M);
         }
         const int64_t tpc = std::max<int64_t>(1, (rhi - rlo + P.tile - 1) / P.tile);
         hipLaunchKernelGGL(k_phase0, dim3((unsigned)(chunk_slots * tpc)), dim3(kBlock), 0, s, B, P.E, P.V, P.M, P.tile,

@@ -90,6 +90,7 @@ struct Plan {
     std::vector<int64_t> off, cap; // per node: certificate region (pairs)
     int64_t cert_pairs = 0;        // sum of caps
     std::vector<int64_t> round_cap;// per round: largest sibling cap
+    int32_t qs = 2;                // union-find state words per vertex (F at +0, F' at +1)
 };
 
 // Certificate regions: node i owns pairs [off[i], off[i]+cap[i]); its F1 grows
@@ -98,7 +99,8 @@ struct DevBufs {
     const int2* edges = nullptr;   // edge i < split is edges[i]
     const int2* edges2 = nullptr;  // edge i >= split is edges2[i - split]
     int64_t split = 0;
-    uint32_t* state = nullptr;     // [M][V][2] offset-encoded parents (0 = root)
+    uint32_t* state = nullptr;     // [M][V][qs] offset-encoded parents (0 = root), F at +0, F' at +1
+    int64_t qs = 2;                // words per vertex of the state (2, or 8: one vertex per 32 bytes)
     int2* cert = nullptr;
     const int64_t* off = nullptr;  // [M]
     const int64_t* cap = nullptr;  // [M]
