@@ -104,9 +104,9 @@ int ensure_pinned(br_ctx* c, size_t bytes) {
     return BR_OK;
 }
 
-// Workspace layout: [err | cnt | state | cert | off | cap]
+// Workspace layout: [err | cnt | state | packed state | cert | off | cap]
 struct Layout {
-    size_t err, cnt, state, cert, off, cap, bws, total;
+    size_t err, cnt, state, packed, cert, off, cap, bws, total;
 };
 static Layout layout(const Plan& P, bool device_final) {
     Layout L;
@@ -114,6 +114,7 @@ static Layout layout(const Plan& P, bool device_final) {
     L.err = o; o += 256;
     L.cnt = o; o = align256(o + sizeof(uint32_t) * 2 * (size_t)P.M);
     L.state = o; o = align256(o + sizeof(uint32_t) * (size_t)P.qs * (size_t)P.V * (size_t)P.M);
+    L.packed = o; if (P.qs != 2 && P.M > 1) o = align256(o + sizeof(uint32_t) * 2 * (size_t)P.V * (size_t)P.M);
     L.cert = o; o = align256(o + sizeof(int2) * (size_t)std::max<int64_t>(P.cert_pairs, 1));
     L.off = o; o = align256(o + sizeof(int64_t) * (size_t)P.M);
     L.cap = o; o = align256(o + sizeof(int64_t) * (size_t)P.M);
@@ -151,6 +152,7 @@ int run_certificate(br_ctx* c, const int32_t* d_a, int64_t Ea, const int32_t* d_
     B.cnt = reinterpret_cast<uint32_t*>(base + L.cnt);
     B.state = reinterpret_cast<uint32_t*>(base + L.state);
     B.qs = P.qs;
+    B.packed = P.qs != 2 && P.M > 1 ? reinterpret_cast<uint32_t*>(base + L.packed) : nullptr;
     B.cert = reinterpret_cast<int2*>(base + L.cert);
     B.off = reinterpret_cast<const int64_t*>(base + L.off);
     B.cap = reinterpret_cast<const int64_t*>(base + L.cap);

@@ -259,6 +259,24 @@ __global__ void k_compress(uint32_t* state, int64_t qs, int32_t V, int64_t slots
     }
 }
 
+// The same full compression, written into a packed copy (two words per
+// vertex) of a state laid out with qs words per vertex; the source is only
+// read, so the copy is exact whatever order the threads run in.
+__global__ void k_compress_pack(const uint32_t* state, int64_t qs, uint32_t* packed, int32_t V, int64_t slots) {
+    const int64_t n = (int64_t)V * slots;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t* q = state + (size_t)(k / V) * (size_t)qs * (size_t)V;
+        const uint32_t x = (uint32_t)(k % V);
+        uint32_t out[2];
+        for (int f = 0; f < 2; f++) {
+            uint32_t r = x;
+            for (uint32_t e = q[qs * (int64_t)r + f]; e != 0; e = q[qs * (int64_t)r + f]) r -= e;
+            out[f] = x - r;
+        }
+        reinterpret_cast<uint2*>(packed)[k] = make_uint2(out[0], out[1]);
+    }
+}
+
 __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
         p[k] = v;
@@ -273,7 +291,12 @@ void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
 }
 
-void launch_phase0(const Plan& P, const DevBufs& B, hipStream_t s) {
+// Stages of phase 0 with a full compression between them.  A state spread
+// over qs > 2 words per vertex (for the stages where hooks happen) is
+// compressed into the packed copy at B.packed before the last stage (mostly
+// rejections), and B is switched to it for that stage and the merges; with a
+// single chunk (no merges) B.packed is null and the state keeps its layout.
+void launch_phase0(const Plan& P, DevBufs& B, hipStream_t s) {
     if (P.E == 0) return;
     const int64_t per = (P.E + P.M - 1) / P.M;
     const int64_t chunk_slots = P.xcd_map ? 8 * (((int64_t)P.M + 7) / 8) : P.M;
@@ -282,8 +305,15 @@ void launch_phase0(const Plan& P, const DevBufs& B, hipStream_t s) {
         if (rlo >= rhi) break;
         if (k > 0) {
             const int64_t n = (int64_t)P.V * P.M;
-            hipLaunchKernelGGL(k_compress, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536))),
-                               dim3(256), 0, s, B.state, B.qs, P.V, (int64_t)P.M);
+            const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536)));
+            if (B.qs != 2 && B.packed && k + 2 == P.stages.size()) {     // before the last stage, merges to come
+                hipLaunchKernelGGL(k_compress_pack, grid, dim3(256), 0, s, (const uint32_t*)B.state, B.qs, B.packed, P.V,
+                                   (int64_t)P.M);
+                B.state = B.packed;
+                B.qs = 2;
+            } else {
+                hipLaunchKernelGGL(k_compress, grid, dim3(256), 0, s, B.state, B.qs, P.V, (int64_t)P.M);
+            }
         }
         const int64_t tpc = std::max<int64_t>(1, (rhi - rlo + P.tile - 1) / P.tile);
         hipLaunchKernelGGL(k_phase0, dim3((unsigned)(chunk_slots * tpc)), dim3(kBlock), 0, s, B, P.E, P.V, P.M, P.tile,

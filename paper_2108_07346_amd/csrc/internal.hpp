@@ -101,6 +101,7 @@ struct DevBufs {
     int64_t split = 0;
     uint32_t* state = nullptr;     // [M][V][qs] offset-encoded parents (0 = root), F at +0, F' at +1
     int64_t qs = 2;                // words per vertex of the state (2, or 8: one vertex per 32 bytes)
+    uint32_t* packed = nullptr;    // [M][V][2]: where a qs = 8 state is compressed to after the first stage
     int2* cert = nullptr;
     const int64_t* off = nullptr;  // [M]
     const int64_t* cap = nullptr;  // [M]
@@ -149,7 +150,7 @@ int32_t batched_max_v_dev();
 int32_t batched_blocks_per_cu();
 
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
-void launch_phase0(const Plan& P, const DevBufs& B, hipStream_t s);
+void launch_phase0(const Plan& P, DevBufs& B, hipStream_t s);
 void launch_merge_round(const Plan& P, const DevBufs& B, int32_t step, hipStream_t s);
 void launch_copy_out(const Plan& P, const DevBufs& B, int32_t* d_out, int64_t out_cap, int64_t* d_counts,
                      hipStream_t s);
