@@ -14,7 +14,7 @@ configuration's sweep {1, 16, 256, 1024} that runs merge rounds; the whole
 sweep is reported under "detail".
 
 Roofline: the dominant kernel is phase 0, the per-chunk certificates (two
-k_phase0 stages with k_compress between them, one query's worth); its
+k_phase0 stages with the compression between them, one query's worth); its
 algorithmic traffic is 8 bytes per input edge (one read of the int32 pair;
 union-find state is meant to stay in cache), divided by its duration from HIP
 events recorded on the call's stream during the timed steps, against the
@@ -504,7 +504,7 @@ def main():
         "config": {"workload": args.workload, "V": g.V, "E": g.E, "M": M, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_GBS, "traffic": traffic,
-                     "kernel": "phase 0 per query: k_phase0 (two stages) + k_compress",
+                     "kernel": "phase 0 per query: k_phase0 (two stages) + k_compress_pack",
                      "algorithmic_bytes_per_launch": 8 * g.E},
         "cpu_baseline": cpu,
         "detail": detail,
