@@ -45,29 +45,31 @@ __device__ __forceinline__ bool excluded(const int32_t* par1, int32_t u, int32_t
 }
 
 // component union-find over the edges (skipping loops and, with par1, the
-// pairs of the first forest); q[x] = x - parent(x), 0 at a root; the larger
+// pairs of the first forest); q[cs x] = x - parent(x), 0 at a root (cs words
+// per vertex: 8 while the state stays within 64 MB, so that a hook, performed
+// at the memory side, disturbs the words of fewer other vertices); the larger
 // root is hooked under the smaller, so each component's root is its smallest id
-__device__ __forceinline__ uint32_t cc_find(uint32_t* q, uint32_t x) {
-    uint32_t d = __hip_atomic_load(q + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+__device__ __forceinline__ uint32_t cc_find(uint32_t* q, int64_t cs, uint32_t x) {
+    uint32_t d = __hip_atomic_load(q + cs * (int64_t)x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     while (d != 0) {
         const uint32_t p = x - d;
-        const uint32_t dp = __hip_atomic_load(q + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        const uint32_t dp = __hip_atomic_load(q + cs * (int64_t)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         if (dp == 0) return p;
-        __hip_atomic_store(q + x, d + dp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        __hip_atomic_store(q + cs * (int64_t)x, d + dp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         x = p - dp;
-        d = __hip_atomic_load(q + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        d = __hip_atomic_load(q + cs * (int64_t)x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     }
     return x;
 }
 
-__device__ __forceinline__ void cc_unite(uint32_t* q, uint32_t u, uint32_t v) {
+__device__ __forceinline__ void cc_unite(uint32_t* q, int64_t cs, uint32_t u, uint32_t v) {
     for (;;) {
-        u = cc_find(q, u);
-        v = cc_find(q, v);
+        u = cc_find(q, cs, u);
+        v = cc_find(q, cs, v);
         if (u == v) return;
         if (u < v) { const uint32_t t = u; u = v; v = t; }
         uint32_t expect = 0;
-        if (__hip_atomic_compare_exchange_strong(q + u, &expect, u - v, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+        if (__hip_atomic_compare_exchange_strong(q + cs * (int64_t)u, &expect, u - v, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT))
             return;
         u = u - expect;
@@ -79,7 +81,7 @@ __device__ __forceinline__ void cc_unite(uint32_t* q, uint32_t u, uint32_t v) {
 // a full compression that parent is the root)
 constexpr int kCcU = 4;
 
-__global__ void k_cc(const int2* edges, int64_t lo, int64_t hi, int32_t V, const int32_t* par1, uint32_t* q,
+__global__ void k_cc(const int2* edges, int64_t lo, int64_t hi, int32_t V, const int32_t* par1, uint32_t* q, int64_t cs,
                      uint32_t* err) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i0 = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i0 < hi; i0 += kCcU * stride) {
@@ -99,23 +101,23 @@ __global__ void k_cc(const int2* edges, int64_t lo, int64_t hi, int32_t V, const
         uint32_t pu[kCcU], pv[kCcU];
 #pragma unroll
         for (int j = 0; j < kCcU; j++) {
-            pu[j] = ok[j] ? (uint32_t)e[j].x - __hip_atomic_load(q + e[j].x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) : 0u;
-            pv[j] = ok[j] ? (uint32_t)e[j].y - __hip_atomic_load(q + e[j].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) : 0u;
+            pu[j] = ok[j] ? (uint32_t)e[j].x - __hip_atomic_load(q + cs * (int64_t)e[j].x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) : 0u;
+            pv[j] = ok[j] ? (uint32_t)e[j].y - __hip_atomic_load(q + cs * (int64_t)e[j].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) : 0u;
         }
 #pragma unroll
         for (int j = 0; j < kCcU; j++)
-            if (ok[j] && pu[j] != pv[j]) cc_unite(q, pu[j], pv[j]);
+            if (ok[j] && pu[j] != pv[j]) cc_unite(q, cs, pu[j], pv[j]);
     }
 }
 
 // every vertex straight under its root (no hook runs concurrently)
-__global__ void k_cc_compress(uint32_t* q, int32_t V) {
+__global__ void k_cc_compress(uint32_t* q, int64_t cs, int32_t V) {
     GRID_LOOP(x, (int64_t)V) {
-        const uint32_t d = q[x];
+        const uint32_t d = q[cs * x];
         if (d == 0) continue;
         uint32_t r = (uint32_t)x - d;
-        for (uint32_t e = q[r]; e != 0; e = q[r]) r -= e;
-        if (r != (uint32_t)x - d) q[x] = (uint32_t)x - r;
+        for (uint32_t e = q[cs * (int64_t)r]; e != 0; e = q[cs * (int64_t)r]) r -= e;
+        if (r != (uint32_t)x - d) q[cs * x] = (uint32_t)x - r;
     }
 }
 
@@ -349,7 +351,7 @@ __device__ __forceinline__ void lds_flush(LevelLds& L, unsigned long long* ring,
 
 // search start: the root of every component is level 0 and the first frontier;
 // block b takes the vertices [V b / G, V (b + 1) / G)
-__global__ void __launch_bounds__(kLvT) k_bfs_start(const uint32_t* q, int32_t V, const uint32_t* head, int32_t* par,
+__global__ void __launch_bounds__(kLvT) k_bfs_start(const uint32_t* q, int64_t cs, int32_t V, const uint32_t* head, int32_t* par,
                                                     uint64_t* cand, int32_t* lvl, int4* frontier,
                                                     unsigned long long* ring) {
     __shared__ LevelLds L;
@@ -359,7 +361,7 @@ __global__ void __launch_bounds__(kLvT) k_bfs_start(const uint32_t* q, int32_t V
     const int64_t end = lo + ((hi - lo + 63) & ~int64_t(63));
     for (int64_t v = lo + threadIdx.x; v < end; v += kLvT) {
         const bool in = v < hi;
-        const bool root = in && q[v] == 0;
+        const bool root = in && q[cs * v] == 0;
         uint32_t h0 = 0, h1 = 0;
         if (in) {
             par[v] = -1;
@@ -534,6 +536,7 @@ struct ApWs {
     int4 *fa, *fb;
     uint64_t *cand, *scan_status;
     int2 *arcs, *f1, *f2;
+    int64_t cs;                 // words per vertex of the component state
     int64_t zero_words, words;
 };
 
@@ -543,7 +546,8 @@ static ApWs ap_carve(char* base, int64_t E, int32_t V) {
     int64_t o = 0;
     auto take = [&](int64_t bytes) { char* p = base ? base + o : nullptr; o += (bytes + 255) & ~int64_t(255); return p; };
     // cleared together at the start
-    w.q = reinterpret_cast<uint32_t*>(take(4 * (int64_t)V));
+    w.cs = (int64_t)V * 32 <= (int64_t(64) << 20) ? 8 : 1;
+    w.q = reinterpret_cast<uint32_t*>(take(4 * (int64_t)V * w.cs));
     w.head = reinterpret_cast<uint32_t*>(take(4 * ((int64_t)V + 1)));
     w.cur = reinterpret_cast<uint32_t*>(take(P.on ? 4 : 4 * (int64_t)V));
     w.btot = reinterpret_cast<uint32_t*>(take(4 * (int64_t)kMaxBuckets));
@@ -579,7 +583,7 @@ static int bfs_forest(const ApWs& W, int32_t V, const int32_t* par1, int32_t* pa
     // ring[0..127]: level counters, ring[128..131]: acc (tree edges and arcs before the level, ping-pong)
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kT), 0, s, reinterpret_cast<uint32_t*>(W.ring), (int64_t)2 * 132);
     const int gs = (int)std::max<int64_t>(1, std::min<int64_t>(kLvBlocks, ((int64_t)V + kLvT - 1) / kLvT));
-    hipLaunchKernelGGL(k_bfs_start, dim3(gs), dim3(kLvT), 0, s, W.q, V, (const uint32_t*)W.head, par, W.cand, W.lvl, W.fa,
+    hipLaunchKernelGGL(k_bfs_start, dim3(gs), dim3(kLvT), 0, s, W.q, W.cs, V, (const uint32_t*)W.head, par, W.cand, W.lvl, W.fa,
                        reinterpret_cast<unsigned long long*>(W.ring));
     int4 *cur_l = W.fa, *nxt_l = W.fb;
     int d = 0;
@@ -605,18 +609,18 @@ static int bfs_forest(const ApWs& W, int32_t V, const int32_t* par1, int32_t* pa
 }
 
 // components of the edges (minus the pairs of par1 when given): union-find in
-// stages with full compression between them; afterwards q[v] == 0 exactly at
+// stages with full compression between them; afterwards q[cs v] == 0 exactly at
 // the smallest vertex of each component
 static void components(const ApWs& W, const int2* edges, int64_t E, int32_t V, const int32_t* par1, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(V)), dim3(kT), 0, s, W.q, (int64_t)V);
+    hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(V * W.cs)), dim3(kT), 0, s, W.q, (int64_t)V * W.cs);
     const int64_t cuts[4] = {0, std::min<int64_t>(E, 2 * (int64_t)V), std::min<int64_t>(E, 8 * (int64_t)V), E};
     for (int k = 0; k < 3; k++) {
         if (cuts[k + 1] <= cuts[k]) continue;
-        if (k > 0) hipLaunchKernelGGL(k_cc_compress, dim3(grid_for(V)), dim3(kT), 0, s, W.q, V);
+        if (k > 0) hipLaunchKernelGGL(k_cc_compress, dim3(grid_for(V)), dim3(kT), 0, s, W.q, W.cs, V);
         hipLaunchKernelGGL(k_cc, dim3(grid_for((cuts[k + 1] - cuts[k] + kCcU - 1) / kCcU)), dim3(kT), 0, s, edges, cuts[k],
-                           cuts[k + 1], V, par1, W.q, W.err);
+                           cuts[k + 1], V, par1, W.q, W.cs, W.err);
     }
-    hipLaunchKernelGGL(k_cc_compress, dim3(grid_for(V)), dim3(kT), 0, s, W.q, V);
+    hipLaunchKernelGGL(k_cc_compress, dim3(grid_for(V)), dim3(kT), 0, s, W.q, W.cs, V);
 }
 
 // The scan-first certificate (F, F') of d_edges, left on the device: F at
