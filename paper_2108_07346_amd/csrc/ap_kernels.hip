@@ -134,7 +134,7 @@ __global__ void k_cc_compress(uint32_t* q, int64_t cs, int32_t V) {
 // vertices than the bucket limit allows use the direct build.
 constexpr int kMaxBuckets = 4096;
 constexpr int kMaxBucketShift = 13;     // 2^13 counters = 32 KB of LDS per block
-constexpr int kBktBlocks = 512;
+constexpr int kBktBlocks = 256;
 
 __device__ __forceinline__ bool arc_edge(int2 e, int32_t V) {
     return (uint32_t)e.x < (uint32_t)V && (uint32_t)e.y < (uint32_t)V && e.x != e.y;
