@@ -24,6 +24,7 @@
 
 #include <cstring>
 
+#include "device_util.hpp"
 #include "internal.hpp"
 
 namespace br {
@@ -33,12 +34,6 @@ namespace {
 constexpr int kT = 256;
 constexpr uint64_t kNoCand = ~uint64_t(0);
 
-#define GRID_LOOP(i, n) for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
-
-int grid_for(int64_t n) {
-    int64_t g = (n + kT - 1) / kT;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 16384));
-}
 
 __device__ __forceinline__ bool excluded(const int32_t* par1, int32_t u, int32_t w) {
     return par1 && (par1[w] == u || par1[u] == w);
@@ -296,10 +291,6 @@ struct LevelLds {
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
-}
-
-__device__ __forceinline__ uint32_t lane_rank(uint64_t m) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
 __device__ __forceinline__ void lds_begin(LevelLds& L) {

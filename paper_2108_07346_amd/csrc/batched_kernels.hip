@@ -19,6 +19,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "device_util.hpp"
 #include "internal.hpp"
 
 namespace br {
@@ -109,9 +110,6 @@ __device__ void lcompress(uint32_t* q, uint32_t V) {
     }
 }
 
-__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
 
 // wavefront-aggregated reservation of slots on an LDS counter
 __device__ __forceinline__ uint32_t reserve(uint32_t* ctr, bool want, uint64_t& mask) {

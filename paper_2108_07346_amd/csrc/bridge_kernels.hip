@@ -18,6 +18,7 @@
 // by pointer jumping gives every arc its position in its tour.
 #include <hip/hip_runtime.h>
 
+#include "device_util.hpp"
 #include "internal.hpp"
 
 namespace br {
@@ -29,7 +30,6 @@ constexpr int kT = 256;
 __device__ __forceinline__ int32_t arc_src(const int2* f1, int32_t a) { const int2 e = f1[a >> 1]; return (a & 1) ? e.y : e.x; }
 __device__ __forceinline__ int32_t arc_dst(const int2* f1, int32_t a) { const int2 e = f1[a >> 1]; return (a & 1) ? e.x : e.y; }
 
-#define GRID_LOOP(i, n) for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
 constexpr int kSB = kT * 4;   // elements per block of the one-pass scans
 
@@ -431,7 +431,7 @@ __device__ __forceinline__ void out_begin(OutLds& L) {
 __device__ __forceinline__ void out_put(OutLds& L, bool add, uint64_t key, uint64_t m, uint64_t* out, uint32_t* nout) {
     const int leader = __ffsll((unsigned long long)m) - 1;
     const uint32_t cnt = (uint32_t)__popcll(m);
-    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    const uint32_t rank = lane_rank(m);
     uint32_t at = 0;
     if (__lane_id() == leader) at = atomicAdd(&L.n, cnt);
     at = __shfl(at, leader);
@@ -608,10 +608,6 @@ __global__ void k_status(const uint32_t* cnt, const uint32_t* err, uint32_t* mis
     }
 }
 
-int grid_for(int64_t n) {
-    int64_t g = (n + kT - 1) / kT;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 16384));
-}
 
 }  // namespace
 

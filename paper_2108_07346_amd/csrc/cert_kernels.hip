@@ -30,6 +30,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "device_util.hpp"
 #include "internal.hpp"
 
 namespace br {
@@ -93,9 +94,6 @@ __device__ __forceinline__ void offer(uint32_t* q, int64_t qs, uint32_t u, uint3
     }
 }
 
-__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
 
 // Accepted edges of one workgroup tile are staged in LDS (F from the front,
 // F' from the back of the stage), then the tile reserves its ranges in the
