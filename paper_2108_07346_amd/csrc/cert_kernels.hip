@@ -313,9 +313,16 @@ void launch_phase0(const Plan& P, DevBufs& B, hipStream_t s) {
                 hipLaunchKernelGGL(k_compress, grid, dim3(256), 0, s, B.state, B.qs, P.V, (int64_t)P.M);
             }
         }
-        const int64_t tpc = std::max<int64_t>(1, (rhi - rlo + P.tile - 1) / P.tile);
-        hipLaunchKernelGGL(k_phase0, dim3((unsigned)(chunk_slots * tpc)), dim3(kBlock), 0, s, B, P.E, P.V, P.M, P.tile,
-                           (int32_t)tpc, P.xcd_map, rlo, rhi);
+        // the first stage (nearly all hooks) in tiles small enough for about
+        // 512 workgroups in all (few chunks: more, shorter hook chains in
+        // flight); later stages (mostly rejections) in full tiles, one
+        // reservation each on the chunk's counters
+        int64_t tile = P.tile;
+        if (k == 0)
+            while (tile > kBlock && (int64_t)P.M * ((rhi - rlo + tile - 1) / tile) < 512) tile /= 2;
+        const int64_t tpc = std::max<int64_t>(1, (rhi - rlo + tile - 1) / tile);
+        hipLaunchKernelGGL(k_phase0, dim3((unsigned)(chunk_slots * tpc)), dim3(kBlock), 0, s, B, P.E, P.V, P.M,
+                           (int32_t)tile, (int32_t)tpc, P.xcd_map, rlo, rhi);
     }
 }
 
