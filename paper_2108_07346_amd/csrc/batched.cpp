@@ -487,16 +487,20 @@ int br_bridges_find_batched(br_ctx* c, const int32_t* d_edges, const int64_t* h_
     const int32_t S = (int32_t)P->small.size();
     std::vector<int64_t> slot(S + 1, 0), nb(G, 0);
     for (int32_t s = 0; s < S; s++) slot[s + 1] = slot[s] + std::max(P->V[P->small[s]] - 1, 0);
-    if (st.outk_n < (size_t)std::max<int64_t>(slot[S], 1)) {
-        st.outk_n = (size_t)std::max<int64_t>(slot[S], 1);
-        st.outk.reset(new uint64_t[st.outk_n]);
+    uint64_t* outk = nullptr;
+    const uint32_t* keys = nullptr;     // mode 1: the device's sorted keys, (u | v << 16)
+    if (mode != 1) {
+        if (st.outk_n < (size_t)std::max<int64_t>(slot[S], 1)) {
+            st.outk_n = (size_t)std::max<int64_t>(slot[S], 1);
+            st.outk.reset(new uint64_t[st.outk_n]);
+        }
+        outk = st.outk.get();
     }
-    uint64_t* outk = st.outk.get();
     if (mode == 1) {
         // per graph: base and count in the key array, keys already sorted
         const size_t guess = std::min<size_t>(std::max<size_t>(P->keys_hint, 4096), (size_t)P->sb_keys);
         const uint32_t* hdr = P->h_sb;
-        const uint32_t* keys = P->h_sb + P->sb_hdr;
+        keys = P->h_sb + P->sb_hdr;
         const uint32_t nk = S ? hdr[0] : 0;
         if (nk > (uint32_t)P->sb_keys) return fail(BR_EINTERNAL, "batched: %u bridge keys for room %lld", nk, (long long)P->sb_keys);
         if (nk > guess) {
@@ -505,14 +509,11 @@ int br_bridges_find_batched(br_ctx* c, const int32_t* d_edges, const int64_t* h_
             BR_HIP(hipStreamSynchronize(st.stream));
         }
         P->keys_hint = nk;
+        // counts only here; the keys go straight to the caller's array below
         for (int32_t s = 0; s < S; s++) {
             const uint32_t base = hdr[16 + 2 * s], cnt = hdr[17 + 2 * s];
             if ((uint64_t)base + cnt > nk || (int64_t)cnt > slot[s + 1] - slot[s])
                 return fail(BR_EINTERNAL, "batched: graph %d reports %u bridges at %u", (int)P->small[s], cnt, base);
-            for (uint32_t i = 0; i < cnt; i++) {
-                const uint32_t k = keys[base + i];
-                outk[slot[s] + i] = ((uint64_t)(k >> 16) << 32) | (uint64_t)(k & 0xffffu);
-            }
             nb[P->small[s]] = cnt;
         }
     } else {
@@ -563,9 +564,17 @@ int br_bridges_find_batched(br_ctx* c, const int32_t* d_edges, const int64_t* h_
         for (int32_t s = 0; s < S; s++) {
             const int32_t g = P->small[s];
             int32_t* o = h_bridges + 2 * h_bridge_off[g];
-            for (int64_t i = 0; i < nb[g]; i++) {
-                o[2 * i] = (int32_t)(outk[slot[s] + i] >> 32);
-                o[2 * i + 1] = (int32_t)(outk[slot[s] + i] & 0xffffffffu);
+            if (mode == 1) {
+                const uint32_t* k = keys + P->h_sb[16 + 2 * s];
+                for (int64_t i = 0; i < nb[g]; i++) {
+                    o[2 * i] = (int32_t)(k[i] >> 16);
+                    o[2 * i + 1] = (int32_t)(k[i] & 0xffffu);
+                }
+            } else {
+                for (int64_t i = 0; i < nb[g]; i++) {
+                    o[2 * i] = (int32_t)(outk[slot[s] + i] >> 32);
+                    o[2 * i + 1] = (int32_t)(outk[slot[s] + i] & 0xffffffffu);
+                }
             }
         }
         for (size_t k = 0; k < P->large.size(); k++)
