@@ -113,6 +113,7 @@ class Context:
         self._lib = load()
         self._h = ctypes.c_void_p()
         self.device = device
+        self._batched_out = np.empty((0, 2), dtype=np.int32)   # reused output room of find_batched
         _check(self._lib.br_create(ctypes.byref(self._h), device))
 
     def close(self):
@@ -206,7 +207,9 @@ class Context:
         if off.shape[0] != G + 1:
             raise ValueError("offsets must have G+1 entries")
         cap = max(int(np.maximum(Vv.astype(np.int64) - 1, 0).sum()), 1)
-        out = np.empty((cap, 2), dtype=np.int32)
+        if self._batched_out.shape[0] < cap:      # room for every possible bridge, kept between calls
+            self._batched_out = np.empty((cap, 2), dtype=np.int32)
+        out = self._batched_out
         boff = np.zeros(G + 1, dtype=np.int64)
         _check(self._lib.br_bridges_find_batched(self._h, ptr, off.ctypes.data, Vv.ctypes.data, G, int(chunk_edges),
                                                  out.ctypes.data, cap, boff.ctypes.data, _stream(stream)))
