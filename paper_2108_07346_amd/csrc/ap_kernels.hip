@@ -348,9 +348,10 @@ __global__ void __launch_bounds__(kLvT) k_bfs_start(const uint32_t* q, int64_t c
     __shared__ LevelLds L;
     lds_begin(L);
     const int64_t lo = (int64_t)V * blockIdx.x / gridDim.x, hi = (int64_t)V * (blockIdx.x + 1) / gridDim.x;
-    // whole wavefronts run the loop (staging is a wavefront operation)
-    const int64_t end = lo + ((hi - lo + 63) & ~int64_t(63));
-    for (int64_t v = lo + threadIdx.x; v < end; v += kLvT) {
+    // every thread of the block runs every turn (staging is a wavefront
+    // operation, and the turns end with a barrier)
+    for (int64_t turn = lo; turn < hi; turn += kLvT) {
+        const int64_t v = turn + threadIdx.x;
         const bool in = v < hi;
         const bool root = in && q[cs * v] == 0;
         uint32_t h0 = 0, h1 = 0;
@@ -365,6 +366,19 @@ __global__ void __launch_bounds__(kLvT) k_bfs_start(const uint32_t* q, int64_t c
         }
         const uint64_t m = __ballot(root);
         if (m) lds_stage(L, root, make_int4((int32_t)v, (int32_t)h0, (int32_t)h1, 0), h1 - h0, m, ring, frontier);
+        // empty the LDS run before the next turn could overflow it (graphs
+        // with many components)
+        __syncthreads();
+        if (L.n > (uint32_t)(kLvBuf - kLvT)) {
+            lds_flush(L, ring, frontier);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                L.n = 0;
+                L.fail = kLvBuf;
+                L.arcs = 0;
+            }
+            __syncthreads();
+        }
     }
     lds_flush(L, ring, frontier);
 }
