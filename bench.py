@@ -287,6 +287,52 @@ def bench_articulation(args):
     ctx.close()
 
 
+def bench_classes(args):
+    """2-edge-connected classes of the dense workload (labels = smallest vertex
+    of each class): the certificate, the bridge test and the union of the
+    non-bridge certificate edges, all on the GPU (the default final step); the
+    oracle (its own low-link search and union on the whole graph) timed beside
+    it."""
+    import numpy as np
+    import torch
+    import graphgen
+    import paper_2108_07346_amd as br
+    g = graphgen.config("dense")
+    M = args.M or 16
+    d = torch.from_numpy(g.edges).cuda()
+    ctx = br.Context(0)
+    stream = torch.cuda.current_stream()
+    for _ in range(max(args.warmup, 1)):
+        lab, n = ctx.two_edge_components(d, g.V, M, stream)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        lab, n = ctx.two_edge_components(d, g.V, M, stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        reps, tc = 0, time.perf_counter()
+        while True:
+            want = oracle.two_edge_labels(g.edges, g.V)
+            reps += 1
+            if time.perf_counter() - tc >= min(args.cpu_budget, 10.0):
+                break
+        dtc = time.perf_counter() - tc
+        assert np.array_equal(want, lab)
+        cpu = {"value": g.E * reps / dtc, "unit": "edges/s", "cores": 1, "kind": "oracle",
+               "sample": "whole dense workload, %d repetition(s) in %.1f s, one host core" % (reps, dtc)}
+    line = {"metric": "2-edge-connected classes: edges/s (certificate, bridges and class union on the GPU)",
+            "value": g.E * args.steps / dt, "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": 1000 * dt / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "int32", "data": "synthetic (seeded planted-cluster generator)",
+            "config": {"workload": "dense", "V": g.V, "E": g.E, "M": M, "parallelism": "single GPU"},
+            "roofline": None, "cpu_baseline": cpu, "detail": {"classes": int(n)}}
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def bench_served(args):
     """Served workload: open-loop Poisson arrivals at fixed QPS; latency from
     each request's scheduled arrival to the moment its answer is back on the
@@ -370,7 +416,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="dense", choices=["small", "dense", "large", "batched", "served", "figures", "articulation"])
+    ap.add_argument("--workload", default="dense", choices=["small", "dense", "large", "batched", "served", "figures", "articulation", "classes"])
     ap.add_argument("--qps", default="100,200,500,1000,2000,5000", help="served: comma-separated QPS")
     ap.add_argument("--seconds", type=float, default=2.0, help="served: seconds per QPS point")
     ap.add_argument("--max-requests", type=int, default=600, help="served: cap per QPS point")
@@ -414,6 +460,8 @@ def main():
         return bench_figures(args)
     if args.workload == "articulation":
         return bench_articulation(args)
+    if args.workload == "classes":
+        return bench_classes(args)
     M = args.M or {"small": 4, "dense": 16, "large": 4096}[args.workload]
     t0 = time.perf_counter()
     g = graphgen.config(args.workload)

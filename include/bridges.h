@@ -109,7 +109,10 @@ int br_bridges_find(br_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t V, i
  * the components left once the bridges of Section I are removed), through the
  * same certificate path: the certificate keeps every single-edge-removal
  * connectivity of the input (Section III), so the classes are those of the
- * certificate without its bridges (found by Algorithm 1 on the host).
+ * certificate without its bridges.  With the default final step (see
+ * br_set_final_step) the bridges and the union of the remaining certificate
+ * edges run on the GPU; with final step 0 the bridges come from Algorithm 1
+ * on the host and the union runs there too.
  *   h_label  host int32 [V]: the smallest vertex id of each vertex's class.
  *   *n_classes number of classes (= number of bridges + number of components).
  * Synchronous; errors as for br_bridges_find.

@@ -412,13 +412,30 @@ int br_two_edge_components(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t
     BR_HIP(hipSetDevice(c->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     BR_HIP(hipEventSynchronize(c->ev[7]));
-    const int saved = c->final_step;
-    c->final_step = 0;
     Plan P;
     DevBufs B;
     rc = run_certificate(c, d_edges, E, nullptr, 0, V, M, s, P, B);
-    c->final_step = saved;
     if (rc) return rc;
+    if (c->final_step == 1) {
+        // bridges and classes on the device: one copy of the status block and labels
+        int32_t* d_label = nullptr;
+        uint32_t* d_n = nullptr;
+        rc = device_classes(P, B, c->bws, &d_label, &d_n, s);
+        if (rc) return rc;
+        BR_HIP(hipGetLastError());
+        rc = ensure_pinned(c, 256 + 4 * (size_t)V);
+        if (rc) return rc;
+        uint32_t* hc = static_cast<uint32_t*>(c->pinned);
+        BR_HIP(hipMemcpyAsync(hc, d_n - 1, 256 + 4 * (size_t)V, hipMemcpyDeviceToHost, s));
+        BR_HIP(hipStreamSynchronize(s));
+        const uint32_t err = hc[4];
+        if (err & 1u) return fail(BR_ERANGE, "br_two_edge_components: an edge has a vertex id outside [0, %d)", V);
+        if (err != 0 || (int64_t)hc[2] + hc[3] > P.cap[0])
+            return fail(BR_EINTERNAL, "br_two_edge_components: region overflow");
+        std::memcpy(h_label, reinterpret_cast<const char*>(hc) + 256, 4 * (size_t)V);
+        *n_classes = hc[1];
+        return BR_OK;
+    }
     const int64_t cap0 = P.cap[0];
     rc = ensure_pinned(c, sizeof(int2) * (size_t)std::max<int64_t>(cap0, 1) + 64);
     if (rc) return rc;

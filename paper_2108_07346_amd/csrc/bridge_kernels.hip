@@ -599,6 +599,51 @@ __global__ void k_tv_list(const uint32_t* q, int32_t qs, const int32_t* head, in
     out_end(L, out, nout);
 }
 
+// ---- 2-edge-connected classes of the certificate ----------------------------
+//
+// The classes are the components left once the bridges are removed.  Every
+// edge of F' is a non-tree edge, so never a bridge; a tree edge (parent(v), v)
+// is a bridge iff no edge of F' leaves v's subtree (the test of k_bridges).
+// The non-bridges are united with the larger root hooked under the smaller, so
+// after full compression each vertex's root is the smallest id of its class.
+__global__ void k_class_tree(const int2* f1, const uint32_t* q, int32_t qs, const int32_t* head, const int32_t* in_arc,
+                             const int32_t* pre, const int32_t* sub, Rmq R, int32_t V, int64_t A, uint32_t* g) {
+    GRID_LOOP(v, (int64_t)V) {
+        if (head[v + 1] == head[v] || q[qs * (size_t)v] == 0) continue;      // no tree edge above v
+        const int32_t a = in_arc[v];
+        if (a < 0 || a >= A) continue;
+        const int32_t l = pre[v], r = pre[v] + sub[v] - 1;
+        if (l < 0 || r < l || r >= V) continue;
+        int32_t mn, mx;
+        range_minmax(R, l, r, mn, mx);
+        if (mn >= l && mx <= r) continue;                                  // a bridge
+        tv_unite(g, (uint32_t)v, (uint32_t)arc_src(f1, a));
+    }
+}
+
+__global__ void k_class_cross(const int2* f2, int32_t dir, const uint32_t* cnt, uint32_t* g) {
+    const int64_t n2 = cnt[1];
+    GRID_LOOP(k, n2) {
+        const int2 e = f2[dir * k];
+        if (e.x != e.y) tv_unite(g, (uint32_t)e.x, (uint32_t)e.y);
+    }
+}
+
+// labels (after full compression) and the number of classes (roots), one
+// reservation per block
+__global__ void k_class_out(const uint32_t* g, int32_t V, int32_t* label, uint32_t* nclass) {
+    __shared__ uint32_t roots;
+    if (threadIdx.x == 0) roots = 0;
+    __syncthreads();
+    GRID_LOOP(v, (int64_t)V) {
+        const uint32_t r = (uint32_t)v - g[v];
+        label[v] = (int32_t)r;
+        if (r == (uint32_t)v) atomicAdd(&roots, 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && roots) atomicAdd(nclass, roots);
+}
+
 // counters of the certificate and the result next to the keys, for one copy
 __global__ void k_status(const uint32_t* cnt, const uint32_t* err, uint32_t* misc) {
     if (threadIdx.x == 0) {
@@ -754,6 +799,39 @@ int device_articulation_cert(const int2* f1, const int2* f2, int32_t dir, const 
                        W.keys, reinterpret_cast<uint32_t*>(W.misc + 1));
     *d_keys = W.keys;
     *d_n = reinterpret_cast<uint32_t*>(W.misc + 1);
+    return BR_OK;
+}
+
+// 2-edge-connected classes of a certificate held on the device (same
+// arguments as device_bridges_cert): int32 labels (smallest id of each class)
+// at *d_label, the number of classes at *d_n, in the same status-block layout
+// (the labels take the place of the keys).
+int device_classes_cert(const int2* f1, const int2* f2, int32_t dir, const uint32_t* cnt, const uint32_t* q,
+                        int32_t qs, int32_t V, int32_t* ws, int32_t** d_label, uint32_t** d_n, hipStream_t s) {
+    const int64_t A = 2 * (int64_t)std::max(V - 1, 1);
+    Rmq R;
+    const BridgeWs W = number_tree(f1, f2, dir, cnt, q, qs, V, V, ws, s, &R);
+    uint32_t* g = reinterpret_cast<uint32_t*>(W.cur);
+    int32_t* label = reinterpret_cast<int32_t*>(W.keys);
+    hipLaunchKernelGGL(k_tv_init, dim3(grid_for(V)), dim3(kT), 0, s, V, g, W.tour_len, W.tree_n, W.posof);
+    hipLaunchKernelGGL(k_class_tree, dim3(grid_for(V)), dim3(kT), 0, s, f1, q, qs, W.head, W.in_arc, W.pre, W.sub, R, V, A,
+                       g);
+    hipLaunchKernelGGL(k_class_cross, dim3(grid_for(V)), dim3(kT), 0, s, f2, dir, cnt, g);
+    hipLaunchKernelGGL(k_tv_compress, dim3(grid_for(V)), dim3(kT), 0, s, g, V);
+    hipLaunchKernelGGL(k_class_out, dim3(std::min(grid_for(V), kOutBlocks)), dim3(kT), 0, s, (const uint32_t*)g, V, label,
+                       reinterpret_cast<uint32_t*>(W.misc + 1));
+    *d_label = label;
+    *d_n = reinterpret_cast<uint32_t*>(W.misc + 1);
+    return BR_OK;
+}
+
+// Classes of node 0's certificate of the plain path, with the status words.
+int device_classes(const Plan& P, const DevBufs& B, int32_t* ws, int32_t** d_label, uint32_t** d_n, hipStream_t s) {
+    const int2* f1 = B.cert + P.off[0];
+    const int2* f2 = B.cert + P.off[0] + P.cap[0] - 1;
+    const int rc = device_classes_cert(f1, f2, -1, B.cnt, B.state, (int32_t)B.qs, P.V, ws, d_label, d_n, s);
+    if (rc) return rc;
+    launch_bridge_status(B.cnt, B.err, *d_n, s);
     return BR_OK;
 }
 

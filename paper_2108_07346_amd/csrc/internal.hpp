@@ -181,6 +181,10 @@ int device_articulation_cert(const int2* f1, const int2* f2, int32_t dir, const 
 // word 1 is the key count d_n of a bridge step (the keys follow the block)
 void launch_bridge_status(const uint32_t* cnt, const uint32_t* err, uint32_t* d_n, hipStream_t s);
 int device_bridges(const Plan& P, const DevBufs& B, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s);
+
+// 2-edge-connected classes of node 0's certificate on the device: int32 labels
+// (smallest id of each class) where the keys would go, their count at *d_n.
+int device_classes(const Plan& P, const DevBufs& B, int32_t* ws, int32_t** d_label, uint32_t** d_n, hipStream_t s);
 int device_bridges_cert(const int2* f1, const int2* f2, int32_t dir, const uint32_t* cnt, const uint32_t* q, int32_t qs,
                         int32_t V, int32_t max_tree, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s);
 
