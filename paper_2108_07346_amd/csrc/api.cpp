@@ -51,8 +51,8 @@ Plan make_plan(int64_t E, int32_t V, int32_t M) {
         if (b < per) P.stages.push_back(b);
     P.stages.push_back(per);
     // state layout: one vertex per 32 bytes while all M states stay within
-    // 64 MB (measured faster at M = 1 and 16 on the dense workload), packed
-    // 8 bytes per vertex otherwise (more chunks: capacity wins)
+    // 128 MB (measured faster at M = 1, 16 and 32 on the dense workload),
+    // packed 8 bytes per vertex otherwise (more chunks: capacity wins)
     P.qs = (int64_t)M * V * 32 <= (int64_t(128) << 20) ? 8 : 2;
     auto lo = [&](int64_t i) { return i * (E / M) + (i * (E % M)) / M; };
     const int64_t bound = 2 * (int64_t(V) - 1);
