@@ -210,6 +210,19 @@ def test_two_million_vertex_path_and_cycle(ctx):
     for M in (1, 8):
         say("long path M=%d" % M)
         assert np.array_equal(ctx.find(dev(e), Vall, M), want)
+    # 2-edge-connected classes in closed form: each chord closes a cycle over
+    # its stretch of the path (one class labelled by its smallest vertex), the
+    # other path vertices stand alone, the detached cycle is one class
+    lab_want = perm.copy()
+    for a, b in ((10, 20), (500_000, 900_000), (1_700_000, 1_700_003)):
+        lab_want[a:b + 1] = perm[a:b + 1].min()
+    pos = np.empty(V, dtype=np.int64)
+    pos[perm] = np.arange(V)
+    lab_want = np.concatenate([lab_want[pos], np.full(1000, V, dtype=np.int32)]).astype(np.int32)
+    say("long path classes")
+    lab, n = ctx.two_edge_components(dev(e), Vall, 8)
+    assert n == (V - (11 + 400_001 + 4)) + 3 + 1
+    assert np.array_equal(lab, lab_want)
 
 
 def test_two_edge_connected_classes(ctx, small, dense):
