@@ -123,6 +123,8 @@ static Layout layout(const Plan& P, bool device_final) {
     return L;
 }
 
+size_t plan_workspace_bytes(const Plan& P, bool device_final) { return layout(P, device_final).total; }
+
 static void ev_record(br_ctx* c, int k, hipStream_t s) {
     if (c->profiling) (void)hipEventRecord(c->ev[k], s);
 }

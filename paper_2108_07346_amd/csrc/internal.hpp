@@ -156,6 +156,9 @@ void launch_copy_out(const Plan& P, const DevBufs& B, int32_t* d_out, int64_t ou
                      hipStream_t s);
 
 Plan make_plan(int64_t E, int32_t V, int32_t M);
+// device workspace of one plain-path query with this plan (state, certificate
+// regions, node tables and, with the device final step, the bridge step's scratch)
+size_t plan_workspace_bytes(const Plan& P, bool device_final);
 
 // Final step on the device (bridge_kernels.hip): scratch words it needs, and
 // the launch sequence over node 0's certificate; the bridges' keys land at

@@ -88,7 +88,7 @@ namespace {
 // bytes a request needs on the device while it runs
 int64_t charge(int64_t E, int32_t V, int32_t M, bool host_edges) {
     const Plan P = make_plan(E, V, M);
-    int64_t b = 8 * (int64_t)V * M + 8 * P.cert_pairs + 64 * (int64_t)M + (1 << 20);
+    int64_t b = (int64_t)plan_workspace_bytes(P, true) + (1 << 20);
     if (host_edges) b += 8 * E;
     return b;
 }
