@@ -238,4 +238,22 @@ def test_two_edge_connected_classes(ctx, small, dense):
         V = int(rng.integers(1, 200))
         e = rng.integers(0, V, size=(int(rng.integers(0, 4 * V)), 2)).astype(np.int32)
         lab, n = ctx.two_edge_components(dev(e), V, int(rng.choice([1, 3, 16])))
-        assert np.array_equal(lab, oracle.two_edge_labels(e, V)), (V, e.shape[0])
+        want = oracle.two_edge_labels(e, V)
+        assert np.array_equal(lab, want), (V, e.shape[0])
+        assert n == np.unique(want).shape[0]
+    # edge cases: no edges, loops only, one vertex, a doubled edge, an id out of range
+    empty = torch.zeros((0, 2), dtype=torch.int32, device="cuda")
+    lab, n = ctx.two_edge_components(empty, 1)
+    assert n == 1 and lab.tolist() == [0]
+    lab, n = ctx.two_edge_components(empty, 5, 3)
+    assert n == 5 and lab.tolist() == [0, 1, 2, 3, 4]
+    lab, n = ctx.two_edge_components(dev([[1, 1], [3, 3]]), 4)
+    assert n == 4 and lab.tolist() == [0, 1, 2, 3]
+    lab, n = ctx.two_edge_components(dev([[2, 1], [1, 2], [2, 3]]), 4)
+    assert n == 3 and lab.tolist() == [0, 1, 1, 3]
+    import paper_2108_07346_amd as br
+    with pytest.raises(br.BridgeError) as ei:
+        ctx.two_edge_components(dev([[0, 1], [1, 7]]), 4)
+    assert ei.value.code == br.BR_ERANGE
+    lab, n = ctx.two_edge_components(dev([[0, 1], [1, 2], [2, 0]]), 3)     # still usable
+    assert n == 1 and lab.tolist() == [0, 0, 0]
