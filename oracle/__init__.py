@@ -19,7 +19,7 @@ Contents
 ``check_certificate(f1, f2, edges, V)``
     The properties any valid certificate has (forests, disjointness, subset
     of the input, size bound of Lemma 1, same components and bridges), used
-    to judge certificates that are correct but not unique.
+    to check certificates that are correct but not unique.
 ``components(edges, V)``
     Number of connected components (scipy's graph routine).
 ``articulation_points(edges, V)`` / ``brute_articulation_points(edges, V)``
