@@ -275,6 +275,24 @@ __global__ void k_compress_pack(const uint32_t* state, int64_t qs, uint32_t* pac
     }
 }
 
+// Full path compression of the packed states of the nodes that receive in a
+// merge round (node n * stride for n < count), between rounds (no hook runs
+// concurrently).
+__global__ void k_compress_nodes(uint32_t* state, int32_t V, int64_t stride, int64_t count) {
+    const int64_t n = (int64_t)V * count;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t* q = state + (size_t)(k / V) * (size_t)stride * 2 * (size_t)V;
+        const uint32_t x = (uint32_t)(k % V);
+        for (int f = 0; f < 2; f++) {
+            const uint32_t d = q[2 * (size_t)x + f];
+            if (d == 0) continue;
+            uint32_t r = x - d;
+            for (uint32_t e = q[2 * (size_t)r + f]; e != 0; e = q[2 * (size_t)r + f]) r -= e;
+            if (r != x - d) q[2 * (size_t)x + f] = x - r;
+        }
+    }
+}
+
 __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
         p[k] = v;
@@ -358,6 +376,22 @@ void launch_merge_round(const Plan& P, const DevBufs& B, int32_t step, hipStream
     tile = (tile + kBlock - 1) / kBlock * kBlock;
     tile = std::max<int64_t>(kBlock, std::min<int64_t>(tile, kTile));
     const int64_t tpm = std::max<int64_t>(1, (maxcap + tile - 1) / tile);
+    // chunks of at most 2V edges (phase 0 in one stage: nearly every edge a
+    // hook, and so are the first merges): after a round whose sibling
+    // certificates held at least 3V/4 edges each, the receiving states carry
+    // deep trees of fresh hooks; compress them so that this round's finds take
+    // one step (measured: dense M = 64 / 256 / 1024 merges -12 / -13 / -9%,
+    // large M = 4096 -13%; with larger chunks the merges mostly reject and the
+    // pass costs more than it saves)
+    if (step >= 2 && B.qs == 2 && P.stages.size() == 2) {
+        int64_t prev = 0;
+        for (int64_t i = 0; i + step / 2 < P.M; i += step) prev = std::max(prev, P.cap[i + step / 2]);
+        if (4 * prev >= 3 * (int64_t)P.V) {
+            const int64_t n = (int64_t)P.V * merges;
+            hipLaunchKernelGGL(k_compress_nodes, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536))),
+                               dim3(256), 0, s, B.state, P.V, 2 * (int64_t)step, merges);
+        }
+    }
     hipLaunchKernelGGL(k_merge, dim3((unsigned)(merges * tpm)), dim3(kBlock), 0, s, B, P.V, P.M, step, (int32_t)tile,
                        (int32_t)tpm);
 }
