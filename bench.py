@@ -7,11 +7,13 @@ canonical sort -- every step of the path, on input already resident in HBM.
 The same steps with Algorithm 1's depth-first search on the host as the final
 step are reported under "detail".  Prints one JSON line (rank 0, N = 1).
 
-Default workload: the dense configuration (V = 66,536 as 256 clusters of
-256 vertices with p = 0.5, cluster tree, 5 extra cross edges, 1,000 pendant
-vertices; E = 4,178,013), at M = 16 chunks -- the smallest chunk count of the
-configuration's sweep {1, 16, 256, 1024} that runs merge rounds; the whole
-sweep is reported under "detail".
+Default workload: the large configuration (V = 267,144 as 1,024 complete
+clusters of 256 vertices, 996,147,200 uniform inter-cluster edges, cluster
+tree, 5,000 pendant vertices; E = 1,029,576,583, 8.2 GB of int32 pairs) at
+M = 4096 chunks -- the largest configuration that fits one GPU; a sweep over
+M and the dense configuration (V = 66,536, E = 4,178,013, M = 16) are
+reported under "detail".  "achievable" is the read bandwidth a plain
+16-byte-load stream over the same edge list reaches on this device.
 
 Roofline: the dominant kernel is phase 0, the per-chunk certificates (two
 k_phase0 stages with the compression between them, one query's worth); its
@@ -54,6 +56,40 @@ def load_traffic(workload, M):
     return rec.get("bytes_per_launch") if sha == rec.get("kernel_sha") else None
 
 
+def host_info():
+    """The host the CPU numbers come from: CPU model and core counts."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu": model, "nproc": os.cpu_count(), "usable_cores": usable}
+
+
+def achievable_read(d, stream, reps=5):
+    """Read bandwidth of one pass of br_probe_read (16-byte loads) over the
+    edge list, timed with events on the launch stream (GB/s)."""
+    import torch
+    import paper_2108_07346_amd as br
+    for _ in range(2):
+        br.probe_read(d, stream)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        br.probe_read(d, stream)
+    b.record(stream)
+    b.synchronize()
+    ms = a.elapsed_time(b) / reps
+    return d.numel() * d.element_size() / (ms / 1000) / 1e9
+
+
 def cpu_baseline(g, budget_s):
     """The oracle as it stands, single-threaded, on the host."""
     import oracle
@@ -73,8 +109,11 @@ def cpu_baseline(g, budget_s):
         dt = time.perf_counter() - t0
         if dt >= budget_s or (dt > 0 and reps >= 50):
             break
+    h = host_info()
     return {"value": e.shape[0] * reps / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": "%s, %d repetition(s) in %.1f s, one host core" % (sample, reps, dt)}
+            "sample": "%s, %d repetition(s) in %.1f s, one thread of %s (nproc %d)" %
+                      (sample, reps, dt, h["cpu"], h["nproc"]),
+            "host": h}
 
 
 def bench_batched(args):
@@ -414,9 +453,10 @@ def bench_served(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="dense", choices=["small", "dense", "large", "batched", "served", "figures", "articulation", "classes"])
+    ap.add_argument("--workload", default="large", choices=["small", "dense", "large", "large_blocked", "batched", "served",
+                                                            "figures", "articulation", "classes"])
     ap.add_argument("--qps", default="100,200,500,1000,2000,5000", help="served: comma-separated QPS")
     ap.add_argument("--seconds", type=float, default=2.0, help="served: seconds per QPS point")
     ap.add_argument("--max-requests", type=int, default=600, help="served: cap per QPS point")
@@ -462,7 +502,7 @@ def main():
         return bench_articulation(args)
     if args.workload == "classes":
         return bench_classes(args)
-    M = args.M or {"small": 4, "dense": 16, "large": 4096}[args.workload]
+    M = args.M or {"small": 4, "dense": 16, "large": 4096, "large_blocked": 4096}[args.workload]
     t0 = time.perf_counter()
     g = graphgen.config(args.workload)
     t_gen = time.perf_counter() - t0
@@ -517,6 +557,8 @@ def main():
                              "ms_d2h": round(hph["ms_d2h"], 5), "ms_dfs": round(hph["ms_dfs"], 5)}
     print("bench: host search %s" % json.dumps(detail["host_search"]), file=sys.stderr, flush=True)
     sweep_ms = {"dense": (1, 16, 256, 1024), "large": (64, 256, 1024, 4096)}.get(args.workload)
+    achievable = achievable_read(d, stream)
+    print("bench: read stream over the edge list %.0f GB/s" % achievable, file=sys.stderr, flush=True)
     if sweep_ms and not args.no_sweep:
         sweep = {}
         reps = 10 if args.workload == "dense" else 2
@@ -530,6 +572,29 @@ def main():
                               if sph["ms_phase0"] > 0 else None}
             print("bench: sweep M=%d %s" % (Mx, json.dumps(sweep[str(Mx)])), file=sys.stderr, flush=True)
         detail["m_sweep"] = sweep
+
+    if args.workload == "large" and not args.no_sweep:
+        # the dense configuration beside it (M = 16), whole query
+        gd = graphgen.config("dense")
+        dd = torch.from_numpy(gd.edges).cuda()
+        for _ in range(3):
+            ctx.find(dd, gd.V, 16, stream)
+        ctx.set_profiling(True)
+        accd = {"ms_phase0": 0.0, "ms_merge": 0.0, "ms_bridge_dev": 0.0}
+        torch.cuda.synchronize()
+        td = time.perf_counter()
+        for _ in range(20):
+            ctx.find(dd, gd.V, 16, stream)
+            p = ctx.profile()
+            for k in accd:
+                accd[k] += p[k] / 20
+        torch.cuda.synchronize()
+        dtd = (time.perf_counter() - td) / 20
+        detail["dense_M16"] = {"V": gd.V, "E": gd.E, "edges_per_s": gd.E / dtd, "ms_per_step": 1000 * dtd,
+                               **{k: round(v, 5) for k, v in accd.items()},
+                               "phase0_frac_hbm": 8.0 * gd.E / (accd["ms_phase0"] / 1000) / 1e9 / PEAK_GBS}
+        print("bench: dense M=16 %s" % json.dumps(detail["dense_M16"]), file=sys.stderr, flush=True)
+        del dd
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -552,8 +617,9 @@ def main():
         "config": {"workload": args.workload, "V": g.V, "E": g.E, "M": M, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_GBS, "traffic": traffic,
-                     "kernel": "phase 0 per query: k_phase0 (two stages) + k_compress_pack",
-                     "algorithmic_bytes_per_launch": 8 * g.E},
+                     "kernel": "phase 0 per query (k_phase0 stages and the compressions between them)",
+                     "algorithmic_bytes_per_launch": 8 * g.E,
+                     "achievable_read_GBs": achievable},
         "cpu_baseline": cpu,
         "detail": detail,
     }

@@ -14,6 +14,10 @@ holds the workload recipes:
   262,144 * 7,600 / 2 i.i.d. uniform inter-cluster edges (drawn with
   replacement, so a few parallel copies occur), cluster tree,
   5,000 pendant vertices; M=4096.
+* ``large_blocked`` -- as ``large`` with 262,144 * 1,300 / 2 cross edges,
+  each inside one of 32 blocks of 32 clusters, and a cluster tree made of a
+  tree per block plus a tree over the blocks: the 31 tree edges between
+  blocks and the 5,000 pendant edges are the bridges.
 * ``batched`` -- 4,096 graphs; graph g has V log-uniform in [64, 4096],
   k uniform in {2..16} near-equal clusters, p uniform in [0.05, 0.5], a
   cluster tree and stochastic round(f * (k-1)) extra edges, f ~ U[0, 0.03].
@@ -60,7 +64,7 @@ def _load():
     lib = ctypes.CDLL(_SO)
     vp, i64, i32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64
     lib.gg_plan.restype = vp
-    lib.gg_plan.argtypes = [u64, i32, i64, ctypes.c_double, i64, i64, i64, ctypes.c_int, ctypes.c_int]
+    lib.gg_plan.argtypes = [u64, i32, i64, ctypes.c_double, i64, i64, i64, ctypes.c_int, ctypes.c_int, i32]
     lib.gg_V.restype = i64
     lib.gg_V.argtypes = [vp]
     lib.gg_E.restype = i64
@@ -99,13 +103,17 @@ class Graph:
 
 
 def planted(seed: int, k: int, vc: int, p: float, n_extra: int = 0, n_cross: int = 0,
-            n_pend: int = 0, relabel: bool = True, shuffle: bool = True) -> Graph:
-    """Generate one planted-cluster graph (see the module docstring)."""
+            n_pend: int = 0, relabel: bool = True, shuffle: bool = True, cross_block: int = 0) -> Graph:
+    """Generate one planted-cluster graph (see the module docstring).  With
+    cross_block = b > 0 (b >= 2 dividing k) the cross edges stay inside blocks
+    of b consecutive clusters and the cluster tree is a tree per block plus a
+    tree over the blocks."""
     lib = _load()
-    h = lib.gg_plan(seed & (2**64 - 1), k, vc, float(p), n_extra, n_cross, n_pend, int(relabel), int(shuffle))
+    h = lib.gg_plan(seed & (2**64 - 1), k, vc, float(p), n_extra, n_cross, n_pend, int(relabel), int(shuffle),
+                    int(cross_block))
     if not h:
-        raise ValueError("graphgen: invalid parameters k=%d vc=%d p=%g extra=%d cross=%d pend=%d"
-                         % (k, vc, p, n_extra, n_cross, n_pend))
+        raise ValueError("graphgen: invalid parameters k=%d vc=%d p=%g extra=%d cross=%d pend=%d block=%d"
+                         % (k, vc, p, n_extra, n_cross, n_pend, cross_block))
     try:
         V, E = lib.gg_V(h), lib.gg_E(h)
         edges = np.empty((E, 2), dtype=np.int32)
@@ -121,7 +129,8 @@ def planted(seed: int, k: int, vc: int, p: float, n_extra: int = 0, n_cross: int
     finally:
         lib.gg_free(h)
     return Graph(edges, int(V), tree, extra, pend, int(n_intra), cluster,
-                 dict(seed=seed, k=k, vc=vc, p=p, n_extra=n_extra, n_cross=n_cross, n_pend=n_pend))
+                 dict(seed=seed, k=k, vc=vc, p=p, n_extra=n_extra, n_cross=n_cross, n_pend=n_pend,
+                      cross_block=cross_block))
 
 
 def unit(seed: int, tag: int, i: int) -> float:
@@ -135,11 +144,16 @@ PLAIN = {
     "small": dict(k=20, vc=2000, p=0.1, n_extra=0, n_cross=0, n_pend=30, M=[4]),
     "dense": dict(k=256, vc=65536, p=0.5, n_extra=5, n_cross=0, n_pend=1000, M=[1, 16, 256, 1024]),
     "large": dict(k=1024, vc=262144, p=1.0, n_extra=0, n_cross=262144 * 7600 // 2, n_pend=5000, M=[4096]),
+    # the large layout with the cross edges kept inside 32 blocks of 32
+    # clusters (average cross degree 1,300: about 2.0e8 edges), so that the 31
+    # tree edges between blocks stay bridges through every merge round
+    "large_blocked": dict(k=1024, vc=262144, p=1.0, n_extra=0, n_cross=262144 * 1300 // 2, n_pend=5000,
+                          cross_block=32, M=[4096, 512]),
 }
 
 
 def config(name: str, seed: int = 0) -> Graph:
-    """One of the plain workloads: 'small', 'dense' or 'large'."""
+    """One of the plain workloads: 'small', 'dense', 'large' or 'large_blocked'."""
     c = dict(PLAIN[name])
     c.pop("M")
     g = planted(seed, **c)

@@ -14,7 +14,12 @@
  *     clusters, resampled so that they repeat no tree edge and no other extra
  *     edge (the graph stays simple);
  *   - n_cross i.i.d. uniform edges between vertices of distinct clusters,
- *     drawn with replacement (parallel copies are kept: multigraph);
+ *     drawn with replacement (parallel copies are kept: multigraph); with
+ *     cross_block = b > 0 the clusters form blocks of b consecutive clusters,
+ *     the cluster tree is a random tree inside every block plus a random tree
+ *     over the blocks (each of its edges joining random clusters of the two
+ *     blocks), and each cross edge joins two distinct clusters of one block;
+ *     the tree edges between blocks then stay uncovered by cross edges;
  *   - n_pend pendant vertices with ids vc..vc+n_pend-1, each joined by one
  *     edge to a uniformly random cluster vertex.
  * Then (optionally) the vertex ids are relabelled by a keyed bijection of
@@ -48,7 +53,7 @@ static inline uint64_t below(uint64_t r, uint64_t n) { return (uint64_t)(((unsig
 
 /* stream tags */
 enum { T_INTRA = 1, T_TREE = 2, T_TREE_END = 3, T_EXTRA = 4, T_PEND = 5, T_CROSS = 6,
-       T_RELABEL = 7, T_SHUFFLE = 8, T_ORIENT = 9 };
+       T_RELABEL = 7, T_SHUFFLE = 8, T_ORIENT = 9, T_BLOCK_TREE = 10 };
 
 /* ---- keyed bijection of [0,n) ------------------------------------------- */
 typedef struct { uint64_t n, key; int half; uint64_t mask; } perm_t;
@@ -75,7 +80,7 @@ static inline uint64_t perm_apply(const perm_t* P, uint64_t x) {
 /* ---- graph description ---------------------------------------------------- */
 typedef struct gg_graph {
     uint64_t key;
-    int32_t k;
+    int32_t k, cross_block;
     int64_t vc, n_pend, n_extra, n_cross;
     double p;
     int relabel, shuffle;
@@ -154,19 +159,42 @@ void gg_free(gg_graph* G) {
     free(G->cl_off); free(G->cnt_off); free(G->tree); free(G->extra); free(G);
 }
 
+/* A uniformly random labelled tree on n nodes (Pruefer sequence of length
+ * n-2 drawn from stream tk at counters base.., decoded in linear time): its
+ * n-1 edges as node pairs into ce[2(n-1)]. */
+static void pruefer_tree(uint64_t tk, uint64_t base, int32_t n, int32_t* ce) {
+    if (n < 2) return;
+    int32_t* seq = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 2 ? n - 2 : 1));
+    int32_t* deg = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    for (int32_t i = 0; i < n; i++) deg[i] = 1;
+    for (int32_t i = 0; i < n - 2; i++) { seq[i] = (int32_t)below(rng_at(tk, base + (uint64_t)i), (uint64_t)n); deg[seq[i]]++; }
+    int32_t ptr = 0; while (deg[ptr] != 1) ptr++;
+    int32_t leaf = ptr, ne = 0;
+    for (int32_t i = 0; i < n - 2; i++) {
+        int32_t x = seq[i];
+        ce[2 * ne] = leaf; ce[2 * ne + 1] = x; ne++;
+        deg[x]--;
+        if (deg[x] == 1 && x < ptr) leaf = x;
+        else { ptr++; while (deg[ptr] != 1) ptr++; leaf = ptr; }
+    }
+    ce[2 * ne] = leaf; ce[2 * ne + 1] = n - 1;
+    free(seq); free(deg);
+}
+
 /*
  * Plan a graph: draws the cluster tree and extra edges, counts the intra
  * edges.  Returns NULL on bad parameters.  gg_V / gg_E then give the sizes.
  */
 gg_graph* gg_plan(uint64_t seed, int32_t k, int64_t vc, double p, int64_t n_extra, int64_t n_cross,
-                  int64_t n_pend, int relabel, int shuffle) {
+                  int64_t n_pend, int relabel, int shuffle, int32_t cross_block) {
     if (k < 1 || vc < k || p < 0.0 || p > 1.0 || n_extra < 0 || n_cross < 0 || n_pend < 0) return NULL;
+    if (cross_block < 0 || cross_block == 1 || (cross_block > 0 && k % cross_block != 0)) return NULL;
     if (vc + n_pend > 2147483647LL) return NULL;
     if (k < 2 && (n_extra > 0 || n_cross > 0)) return NULL;
     gg_graph* G = (gg_graph*)calloc(1, sizeof(gg_graph));
     G->key = mix64(seed ^ 0x5EEDBA5E5EEDBA5EULL);
     G->k = k; G->vc = vc; G->p = p; G->n_extra = n_extra; G->n_cross = n_cross; G->n_pend = n_pend;
-    G->relabel = relabel; G->shuffle = shuffle;
+    G->relabel = relabel; G->shuffle = shuffle; G->cross_block = cross_block;
     G->V = vc + n_pend;
     G->thr = (p >= 1.0) ? ((uint64_t)1 << 53) : (uint64_t)(p * 9007199254740992.0);
     G->cl_off = (int64_t*)malloc(sizeof(int64_t) * (size_t)(k + 1));
@@ -184,32 +212,39 @@ gg_graph* gg_plan(uint64_t seed, int32_t k, int64_t vc, double p, int64_t n_extr
     for (int32_t j = 0; j < k; j++) G->cnt_off[j + 1] += G->cnt_off[j];
     G->n_intra = G->cnt_off[k];
 
-    /* cluster tree: Pruefer sequence of length k-2, decoded in linear time */
+    /* cluster tree: Pruefer sequence of length k-2, decoded in linear time;
+       with blocks, a tree inside each block (counters after the block's
+       first) and a tree over the blocks (a separate stream) */
     G->tree = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)(k > 1 ? k - 1 : 1));
     if (k >= 2) {
         uint64_t tk = subkey(G->key, T_TREE);
-        int32_t* seq = (int32_t*)malloc(sizeof(int32_t) * (size_t)(k > 2 ? k - 2 : 1));
-        int32_t* deg = (int32_t*)malloc(sizeof(int32_t) * (size_t)k);
-        for (int32_t i = 0; i < k; i++) deg[i] = 1;
-        for (int32_t i = 0; i < k - 2; i++) { seq[i] = (int32_t)below(rng_at(tk, (uint64_t)i), (uint64_t)k); deg[seq[i]]++; }
-        int32_t ptr = 0; while (deg[ptr] != 1) ptr++;
-        int32_t leaf = ptr, ne = 0;
         int32_t* ce = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)(k - 1));
-        for (int32_t i = 0; i < k - 2; i++) {
-            int32_t x = seq[i];
-            ce[2 * ne] = leaf; ce[2 * ne + 1] = x; ne++;
-            deg[x]--;
-            if (deg[x] == 1 && x < ptr) leaf = x;
-            else { ptr++; while (deg[ptr] != 1) ptr++; leaf = ptr; }
+        int32_t ne = 0;
+        if (cross_block == 0) {
+            pruefer_tree(tk, 0, k, ce);
+            ne = k - 1;
+        } else {
+            const int32_t b = cross_block, nb = k / b;
+            int32_t* be = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)(b > nb ? b : nb));
+            for (int32_t t = 0; t < nb; t++) {
+                pruefer_tree(tk, (uint64_t)t * (uint64_t)b, b, be);
+                for (int32_t i = 0; i < b - 1; i++, ne++) { ce[2 * ne] = t * b + be[2 * i]; ce[2 * ne + 1] = t * b + be[2 * i + 1]; }
+            }
+            uint64_t bk = subkey(G->key, T_BLOCK_TREE);
+            pruefer_tree(bk, 0, nb, be);
+            for (int32_t i = 0; i + 1 < nb; i++, ne++) {
+                ce[2 * ne] = be[2 * i] * b + (int32_t)below(rng_at(bk, (uint64_t)k + 2 * (uint64_t)i), (uint64_t)b);
+                ce[2 * ne + 1] = be[2 * i + 1] * b + (int32_t)below(rng_at(bk, (uint64_t)k + 2 * (uint64_t)i + 1), (uint64_t)b);
+            }
+            free(be);
         }
-        ce[2 * ne] = leaf; ce[2 * ne + 1] = k - 1; ne++;
         uint64_t ek = subkey(G->key, T_TREE_END);
         for (int32_t i = 0; i < ne; i++) {
             int32_t ca = ce[2 * i], cb = ce[2 * i + 1];
             G->tree[2 * i] = (int32_t)(G->cl_off[ca] + (int64_t)below(rng_at(ek, 2 * (uint64_t)i), (uint64_t)cl_size(G, ca)));
             G->tree[2 * i + 1] = (int32_t)(G->cl_off[cb] + (int64_t)below(rng_at(ek, 2 * (uint64_t)i + 1), (uint64_t)cl_size(G, cb)));
         }
-        free(seq); free(deg); free(ce);
+        free(ce);
     }
     /* extra inter-cluster edges, resampled on repeats (simple graph) */
     G->extra = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)(n_extra > 0 ? n_extra : 1));
@@ -267,8 +302,16 @@ static void task_cross(void* a, int64_t t) {
     for (int64_t i = lo; i < hi; i++) {
         int64_t u = (int64_t)below(rng_at(ck, 2 * (uint64_t)i), (uint64_t)G->vc);
         int32_t cu = cl_of(G, u);
-        int64_t v = (int64_t)below(rng_at(ck, 2 * (uint64_t)i + 1), (uint64_t)(G->vc - cl_size(G, cu)));
-        if (v >= G->cl_off[cu]) v += cl_size(G, cu);
+        int64_t v;
+        if (G->cross_block == 0) {
+            v = (int64_t)below(rng_at(ck, 2 * (uint64_t)i + 1), (uint64_t)(G->vc - cl_size(G, cu)));
+            if (v >= G->cl_off[cu]) v += cl_size(G, cu);
+        } else {       /* a vertex of another cluster of u's block */
+            const int32_t b0 = cu / G->cross_block * G->cross_block;
+            const int64_t lo_v = G->cl_off[b0], hi_v = G->cl_off[b0 + G->cross_block];
+            v = lo_v + (int64_t)below(rng_at(ck, 2 * (uint64_t)i + 1), (uint64_t)(hi_v - lo_v - cl_size(G, cu)));
+            if (v >= G->cl_off[cu]) v += cl_size(G, cu);
+        }
         dst[2 * i] = (int32_t)u; dst[2 * i + 1] = (int32_t)v;
     }
 }

@@ -18,7 +18,12 @@
  *     depth-first search itself on the host (br_set_final_step).
  *
  * Conventions for every entry point
- *   - Vertex ids are int32 in [0, V) with 1 <= V <= 2^31 - 1.
+ *   - Vertex ids are int32 in [0, V) with 1 <= V <= 2^31 - 1 for the
+ *     certificate calls (br_cert_build, br_cert_merge); the calls that run a
+ *     final step on the certificate (br_bridges_find, br_two_edge_components,
+ *     br_articulation_points, br_certificate_bridges) take 1 <= V <= 2^29:
+ *     they count the 2(V-1) arcs of the certificate forest's tours in 30-bit
+ *     fields.  A larger V is BR_EINVAL before any device work.
  *   - An edge list is int32 [E][2] (array of pairs, 8 bytes per edge), each
  *     undirected edge listed once in either orientation.  Self-loops are
  *     accepted and never bridges; parallel edges are accepted (multigraph:
@@ -31,6 +36,11 @@
  *   - A stream argument is a hipStream_t passed as void* (NULL = the null
  *     stream).  Calls marked "asynchronous" enqueue work on it and return;
  *     calls marked "synchronous" return after the result is on the host.
+ *     Every call on a context is ordered after the device work of the
+ *     previous call on that context, whatever streams the two use (they
+ *     share the context's workspace); the caller orders its own buffers
+ *     (inputs ready before the call, outputs read after the stream).  Device
+ *     inputs are read on the stream passed in.
  *   - Return value: BR_OK or a negative BR_E* code; br_last_error() then
  *     gives a message (thread-local).  Nothing is thrown across the ABI.
  *   - A context is used by one host thread at a time.
@@ -224,7 +234,10 @@ int br_articulation_points(br_ctx* ctx, const int32_t* d_edges, int64_t E, int32
 /*
  * Serving: continuous batching of bridge queries on one device.
  *   br_server_create  device, device-memory budget in bytes for resident
- *                     requests (edge lists, union-find state, certificates),
+ *                     requests (edge lists, union-find state, certificates;
+ *                     a slot keeps its buffers between requests and they stay
+ *                     charged until the scheduler releases them to admit a
+ *                     request that would not fit otherwise),
  *                     max_slots (1..64) requests in flight on the device at
  *                     once, each on its own stream; a request is admitted,
  *                     in arrival order, as soon as a slot is free and the
@@ -250,19 +263,36 @@ typedef struct br_server_stats_t {
     double p50_ms, p99_ms, mean_ms, max_ms;
     double edges_per_s;    /* edges of completed requests / busy wall time */
     int64_t peak_inflight; /* most requests resident on the device at once */
+    int64_t device_bytes;  /* device memory the slots hold now (charged to the budget) */
+    int64_t peak_device_bytes; /* the most they held at once (never above the budget
+                                  unless a single request larger than the others' room ran alone) */
 } br_server_stats_t;
 int br_server_create(br_server** srv, int device, int64_t mem_budget, int32_t max_slots);
 int br_submit(br_server* srv, const int32_t* h_edges, int64_t E, int32_t V, uint64_t* ticket);
 /* As br_submit for an edge list already resident on the server's device
  * (d_edges [E][2]); the caller keeps it alive and unchanged until the ticket
- * is done.  Nothing is copied. */
+ * is done.  Nothing is copied.  The edges must be complete when the call is
+ * made (the server reads them on its own streams, unordered with the
+ * caller's: synchronise the stream that wrote them first). */
 int br_submit_device(br_server* srv, const int32_t* d_edges, int64_t E, int32_t V, uint64_t* ticket);
 int br_poll(br_server* srv, uint64_t ticket, int32_t* h_out, int64_t cap, int64_t* n, int* done);
 int br_wait(br_server* srv, uint64_t ticket, int32_t* h_out, int64_t cap, int64_t* n);
 int br_server_stats(br_server* srv, br_server_stats_t* out, int reset);
-/* Final step of the requests admitted from now on (see br_set_final_step). */
+/* Final step of the requests admitted from now on (see br_set_final_step);
+ * each request keeps the mode it was admitted with, requests already queued
+ * or running are not affected. */
 int br_server_set_final_step(br_server* srv, int mode);
 int br_server_destroy(br_server* srv);
+
+/*
+ * br_probe_read -- measurement utility, not a step of the method: reads
+ * d_buf [bytes] once with 16-byte loads (d_buf 16-byte aligned) and adds a
+ * fold of what it read to *d_sink (device uint64), asynchronously on
+ * `stream`.  Timed around its launch it gives the read bandwidth the device
+ * reaches, which benchmarks report beside the HBM peak.  BR_EINVAL for a null
+ * or misaligned pointer or bytes < 0.
+ */
+int br_probe_read(const void* d_buf, int64_t bytes, uint64_t* d_sink, void* stream);
 
 #ifdef __cplusplus
 }

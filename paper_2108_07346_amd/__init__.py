@@ -22,7 +22,7 @@ EXPORTS = ["br_last_error", "br_create", "br_destroy", "br_cert_build", "br_cert
            "br_certificate_bridges", "br_two_edge_components", "br_articulation_points",
            "br_bridges_find_batched", "br_batched_max_v", "br_set_profiling", "br_set_final_step", "br_get_profile",
            "br_server_create", "br_submit", "br_submit_device", "br_poll", "br_wait", "br_server_stats",
-           "br_server_set_final_step", "br_server_destroy"]
+           "br_server_set_final_step", "br_server_destroy", "br_probe_read"]
 
 
 class BridgeError(RuntimeError):
@@ -41,7 +41,8 @@ class _Profile(ctypes.Structure):
 class _ServerStats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_int64), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
                 ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double), ("edges_per_s", ctypes.c_double),
-                ("peak_inflight", ctypes.c_int64)]
+                ("peak_inflight", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("peak_device_bytes", ctypes.c_int64)]
 
 
 _lib = None
@@ -79,6 +80,7 @@ def load():
     lib.br_server_stats.argtypes = [vp, ctypes.POINTER(_ServerStats), ctypes.c_int]
     lib.br_server_set_final_step.argtypes = [vp, ctypes.c_int]
     lib.br_server_destroy.argtypes = [vp]
+    lib.br_probe_read.argtypes = [vp, i64, vp, vp]
     _lib = lib
     return lib
 
@@ -131,7 +133,8 @@ class Context:
         _check(self._lib.br_set_profiling(self._h, int(on)))
 
     def set_final_step(self, mode: int):
-        """0: host search (Algorithm 1, default); 1: device bridge step."""
+        """1: bridge step on the GPU (the library's default); 0: Algorithm 1's
+        search on the host over the copied certificate."""
         _check(self._lib.br_set_final_step(self._h, int(mode)))
 
     def profile(self) -> dict:
@@ -167,9 +170,14 @@ class Context:
                                                 _stream(stream)))
         return out[:n.value].copy()
 
-    def _cert_result(self, out, counts):
+    def _cert_result(self, out, counts, stream):
         import torch
-        torch.cuda.current_stream().synchronize()
+        if stream is None:
+            torch.cuda.current_stream().synchronize()
+        elif hasattr(stream, "synchronize"):
+            stream.synchronize()
+        else:                                   # a raw hipStream_t handle
+            torch.cuda.ExternalStream(int(stream)).synchronize()
         n1, n2, st = (int(x) for x in counts.cpu().tolist())
         if st != BR_OK:
             raise BridgeError(st, "certificate kernel reported status %d" % st)
@@ -184,7 +192,7 @@ class Context:
         counts = torch.zeros(3, dtype=torch.int64, device=edges.device)
         _check(self._lib.br_cert_build(self._h, ptr, E, int(V), int(M), ctypes.c_void_p(out.data_ptr()), cap,
                                        ctypes.c_void_p(counts.data_ptr()), _stream(stream)))
-        return self._cert_result(out, counts)
+        return self._cert_result(out, counts, stream)
 
     def cert_merge(self, a, b, V: int, stream=None):
         """Certificate of the union of two edge lists; device tensors (F, F')."""
@@ -196,7 +204,7 @@ class Context:
         counts = torch.zeros(3, dtype=torch.int64, device=a.device)
         _check(self._lib.br_cert_merge(self._h, pa, Ea, pb, Eb, int(V), ctypes.c_void_p(out.data_ptr()), cap,
                                        ctypes.c_void_p(counts.data_ptr()), _stream(stream)))
-        return self._cert_result(out, counts)
+        return self._cert_result(out, counts, stream)
 
     def find_batched(self, edges, offsets, Vs, chunk_edges: int = 0, stream=None):
         """Bridges of G packed graphs; returns (pairs int32 [B,2], offsets int64 [G+1])."""
@@ -229,7 +237,11 @@ class Server:
         int32 [E, 2] CUDA tensor that must stay alive until the ticket is done."""
         t = ctypes.c_uint64(0)
         if hasattr(edges, "is_cuda") and edges.is_cuda:
+            import torch
             ptr, E = _edges_arg(edges)
+            # the server reads the edges on its own streams: the stream that
+            # produced them must be done first
+            torch.cuda.current_stream(edges.device).synchronize()
             _check(self._lib.br_submit_device(self._h, ptr, E, int(V), ctypes.byref(t)))
         else:
             e = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
@@ -309,6 +321,16 @@ def certificate_bridges(f1, f2, V: int) -> np.ndarray:
                                          b.ctypes.data if b.shape[0] else None, b.shape[0], int(V),
                                          out.ctypes.data, cap, ctypes.byref(n)))
     return out[:n.value].copy()
+
+
+def probe_read(buf, stream=None) -> None:
+    """Read a device tensor once with 16-byte loads (a measurement utility,
+    not a step of the method; time it with events on `stream`)."""
+    import torch
+    sink = torch.zeros(1, dtype=torch.int64, device=buf.device)
+    _check(load().br_probe_read(ctypes.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size(),
+                                ctypes.c_void_p(sink.data_ptr()), _stream(stream)))
+    return sink
 
 
 def batched_max_v() -> int:

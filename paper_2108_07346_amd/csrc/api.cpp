@@ -76,10 +76,24 @@ Plan make_plan(int64_t E, int32_t V, int32_t M) {
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+int ctx_begin(br_ctx* c, hipStream_t s) {
+    if (c->done_recorded) BR_HIP(hipStreamWaitEvent(s, c->ev_done, 0));
+    return BR_OK;
+}
+
+int ctx_end(br_ctx* c, hipStream_t s) {
+    BR_HIP(hipEventRecord(c->ev_done, s));
+    c->done_recorded = true;
+    return BR_OK;
+}
+
 int ensure_workspace(br_ctx* c, size_t bytes, hipStream_t s) {
     if (c->ws.size >= bytes) return BR_OK;
-    size_t want = std::max(bytes, c->ws.size + c->ws.size / 4);
+    // a context that serves requests under a memory budget holds exactly what
+    // it was charged for; others grow by a quarter to avoid reallocating often
+    size_t want = c->exact_ws ? bytes : std::max(bytes, c->ws.size + c->ws.size / 4);
     BR_HIP(hipStreamSynchronize(s));
+    if (c->done_recorded) BR_HIP(hipEventSynchronize(c->ev_done));
     if (c->ws.base) BR_HIP(hipFree(c->ws.base));
     c->ws.base = nullptr;
     c->ws.size = 0;
@@ -138,10 +152,10 @@ static double ev_ms(br_ctx* c, int a, int b) {
 }
 
 int run_certificate(br_ctx* c, const int32_t* d_a, int64_t Ea, const int32_t* d_b, int64_t Eb, int32_t V, int32_t M,
-                    hipStream_t s, Plan& P, DevBufs& B) {
+                    hipStream_t s, Plan& P, DevBufs& B, bool device_final) {
     const int64_t E = Ea + Eb;
     P = make_plan(E, V, M);
-    const Layout L = layout(P, c->final_step == 1);
+    const Layout L = layout(P, device_final);
     int rc = ensure_workspace(c, L.total, s);
     if (rc) return rc;
     rc = ensure_pinned(c, 64 << 10);
@@ -182,11 +196,11 @@ int run_certificate(br_ctx* c, const int32_t* d_a, int64_t Ea, const int32_t* d_
     ev_record(c, 1, s);
     launch_phase0(P, B, s);
     BR_HIP(hipGetLastError());
+    c->prof.launches += phase0_launches(P);
     ev_record(c, 2, s);
     for (int32_t step = 1; step < M; step *= 2) {
-        launch_merge_round(P, B, step, s);
+        c->prof.launches += launch_merge_round(P, B, step, s);
         BR_HIP(hipGetLastError());
-        c->prof.launches++;
     }
     ev_record(c, 3, s);
     c->prof.rounds = P.rounds;
@@ -211,9 +225,13 @@ int br_create(br_ctx** out, int device) {
     c->device = device;
     for (auto& e : c->ev) {
         if (hipEventCreate(&e) != hipSuccess) {
-            delete c;
+            br_destroy(c);
             return hip_fail(hipGetLastError(), "hipEventCreate");
         }
+    }
+    if (hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming) != hipSuccess) {
+        br_destroy(c);
+        return hip_fail(hipGetLastError(), "hipEventCreate");
     }
     *out = c;
     return BR_OK;
@@ -229,6 +247,7 @@ int br_destroy(br_ctx* c) {
     if (c->h_meta) (void)hipHostFree(c->h_meta);
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
+    if (c->ev_done) (void)hipEventDestroy(c->ev_done);
     delete c;
     return BR_OK;
 }
@@ -272,13 +291,15 @@ int br_cert_build(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int32
     BR_HIP(hipSetDevice(c->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     BR_HIP(hipEventSynchronize(c->ev[7]));
+    rc = ctx_begin(c, s);
+    if (rc) return rc;
     Plan P;
     DevBufs B;
-    rc = run_certificate(c, d_edges, E, nullptr, 0, V, M, s, P, B);
+    rc = run_certificate(c, d_edges, E, nullptr, 0, V, M, s, P, B, false);
     if (rc) return rc;
     launch_copy_out(P, B, d_cert, cert_cap, d_counts, s);
     BR_HIP(hipGetLastError());
-    return BR_OK;
+    return ctx_end(c, s);
 }
 
 int br_cert_merge(br_ctx* c, const int32_t* d_a, int64_t Ea, const int32_t* d_b, int64_t Eb, int32_t V,
@@ -294,15 +315,17 @@ int br_cert_merge(br_ctx* c, const int32_t* d_a, int64_t Ea, const int32_t* d_b,
     BR_HIP(hipSetDevice(c->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     BR_HIP(hipEventSynchronize(c->ev[7]));
+    int rc = ctx_begin(c, s);
+    if (rc) return rc;
     // Certificate(A u B): one fused pass over the concatenation (Section III's
     // merge step re-runs the certificate algorithm on the union).
     Plan P;
     DevBufs B;
-    int rc = run_certificate(c, d_a, Ea, d_b, Eb, V, 1, s, P, B);
+    rc = run_certificate(c, d_a, Ea, d_b, Eb, V, 1, s, P, B, false);
     if (rc) return rc;
     launch_copy_out(P, B, d_out, cap, d_counts, s);
     BR_HIP(hipGetLastError());
-    return BR_OK;
+    return ctx_end(c, s);
 }
 
 int br_bridges_find(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int32_t M, int32_t* h_bridges,
@@ -312,20 +335,23 @@ int br_bridges_find(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int
     if (rc) return rc;
     if (M < 1) return fail(BR_EINVAL, "M = %d < 1", M);
     if (cap < 0) return fail(BR_EINVAL, "cap < 0");
-    if (V > (1 << 29)) return fail(BR_EINVAL, "V = %d above the host search limit 2^29", V);
+    if (V > kFinalStepMaxV) return fail(BR_EINVAL, "V = %d above the final step's limit 2^29", V);
     auto t0 = std::chrono::steady_clock::now();
     BR_HIP(hipSetDevice(c->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     BR_HIP(hipEventSynchronize(c->ev[7]));
+    rc = ctx_begin(c, s);
+    if (rc) return rc;
+    const int mode = c->final_step;   // read once: the workspace layout depends on it
     Plan P;
     DevBufs B;
-    rc = run_certificate(c, d_edges, E, nullptr, 0, V, M, s, P, B);
+    rc = run_certificate(c, d_edges, E, nullptr, 0, V, M, s, P, B, mode == 1);
     if (rc) return rc;
     const int64_t cap0 = P.cap[0];
     uint32_t n1 = 0, n2 = 0, err = 0;
     std::chrono::steady_clock::time_point t1, t2;
     c->keys.clear();
-    if (c->final_step == 1) {
+    if (mode == 1) {
         // final step on the device: only the bridges come back
         uint64_t* d_keys = nullptr;
         uint32_t* d_n = nullptr;
@@ -341,6 +367,8 @@ int br_bridges_find(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int
         uint64_t* hk = reinterpret_cast<uint64_t*>(static_cast<char*>(c->pinned) + 256);
         const size_t guess = std::min<size_t>(std::max<size_t>(c->keys_hint, 1024), (size_t)V);
         BR_HIP(hipMemcpyAsync(hc, d_n - 1, 256 + 8 * guess, hipMemcpyDeviceToHost, s));
+        rc = ctx_end(c, s);
+        if (rc) return rc;
         BR_HIP(hipStreamSynchronize(s));
         n1 = hc[2]; n2 = hc[3]; err = hc[4];
         const uint32_t nk = std::min<uint32_t>(hc[1], (uint32_t)std::max(V - 1, 0));
@@ -368,6 +396,8 @@ int br_bridges_find(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int
         BR_HIP(hipMemcpyAsync(hc + 2, B.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         if (cap0 > 0) BR_HIP(hipMemcpyAsync(hx, B.cert + P.off[0], sizeof(int2) * cap0, hipMemcpyDeviceToHost, s));
         ev_record(c, 4, s);
+        rc = ctx_end(c, s);
+        if (rc) return rc;
         BR_HIP(hipStreamSynchronize(s));
         t1 = std::chrono::steady_clock::now();
         n1 = hc[0]; n2 = hc[1]; err = hc[2];
@@ -389,7 +419,7 @@ int br_bridges_find(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int
         c->prof.ms_merge = ev_ms(c, 2, 3);
         c->prof.ms_cert = ev_ms(c, 0, 3);
         c->prof.ms_d2h = ev_ms(c, 3, 4);
-        c->prof.ms_bridge_dev = c->final_step == 1 ? ev_ms(c, 3, 5) : 0.0;
+        c->prof.ms_bridge_dev = mode == 1 ? ev_ms(c, 3, 5) : 0.0;
         c->prof.cert_f1 = n1;
         c->prof.cert_f2 = n2;
     }
@@ -410,15 +440,18 @@ int br_two_edge_components(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t
     int rc = check_common(d_edges, E, V);
     if (rc) return rc;
     if (M < 1) return fail(BR_EINVAL, "M = %d < 1", M);
-    if (V > (1 << 29)) return fail(BR_EINVAL, "V = %d above the host search limit 2^29", V);
+    if (V > kFinalStepMaxV) return fail(BR_EINVAL, "V = %d above the final step's limit 2^29", V);
     BR_HIP(hipSetDevice(c->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     BR_HIP(hipEventSynchronize(c->ev[7]));
+    rc = ctx_begin(c, s);
+    if (rc) return rc;
+    const int mode = c->final_step;   // read once: the workspace layout depends on it
     Plan P;
     DevBufs B;
-    rc = run_certificate(c, d_edges, E, nullptr, 0, V, M, s, P, B);
+    rc = run_certificate(c, d_edges, E, nullptr, 0, V, M, s, P, B, mode == 1);
     if (rc) return rc;
-    if (c->final_step == 1) {
+    if (mode == 1) {
         // bridges and classes on the device: one copy of the status block and labels
         int32_t* d_label = nullptr;
         uint32_t* d_n = nullptr;
@@ -429,6 +462,8 @@ int br_two_edge_components(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t
         if (rc) return rc;
         uint32_t* hc = static_cast<uint32_t*>(c->pinned);
         BR_HIP(hipMemcpyAsync(hc, d_n - 1, 256 + 4 * (size_t)V, hipMemcpyDeviceToHost, s));
+        rc = ctx_end(c, s);
+        if (rc) return rc;
         BR_HIP(hipStreamSynchronize(s));
         const uint32_t err = hc[4];
         if (err & 1u) return fail(BR_ERANGE, "br_two_edge_components: an edge has a vertex id outside [0, %d)", V);
@@ -447,6 +482,8 @@ int br_two_edge_components(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t
     BR_HIP(hipMemcpyAsync(hc, B.cnt, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     BR_HIP(hipMemcpyAsync(hc + 2, B.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     if (cap0 > 0) BR_HIP(hipMemcpyAsync(hx, B.cert + P.off[0], sizeof(int2) * cap0, hipMemcpyDeviceToHost, s));
+    rc = ctx_end(c, s);
+    if (rc) return rc;
     BR_HIP(hipStreamSynchronize(s));
     const uint32_t n1 = hc[0], n2 = hc[1], err = hc[2];
     if (err & 1u) return fail(BR_ERANGE, "br_two_edge_components: an edge has a vertex id outside [0, %d)", V);
@@ -485,13 +522,16 @@ int br_articulation_points(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t
     if (rc) return rc;
     if (cap < 0) return fail(BR_EINVAL, "cap < 0");
     if (E > 2147483647LL) return fail(BR_EINVAL, "br_articulation_points: E = %lld above 2^31 - 1", (long long)E);
-    if (V > (1 << 29)) return fail(BR_EINVAL, "V = %d above the host search limit 2^29", V);
+    if (V > kFinalStepMaxV) return fail(BR_EINVAL, "V = %d above the final step's limit 2^29", V);
     auto t0 = std::chrono::steady_clock::now();
     BR_HIP(hipSetDevice(c->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     BR_HIP(hipEventSynchronize(c->ev[7]));
+    rc = ctx_begin(c, s);
+    if (rc) return rc;
+    const int mode = c->final_step;   // read once: the workspace layout depends on it
     const size_t ws_cert = 4 * (size_t)scan_first_words(E, V);
-    const size_t ws_test = c->final_step == 1 ? 4 * (size_t)device_bridges_words(V) : 0;
+    const size_t ws_test = mode == 1 ? 4 * (size_t)device_bridges_words(V) : 0;
     rc = ensure_workspace(c, ws_cert + ws_test + 256, s);
     if (rc) return rc;
     rc = ensure_pinned(c, 256 + 2 * sizeof(int2) * (size_t)std::max(V, 1));
@@ -503,7 +543,7 @@ int br_articulation_points(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t
     std::vector<int32_t> aps;
     std::chrono::steady_clock::time_point t1;
     char* wsb = static_cast<char*>(c->ws.base);
-    if (c->final_step == 1) {
+    if (mode == 1) {
         // test on the device: only the articulation points come back
         int2 *f1 = nullptr, *f2 = nullptr;
         uint32_t *cnt = nullptr, *err = nullptr, *roots = nullptr;
@@ -520,6 +560,8 @@ int br_articulation_points(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t
         uint64_t* hk = reinterpret_cast<uint64_t*>(h + 256);
         const size_t guess = std::min<size_t>(std::max<size_t>(c->keys_hint, 1024), (size_t)std::max(V, 1));
         BR_HIP(hipMemcpyAsync(hs, d_n - 1, 256 + 8 * guess, hipMemcpyDeviceToHost, s));
+        rc = ctx_end(c, s);
+        if (rc) return rc;
         BR_HIP(hipStreamSynchronize(s));
         n1 = hs[2]; n2 = hs[3];
         const uint32_t e = hs[4], nk = std::min<uint32_t>(hs[1], (uint32_t)std::max(V, 1));
@@ -540,6 +582,8 @@ int br_articulation_points(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t
         int2* hf2 = hf1 + std::max(V, 1);
         rc = scan_first_certificate(reinterpret_cast<const int2*>(d_edges), E, V, wsb, s, hs, hf1, hf2, &n1, &n2, &l1,
                                     &l2);
+        if (rc) return rc;
+        rc = ctx_end(c, s);
         if (rc) return rc;
         t1 = std::chrono::steady_clock::now();
         certificate_articulation(hf1, n1, hf2, n2, V, c->dfs, aps);

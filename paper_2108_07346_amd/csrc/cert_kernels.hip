@@ -362,7 +362,30 @@ void launch_phase0(const Plan& P, DevBufs& B, hipStream_t s) {
     }
 }
 
-void launch_merge_round(const Plan& P, const DevBufs& B, int32_t step, hipStream_t s) {
+int phase0_launches(const Plan& P) {
+    // mirrors launch_phase0's choices
+    if (P.E == 0) return 0;
+    const int64_t per = (P.E + P.M - 1) / P.M;
+    const bool has_packed = P.qs != 2 && P.M > 1;
+    bool packed_now = P.qs == 2;
+    int n = 0;
+    for (size_t k = 0; k + 1 < P.stages.size(); k++) {
+        if (P.stages[k] >= std::min(P.stages[k + 1], per)) break;
+        if (k > 0) {
+            n++;   // compression between stages
+            if (!packed_now && has_packed && k + 2 == P.stages.size()) packed_now = true;
+        }
+        n++;
+    }
+    if (P.M > 1) {
+        if (!packed_now && has_packed) n++;
+        else if (P.stages.size() == 2 && 4 * per >= 3 * (int64_t)P.V) n++;
+    }
+    return n;
+}
+
+int launch_merge_round(const Plan& P, const DevBufs& B, int32_t step, hipStream_t s) {
+    int launches = 1;
     const int64_t merges = (P.M - step - 1) / (2 * (int64_t)step) + 1;
     int64_t maxcap = 0, total = 0;
     for (int64_t i = 0; i + step < P.M; i += 2 * (int64_t)step) {
@@ -390,10 +413,12 @@ void launch_merge_round(const Plan& P, const DevBufs& B, int32_t step, hipStream
             const int64_t n = (int64_t)P.V * merges;
             hipLaunchKernelGGL(k_compress_nodes, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536))),
                                dim3(256), 0, s, B.state, P.V, 2 * (int64_t)step, merges);
+            launches++;
         }
     }
     hipLaunchKernelGGL(k_merge, dim3((unsigned)(merges * tpm)), dim3(kBlock), 0, s, B, P.V, P.M, step, (int32_t)tile,
                        (int32_t)tpm);
+    return launches;
 }
 
 void launch_copy_out(const Plan& P, const DevBufs& B, int32_t* d_out, int64_t out_cap, int64_t* d_counts,

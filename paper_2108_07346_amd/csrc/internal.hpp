@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <condition_variable>
 #include <cstdint>
 #include <functional>
@@ -149,9 +150,15 @@ int32_t small_bridges_max_v();   // largest V the kernel above takes
 int32_t batched_max_v_dev();
 int32_t batched_blocks_per_cu();
 
+// Largest V the final steps take: they count the 2(V-1) arcs of the
+// certificate's forest tours in 30-bit fields (and the host search in int32).
+constexpr int32_t kFinalStepMaxV = 1 << 29;
+
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 void launch_phase0(const Plan& P, DevBufs& B, hipStream_t s);
-void launch_merge_round(const Plan& P, const DevBufs& B, int32_t step, hipStream_t s);
+int phase0_launches(const Plan& P);   // kernels launch_phase0 enqueues for this plan
+// enqueues one merge round; returns the number of kernels launched
+int launch_merge_round(const Plan& P, const DevBufs& B, int32_t step, hipStream_t s);
 void launch_copy_out(const Plan& P, const DevBufs& B, int32_t* d_out, int64_t out_cap, int64_t* d_counts,
                      hipStream_t s);
 
@@ -230,6 +237,11 @@ struct br_ctx {
     int32_t* bws = nullptr;        // device bridge-step scratch inside the workspace
     br_profile prof{};
     hipEvent_t ev[8] = {};
+    // recorded at the end of the work every entry point enqueues; the next call
+    // orders its stream after it before touching the shared workspace
+    hipEvent_t ev_done = nullptr;
+    bool done_recorded = false;
+    bool exact_ws = false;         // workspace sized exactly to the request (server slots)
     // batched path state
     void* batched = nullptr;
 };
@@ -240,6 +252,11 @@ void batched_release(br_ctx* c);
 int ensure_pinned(br_ctx* c, size_t bytes);
 // Run phases a1..a5 on d_edges; on return (asynchronously) node 0 holds the final certificate.
 // The input is the concatenation of d_a [Ea] and d_b [Eb] (d_b may be null with Eb = 0).
+// device_final: reserve the device bridge step's scratch in the workspace.
 int run_certificate(br_ctx* c, const int32_t* d_a, int64_t Ea, const int32_t* d_b, int64_t Eb, int32_t V, int32_t M,
-                    hipStream_t s, Plan& P, DevBufs& B);
+                    hipStream_t s, Plan& P, DevBufs& B, bool device_final);
+// Order stream s after everything earlier calls on this context enqueued
+// (they may have used another stream), and mark the end of this call's work.
+int ctx_begin(br_ctx* c, hipStream_t s);
+int ctx_end(br_ctx* c, hipStream_t s);
 }  // namespace br

@@ -34,7 +34,9 @@ struct Request {
     int64_t E = 0;
     int32_t V = 0;
     int32_t M = 1;
-    int64_t bytes = 0;                 // budget charge
+    int mode = 1;                      // final step, fixed when the request is admitted
+    int64_t ws_bytes = 0;              // device workspace it needs (for its final step)
+    int64_t buf_bytes = 0;             // device copy of its edges (host submissions)
     Clock::time_point t_submit;
     // result
     int status = BR_OK;
@@ -49,6 +51,8 @@ struct Slot {
     hipStream_t stream = nullptr;
     void* d_buf = nullptr;             // device copy of host-submitted edges
     size_t d_cap = 0;
+    int64_t held = 0;                  // device bytes charged to this slot (kept after a request)
+    bool trimming = false;             // its buffers are being released by the scheduler
     std::shared_ptr<Request> job;
     std::thread th;
 };
@@ -60,7 +64,11 @@ constexpr size_t kQueueMax = 65536;
 
 struct br_server {
     int device = 0;
-    int64_t budget = 0, in_use = 0;
+    int final_step = 1;                // of the requests admitted from now on
+    // in_use: device bytes the slots hold -- a slot keeps its workspace and
+    // edge buffer after a request (sized exactly to what it was charged), so
+    // idle slots count too until the scheduler releases them
+    int64_t budget = 0, in_use = 0, peak_in_use = 0;
     std::vector<std::unique_ptr<br::Slot>> slots;
     std::deque<std::shared_ptr<br::Request>> queue;
     std::map<uint64_t, std::shared_ptr<br::Request>> all;
@@ -85,12 +93,30 @@ struct br_server {
 namespace br {
 namespace {
 
-// bytes a request needs on the device while it runs
-int64_t charge(int64_t E, int32_t V, int32_t M, bool host_edges) {
-    const Plan P = make_plan(E, V, M);
-    int64_t b = (int64_t)plan_workspace_bytes(P, true) + (1 << 20);
-    if (host_edges) b += 8 * E;
-    return b;
+// device bytes a request needs while it runs: the plain path's workspace for
+// its final step, and the copy of its edges when they came from the host
+void charge(Request& r, bool host_edges, int mode) {
+    const Plan P = make_plan(r.E, r.V, r.M);
+    r.ws_bytes = (int64_t)plan_workspace_bytes(P, mode == 1);
+    r.buf_bytes = host_edges ? 8 * r.E : 0;
+}
+
+// what slot sl holds after running r (buffers only ever grow to what is needed)
+int64_t held_after(const Slot& sl, const Request& r) {
+    return std::max<int64_t>((int64_t)sl.ctx->ws.size, r.ws_bytes) + std::max<int64_t>((int64_t)sl.d_cap, r.buf_bytes);
+}
+
+// release an idle slot's device buffers (scheduler thread, slot not running)
+void release_slot(Slot& sl) {
+    (void)hipSetDevice(sl.ctx->device);
+    (void)hipStreamSynchronize(sl.stream);
+    if (sl.ctx->ws.base) (void)hipFree(sl.ctx->ws.base);
+    sl.ctx->ws.base = nullptr;
+    sl.ctx->ws.size = 0;
+    if (sl.d_buf) (void)hipFree(sl.d_buf);
+    sl.d_buf = nullptr;
+    sl.d_cap = 0;
+    (void)hipGetLastError();
 }
 
 // a pinned buffer of at least `bytes` (best fit among the free ones, else a new
@@ -148,6 +174,7 @@ int32_t choose_m(int64_t E, int32_t V) {
 }
 
 void run_request(br_server* S, Slot& sl, Request& r) {
+    br_set_final_step(sl.ctx, r.mode);
     const int32_t* d = r.d_edges;
     if (!d && r.E > 0) {
         const size_t bytes = 8 * (size_t)r.E;
@@ -206,7 +233,11 @@ void slot_loop(br_server* S, Slot* sl) {
                 S->pin_free.emplace_back(r->pin, r->pin_cap);
                 r->pin = nullptr;
             }
-            S->in_use -= r->bytes;
+            // the slot keeps what it allocated; charge what it really holds
+            const int64_t now = (int64_t)sl->ctx->ws.size + (int64_t)sl->d_cap;
+            S->in_use += now - sl->held;
+            sl->held = now;
+            S->peak_in_use = std::max(S->peak_in_use, S->in_use);
             S->inflight--;
             if (S->inflight == 0) S->busy_ms += std::chrono::duration<double, std::milli>(Clock::now() - S->busy_start).count();
             if (r->status == BR_OK) {
@@ -220,29 +251,79 @@ void slot_loop(br_server* S, Slot* sl) {
     }
 }
 
+// The free slot for r that needs the fewest new bytes, and that number.
+Slot* pick_slot(br_server* S, const Request& r, int64_t* extra) {
+    Slot* best = nullptr;
+    for (auto& s : S->slots) {
+        if (s->job || s->trimming) continue;
+        const int64_t x = held_after(*s, r) - s->held;
+        if (!best || x < *extra) {
+            best = s.get();
+            *extra = x;
+        }
+    }
+    return best;
+}
+
 void sched_loop(br_server* S) {
     std::unique_lock<std::mutex> g(S->mu);
     for (;;) {
         S->cv_sched.wait(g, [&] {
             if (S->stop) return true;
             if (S->queue.empty()) return false;
-            const auto& h = S->queue.front();
-            if (S->in_use + h->bytes > S->budget && S->inflight > 0) return false;
             for (auto& s : S->slots)
-                if (!s->job) return true;
+                if (!s->job && !s->trimming) return true;
             return false;
         });
         if (S->stop) return;
-        // admit the head (FIFO); one that exceeds the budget on its own runs alone
         auto r = S->queue.front();
-        S->queue.pop_front();
-        for (auto& s : S->slots) {
-            if (!s->job) {
-                s->job = r;
-                break;
+        r->mode = S->final_step;
+        charge(*r, r->d_edges == nullptr, r->mode);
+        int64_t extra = 0;
+        Slot* sl = pick_slot(S, *r, &extra);
+        if (S->in_use + extra > S->budget) {
+            // release what idle slots hold (largest first) until the request fits
+            std::vector<Slot*> idle;
+            for (auto& s : S->slots)
+                if (!s->job && !s->trimming && s.get() != sl && s->held > 0) idle.push_back(s.get());
+            std::sort(idle.begin(), idle.end(), [](Slot* a, Slot* b) { return a->held > b->held; });
+            std::vector<Slot*> rel;
+            int64_t freed = 0;
+            for (Slot* s : idle) {
+                if (S->in_use - freed + extra <= S->budget) break;
+                rel.push_back(s);
+                freed += s->held;
+            }
+            if (S->in_use - freed + extra > S->budget && S->inflight == 0 && sl->held > 0) {
+                // nothing runs: the chosen slot starts over from nothing too
+                rel.push_back(sl);
+                freed += sl->held;
+            }
+            if (!rel.empty()) {
+                for (Slot* s : rel) s->trimming = true;
+                g.unlock();
+                for (Slot* s : rel) release_slot(*s);
+                g.lock();
+                for (Slot* s : rel) {
+                    S->in_use -= s->held;
+                    s->held = 0;
+                    s->trimming = false;
+                }
+                continue;   // decide again with the memory released
+            }
+            // one that exceeds the budget on its own runs alone
+            if (S->inflight > 0) {
+                S->cv_sched.wait(g);
+                continue;
             }
         }
-        S->in_use += r->bytes;
+        // admit the head (FIFO)
+        S->queue.pop_front();
+        const int64_t after = held_after(*sl, *r);
+        S->in_use += after - sl->held;
+        sl->held = after;
+        S->peak_in_use = std::max(S->peak_in_use, S->in_use);
+        sl->job = r;
         if (S->inflight == 0) S->busy_start = Clock::now();
         S->inflight++;
         S->peak_inflight = std::max(S->peak_inflight, S->inflight);
@@ -306,6 +387,7 @@ int br_server_create(br_server** out, int device, int64_t mem_budget, int32_t ma
             for (auto& s : S->slots) br_destroy(s->ctx);
             return rc;
         }
+        sl->ctx->exact_ws = true;
         if (hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess) {
             br_destroy(sl->ctx);
             for (auto& s : S->slots) br_destroy(s->ctx);
@@ -322,10 +404,10 @@ int br_server_create(br_server** out, int device, int64_t mem_budget, int32_t ma
 
 static int submit_common(br_server* S, std::shared_ptr<Request> r, uint64_t* ticket, bool host) {
     r->M = choose_m(r->E, r->V);
-    r->bytes = charge(r->E, r->V, r->M, host);
-    if (r->bytes > S->budget)
-        return fail(BR_ENOMEM, "server: request needs %lld bytes, budget is %lld", (long long)r->bytes,
-                    (long long)S->budget);
+    charge(*r, host, 1);   // the larger of the two final steps' needs
+    if (r->ws_bytes + r->buf_bytes > S->budget)
+        return fail(BR_ENOMEM, "server: request needs %lld bytes, budget is %lld",
+                    (long long)(r->ws_bytes + r->buf_bytes), (long long)S->budget);
     return enqueue(S, std::move(r), ticket);
 }
 
@@ -391,11 +473,14 @@ int br_server_stats(br_server* S, br_server_stats_t* out, int reset) {
     if (S->inflight > 0) busy += std::chrono::duration<double, std::milli>(Clock::now() - S->busy_start).count();
     out->edges_per_s = busy > 0 ? S->edges_done / (busy / 1000.0) : 0.0;
     out->peak_inflight = S->peak_inflight;
+    out->device_bytes = S->in_use;
+    out->peak_device_bytes = S->peak_in_use;
     if (reset) {
         S->lat.clear();
         S->edges_done = 0;
         S->busy_ms = 0;
         S->peak_inflight = S->inflight;
+        S->peak_in_use = S->in_use;
         if (S->inflight > 0) S->busy_start = Clock::now();
     }
     return BR_OK;
@@ -404,7 +489,7 @@ int br_server_stats(br_server* S, br_server_stats_t* out, int reset) {
 int br_server_set_final_step(br_server* S, int mode) {
     if (!S || mode < 0 || mode > 1) return fail(BR_EINVAL, "br_server_set_final_step: bad argument");
     std::lock_guard<std::mutex> g(S->mu);
-    for (auto& sl : S->slots) br_set_final_step(sl->ctx, mode);
+    S->final_step = mode;     // taken by each request when it is admitted
     return BR_OK;
 }
 

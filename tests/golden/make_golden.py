@@ -3,7 +3,8 @@
 Calls only the input generator (graphgen) and the CPU oracle (oracle): no
 value here comes from the GPU path.  Run from the repository root:
 
-    python tests/golden/make_golden.py large      # ~1.03e9 edges, ~45 GB host RAM
+    python tests/golden/make_golden.py large          # ~1.03e9 edges, ~45 GB host RAM
+    python tests/golden/make_golden.py large_blocked  # ~2.0e8 edges
 
 Each output file lists one bridge "u v" per line (u < v, ascending) after a
 header naming the workload, V, E and a SHA-256 of the edge bytes.

@@ -152,10 +152,18 @@ def test_edge_cases(ctx):
 
 
 def test_concurrency_stress_same_bridges(ctx, dense):
-    # many interleavings (permutations, chunk counts): certificates vary, bridges must not
-    g, want, _ = dense
+    # many interleavings (permutations, chunk counts, repeated runs of one
+    # input): certificates vary, bridges must not
+    g, want, d0 = dense
     rng = np.random.default_rng(23)
-    hashes = set()
+
+    def cert_key(f1, f2):
+        # the certificate as a set of forest edges (the order of appends
+        # within a region is not compared)
+        k = lambda f: np.sort(np.minimum(f[:, 0], f[:, 1]).astype(np.int64) << 32 | np.maximum(f[:, 0], f[:, 1]))
+        return hash(k(f1.cpu().numpy()).tobytes()) ^ (hash(k(f2.cpu().numpy()).tobytes()) * 3)
+
+    perm_sets, repeat_sets = set(), set()
     for t in range(6):
         e = g.edges[rng.permutation(g.E)]
         d = dev(e)
@@ -163,8 +171,15 @@ def test_concurrency_stress_same_bridges(ctx, dense):
         say("stress t=%d M=%d" % (t, M))
         assert np.array_equal(ctx.find(d, g.V, M), want)
         f1, f2 = ctx.cert_build(d, g.V, 1)
-        hashes.add(hash(f1.cpu().numpy().tobytes()))
-    say("distinct certificates over runs: %d" % len(hashes))
+        perm_sets.add(cert_key(f1, f2))
+    for t in range(6):                     # one input, run again: only the schedule differs
+        f1, f2 = ctx.cert_build(d0, g.V, 16)
+        assert oracle.check_certificate(f1.cpu().numpy(), f2.cpu().numpy(), g.edges, g.V, check_bridges=False) == []
+        repeat_sets.add(cert_key(f1, f2))
+        assert np.array_equal(ctx.find(d0, g.V, 16), want)
+    say("distinct certificates: %d over 6 edge orders, %d over 6 runs of one order" % (len(perm_sets), len(repeat_sets)))
+    assert len(perm_sets) >= 2
+    assert len(perm_sets | repeat_sets) >= 3
 
 
 def test_deep_trees_paths_and_random(ctx, small, dense):

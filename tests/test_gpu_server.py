@@ -110,3 +110,76 @@ def test_budget_errors_and_polling(br):
     with pytest.raises(br.BridgeError):
         srv.poll(t, 4)                           # the ticket was released
     srv.close()
+
+
+@pytest.fixture(scope="module")
+def served32():
+    # the served workload's own requests (graphgen.served_request): V up to
+    # 131,072, average degree up to 2,048, up to 7.0e7 edges each
+    reqs = []
+    for r in range(32):
+        g = graphgen.served_request(0, r)
+        reqs.append((g.edges, g.V, oracle.bridges(g.edges, g.V)))
+    say("served requests: %d, %d edges" % (len(reqs), sum(e.shape[0] for e, _, _ in reqs)))
+    return reqs
+
+
+@pytest.mark.parametrize("final_step", [1, 0], ids=["gpu_final_step", "host_search"])
+def test_served_config_requests_equal_oracle_and_alone(br, served32, final_step):
+    dev = [torch.from_numpy(e).cuda() for e, _, _ in served32]
+    alone_ctx = br.Context(0)
+    alone_ctx.set_final_step(final_step)
+    alone = [alone_ctx.find(d, V, 1) for d, (_, V, _) in zip(dev, served32)]
+    alone_ctx.close()
+    for host in (True, False):
+        srv = br.Server(0, mem_budget=64 << 30, max_slots=8)
+        srv.set_final_step(final_step)
+        tickets = [srv.submit(e if host else d, V) for (e, V, _), d in zip(served32, dev)]
+        got = [srv.wait(t, V) for t, (_, V, _) in zip(tickets, served32)]
+        st = srv.stats()
+        srv.close()
+        say("served config, %s submission, final step %d: %d done, peak in flight %d" %
+            ("host" if host else "device", final_step, st["completed"], st["peak_inflight"]))
+        assert st["completed"] == len(served32)
+        for i, (g, (e, V, want)) in enumerate(zip(got, served32)):
+            assert np.array_equal(g, want), i
+            assert np.array_equal(g, alone[i]), i
+
+
+def test_final_step_changes_only_later_admissions(br):
+    # the mode is flipped while requests are queued and running; every answer
+    # is still the oracle's (a request keeps the mode it was admitted with)
+    reqs = request_mix(48, seed=7)
+    srv = br.Server(0, mem_budget=8 << 30, max_slots=4)
+    tickets = []
+    for i, (e, V) in enumerate(reqs):
+        if i % 5 == 0:
+            srv.set_final_step((i // 5) % 2)
+        tickets.append(srv.submit(e, V))
+    for t, (e, V) in zip(tickets, reqs):
+        assert np.array_equal(srv.wait(t, V), oracle.bridges(e, V))
+    srv.close()
+
+
+def test_tight_budget_releases_idle_slots(br):
+    # a large request on one slot, then another on a second slot under a budget
+    # that cannot hold both slots' buffers: the idle slot's memory is released
+    # and both succeed; what the slots hold never exceeds the budget
+    a = graphgen.planted(11, k=8, vc=40000, p=0.05, n_pend=20)
+    b = graphgen.planted(12, k=8, vc=40000, p=0.05, n_pend=20)
+    srv0 = br.Server(0, mem_budget=64 << 30, max_slots=1)
+    ta = srv0.submit(a.edges, a.V)
+    srv0.wait(ta, a.V)
+    one = srv0.stats()["peak_device_bytes"]
+    srv0.close()
+    budget = int(one * 1.5)
+    srv = br.Server(0, mem_budget=budget, max_slots=2)
+    for rep in range(3):
+        ta = srv.submit(a.edges, a.V)
+        tb = srv.submit(b.edges, b.V)        # may run while a's slot still holds its buffers
+        assert np.array_equal(srv.wait(ta, a.V), oracle.bridges(a.edges, a.V))
+        assert np.array_equal(srv.wait(tb, b.V), oracle.bridges(b.edges, b.V))
+    st = srv.stats()
+    srv.close()
+    say("tight budget: one request holds %d bytes, budget %d, peak held %d" % (one, budget, st["peak_device_bytes"]))
+    assert 0 < st["peak_device_bytes"] <= budget

@@ -1,5 +1,6 @@
 """The seeded generator: determinism, sizes and planted structure."""
 import numpy as np
+import pytest
 
 import graphgen
 
@@ -75,3 +76,28 @@ def test_batched_and_served_recipes():
     sp = [graphgen.served_params(0, r) for r in range(2000)]
     Vr = np.array([p["vc"] for p in sp])
     assert Vr.min() >= 256 and Vr.max() <= 131072
+
+
+def test_blocked_cross_edges_stay_in_blocks_and_leave_the_block_tree_bridges():
+    # cross edges join two clusters of one block; the cluster tree is a tree
+    # per block plus a tree over the blocks, so the bridges are exactly the
+    # pendant edges and the tree edges between blocks (checked by the oracle)
+    import oracle
+    for seed in range(3):
+        g = graphgen.planted(seed, k=16, vc=640, p=0.5, n_cross=2000, n_pend=10, cross_block=4)
+        blk = np.where(g.cluster >= 0, g.cluster // 4, -1)
+        e = g.edges
+        cross = (g.cluster[e[:, 0]] >= 0) & (g.cluster[e[:, 1]] >= 0) & (g.cluster[e[:, 0]] != g.cluster[e[:, 1]])
+        between = blk[e[:, 0]] != blk[e[:, 1]]
+        assert (cross & between).sum() == 3                    # only the 3 tree edges between 4 blocks
+        ct = g.cluster[g.tree]
+        assert oracle.components(ct, 16) == 1 and ct.shape[0] == 15
+        bt = blk[g.tree]
+        inter = g.tree[bt[:, 0] != bt[:, 1]]
+        assert inter.shape[0] == 3
+        assert oracle.components(bt[bt[:, 0] != bt[:, 1]], 4) == 1   # the block tree spans the blocks
+        want = np.sort(np.concatenate([g.pend, inter]), 1)
+        want = want[np.lexsort((want[:, 1], want[:, 0]))]
+        assert np.array_equal(oracle.bridges(e, g.V), want)
+    with pytest.raises(ValueError):
+        graphgen.planted(0, k=10, vc=100, p=0.5, n_cross=10, cross_block=4)      # 4 does not divide 10
