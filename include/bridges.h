@@ -91,6 +91,27 @@ int br_cert_build(br_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t V, int
                   int64_t cert_cap, int64_t* d_counts, void* stream);
 
 /*
+ * br_cert_build_static -- br_cert_build for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  It computes the same certificate through
+ * the same kernels, in a fixed device array of BR_STATIC_SCRATCH_BYTES that
+ * the library holds on every GPU it runs on until the process ends, instead
+ * of the context's workspace; it allocates no device memory and clears that
+ * array with kernels (no memset).  The array holds, 256-byte aligned: the
+ * error word, 8M bytes of counters, 8VM bytes of union-find state, 8 bytes
+ * per pair of the node regions (sum over the M nodes of min(edges under the
+ * node, 2(V-1))) and 16M bytes of node tables; a request that does not fit
+ * returns BR_ENOMEM naming the size it needs, before any device work.  Every
+ * call on one GPU uses that GPU's one array, which keeps the last call's
+ * contents: calls that overlap on one GPU (other streams, other contexts)
+ * race, and the caller serialises them.  Arguments, the layout of d_cert and
+ * d_counts, asynchrony and the other errors are those of br_cert_build.
+ */
+#define BR_STATIC_SCRATCH_BYTES ((int64_t)64 << 20)
+int br_cert_build_static(br_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t V, int32_t M, int32_t* d_cert,
+                         int64_t cert_cap, int64_t* d_counts, void* stream);
+
+/*
  * br_cert_merge -- certificate of the union of two edge lists, the merge step
  * of Section III (usually both lists are certificates; any lists work).
  *   d_a [Ea][2], d_b [Eb][2], d_out [cap][2], d_counts [3] as for br_cert_build.

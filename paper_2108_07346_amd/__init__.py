@@ -22,7 +22,7 @@ EXPORTS = ["br_last_error", "br_create", "br_destroy", "br_cert_build", "br_cert
            "br_certificate_bridges", "br_two_edge_components", "br_articulation_points",
            "br_bridges_find_batched", "br_batched_max_v", "br_set_profiling", "br_set_final_step", "br_get_profile",
            "br_server_create", "br_submit", "br_submit_device", "br_poll", "br_wait", "br_server_stats",
-           "br_server_set_final_step", "br_server_destroy", "br_probe_read"]
+           "br_server_set_final_step", "br_server_destroy", "br_probe_read", "br_cert_build_static"]
 
 
 class BridgeError(RuntimeError):
@@ -63,6 +63,7 @@ def load():
     lib.br_destroy.argtypes = [vp]
     lib.br_cert_build.argtypes = [vp, vp, i64, i32, i32, vp, i64, vp, vp]
     lib.br_cert_merge.argtypes = [vp, vp, i64, vp, i64, i32, vp, i64, vp, vp]
+    lib.br_cert_build_static.argtypes = [vp, vp, i64, i32, i32, vp, i64, vp, vp]
     lib.br_bridges_find.argtypes = [vp, vp, i64, i32, i32, vp, i64, p64, vp]
     lib.br_two_edge_components.argtypes = [vp, vp, i64, i32, i32, vp, p64, vp]
     lib.br_articulation_points.argtypes = [vp, vp, i64, i32, vp, i64, p64, vp]
@@ -192,6 +193,22 @@ class Context:
         counts = torch.zeros(3, dtype=torch.int64, device=edges.device)
         _check(self._lib.br_cert_build(self._h, ptr, E, int(V), int(M), ctypes.c_void_p(out.data_ptr()), cap,
                                        ctypes.c_void_p(counts.data_ptr()), _stream(stream)))
+        return self._cert_result(out, counts, stream)
+
+    def cert_build_static(self, edges, V: int, M: int = 1, out=None, counts=None, stream=None):
+        """As cert_build, computed in the library's fixed device array (no
+        device allocation inside the library); `out` (int32 [cap, 2]) and
+        `counts` (int64 [3]) may be passed in so that nothing is allocated here
+        either."""
+        import torch
+        ptr, E = _edges_arg(edges)
+        cap = max(min(E, 2 * (int(V) - 1)), 1)
+        if out is None:
+            out = torch.empty((cap, 2), dtype=torch.int32, device=edges.device)
+        if counts is None:
+            counts = torch.zeros(3, dtype=torch.int64, device=edges.device)
+        _check(self._lib.br_cert_build_static(self._h, ptr, E, int(V), int(M), ctypes.c_void_p(out.data_ptr()),
+                                              int(out.shape[0]), ctypes.c_void_p(counts.data_ptr()), _stream(stream)))
         return self._cert_result(out, counts, stream)
 
     def cert_merge(self, a, b, V: int, stream=None):

@@ -233,6 +233,11 @@ int br_create(br_ctx** out, int device) {
         br_destroy(c);
         return hip_fail(hipGetLastError(), "hipEventCreate");
     }
+    const int rc = static_scratch_init(device);
+    if (rc) {
+        br_destroy(c);
+        return rc;
+    }
     *out = c;
     return BR_OK;
 }

@@ -198,6 +198,10 @@ int device_classes(const Plan& P, const DevBufs& B, int32_t* ws, int32_t** d_lab
 int device_bridges_cert(const int2* f1, const int2* f2, int32_t dir, const uint32_t* cnt, const uint32_t* q, int32_t qs,
                         int32_t V, int32_t max_tree, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s);
 
+// device address of the fixed scratch array on `device` (current on the
+// calling thread), looked up once; br_create calls it
+int static_scratch_init(int device);
+
 // ---- host side of the path --------------------------------------------------
 // Algorithm 1 (iterative) on the certificate; appends canonical keys (min<<32|max).
 struct DfsScratch {
