@@ -152,6 +152,25 @@ int br_two_edge_components(br_ctx* ctx, const int32_t* d_edges, int64_t E, int32
                            int64_t* n_classes, void* stream);
 
 /*
+ * br_bridge_tree -- the bridge tree: the graph obtained by contracting every
+ * 2-edge-connected class to one node (Section I's bridges are exactly the
+ * edges left between classes), a forest with one tree per connected
+ * component.  Computed as br_two_edge_components does; a tree edge of the
+ * certificate's forest F whose endpoints lie in different classes is a bridge
+ * and becomes the tree edge between the two classes.
+ *   h_label  host int32 [V]: class of each vertex (its smallest vertex id), as
+ *            br_two_edge_components.
+ *   h_tree   host int32 [cap][2]: the tree's edges as (min, max) class labels,
+ *            ascending; one per bridge, so cap >= V-1 always suffices.
+ *   *n_classes number of classes (the tree's nodes); *n_tree number of edges
+ *            (the bridges).  BR_ECAP (labels and counts written, no edges) if
+ *            *n_tree exceeds cap.
+ * Synchronous; errors as for br_bridges_find.
+ */
+int br_bridge_tree(br_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t V, int32_t M, int32_t* h_label,
+                   int32_t* h_tree, int64_t cap, int64_t* n_classes, int64_t* n_tree, void* stream);
+
+/*
  * br_certificate_bridges -- the final step alone, on the host: Algorithm 1's
  * depth-first search (Section IV-A) on a certificate S = F u F' given as two
  * host edge lists, then canonical order.  Any edge lists are accepted (the
@@ -184,6 +203,32 @@ int br_bridges_find_batched(br_ctx* ctx, const int32_t* d_edges, const int64_t* 
                             int32_t G, int32_t chunk_edges, int32_t* h_bridges, int64_t cap, int64_t* h_bridge_off,
                             void* stream);
 int32_t br_batched_max_v(void);
+/* Largest V for which a plain-path call can run the whole phase tree of
+ * Section III inside one workgroup's LDS per chunk (the union-find of
+ * Algorithm 2 as two 16-bit parent offsets per vertex in 160 KB); such calls
+ * do when their chunks are short enough for one CU each. */
+int32_t br_lds_max_v(void);
+
+/*
+ * br_autotune -- measure the launch shapes of the certificate path for this
+ * device and input shape and keep the fastest for later calls on inputs of
+ * the same shape bucket (V and E in powers of two, the same M): the team
+ * path (many workgroups per chunk) with three first-stage tiles, and, where
+ * its LDS bitmaps fit, the one-workgroup-per-node path in each worker shape
+ * with three depths of the merges it does itself.  Each candidate computes
+ * the certificate of d_edges (one settling run, best of two timed runs, HIP
+ * events on `stream`).  The choice is kept in memory and, when the
+ * environment variable BR_AUTOTUNE_CACHE names a file, in that file (JSON,
+ * keyed by GPU architecture and shape bucket), where later processes find it
+ * without measuring; a shape already in the cache is not measured again.
+ * br_bridges_find_batched with chunk_edges = 0 tunes its chunk size and
+ * workgroups per CU the same way.
+ *   out  host char [out_cap]: the choice as a JSON object ("source":
+ *        "measured" or "cache"), truncated to fit; may be null with out_cap 0.
+ * Synchronous.  Errors as for br_cert_build.
+ */
+int br_autotune(br_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t V, int32_t M, char* out, int64_t out_cap,
+                void* stream);
 
 /*
  * Phase timings of the last br_bridges_find / br_bridges_find_batched on this
@@ -203,6 +248,9 @@ typedef struct br_profile {
     int64_t rounds;        /* merge rounds run                                    */
     int64_t launches;      /* kernel launches                                     */
     double ms_bridge_dev;  /* device bridge step (final step 1 only)              */
+    int64_t plan_kind;     /* certificate plan of the last plain-path call: 0 many
+                              workgroups per chunk, 1 one workgroup per node
+                              (resident slots), 2 the whole tree in LDS        */
 } br_profile;
 int br_set_profiling(br_ctx* ctx, int on);
 

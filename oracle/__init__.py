@@ -156,6 +156,23 @@ def two_edge_labels(edges, V: int) -> np.ndarray:
     return np.array([find(x) for x in range(V)], dtype=np.int32)
 
 
+def bridge_tree(edges, V: int):
+    """The bridge tree of Section I's bridges: the graph whose nodes are the
+    2-edge-connected classes (labelled by their smallest vertex, as in
+    two_edge_labels) and whose edges are the bridges, each joining the classes
+    of its two endpoints.  Returns (labels int32 [V], tree edges int32 [B, 2]
+    as (min, max) class labels, sorted).  A forest: one tree per connected
+    component of the graph."""
+    e = _as_edges(edges)
+    lab = two_edge_labels(e, V)
+    b = bridges(e, V)
+    t = np.stack([lab[b[:, 0]], lab[b[:, 1]]], 1) if b.shape[0] else np.zeros((0, 2), np.int32)
+    t = np.sort(t, 1).astype(np.int32)
+    if t.shape[0]:
+        t = t[np.lexsort((t[:, 1], t[:, 0]))]
+    return lab, t
+
+
 def brute_two_edge_labels(edges, V: int) -> np.ndarray:
     """The definition for tiny graphs: u and v share a class iff they stay
     connected after removing any single edge."""

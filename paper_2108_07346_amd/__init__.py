@@ -22,7 +22,8 @@ EXPORTS = ["br_last_error", "br_create", "br_destroy", "br_cert_build", "br_cert
            "br_certificate_bridges", "br_two_edge_components", "br_articulation_points",
            "br_bridges_find_batched", "br_batched_max_v", "br_set_profiling", "br_set_final_step", "br_get_profile",
            "br_server_create", "br_submit", "br_submit_device", "br_poll", "br_wait", "br_server_stats",
-           "br_server_set_final_step", "br_server_destroy", "br_probe_read", "br_cert_build_static"]
+           "br_server_set_final_step", "br_server_destroy", "br_probe_read", "br_cert_build_static",
+           "br_bridge_tree", "br_autotune", "br_lds_max_v"]
 
 
 class BridgeError(RuntimeError):
@@ -35,7 +36,8 @@ class _Profile(ctypes.Structure):
     _fields_ = [("ms_phase0", ctypes.c_double), ("ms_merge", ctypes.c_double), ("ms_cert", ctypes.c_double),
                 ("ms_d2h", ctypes.c_double), ("ms_dfs", ctypes.c_double), ("ms_canon", ctypes.c_double),
                 ("ms_total", ctypes.c_double), ("cert_f1", ctypes.c_int64), ("cert_f2", ctypes.c_int64),
-                ("rounds", ctypes.c_int64), ("launches", ctypes.c_int64), ("ms_bridge_dev", ctypes.c_double)]
+                ("rounds", ctypes.c_int64), ("launches", ctypes.c_int64), ("ms_bridge_dev", ctypes.c_double),
+                ("plan_kind", ctypes.c_int64)]
 
 
 class _ServerStats(ctypes.Structure):
@@ -66,10 +68,13 @@ def load():
     lib.br_cert_build_static.argtypes = [vp, vp, i64, i32, i32, vp, i64, vp, vp]
     lib.br_bridges_find.argtypes = [vp, vp, i64, i32, i32, vp, i64, p64, vp]
     lib.br_two_edge_components.argtypes = [vp, vp, i64, i32, i32, vp, p64, vp]
+    lib.br_bridge_tree.argtypes = [vp, vp, i64, i32, i32, vp, vp, i64, p64, p64, vp]
+    lib.br_autotune.argtypes = [vp, vp, i64, i32, i32, ctypes.c_char_p, i64, vp]
     lib.br_articulation_points.argtypes = [vp, vp, i64, i32, vp, i64, p64, vp]
     lib.br_certificate_bridges.argtypes = [vp, i64, vp, i64, i32, vp, i64, p64]
     lib.br_bridges_find_batched.argtypes = [vp, vp, vp, vp, i32, i32, vp, i64, vp, vp]
     lib.br_batched_max_v.restype = i32
+    lib.br_lds_max_v.restype = i32
     lib.br_set_profiling.argtypes = [vp, ctypes.c_int]
     lib.br_set_final_step.argtypes = [vp, ctypes.c_int]
     lib.br_get_profile.argtypes = [vp, ctypes.POINTER(_Profile)]
@@ -143,6 +148,15 @@ class Context:
         _check(self._lib.br_get_profile(self._h, ctypes.byref(p)))
         return {k: getattr(p, k) for k, _ in _Profile._fields_}
 
+    def autotune(self, edges, V: int, M: int = 1, stream=None) -> dict:
+        """Measure and keep the fastest launch shapes for this input shape
+        (see br_autotune); returns the choice."""
+        import json
+        ptr, E = _edges_arg(edges)
+        buf = ctypes.create_string_buffer(1024)
+        _check(self._lib.br_autotune(self._h, ptr, E, int(V), int(M), buf, len(buf), _stream(stream)))
+        return json.loads(buf.value.decode())
+
     def find(self, edges, V: int, M: int = 1, stream=None) -> np.ndarray:
         """Canonical bridge set (int32 [B, 2], u < v, sorted) of the graph."""
         ptr, E = _edges_arg(edges)
@@ -161,6 +175,19 @@ class Context:
         _check(self._lib.br_two_edge_components(self._h, ptr, E, int(V), int(M), lab.ctypes.data, ctypes.byref(n),
                                                 _stream(stream)))
         return lab[:int(V)].copy(), n.value
+
+    def bridge_tree(self, edges, V: int, M: int = 1, stream=None):
+        """(labels int32 [V], tree edges int32 [B, 2]): the 2-edge-connected
+        classes and the bridge tree between them (edges as (min, max) class
+        labels, ascending)."""
+        ptr, E = _edges_arg(edges)
+        lab = np.empty(max(int(V), 1), dtype=np.int32)
+        cap = max(int(V) - 1, 1)
+        tree = np.empty((cap, 2), dtype=np.int32)
+        nc, nt = ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(self._lib.br_bridge_tree(self._h, ptr, E, int(V), int(M), lab.ctypes.data, tree.ctypes.data, cap,
+                                        ctypes.byref(nc), ctypes.byref(nt), _stream(stream)))
+        return lab[:int(V)].copy(), tree[:nt.value].copy()
 
     def articulation_points(self, edges, V: int, stream=None) -> np.ndarray:
         """Articulation points (int32 vertex ids ascending) through the scan-first certificate."""
@@ -348,6 +375,11 @@ def probe_read(buf, stream=None) -> None:
     _check(load().br_probe_read(ctypes.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size(),
                                 ctypes.c_void_p(sink.data_ptr()), _stream(stream)))
     return sink
+
+
+def lds_max_v() -> int:
+    """Largest V whose whole phase tree the library can run in one workgroup's LDS."""
+    return int(load().br_lds_max_v())
 
 
 def batched_max_v() -> int:

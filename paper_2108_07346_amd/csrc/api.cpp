@@ -4,6 +4,7 @@
 #include <chrono>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "internal.hpp"
@@ -28,7 +29,36 @@ int hip_fail(hipError_t e, const char* what) {
 int32_t block_size();
 int32_t tile_size();
 
-Plan make_plan(int64_t E, int32_t V, int32_t M) {
+int g_cus = 0;
+int g_max_lds = 64 * 1024;
+
+// BR_SOLO (1 on, 0 off, unset: by size) and BR_SOLO_TOP (merge levels inside
+// the one-workgroup-per-node kernel) override the plan's choice
+static int env_int(const char* name, int dflt) {
+    const char* s = getenv(name);
+    return s && *s ? atoi(s) : dflt;
+}
+
+std::string plain_tune_key(int device, int64_t E, int32_t V, int32_t M) {
+    return arch_name(device) + "|plain|v" + std::to_string(log2_bucket(V)) + "|e" + std::to_string(log2_bucket(E)) +
+           "|m" + std::to_string(M);
+}
+
+Plan plan_for(int device, int64_t E, int32_t V, int32_t M) {
+    TuneEntry t;
+    const bool have = tune_get(plain_tune_key(device, E, V, M), t);
+    return make_plan(E, V, M, true, have ? &t : nullptr);
+}
+
+Plan make_plan(int64_t E, int32_t V, int32_t M, bool allow_solo, const TuneEntry* tuned) {
+    auto knob = [&](const char* env, const char* name, int dflt) {
+        int v = dflt;
+        if (tuned) {
+            auto it = tuned->find(name);
+            if (it != tuned->end()) v = (int)it->second;
+        }
+        return env_int(env, v);
+    };
     Plan P;
     P.E = E;
     P.V = V;
@@ -71,6 +101,43 @@ Plan make_plan(int64_t E, int32_t V, int32_t M) {
         acc += P.cap[i];
     }
     P.cert_pairs = acc;
+    // One workgroup per node when there is at least one chunk per workgroup
+    // in flight (chunks of at most a few V edges: the hook-bound regime) and
+    // the LDS bitmaps of the hooks fit: merge levels 1..top inside that
+    // kernel, while each level still has about a merge per workgroup.
+    const int cus = g_cus > 0 ? g_cus : 256;
+    P.tile0_max = knob("BR_TILE0", "tile", 0);
+    // the whole tree in LDS: V within a workgroup's LDS, chunks short enough
+    // for one CU each (a CU offers about 10^9 edges/s in LDS)
+    const int lds = knob("BR_LDS", "lds", -1);
+    if (allow_solo && E > 0 && V <= batched_max_v_big() && M < (1 << 20) &&
+        (lds == 1 || (lds < 0 && per <= (int64_t(1) << 18)))) {
+        P.lds = true;
+        P.lds_big = V > batched_max_v_dev();
+        P.lds_blocks = (int32_t)std::min<int64_t>(M, (int64_t)cus * (P.lds_big ? 1 : batched_blocks_per_cu()));
+        P.lds_counters = (int64_t)P.rounds * (((int64_t)M + 1) / 2) + 2;
+        return P;
+    }
+    const int want = knob("BR_SOLO", "solo", -1);
+    if (allow_solo && E > 0 && V <= solo_max_v() &&
+        (want == 1 || (want < 0 && M >= cus && per <= (int64_t)V && V >= (1 << 17)))) {
+        P.solo = true;
+        P.solo_variant = std::max(0, std::min(knob("BR_SOLO_VARIANT", "variant", 2), solo_variants() - 1));
+        // 1024 threads per CU, as many workers as that takes where their LDS
+        // bitmaps fit side by side
+        const int per_cu = std::max(1, 1024 / solo_block(P.solo_variant));
+        const int fit = std::max<int>(1, (int)std::min<size_t>(per_cu, (size_t)g_max_lds / solo_lds_bytes(V)));
+        const int wpc = std::max(1, std::min(knob("BR_SOLO_WPC", "wpc", fit), fit));
+        P.workers = cus * wpc;
+        // merge levels inside the kernel while they still hold four merges
+        // per worker (measured on the large workload at M = 4096: two levels
+        // 193 ms, three 206 ms, four 203 ms, five 210 ms)
+        int top = 0;
+        while (top < P.rounds && (int64_t)(M >> (top + 1)) >= 4 * (int64_t)P.workers) top++;
+        P.solo_top = std::max(0, std::min(P.rounds, knob("BR_SOLO_TOP", "top", top)));
+        P.nslots = 3 * P.workers;
+        P.qs = 2;
+    }
     return P;
 }
 
@@ -97,6 +164,7 @@ int ensure_workspace(br_ctx* c, size_t bytes, hipStream_t s) {
     if (c->ws.base) BR_HIP(hipFree(c->ws.base));
     c->ws.base = nullptr;
     c->ws.size = 0;
+    c->solo_key_base = nullptr;    // new memory: the solo slots start over
     hipError_t e = hipMalloc(&c->ws.base, want);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -118,20 +186,41 @@ int ensure_pinned(br_ctx* c, size_t bytes) {
     return BR_OK;
 }
 
-// Workspace layout: [err | cnt | state | packed state | cert | off | cap]
+// Workspace layout: [err | cnt | state | packed state | cert | off | cap |
+// solo: pool | park + arrivals | queue | dense node states | slot tags | slots |
+// bridge step]; everything before `cert` is cleared per call.
 struct Layout {
-    size_t err, cnt, state, packed, cert, off, cap, bws, total;
+    size_t err, cnt, state, packed, cert, off, cap, pool, park, queue, dense, tags, slots, lmeta, rootw, bws, total;
 };
+// the one-graph batch description of the LDS plan: eoff[2], then V, M,
+// rbase, cbase, vbase, n_items (one int64 word each), then the M work items
+constexpr size_t kLdsMetaWords = 8;
 static Layout layout(const Plan& P, bool device_final) {
     Layout L;
     size_t o = 0;
     L.err = o; o += 256;
     L.cnt = o; o = align256(o + sizeof(uint32_t) * 2 * (size_t)P.M);
-    L.state = o; o = align256(o + sizeof(uint32_t) * (size_t)P.qs * (size_t)P.V * (size_t)P.M);
-    L.packed = o; if (P.qs != 2 && P.M > 1) o = align256(o + sizeof(uint32_t) * 2 * (size_t)P.V * (size_t)P.M);
+    L.state = o;
+    if (P.lds) o = align256(o + sizeof(uint32_t) * (size_t)P.lds_counters);     // arrivals, queue
+    else if (!P.solo) o = align256(o + sizeof(uint32_t) * (size_t)P.qs * (size_t)P.V * (size_t)P.M);
+    L.packed = o; if (!P.solo && !P.lds && P.qs != 2 && P.M > 1) o = align256(o + sizeof(uint32_t) * 2 * (size_t)P.V * (size_t)P.M);
     L.cert = o; o = align256(o + sizeof(int2) * (size_t)std::max<int64_t>(P.cert_pairs, 1));
     L.off = o; o = align256(o + sizeof(int64_t) * (size_t)P.M);
     L.cap = o; o = align256(o + sizeof(int64_t) * (size_t)P.M);
+    L.pool = L.park = L.queue = L.dense = L.tags = L.slots = L.lmeta = L.rootw = o;
+    if (P.lds) {
+        L.lmeta = o; o = align256(o + sizeof(int64_t) * (kLdsMetaWords + (size_t)P.M));
+        L.rootw = o; o = align256(o + sizeof(uint32_t) * (size_t)P.V);
+    }
+    if (P.solo) {
+        const int64_t top_nodes = ((int64_t)P.M + (int64_t(1) << P.solo_top) - 1) >> P.solo_top;
+        L.pool = o; o = align256(o + 4 * (size_t)((P.nslots + 31) / 32));
+        L.park = o; o = align256(o + 4 * 2 * (size_t)P.M);
+        L.queue = o; o = align256(o + 4);
+        L.dense = o; o = align256(o + 4 * 2 * (size_t)P.V * (size_t)top_nodes);
+        L.tags = o; o = align256(o + 4 * (size_t)P.nslots);
+        L.slots = o; o = align256(o + 4 * 2 * (size_t)P.V * (size_t)P.nslots);
+    }
     L.bws = o; if (device_final) o = align256(o + sizeof(int32_t) * (size_t)device_bridges_words(P.V));
     L.total = o;
     return L;
@@ -151,10 +240,16 @@ static double ev_ms(br_ctx* c, int a, int b) {
     return ms;
 }
 
+int run_certificate_with(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int32_t M, hipStream_t s, Plan& P,
+                         DevBufs& B, bool device_final, const TuneEntry* plan_knobs) {
+    return run_certificate(c, d_edges, E, nullptr, 0, V, M, s, P, B, device_final, plan_knobs);
+}
+
 int run_certificate(br_ctx* c, const int32_t* d_a, int64_t Ea, const int32_t* d_b, int64_t Eb, int32_t V, int32_t M,
-                    hipStream_t s, Plan& P, DevBufs& B, bool device_final) {
+                    hipStream_t s, Plan& P, DevBufs& B, bool device_final, const TuneEntry* plan_knobs) {
     const int64_t E = Ea + Eb;
-    P = make_plan(E, V, M);
+    P = plan_knobs ? make_plan(E, V, M, true, plan_knobs) : plan_for(c->device, E, V, M);
+    if (Eb > 0 && P.lds) P = make_plan(E, V, M, false, nullptr);   // the LDS kernel reads one edge array
     const Layout L = layout(P, device_final);
     int rc = ensure_workspace(c, L.total, s);
     if (rc) return rc;
@@ -176,29 +271,103 @@ int run_certificate(br_ctx* c, const int32_t* d_a, int64_t Ea, const int32_t* d_
     // node regions: staged through pinned memory (the previous call's copy has
     // completed: every entry point ends with a stream synchronisation or an
     // event wait on the staging copy)
-    const size_t meta = sizeof(int64_t) * 2 * (size_t)M;
-    if (c->h_meta_n < 2 * (size_t)M) {
+    const size_t meta_words = 2 * (size_t)M + (P.lds ? kLdsMetaWords + (size_t)M : 0);
+    if (c->h_meta_n < meta_words) {
         if (c->h_meta) BR_HIP(hipHostFree(c->h_meta));
         c->h_meta = nullptr;
         c->h_meta_n = 0;
-        BR_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_meta), meta, hipHostMallocDefault));
-        c->h_meta_n = 2 * (size_t)M;
+        BR_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_meta), sizeof(int64_t) * meta_words, hipHostMallocDefault));
+        c->h_meta_n = meta_words;
     }
     std::memcpy(c->h_meta, P.off.data(), sizeof(int64_t) * M);
     std::memcpy(c->h_meta + M, P.cap.data(), sizeof(int64_t) * M);
     ev_record(c, 0, s);
     BR_HIP(hipMemcpyAsync(base + L.off, c->h_meta, sizeof(int64_t) * M, hipMemcpyHostToDevice, s));
     BR_HIP(hipMemcpyAsync(base + L.cap, c->h_meta + M, sizeof(int64_t) * M, hipMemcpyHostToDevice, s));
+    if (P.lds) {
+        int64_t* lm = c->h_meta + 2 * M;
+        lm[0] = 0;                 // eoff: graph 0 is edges [0, E)
+        lm[1] = E;
+        lm[2] = V | ((int64_t)M << 32);   // V[0] and Mg[0] as two int32 words
+        lm[3] = 1;                 // rbase: node k > 0 of graph 0 at index k
+        lm[4] = 0;                 // cbase
+        lm[5] = 0;                 // vbase
+        lm[6] = 0;
+        lm[7] = 0;
+        for (int64_t k = 0; k < M; k++) lm[kLdsMetaWords + k] = k;   // items: graph 0, chunk k
+        BR_HIP(hipMemcpyAsync(base + L.lmeta, lm, sizeof(int64_t) * (kLdsMetaWords + (size_t)M), hipMemcpyHostToDevice, s));
+    }
     BR_HIP(hipEventRecord(c->ev[7], s));
     // all-singleton forests, zero counters and error word
     BR_HIP(hipMemsetAsync(base, 0, L.cert, s));
     c->prof.launches = 1;
-    ev_record(c, 1, s);
-    launch_phase0(P, B, s);
+    c->prof.plan_kind = P.lds ? 2 : (P.solo ? 1 : 0);
+    int32_t first_step = 1;
+    if (P.lds) {
+        c->solo_key_base = nullptr;
+        const int64_t* lm = reinterpret_cast<const int64_t*>(base + L.lmeta);
+        BatchDev BD{};
+        BD.edges = B.edges;
+        BD.eoff = lm;
+        BD.V = reinterpret_cast<const int32_t*>(lm + 2);
+        BD.Mg = reinterpret_cast<const int32_t*>(lm + 2) + 1;
+        BD.rbase = lm + 3;
+        BD.cbase = lm + 4;
+        BD.vbase = lm + 5;
+        BD.noff = B.off;
+        BD.ncap = B.cap;
+        BD.items = lm + kLdsMetaWords;
+        BD.n_items = M;
+        BD.cert = B.cert;
+        BD.ncnt = B.cnt;
+        BD.arrive = reinterpret_cast<uint32_t*>(base + L.state);
+        BD.queue = BD.arrive + P.lds_counters - 1;
+        BD.err = B.err;
+        BD.rootw = reinterpret_cast<uint32_t*>(base + L.rootw);
+        ev_record(c, 1, s);
+        launch_batched(BD, P.lds_blocks, s, P.lds_big);
+        // the bridge step reads F's roots from the flags the kernel wrote (0 at a root)
+        B.state = BD.rootw;
+        B.qs = 1;
+        B.packed = nullptr;
+        first_step = M;            // every merge ran inside the kernel
+    } else if (P.solo) {
+        rc = solo_prepare(V);
+        if (rc) return rc;
+        SoloBufs Sb;
+        Sb.slots = reinterpret_cast<uint32_t*>(base + L.slots);
+        Sb.slot_tag = reinterpret_cast<uint32_t*>(base + L.tags);
+        Sb.pool = reinterpret_cast<uint32_t*>(base + L.pool);
+        Sb.park = reinterpret_cast<uint32_t*>(base + L.park);
+        Sb.queue = reinterpret_cast<uint32_t*>(base + L.queue);
+        Sb.dense = reinterpret_cast<uint32_t*>(base + L.dense);
+        Sb.nslots = P.nslots;
+        Sb.workers = P.workers;
+        // slot words carry tags from earlier calls on this workspace; a new
+        // workspace, V or slot count starts them over from "all roots"
+        if (c->solo_key_base != base + L.slots || c->solo_key_v != V || c->solo_key_slots != P.nslots) {
+            launch_fill_u32(Sb.slot_tag, (int64_t)(L.bws - L.tags) / 4, 0u, s);
+            c->solo_key_base = base + L.slots;
+            c->solo_key_v = V;
+            c->solo_key_slots = P.nslots;
+            c->prof.launches++;
+        }
+        B.state = Sb.dense;
+        B.qs = 2;
+        B.packed = nullptr;
+        B.shift = P.solo_top;
+        ev_record(c, 1, s);
+        launch_solo(P, B, Sb, s);
+        first_step = 1 << P.solo_top;
+    } else {
+        c->solo_key_base = nullptr;    // this call's layout overwrites where slots may have been
+        ev_record(c, 1, s);
+        launch_phase0(P, B, s);
+    }
     BR_HIP(hipGetLastError());
     c->prof.launches += phase0_launches(P);
     ev_record(c, 2, s);
-    for (int32_t step = 1; step < M; step *= 2) {
+    for (int32_t step = first_step; step < M; step *= 2) {
         c->prof.launches += launch_merge_round(P, B, step, s);
         BR_HIP(hipGetLastError());
     }
@@ -221,6 +390,13 @@ int br_create(br_ctx** out, int device) {
     BR_HIP(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) return fail(BR_EINVAL, "br_create: device %d not in [0,%d)", device, n);
     BR_HIP(hipSetDevice(device));
+    if (g_cus == 0) {
+        int cus = 0, lds = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeSharedMemPerBlockOptin, device) == hipSuccess && lds > 0)
+            g_max_lds = lds;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0) g_cus = cus;
+        (void)hipGetLastError();
+    }
     br_ctx* c = new br_ctx();
     c->device = device;
     for (auto& e : c->ev) {
@@ -439,9 +615,11 @@ int br_bridges_find(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int
     return BR_OK;
 }
 
-int br_two_edge_components(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int32_t M, int32_t* h_label,
-                           int64_t* n_classes, void* stream) {
-    if (!c || !h_label || !n_classes) return fail(BR_EINVAL, "br_two_edge_components: null argument");
+// 2-edge-connected classes, and with h_tree the bridge tree's edges too
+// (br_two_edge_components, br_bridge_tree)
+static int classes_common(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int32_t M, int32_t* h_label,
+                          int64_t* n_classes, int32_t* h_tree, int64_t cap, int64_t* n_tree, void* stream,
+                          const char* who) {
     int rc = check_common(d_edges, E, V);
     if (rc) return rc;
     if (M < 1) return fail(BR_EINVAL, "M = %d < 1", M);
@@ -456,11 +634,16 @@ int br_two_edge_components(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t
     DevBufs B;
     rc = run_certificate(c, d_edges, E, nullptr, 0, V, M, s, P, B, mode == 1);
     if (rc) return rc;
+    std::vector<uint64_t>& tkeys = c->keys;
+    tkeys.clear();
     if (mode == 1) {
-        // bridges and classes on the device: one copy of the status block and labels
+        // bridges and classes on the device: one copy of the status block and
+        // labels (and one of the tree's edges)
         int32_t* d_label = nullptr;
         uint32_t* d_n = nullptr;
-        rc = device_classes(P, B, c->bws, &d_label, &d_n, s);
+        uint64_t* d_tkeys = nullptr;
+        rc = h_tree ? device_bridge_tree(P, B, c->bws, &d_label, &d_n, &d_tkeys, s)
+                    : device_classes(P, B, c->bws, &d_label, &d_n, s);
         if (rc) return rc;
         BR_HIP(hipGetLastError());
         rc = ensure_pinned(c, 256 + 4 * (size_t)V);
@@ -471,53 +654,91 @@ int br_two_edge_components(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t
         if (rc) return rc;
         BR_HIP(hipStreamSynchronize(s));
         const uint32_t err = hc[4];
-        if (err & 1u) return fail(BR_ERANGE, "br_two_edge_components: an edge has a vertex id outside [0, %d)", V);
-        if (err != 0 || (int64_t)hc[2] + hc[3] > P.cap[0])
-            return fail(BR_EINTERNAL, "br_two_edge_components: region overflow");
+        if (err & 1u) return fail(BR_ERANGE, "%s: an edge has a vertex id outside [0, %d)", who, V);
+        if (err != 0 || (int64_t)hc[2] + hc[3] > P.cap[0]) return fail(BR_EINTERNAL, "%s: region overflow", who);
         std::memcpy(h_label, reinterpret_cast<const char*>(hc) + 256, 4 * (size_t)V);
         *n_classes = hc[1];
-        return BR_OK;
+        if (h_tree) {
+            const uint32_t nt = hc[5];
+            if (nt > (uint32_t)std::max(V - 1, 0)) return fail(BR_EINTERNAL, "%s: %u tree edges", who, nt);
+            tkeys.resize(nt);
+            if (nt) {
+                BR_HIP(hipMemcpyAsync(tkeys.data(), d_tkeys, 8 * (size_t)nt, hipMemcpyDeviceToHost, s));
+                BR_HIP(hipStreamSynchronize(s));
+            }
+        }
+    } else {
+        const int64_t cap0 = P.cap[0];
+        rc = ensure_pinned(c, sizeof(int2) * (size_t)std::max<int64_t>(cap0, 1) + 64);
+        if (rc) return rc;
+        char* h = static_cast<char*>(c->pinned);
+        uint32_t* hc = reinterpret_cast<uint32_t*>(h);
+        int2* hx = reinterpret_cast<int2*>(h + 64);
+        BR_HIP(hipMemcpyAsync(hc, B.cnt, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        BR_HIP(hipMemcpyAsync(hc + 2, B.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        if (cap0 > 0) BR_HIP(hipMemcpyAsync(hx, B.cert + P.off[0], sizeof(int2) * cap0, hipMemcpyDeviceToHost, s));
+        rc = ctx_end(c, s);
+        if (rc) return rc;
+        BR_HIP(hipStreamSynchronize(s));
+        const uint32_t n1 = hc[0], n2 = hc[1], err = hc[2];
+        if (err & 1u) return fail(BR_ERANGE, "%s: an edge has a vertex id outside [0, %d)", who, V);
+        if (err != 0 || (int64_t)n1 + n2 > cap0) return fail(BR_EINTERNAL, "%s: region overflow", who);
+        std::vector<uint64_t> bkeys;
+        certificate_bridges(hx, n1, hx + cap0 - n2, n2, V, c->dfs, bkeys);
+        canonical_sort(bkeys);
+        // union of the certificate's non-bridge edges (a bridge has no parallel copy)
+        std::vector<int32_t> par((size_t)V);
+        for (int32_t v = 0; v < V; v++) par[v] = v;
+        auto find = [&](int32_t x) {
+            while (par[x] != x) { par[x] = par[par[x]]; x = par[x]; }
+            return x;
+        };
+        int64_t classes = V;
+        auto join = [&](const int2& e) {
+            const uint64_t k = (uint64_t)(uint32_t)std::min(e.x, e.y) << 32 | (uint32_t)std::max(e.x, e.y);
+            if (std::binary_search(bkeys.begin(), bkeys.end(), k)) return;
+            int32_t a = find(e.x), b = find(e.y);
+            if (a == b) return;
+            if (a < b) std::swap(a, b);
+            par[a] = b;     // the smaller id stays the root: the label is the class minimum
+            classes--;
+        };
+        for (uint32_t k = 0; k < n1; k++) join(hx[k]);
+        for (uint32_t k = 0; k < n2; k++) join(hx[cap0 - n2 + k]);
+        for (int32_t v = 0; v < V; v++) h_label[v] = find(v);
+        *n_classes = classes;
+        if (h_tree)
+            for (uint64_t k : bkeys) {
+                const uint32_t a = (uint32_t)h_label[k >> 32], b = (uint32_t)h_label[k & 0xffffffffu];
+                tkeys.push_back((uint64_t)std::min(a, b) << 32 | std::max(a, b));
+            }
     }
-    const int64_t cap0 = P.cap[0];
-    rc = ensure_pinned(c, sizeof(int2) * (size_t)std::max<int64_t>(cap0, 1) + 64);
-    if (rc) return rc;
-    char* h = static_cast<char*>(c->pinned);
-    uint32_t* hc = reinterpret_cast<uint32_t*>(h);
-    int2* hx = reinterpret_cast<int2*>(h + 64);
-    BR_HIP(hipMemcpyAsync(hc, B.cnt, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    BR_HIP(hipMemcpyAsync(hc + 2, B.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    if (cap0 > 0) BR_HIP(hipMemcpyAsync(hx, B.cert + P.off[0], sizeof(int2) * cap0, hipMemcpyDeviceToHost, s));
-    rc = ctx_end(c, s);
-    if (rc) return rc;
-    BR_HIP(hipStreamSynchronize(s));
-    const uint32_t n1 = hc[0], n2 = hc[1], err = hc[2];
-    if (err & 1u) return fail(BR_ERANGE, "br_two_edge_components: an edge has a vertex id outside [0, %d)", V);
-    if (err != 0 || (int64_t)n1 + n2 > cap0) return fail(BR_EINTERNAL, "br_two_edge_components: region overflow");
-    c->keys.clear();
-    certificate_bridges(hx, n1, hx + cap0 - n2, n2, V, c->dfs, c->keys);
-    canonical_sort(c->keys);
-    // union of the certificate's non-bridge edges (a bridge has no parallel copy)
-    std::vector<int32_t> par((size_t)V);
-    for (int32_t v = 0; v < V; v++) par[v] = v;
-    auto find = [&](int32_t x) {
-        while (par[x] != x) { par[x] = par[par[x]]; x = par[x]; }
-        return x;
-    };
-    int64_t classes = V;
-    auto join = [&](const int2& e) {
-        const uint64_t k = (uint64_t)(uint32_t)std::min(e.x, e.y) << 32 | (uint32_t)std::max(e.x, e.y);
-        if (std::binary_search(c->keys.begin(), c->keys.end(), k)) return;
-        int32_t a = find(e.x), b = find(e.y);
-        if (a == b) return;
-        if (a < b) std::swap(a, b);
-        par[a] = b;     // the smaller id stays the root: the label is the class minimum
-        classes--;
-    };
-    for (uint32_t k = 0; k < n1; k++) join(hx[k]);
-    for (uint32_t k = 0; k < n2; k++) join(hx[cap0 - n2 + k]);
-    for (int32_t v = 0; v < V; v++) h_label[v] = find(v);
-    *n_classes = classes;
+    if (!h_tree) return BR_OK;
+    canonical_sort(tkeys);
+    const int64_t nt = (int64_t)tkeys.size();
+    *n_tree = nt;
+    if (nt > cap) return fail(BR_ECAP, "%s: %lld tree edges, capacity %lld", who, (long long)nt, (long long)cap);
+    for (int64_t i = 0; i < nt; i++) {
+        h_tree[2 * i] = (int32_t)(tkeys[i] >> 32);
+        h_tree[2 * i + 1] = (int32_t)(tkeys[i] & 0xffffffffu);
+    }
     return BR_OK;
+}
+
+int br_two_edge_components(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int32_t M, int32_t* h_label,
+                           int64_t* n_classes, void* stream) {
+    if (!c || !h_label || !n_classes) return fail(BR_EINVAL, "br_two_edge_components: null argument");
+    return classes_common(c, d_edges, E, V, M, h_label, n_classes, nullptr, 0, nullptr, stream,
+                          "br_two_edge_components");
+}
+
+int br_bridge_tree(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int32_t M, int32_t* h_label,
+                   int32_t* h_tree, int64_t cap, int64_t* n_classes, int64_t* n_tree, void* stream) {
+    if (!c || !h_label || !n_classes || !n_tree || cap < 0 || (cap > 0 && !h_tree))
+        return fail(BR_EINVAL, "br_bridge_tree: null argument");
+    int32_t dummy[2];
+    return classes_common(c, d_edges, E, V, M, h_label, n_classes, h_tree ? h_tree : dummy, cap, n_tree, stream,
+                          "br_bridge_tree");
 }
 
 int br_articulation_points(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int32_t* h_out, int64_t cap,
@@ -537,6 +758,7 @@ int br_articulation_points(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t
     const int mode = c->final_step;   // read once: the workspace layout depends on it
     const size_t ws_cert = 4 * (size_t)scan_first_words(E, V);
     const size_t ws_test = mode == 1 ? 4 * (size_t)device_bridges_words(V) : 0;
+    c->solo_key_base = nullptr;        // the scan-first search reuses the workspace
     rc = ensure_workspace(c, ws_cert + ws_test + 256, s);
     if (rc) return rc;
     rc = ensure_pinned(c, 256 + 2 * sizeof(int2) * (size_t)std::max(V, 1));
@@ -605,6 +827,81 @@ int br_articulation_points(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t
         return fail(BR_ECAP, "br_articulation_points: %lld articulation points, capacity %lld", (long long)aps.size(),
                     (long long)cap);
     std::copy(aps.begin(), aps.end(), h_out);
+    return BR_OK;
+}
+
+int br_autotune(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int32_t M, char* out, int64_t out_cap,
+                void* stream) {
+    if (!c || (out_cap > 0 && !out) || out_cap < 0) return fail(BR_EINVAL, "br_autotune: bad argument");
+    int rc = check_common(d_edges, E, V);
+    if (rc) return rc;
+    if (M < 1) return fail(BR_EINVAL, "M = %d < 1", M);
+    BR_HIP(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const std::string key = plain_tune_key(c->device, E, V, M);
+    TuneEntry best;
+    int source = 0;   // 0: from the cache, 1: measured now
+    if (!tune_get(key, best)) {
+        source = 1;
+        // candidate plans: the team path with three first-stage tiles, and
+        // (where its bitmaps fit) the one-workgroup-per-node path in each
+        // worker shape with three merge depths
+        std::vector<TuneEntry> cands;
+        for (int tile : {4096, 2048, 1024}) cands.push_back({{"lds", 0}, {"solo", 0}, {"tile", tile}});
+        if (E > 0 && V <= batched_max_v_big() && M < (1 << 20)) cands.push_back({{"lds", 1}});
+        if (E > 0 && V <= solo_max_v()) {
+            const Plan d = make_plan(E, V, M, true, nullptr);
+            TuneEntry on{{"lds", 0}, {"solo", 1}};
+            const Plan ds = make_plan(E, V, M, true, &on);
+            for (int v = 0; v < solo_variants(); v++)
+                for (int dt : {-1, 0, 1}) {
+                    const int top = ds.solo_top + dt;
+                    if (top < 0 || top > d.rounds) continue;
+                    cands.push_back({{"lds", 0}, {"solo", 1}, {"variant", v}, {"top", top}});
+                }
+        }
+        double best_ms = 1e30;
+        BR_HIP(hipEventSynchronize(c->ev[7]));
+        rc = ctx_begin(c, s);
+        if (rc) return rc;
+        for (const TuneEntry& t : cands) {
+            // time the certificate (phase 0 and merges) of this plan: one run
+            // to settle the workspace, then the best of two
+            double ms = 1e30;
+            for (int rep = 0; rep < 3; rep++) {
+                Plan P;
+                DevBufs B;
+                TuneEntry tt = t;
+                BR_HIP(hipEventSynchronize(c->ev[7]));
+                BR_HIP(hipEventRecord(c->ev[5], s));
+                rc = run_certificate_with(c, d_edges, E, V, M, s, P, B, false, &tt);
+                if (rc) return rc;
+                BR_HIP(hipEventRecord(c->ev[6], s));
+                BR_HIP(hipEventSynchronize(c->ev[6]));
+                float f = 0.f;
+                BR_HIP(hipEventElapsedTime(&f, c->ev[5], c->ev[6]));
+                if (rep > 0) ms = std::min(ms, (double)f);
+            }
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = t;
+            }
+        }
+        rc = ctx_end(c, s);
+        if (rc) return rc;
+        best["ms"] = best_ms;
+        tune_put(key, best);
+    }
+    if (out_cap > 0) {
+        std::string js = "{\"key\": \"" + key + "\", \"source\": \"" + (source ? "measured" : "cache") + "\"";
+        for (const auto& kv : best) {
+            char buf[96];
+            std::snprintf(buf, sizeof buf, ", \"%s\": %.6g", kv.first.c_str(), kv.second);
+            js += buf;
+        }
+        js += "}";
+        std::snprintf(out, (size_t)out_cap, "%s", js.c_str());
+    }
     return BR_OK;
 }
 

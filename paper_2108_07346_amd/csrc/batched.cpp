@@ -6,8 +6,9 @@
 // certificates to the host" in a HIP graph that is replayed while the batch
 // shape and input buffer stay the same, then runs the final depth-first
 // search of every graph on a pool of host threads.  chunk_edges = 0 asks the
-// built-in tuner, which times the candidate chunk sizes on the batch itself
-// and remembers the winner per batch shape.
+// library's tuner, which times candidate chunk sizes and workgroups per CU on
+// the batch itself and remembers the winner per device and batch shape
+// (tuner.cpp).
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -32,7 +33,7 @@ namespace {
 
 struct BatchPlan {
     // key
-    int32_t G = 0, C = 0;
+    int32_t G = 0, C = 0, bpc = 0;
     std::vector<int64_t> eoff;
     std::vector<int32_t> V;
     // small graphs are the ones certified in LDS; the others go through br_bridges_find
@@ -87,7 +88,6 @@ struct BatchState {
     hipStream_t stream2 = nullptr;           // second branch of the captured final step (default priority)
     hipEvent_t fork = nullptr, join = nullptr;
     std::vector<std::unique_ptr<BatchPlan>> plans;      // small LRU
-    std::map<std::string, int32_t> tuned;               // batch shape -> chunk_edges
     std::vector<DfsScratch> scratch;
     std::vector<std::vector<uint64_t>> keys;
     std::unique_ptr<uint64_t[]> outk;           // per-graph bridge slots (reused, never zero-filled)
@@ -106,9 +106,10 @@ int64_t part_lo(int64_t E, int64_t M, int64_t i) { return i * (E / M) + (i * (E 
 
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
-int build_plan(BatchPlan& P, const int64_t* eoff, const int32_t* V, int32_t G, int32_t C, int cus) {
+int build_plan(BatchPlan& P, const int64_t* eoff, const int32_t* V, int32_t G, int32_t C, int32_t bpc, int cus) {
     P.G = G;
     P.C = C;
+    P.bpc = bpc;
     P.eoff.assign(eoff, eoff + G + 1);
     P.V.assign(V, V + G);
     const int32_t maxv = batched_max_v_dev();
@@ -246,7 +247,7 @@ int build_plan(BatchPlan& P, const int64_t* eoff, const int32_t* V, int32_t G, i
     P.h_err = P.h_cnt0 + 2 * (size_t)std::max(S, 1);
     P.h_sb = reinterpret_cast<uint32_t*>(h + a256(8 * (size_t)std::max<int64_t>(P.area0, 1)) +
                                          a256(8 * (size_t)std::max(S, 1)) + 256);
-    P.blocks = std::max(1, cus * batched_blocks_per_cu());
+    P.blocks = std::max(1, cus * bpc);
     return BR_OK;
 }
 
@@ -337,19 +338,19 @@ int run_device(BatchState& st, BatchPlan& P, const int32_t* d_edges, int mode) {
     return copy_back(P, s, mode);
 }
 
-std::string shape_key(const int64_t* eoff, const int32_t* V, int32_t G) {
-    // batch shape bucket for the tuner: G, total edges and largest V (log2 buckets)
+std::string shape_key(int device, const int64_t* eoff, const int32_t* V, int32_t G) {
+    // batch shape bucket for the tuner: device arch, G, total edges and
+    // largest V (log2 buckets)
     int64_t E = eoff[G] - eoff[0];
     int32_t mv = 0;
     for (int32_t g = 0; g < G; g++) mv = std::max(mv, V[g]);
-    int eb = 0, vb = 0;
-    while ((int64_t(1) << eb) < E) eb++;
-    while ((1 << vb) < mv) vb++;
-    return std::to_string(G) + ":" + std::to_string(eb) + ":" + std::to_string(vb);
+    return arch_name(device) + "|batched|g" + std::to_string(log2_bucket(G)) + "|e" + std::to_string(log2_bucket(E)) +
+           "|v" + std::to_string(log2_bucket(mv));
 }
 
-bool same_shape(const BatchPlan& P, const int64_t* eoff, const int32_t* V, int32_t G, int32_t C) {
-    return P.G == G && P.C == C && std::equal(P.eoff.begin(), P.eoff.end(), eoff) && std::equal(P.V.begin(), P.V.end(), V);
+bool same_shape(const BatchPlan& P, const int64_t* eoff, const int32_t* V, int32_t G, int32_t C, int32_t bpc) {
+    return P.G == G && P.C == C && P.bpc == bpc && std::equal(P.eoff.begin(), P.eoff.end(), eoff) &&
+           std::equal(P.V.begin(), P.V.end(), V);
 }
 
 }  // namespace
@@ -373,9 +374,9 @@ void batched_release(br_ctx* c) {
 }
 
 static int get_plan(br_ctx* c, BatchState& st, const int64_t* eoff, const int32_t* V, int32_t G, int32_t C,
-                    BatchPlan** out) {
+                    int32_t bpc, BatchPlan** out) {
     for (size_t i = 0; i < st.plans.size(); i++) {
-        if (same_shape(*st.plans[i], eoff, V, G, C)) {
+        if (same_shape(*st.plans[i], eoff, V, G, C, bpc)) {
             std::rotate(st.plans.begin(), st.plans.begin() + i, st.plans.begin() + i + 1);
             *out = st.plans[0].get();
             return BR_OK;
@@ -384,7 +385,7 @@ static int get_plan(br_ctx* c, BatchState& st, const int64_t* eoff, const int32_
     hipDeviceProp_t prop;
     BR_HIP(hipGetDeviceProperties(&prop, c->device));
     auto P = std::make_unique<BatchPlan>();
-    int rc = build_plan(*P, eoff, V, G, C, prop.multiProcessorCount);
+    int rc = build_plan(*P, eoff, V, G, C, bpc, prop.multiProcessorCount);
     if (rc) return rc;
     st.plans.insert(st.plans.begin(), std::move(P));
     if (st.plans.size() > 4) st.plans.pop_back();
@@ -399,6 +400,7 @@ using namespace br;
 extern "C" {
 
 int32_t br_batched_max_v(void) { return batched_max_v_dev(); }
+int32_t br_lds_max_v(void) { return batched_max_v_big(); }
 
 int br_bridges_find_batched(br_ctx* c, const int32_t* d_edges, const int64_t* h_edge_off, const int32_t* h_V,
                             int32_t G, int32_t chunk_edges, int32_t* h_bridges, int64_t cap, int64_t* h_bridge_off,
@@ -437,40 +439,49 @@ int br_bridges_find_batched(br_ctx* c, const int32_t* d_edges, const int64_t* h_
     // the caller's stream must have produced the input
     BR_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
 
-    int32_t C = chunk_edges;
+    // chunk size and workgroups per CU: given, or the tuner's (measured on
+    // this batch the first time its shape bucket is seen on this device,
+    // and kept in BR_AUTOTUNE_CACHE when that names a file)
+    int32_t C = chunk_edges, bpc = batched_blocks_per_cu();
     if (C == 0) {
-        const std::string key = shape_key(h_edge_off, h_V, G);
-        auto it = st.tuned.find(key);
-        if (it != st.tuned.end()) {
-            C = it->second;
+        const std::string key = shape_key(c->device, h_edge_off, h_V, G);
+        TuneEntry t;
+        if (tune_get(key, t) && t.count("chunk_edges") && t.count("blocks_per_cu")) {
+            C = (int32_t)t["chunk_edges"];
+            bpc = (int32_t)t["blocks_per_cu"];
         } else {
-            // tune: time each candidate chunk size on this batch (device part only)
+            // time every candidate on this batch (device part only)
             float best = 1e30f;
-            int32_t bestC = 16384;
-            for (int32_t cand : {4096, 8192, 16384, 32768, 65536, 131072}) {
-                BatchPlan* P = nullptr;
-                int rc = get_plan(c, st, h_edge_off, h_V, G, cand, &P);
-                if (rc) return rc;
-                float ms = 0.f;
-                for (int rep = 0; rep < 2; rep++) {
-                    BR_HIP(hipEventRecord(st.e0, st.stream));
-                    rc = run_device(st, *P, d_edges, 0);
+            int32_t bestC = 16384, bestB = bpc;
+            for (int32_t b = 1; b <= batched_max_blocks_per_cu(); b++)
+                for (int32_t cand : {4096, 8192, 16384, 32768, 65536, 131072}) {
+                    BatchPlan* P = nullptr;
+                    int rc = get_plan(c, st, h_edge_off, h_V, G, cand, b, &P);
                     if (rc) return rc;
-                    BR_HIP(hipEventRecord(st.e1, st.stream));
-                    BR_HIP(hipEventSynchronize(st.e1));
-                    BR_HIP(hipEventElapsedTime(&ms, st.e0, st.e1));
+                    float ms = 1e30f;
+                    for (int rep = 0; rep < 3; rep++) {
+                        BR_HIP(hipEventRecord(st.e0, st.stream));
+                        rc = run_device(st, *P, d_edges, 0);
+                        if (rc) return rc;
+                        BR_HIP(hipEventRecord(st.e1, st.stream));
+                        BR_HIP(hipEventSynchronize(st.e1));
+                        float f = 0.f;
+                        BR_HIP(hipEventElapsedTime(&f, st.e0, st.e1));
+                        if (rep > 0) ms = std::min(ms, f);
+                    }
+                    if (ms < best) {
+                        best = ms;
+                        bestC = cand;
+                        bestB = b;
+                    }
                 }
-                if (ms < best) {
-                    best = ms;
-                    bestC = cand;
-                }
-            }
-            st.tuned[key] = bestC;
+            tune_put(key, {{"chunk_edges", bestC}, {"blocks_per_cu", bestB}, {"ms", best}});
             C = bestC;
+            bpc = bestB;
         }
     }
     BatchPlan* P = nullptr;
-    int rc = get_plan(c, st, h_edge_off, h_V, G, C, &P);
+    int rc = get_plan(c, st, h_edge_off, h_V, G, C, bpc, &P);
     if (rc) return rc;
     const int mode = c->final_step;
     if (c->profiling) BR_HIP(hipEventRecord(st.e0, st.stream));

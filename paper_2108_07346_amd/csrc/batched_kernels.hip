@@ -11,7 +11,9 @@
 // the graph's certificate: F from the front, F' from the back.
 //
 // LDS union-find: one 32-bit word per vertex, low half = x - parent in F,
-// high half = x - parent in F' (0 = root; V <= kMaxV keeps both in 16 bits).
+// high half = x - parent in F' (0 = root; V <= 65,536 keeps both in 16 bits).
+// Two instances: graphs up to 4,096 vertices (three workgroups per CU) and
+// graphs up to 40,944 vertices (the whole LDS of a CU, one workgroup).
 // Hooking is a 32-bit LDS compare-and-swap that changes one half; a swap that
 // fails because the other half moved is simply retried.  The larger root is
 // hooked under the smaller representative, so chains decrease and the loop
@@ -27,11 +29,22 @@ namespace br {
 namespace {
 
 constexpr int kBB = 512;          // threads per workgroup
-constexpr int kMaxV = 4096;       // vertices per graph in LDS
-constexpr int kStage = 2 * (kMaxV - 1);
+constexpr int kMaxV = 4096;       // vertices per graph of the small kernel
+// the large kernel: the whole 160 KB of a CU's LDS for one graph's state, less
+// the counters (the offsets stay 16-bit: V <= 65,536)
+constexpr int kMaxVBig = (160 * 1024 - 64) / 4;
 
+// Staged = true: a merge re-runs the certificate on X_i u X_j into a fresh
+// state, staging the result in LDS before writing node i's region back (the
+// small kernel).  Staged = false: a merge rebuilds node i's state from its
+// own certificate (F's edges into F, F''s into F' -- all accepted, nothing
+// written) and streams X_j in, appending what is accepted to node i's region
+// after its edges (the same certificate as the state-carrying merge; no
+// stage, so the state can take all of LDS).
+template <int MaxV, bool Staged>
 struct LdsState {
-    uint32_t q[kMaxV];            // packed F / F' offsets
+    static constexpr int kStage = Staged ? 2 * (MaxV - 1) : 1;
+    uint32_t q[MaxV];             // packed F / F' offsets
     uint32_t stage[kStage];       // merged certificate: (u | v << 16), F from front, F' from back
     uint32_t n1, n2;              // counters of the current certificate
     int32_t item, last, errv;
@@ -143,7 +156,8 @@ __device__ __forceinline__ void load_step(const BatchDev& B, int64_t base, int64
     }
 }
 
-__device__ void certify_chunk(LdsState& S, const BatchDev& B, int64_t t0, int64_t t1, uint32_t V, int64_t off,
+template <class LS>
+__device__ void certify_chunk(LS& S, const BatchDev& B, int64_t t0, int64_t t1, uint32_t V, int64_t off,
                               int64_t cap) {
     for (uint32_t x = threadIdx.x; x < V; x += kBB) S.q[x] = 0;
     if (threadIdx.x == 0) { S.n1 = 0; S.n2 = 0; }
@@ -183,7 +197,10 @@ __device__ void certify_chunk(LdsState& S, const BatchDev& B, int64_t t0, int64_
 
 // Offer the certificate stored in node region (off, cap) with counts (n1, n2)
 // to the LDS state, staging accepted edges in S.stage.
-__device__ void offer_region(LdsState& S, const BatchDev& B, int64_t off, int64_t cap, uint32_t n1, uint32_t n2) {
+template <class LS>
+__device__ void offer_region(LS& S, const BatchDev& B, int64_t off, int64_t cap, uint32_t n1, uint32_t n2,
+                             uint32_t maxv) {
+    constexpr int kStage = LS::kStage;
     const int64_t total = (int64_t)n1 + n2;
     for (int64_t base = 0; base < total; base += kBB) {
         const int64_t k = base + threadIdx.x;
@@ -193,7 +210,7 @@ __device__ void offer_region(LdsState& S, const BatchDev& B, int64_t off, int64_
             const uint64_t r = __hip_atomic_load(reinterpret_cast<const uint64_t*>(B.cert + (k < n1 ? off + k : off + cap - n2 + (k - n1))),
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             e = make_int2((int32_t)(uint32_t)r, (int32_t)(uint32_t)(r >> 32));
-            if ((uint32_t)e.x < kMaxV && (uint32_t)e.y < kMaxV) loffer(S.q, (uint32_t)e.x, (uint32_t)e.y, a1, a2);
+            if ((uint32_t)e.x < maxv && (uint32_t)e.y < maxv) loffer(S.q, (uint32_t)e.x, (uint32_t)e.y, a1, a2);
             else atomicOr(B.err, 2u);
         }
         const uint32_t w = (uint32_t)e.x | ((uint32_t)e.y << 16);
@@ -205,10 +222,62 @@ __device__ void offer_region(LdsState& S, const BatchDev& B, int64_t off, int64_
     }
 }
 
+__device__ __forceinline__ int2 region_edge(const BatchDev& B, int64_t off, int64_t cap, uint32_t n1, uint32_t n2,
+                                            int64_t k) {
+    const uint64_t r = __hip_atomic_load(reinterpret_cast<const uint64_t*>(B.cert + (k < n1 ? off + k : off + cap - n2 + (k - n1))),
+                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_int2((int32_t)(uint32_t)r, (int32_t)(uint32_t)(r >> 32));
+}
+
+// Node i's state from its certificate in (off, cap): F's edges hooked in F,
+// then (after a barrier) F''s in F'.  Each set is a forest, so every edge is
+// accepted whatever the order; nothing is written.
+template <class LS>
+__device__ void rebuild_state(LS& S, const BatchDev& B, int64_t off, int64_t cap, uint32_t n1, uint32_t n2,
+                              uint32_t V) {
+    for (int64_t k = threadIdx.x; k < n1; k += kBB) {
+        const int2 e = region_edge(B, off, cap, n1, n2, k);
+        if ((uint32_t)e.x < V && (uint32_t)e.y < V) (void)lunite<0>(S.q, (uint32_t)e.x, (uint32_t)e.y);
+        else atomicOr(B.err, 2u);
+    }
+    __syncthreads();
+    for (int64_t k = (int64_t)n1 + threadIdx.x; k < (int64_t)n1 + n2; k += kBB) {
+        const int2 e = region_edge(B, off, cap, n1, n2, k);
+        if ((uint32_t)e.x < V && (uint32_t)e.y < V) (void)lunite<1>(S.q, (uint32_t)e.x, (uint32_t)e.y);
+        else atomicOr(B.err, 2u);
+    }
+}
+
+// The certificate in (offj, capj) offered to the state; accepted edges are
+// appended to region (offi, capi) after the S.n1 / S.n2 edges already there.
+template <class LS>
+__device__ void offer_region_append(LS& S, const BatchDev& B, int64_t offj, int64_t capj, uint32_t n1, uint32_t n2,
+                                    uint32_t V, int64_t offi, int64_t capi) {
+    const int64_t total = (int64_t)n1 + n2;
+    for (int64_t base = 0; base < total; base += kBB) {
+        const int64_t k = base + threadIdx.x;
+        bool a1 = false, a2 = false;
+        int2 e = make_int2(0, 0);
+        if (k < total) {
+            e = region_edge(B, offj, capj, n1, n2, k);
+            if ((uint32_t)e.x < V && (uint32_t)e.y < V) loffer(S.q, (uint32_t)e.x, (uint32_t)e.y, a1, a2);
+            else atomicOr(B.err, 2u);
+        }
+        uint64_t m;
+        const uint32_t p1 = reserve(&S.n1, a1, m);
+        if (a1) { if (p1 < capi) B.cert[offi + p1] = e; else atomicOr(B.err, 2u); }
+        const uint32_t p2 = reserve(&S.n2, a2, m);
+        if (a2) { if (p2 < capi) B.cert[offi + capi - 1 - p2] = e; else atomicOr(B.err, 2u); }
+    }
+}
+
 }  // namespace
 
+template <int MaxV, bool Staged>
 __global__ void __launch_bounds__(kBB) k_batched(BatchDev B) {
-    __shared__ LdsState S;
+    using LS = LdsState<MaxV, Staged>;
+    constexpr int kStage = LS::kStage;
+    __shared__ LS S;
     for (;;) {
         if (threadIdx.x == 0) S.item = (int32_t)atomicAdd(B.queue, 1u);
         __syncthreads();
@@ -269,20 +338,33 @@ __global__ void __launch_bounds__(kBB) k_batched(BatchDev B) {
             const uint32_t aj2 = __hip_atomic_load(&B.ncnt[2 * nidx(j) + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const int64_t offi = B.noff[nidx(i)], capi = B.ncap[nidx(i)];
             const int64_t offj = B.noff[nidx(j)], capj = B.ncap[nidx(j)];
-            offer_region(S, B, offi, capi, min(ai1, (uint32_t)capi), min(ai2, (uint32_t)capi - min(ai1, (uint32_t)capi)));
-            offer_region(S, B, offj, capj, min(aj1, (uint32_t)capj), min(aj2, (uint32_t)capj - min(aj1, (uint32_t)capj)));
-            __syncthreads();
-            n1 = min(S.n1, (uint32_t)kStage);
-            n2 = min(S.n2, (uint32_t)kStage - n1);
-            if ((int64_t)n1 + n2 > capi) {
-                if (threadIdx.x == 0) atomicOr(B.err, 2u);
-                n1 = 0;
-                n2 = 0;
-            }
-            for (uint32_t k = threadIdx.x; k < n1 + n2; k += kBB) {
-                const uint32_t w = k < n1 ? S.stage[k] : S.stage[kStage - n2 + (k - n1)];
-                const int64_t pos = k < n1 ? offi + k : offi + capi - n2 + (k - n1);
-                B.cert[pos] = make_int2((int32_t)(w & 0xffffu), (int32_t)(w >> 16));
+            const uint32_t ci1 = min(ai1, (uint32_t)capi), ci2 = min(ai2, (uint32_t)capi - ci1);
+            const uint32_t cj1 = min(aj1, (uint32_t)capj), cj2 = min(aj2, (uint32_t)capj - cj1);
+            if constexpr (Staged) {
+                offer_region(S, B, offi, capi, ci1, ci2, (uint32_t)MaxV);
+                offer_region(S, B, offj, capj, cj1, cj2, (uint32_t)MaxV);
+                __syncthreads();
+                n1 = min(S.n1, (uint32_t)kStage);
+                n2 = min(S.n2, (uint32_t)kStage - n1);
+                if ((int64_t)n1 + n2 > capi) {
+                    if (threadIdx.x == 0) atomicOr(B.err, 2u);
+                    n1 = 0;
+                    n2 = 0;
+                }
+                for (uint32_t k = threadIdx.x; k < n1 + n2; k += kBB) {
+                    const uint32_t w = k < n1 ? S.stage[k] : S.stage[kStage - n2 + (k - n1)];
+                    const int64_t pos = k < n1 ? offi + k : offi + capi - n2 + (k - n1);
+                    B.cert[pos] = make_int2((int32_t)(w & 0xffffu), (int32_t)(w >> 16));
+                }
+            } else {
+                rebuild_state(S, B, offi, capi, ci1, ci2, V);
+                if (threadIdx.x == 0) { S.n1 = ci1; S.n2 = ci2; }
+                __syncthreads();
+                offer_region_append(S, B, offj, capj, cj1, cj2, V, offi, capi);
+                __syncthreads();
+                n1 = S.n1;
+                n2 = S.n2;
+                if ((int64_t)n1 + n2 > capi && threadIdx.x == 0) atomicOr(B.err, 2u);
             }
             __syncthreads();
             node = i;
@@ -293,11 +375,17 @@ __global__ void __launch_bounds__(kBB) k_batched(BatchDev B) {
     }
 }
 
-void launch_batched(const BatchDev& B, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_batched, dim3(blocks), dim3(kBB), 0, s, B);
+void launch_batched(const BatchDev& B, int blocks, hipStream_t s, bool big) {
+    if (big) hipLaunchKernelGGL((k_batched<kMaxVBig, false>), dim3(blocks), dim3(kBB), 0, s, B);
+    else hipLaunchKernelGGL((k_batched<kMaxV, true>), dim3(blocks), dim3(kBB), 0, s, B);
 }
 
 int32_t batched_max_v_dev() { return kMaxV; }
+int32_t batched_max_v_big() { return kMaxVBig; }
 int32_t batched_blocks_per_cu() { return 3; }
+// workgroups of the small kernel that fit one CU's LDS together
+int32_t batched_max_blocks_per_cu() {
+    return std::max<int32_t>(1, (int32_t)((160 * 1024) / sizeof(LdsState<kMaxV, true>)));
+}
 
 }  // namespace br

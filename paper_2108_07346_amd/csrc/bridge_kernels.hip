@@ -644,6 +644,32 @@ __global__ void k_class_out(const uint32_t* g, int32_t V, int32_t* label, uint32
     if (threadIdx.x == 0 && roots) atomicAdd(nclass, roots);
 }
 
+// Edges of the bridge tree: a tree edge (u, v) of F joins two classes iff it
+// is a bridge (an edge of F inside a class lies on a cycle; every bridge lies
+// in every spanning forest), and then it becomes the tree edge between the
+// two classes' labels, as the key min << 32 | max.  Keys staged in LDS, one
+// reservation per block on *ntree.
+__global__ void k_tree_keys(const int2* f1, const uint32_t* cnt, const int32_t* label, uint64_t* keys, uint32_t* ntree) {
+    __shared__ uint64_t stage[kT];
+    __shared__ uint32_t n, base;
+    const int64_t m = cnt[0];
+    for (int64_t b0 = blockIdx.x * (int64_t)kT; b0 < m; b0 += (int64_t)gridDim.x * kT) {
+        if (threadIdx.x == 0) n = 0;
+        __syncthreads();
+        const int64_t k = b0 + threadIdx.x;
+        if (k < m) {
+            const int2 e = f1[k];
+            const uint32_t a = (uint32_t)label[e.x], c = (uint32_t)label[e.y];
+            if (a != c) stage[atomicAdd(&n, 1u)] = (uint64_t)min(a, c) << 32 | max(a, c);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) base = n ? atomicAdd(ntree, n) : 0u;
+        __syncthreads();
+        if (threadIdx.x < n) keys[base + threadIdx.x] = stage[threadIdx.x];
+        __syncthreads();
+    }
+}
+
 // counters of the certificate and the result next to the keys, for one copy
 __global__ void k_status(const uint32_t* cnt, const uint32_t* err, uint32_t* misc) {
     if (threadIdx.x == 0) {
@@ -822,6 +848,26 @@ int device_classes_cert(const int2* f1, const int2* f2, int32_t dir, const uint3
                        reinterpret_cast<uint32_t*>(W.misc + 1));
     *d_label = label;
     *d_n = reinterpret_cast<uint32_t*>(W.misc + 1);
+    return BR_OK;
+}
+
+// The bridge tree of node 0's certificate: labels and class count as
+// device_classes; the tree's edges (keys min << 32 | max of the two classes,
+// unordered) at *d_tkeys, their number at (*d_n)[4] (status word 5).
+int device_bridge_tree(const Plan& P, const DevBufs& B, int32_t* ws, int32_t** d_label, uint32_t** d_n,
+                       uint64_t** d_tkeys, hipStream_t s) {
+    const int2* f1 = B.cert + P.off[0];
+    const int2* f2 = B.cert + P.off[0] + P.cap[0] - 1;
+    int rc = device_classes_cert(f1, f2, -1, B.cnt, B.state, (int32_t)B.qs, P.V, ws, d_label, d_n, s);
+    if (rc) return rc;
+    // the list-ranking links are free once the tree is numbered: room for V - 1 keys
+    const BridgeWs W = carve(ws, P.V);
+    uint64_t* tkeys = reinterpret_cast<uint64_t*>(W.link);
+    const int64_t m = std::max<int64_t>(P.cap[0], 1);
+    hipLaunchKernelGGL(k_tree_keys, dim3((unsigned)std::min<int64_t>((m + kT - 1) / kT, kOutBlocks)), dim3(kT), 0, s, f1,
+                       B.cnt, (const int32_t*)*d_label, tkeys, *d_n + 4);
+    launch_bridge_status(B.cnt, B.err, *d_n, s);
+    *d_tkeys = tkeys;
     return BR_OK;
 }
 

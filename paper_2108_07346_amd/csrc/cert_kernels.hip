@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(kBlock) k_merge(DevBufs B, int32_t V, int32_t 
     if (t0 >= t1) return;
     __shared__ Stage S;
     stage_reset(S);
-    uint32_t* q = B.state + (size_t)i * (size_t)B.qs * (size_t)V;
+    uint32_t* q = B.state + (size_t)(i >> B.shift) * (size_t)B.qs * (size_t)V;
     for (int64_t base = t0; base < t1; base += kBlock) {
         const int64_t k = base + threadIdx.x;
         bool a1 = false, a2 = false;
@@ -337,8 +337,10 @@ void launch_phase0(const Plan& P, DevBufs& B, hipStream_t s) {
         // flight); later stages (mostly rejections) in full tiles, one
         // reservation each on the chunk's counters
         int64_t tile = P.tile;
-        if (k == 0)
+        if (k == 0) {
+            if (P.tile0_max >= kBlock) tile = std::min<int64_t>(tile, P.tile0_max / kBlock * kBlock);
             while (tile > kBlock && (int64_t)P.M * ((rhi - rlo + tile - 1) / tile) < 512) tile /= 2;
+        }
         const int64_t tpc = std::max<int64_t>(1, (rhi - rlo + tile - 1) / tile);
         hipLaunchKernelGGL(k_phase0, dim3((unsigned)(chunk_slots * tpc)), dim3(kBlock), 0, s, B, P.E, P.V, P.M,
                            (int32_t)tile, (int32_t)tpc, P.xcd_map, rlo, rhi);
@@ -364,6 +366,8 @@ void launch_phase0(const Plan& P, DevBufs& B, hipStream_t s) {
 
 int phase0_launches(const Plan& P) {
     // mirrors launch_phase0's choices
+    if (P.solo) return 2;
+    if (P.lds) return 1;
     if (P.E == 0) return 0;
     const int64_t per = (P.E + P.M - 1) / P.M;
     const bool has_packed = P.qs != 2 && P.M > 1;
@@ -412,7 +416,7 @@ int launch_merge_round(const Plan& P, const DevBufs& B, int32_t step, hipStream_
         if (4 * prev >= 3 * (int64_t)P.V) {
             const int64_t n = (int64_t)P.V * merges;
             hipLaunchKernelGGL(k_compress_nodes, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536))),
-                               dim3(256), 0, s, B.state, P.V, 2 * (int64_t)step, merges);
+                               dim3(256), 0, s, B.state, P.V, (2 * (int64_t)step) >> B.shift, merges);
             launches++;
         }
     }

@@ -7,6 +7,7 @@
 #include <condition_variable>
 #include <cstdint>
 #include <functional>
+#include <map>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -77,6 +78,14 @@ class Pool {
     bool stop_ = false;
 };
 
+// ---- tuner (tuner.cpp) ----------------------------------------------------------
+// A tuned choice: named numbers ("solo", "variant", "chunk_edges", ...).
+using TuneEntry = std::map<std::string, double>;
+std::string arch_name(int device);      // e.g. "gfx950"
+int log2_bucket(int64_t x);             // smallest b with 2^b >= x
+bool tune_get(const std::string& key, TuneEntry& out);
+void tune_put(const std::string& key, const TuneEntry& e);   // also saved to BR_AUTOTUNE_CACHE if set
+
 // ---- device geometry shared with the kernels ---------------------------------
 // Chunk i of the phase tree is edges [lo(i), lo(i+1)) with lo(i) = floor(iE/M).
 struct Plan {
@@ -92,6 +101,20 @@ struct Plan {
     int64_t cert_pairs = 0;        // sum of caps
     std::vector<int64_t> round_cap;// per round: largest sibling cap
     int32_t qs = 2;                // union-find state words per vertex (F at +0, F' at +1)
+    // one workgroup per node (solo_kernels.hip) for phase 0 and merge levels
+    // 1..solo_top; the rounds above run as team launches on the dense states
+    bool solo = false;
+    int32_t solo_top = 0;
+    int32_t solo_variant = 0;      // worker shape (solo_kernels.hip)
+    int32_t workers = 0;           // persistent workgroups
+    int32_t nslots = 0;            // union-find slots (workers' own + free pool)
+    int32_t tile0_max = 0;         // team path: largest first-stage tile (0 = the kernel's)
+    // the whole phase tree in LDS (batched_kernels.hip: one graph, a
+    // workgroup per chunk and last-arriver merges) when V fits a workgroup's LDS
+    bool lds = false;
+    bool lds_big = false;          // the 160 KB kernel (V above the small kernel's limit)
+    int32_t lds_blocks = 0;
+    int64_t lds_counters = 0;      // merge arrival counters
 };
 
 // Certificate regions: node i owns pairs [off[i], off[i]+cap[i]); its F1 grows
@@ -108,7 +131,29 @@ struct DevBufs {
     const int64_t* cap = nullptr;  // [M]
     uint32_t* cnt = nullptr;       // [M][2]
     uint32_t* err = nullptr;       // bit 0: id out of range; bit 1: region overflow
+    int32_t shift = 0;             // node i's state is state + (i >> shift) * qs * V
 };
+
+// Buffers of the one-workgroup-per-node path (solo_kernels.hip).
+struct SoloBufs {
+    uint32_t* slots = nullptr;     // [nslots][2][V] tagged union-find words
+    uint32_t* slot_tag = nullptr;  // [nslots] (kept across calls; zero = slot cleared)
+    uint32_t* pool = nullptr;      // [ceil(nslots / 32)] free-slot bits
+    uint32_t* park = nullptr;      // [2M]: parked slot per left node, then arrival counters
+    uint32_t* queue = nullptr;     // [1]
+    uint32_t* dense = nullptr;     // [ceil(M / 2^top)][V][2] node states at level top
+    int32_t nslots = 0, workers = 0;
+};
+size_t solo_lds_bytes(int32_t V);
+int solo_prepare(int32_t V);       // once per process: the kernel's LDS limit
+int32_t solo_max_v();
+int solo_block(int variant);       // threads per worker of a worker shape
+int solo_variants();
+void launch_solo(const Plan& P, const DevBufs& B, const SoloBufs& S, hipStream_t s);
+// compute units and the LDS a workgroup may use on the device the library
+// runs on (set by br_create; 256 and 64 KB until then)
+extern int g_cus;
+extern int g_max_lds;
 
 // Batched path (one persistent launch over many small graphs).  Graph s of
 // the launch has edges [eoff[2s], eoff[2s+1]), V[s] vertices, Mg[s] chunks;
@@ -133,7 +178,10 @@ struct BatchDev {
     const int64_t* vbase;     // [S] first vertex of graph s in the combined numbering
     uint32_t* rootw;          // [sum V] 0 at each root of F of the graph's final certificate, else 1
 };
-void launch_batched(const BatchDev& B, int blocks, hipStream_t s);
+// big: the kernel for graphs of up to batched_max_v_big() vertices (one
+// workgroup per CU); else up to batched_max_v_dev()
+void launch_batched(const BatchDev& B, int blocks, hipStream_t s, bool big = false);
+int32_t batched_max_v_big();
 // Final step on the device for the batched path: one workgroup per small graph
 // finds the bridges of node 0's certificate in LDS; keys (u << 16 | v, sorted)
 // go to out_keys at a base taken from out_hdr[0]; out_hdr[16 + 2s] / [17 + 2s]
@@ -149,6 +197,7 @@ int32_t small_bridges_split_v();
 int32_t small_bridges_max_v();   // largest V the kernel above takes
 int32_t batched_max_v_dev();
 int32_t batched_blocks_per_cu();
+int32_t batched_max_blocks_per_cu();
 
 // Largest V the final steps take: they count the 2(V-1) arcs of the
 // certificate's forest tours in 30-bit fields (and the host search in int32).
@@ -162,7 +211,13 @@ int launch_merge_round(const Plan& P, const DevBufs& B, int32_t step, hipStream_
 void launch_copy_out(const Plan& P, const DevBufs& B, int32_t* d_out, int64_t out_cap, int64_t* d_counts,
                      hipStream_t s);
 
-Plan make_plan(int64_t E, int32_t V, int32_t M);
+// The plan of one query.  tuned: a tuner entry for this shape (knobs it
+// names replace the size rules); environment variables BR_SOLO, BR_SOLO_TOP,
+// BR_SOLO_WPC and BR_SOLO_VARIANT replace both (measurements).
+Plan make_plan(int64_t E, int32_t V, int32_t M, bool allow_solo = true, const TuneEntry* tuned = nullptr);
+// make_plan with the tuner's entry for this device and shape, if any
+Plan plan_for(int device, int64_t E, int32_t V, int32_t M);
+std::string plain_tune_key(int device, int64_t E, int32_t V, int32_t M);
 // device workspace of one plain-path query with this plan (state, certificate
 // regions, node tables and, with the device final step, the bridge step's scratch)
 size_t plan_workspace_bytes(const Plan& P, bool device_final);
@@ -195,6 +250,10 @@ int device_bridges(const Plan& P, const DevBufs& B, int32_t* ws, uint64_t** d_ke
 // 2-edge-connected classes of node 0's certificate on the device: int32 labels
 // (smallest id of each class) where the keys would go, their count at *d_n.
 int device_classes(const Plan& P, const DevBufs& B, int32_t* ws, int32_t** d_label, uint32_t** d_n, hipStream_t s);
+// ... and the bridge tree's edges (class-label keys min << 32 | max, unordered;
+// their number in status word 5, (*d_n)[4]) at *d_tkeys
+int device_bridge_tree(const Plan& P, const DevBufs& B, int32_t* ws, int32_t** d_label, uint32_t** d_n,
+                       uint64_t** d_tkeys, hipStream_t s);
 int device_bridges_cert(const int2* f1, const int2* f2, int32_t dir, const uint32_t* cnt, const uint32_t* q, int32_t qs,
                         int32_t V, int32_t max_tree, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s);
 
@@ -246,6 +305,10 @@ struct br_ctx {
     hipEvent_t ev_done = nullptr;
     bool done_recorded = false;
     bool exact_ws = false;         // workspace sized exactly to the request (server slots)
+    // the solo path's slots keep their tags across calls: cleared again when
+    // the workspace, V or the slot count change
+    const void* solo_key_base = nullptr;
+    int32_t solo_key_v = 0, solo_key_slots = 0;
     // batched path state
     void* batched = nullptr;
 };
@@ -257,8 +320,11 @@ int ensure_pinned(br_ctx* c, size_t bytes);
 // Run phases a1..a5 on d_edges; on return (asynchronously) node 0 holds the final certificate.
 // The input is the concatenation of d_a [Ea] and d_b [Eb] (d_b may be null with Eb = 0).
 // device_final: reserve the device bridge step's scratch in the workspace.
+// plan_knobs: plan with these tuner knobs instead of the tuner's entry.
 int run_certificate(br_ctx* c, const int32_t* d_a, int64_t Ea, const int32_t* d_b, int64_t Eb, int32_t V, int32_t M,
-                    hipStream_t s, Plan& P, DevBufs& B, bool device_final);
+                    hipStream_t s, Plan& P, DevBufs& B, bool device_final, const TuneEntry* plan_knobs = nullptr);
+int run_certificate_with(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int32_t M, hipStream_t s, Plan& P,
+                         DevBufs& B, bool device_final, const TuneEntry* plan_knobs);
 // Order stream s after everything earlier calls on this context enqueued
 // (they may have used another stream), and mark the end of this call's work.
 int ctx_begin(br_ctx* c, hipStream_t s);

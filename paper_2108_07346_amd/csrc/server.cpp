@@ -95,8 +95,8 @@ namespace {
 
 // device bytes a request needs while it runs: the plain path's workspace for
 // its final step, and the copy of its edges when they came from the host
-void charge(Request& r, bool host_edges, int mode) {
-    const Plan P = make_plan(r.E, r.V, r.M);
+void charge(Request& r, bool host_edges, int mode, int device) {
+    const Plan P = plan_for(device, r.E, r.V, r.M);
     r.ws_bytes = (int64_t)plan_workspace_bytes(P, mode == 1);
     r.buf_bytes = host_edges ? 8 * r.E : 0;
 }
@@ -113,6 +113,7 @@ void release_slot(Slot& sl) {
     if (sl.ctx->ws.base) (void)hipFree(sl.ctx->ws.base);
     sl.ctx->ws.base = nullptr;
     sl.ctx->ws.size = 0;
+    sl.ctx->solo_key_base = nullptr;
     if (sl.d_buf) (void)hipFree(sl.d_buf);
     sl.d_buf = nullptr;
     sl.d_cap = 0;
@@ -278,7 +279,7 @@ void sched_loop(br_server* S) {
         if (S->stop) return;
         auto r = S->queue.front();
         r->mode = S->final_step;
-        charge(*r, r->d_edges == nullptr, r->mode);
+        charge(*r, r->d_edges == nullptr, r->mode, S->device);
         int64_t extra = 0;
         Slot* sl = pick_slot(S, *r, &extra);
         if (S->in_use + extra > S->budget) {
@@ -404,7 +405,7 @@ int br_server_create(br_server** out, int device, int64_t mem_budget, int32_t ma
 
 static int submit_common(br_server* S, std::shared_ptr<Request> r, uint64_t* ticket, bool host) {
     r->M = choose_m(r->E, r->V);
-    charge(*r, host, 1);   // the larger of the two final steps' needs
+    charge(*r, host, 1, S->device);   // the larger of the two final steps' needs
     if (r->ws_bytes + r->buf_bytes > S->budget)
         return fail(BR_ENOMEM, "server: request needs %lld bytes, budget is %lld",
                     (long long)(r->ws_bytes + r->buf_bytes), (long long)S->budget);

@@ -1,0 +1,551 @@
+// The phase tree with one workgroup per node (paper, Section III; Algorithm 2
+// per chunk and per merge), for plans with at least as many chunks as
+// workgroups in flight.
+//
+// A persistent kernel: every workgroup ("worker") takes chunks in order from a
+// queue, builds the chunk's certificate alone (phase 0), then climbs the merge
+// tree while it is the second of a pair to finish (an arrival counter per
+// merge): it streams the sibling's certificate into the left node's
+// union-find state (the state-carrying merge), up to level `top`; there it
+// writes the node's fully compressed state into a dense array for the merge
+// rounds above, which run as team launches (cert_kernels.hip).
+//
+// Union-find state in resident slots.  A slot holds, for each vertex, one
+// 32-bit word per forest (F in the first V words, F' in the next V):
+// tag << ob | (x - parent), with ob = bit width of V - 1.  A word whose tag is
+// not the slot's current tag reads as a root, so a slot is reset for a new
+// chunk by taking the next tag (the slot is cleared only when its tags run
+// out).  Parents always have smaller ids than their children.
+//
+// Hooks without global atomics.  Only the owning workgroup touches a slot
+// while it works on it, so two lanes can race only within the workgroup: a
+// hook first sets the root's bit in a bitmap in LDS (one bit per vertex and
+// forest, cleared per task) and only the lane that sets it writes the root's
+// parent word, with a plain store.  The bit is the root test that cannot be
+// stale; a lane that finds the bit already set lost a race whose winner's
+// store it may not see yet, and retries the edge after the next barrier, when
+// every store of the workgroup is visible.  Lanes read parent words with plain
+// loads: a value, however stale, names a vertex of the same component with a
+// smaller id, so finds that meet prove the endpoints connected; and the root
+// a winning lane hooks is a root of a component other than the one of the
+// vertex it hooks it under (that vertex has the smaller id, and chains only
+// decrease).  So F is a maximal forest of the edges offered to it and F' of
+// the edges F rejected, as Algorithm 2 requires.
+//
+// Slots change hands between workers only through the free pool and the
+// parking table; whoever gives a slot away first makes its writes visible
+// device-wide (release fence), whoever takes one first invalidates what its
+// caches may hold (acquire fence).
+
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+
+#include "device_util.hpp"
+#include "internal.hpp"
+
+namespace br {
+
+namespace {
+
+// a worker is SB threads; each thread offers SU edges of a tile together
+
+struct SoloLds {
+    uint32_t flag[2];               // block_any
+    uint32_t n1, n2;                // counts of the node being written
+    int32_t item, slot, act, pad0;
+    uint32_t tag, nj1, nj2, pad1;
+};
+
+// kernel parameters
+struct SoloArgs {
+    const int2* edges;
+    const int2* edges2;
+    int64_t split;
+    int64_t E;
+    int32_t V, M;
+    int32_t ob;                     // bits of the offset field of a state word
+    int32_t top;                    // merges of levels 1..top run here
+    int32_t nslots;
+    int32_t bm_words;               // words of one LDS bitmap
+    uint32_t* slots;                // [nslots][2][V]
+    uint32_t* slot_tag;             // [nslots] current tag of each slot (kept across calls)
+    uint32_t* pool;                 // [ceil(nslots / 32)] bit set = slot free
+    uint32_t* park;                 // [M] slot + 1 parked by left node i, 0 = none
+    uint32_t* arrive;               // [M] arrivals at the merge whose right node is j
+    uint32_t* queue;                // [1] next chunk
+    uint32_t* dense;                // [ceil(M / 2^top)][V][2] node states at level top, compressed, untagged
+    int2* cert;
+    const int64_t* off;
+    const int64_t* cap;
+    uint32_t* cnt;                  // [M][2]
+    uint32_t* err;                  // bit 0: id out of range; bit 1: region overflow
+};
+
+struct St {
+    uint32_t* q;                    // slot base: F at q[x], F' at q[V + x]
+    uint32_t V, tag, ob, mask;
+    // x - parent(x) from x's word; a word of another tag, or one that could
+    // not belong to x, reads as a root
+    __device__ __forceinline__ uint32_t off(uint32_t w, uint32_t x) const {
+        const uint32_t d = w & mask;
+        return ((w >> ob) == tag && d <= x) ? d : 0u;
+    }
+    __device__ __forceinline__ uint32_t word(uint32_t d) const { return (tag << ob) | d; }
+};
+
+__device__ __forceinline__ uint32_t sld(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void sst(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// representative of x in forest F (path halving on the way)
+template <int F>
+__device__ __forceinline__ uint32_t sfind(const St& S, uint32_t x) {
+    uint32_t* q = S.q + (F ? S.V : 0u);
+    uint32_t d = S.off(sld(q + x), x);
+    while (d != 0) {
+        const uint32_t p = x - d;
+        const uint32_t dp = S.off(sld(q + p), p);
+        if (dp == 0) return p;
+        sst(q + x, S.word(d + dp));
+        x = p - dp;
+        d = S.off(sld(q + x), x);
+    }
+    return x;
+}
+
+// wavefront-aggregated reservation of slots on an LDS counter
+__device__ __forceinline__ uint32_t lreserve(uint32_t* ctr, bool want) {
+    const uint64_t m = __ballot(want);
+    if (m == 0) return 0;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    uint32_t base = 0;
+    if (__lane_id() == leader) base = atomicAdd(ctr, (uint32_t)__popcll(m));
+    return __shfl(base, leader) + lane_rank(m);
+}
+
+// accepted edges go to the node's region: F from the front, F' from the back
+// (every lane calls this: ballots)
+__device__ __forceinline__ void emit(SoloLds& L, const SoloArgs& A, int64_t off, int64_t cap, int acc, int2 e) {
+    const uint32_t p1 = lreserve(&L.n1, acc == 0);
+    const uint32_t p2 = lreserve(&L.n2, acc == 1);
+    if (acc == 0) { if (p1 < cap) A.cert[off + p1] = e; else atomicOr(A.err, 2u); }
+    if (acc == 1) { if (p2 < cap) A.cert[off + cap - 1 - p2] = e; else atomicOr(A.err, 2u); }
+}
+
+// Barrier for the whole workgroup (global and LDS stores before it are
+// visible after it) that also tells every lane whether any lane had p set.
+__device__ __forceinline__ bool block_any(SoloLds& L, bool p, int& ph) {
+    __syncthreads();
+    if (p) L.flag[ph] = 1u;
+    __syncthreads();
+    const bool any = L.flag[ph] != 0;
+    if (threadIdx.x == 0) L.flag[ph ^ 1] = 0u;
+    ph ^= 1;
+    return any;
+}
+
+// Offer the edges of mask m (bit j: edge (u[j], v[j])) to forest F, all of
+// them together: the endpoints' words, then their parents' words, are loaded
+// for every edge before any is decided, so that the loads of the thread's
+// edges are in flight at once; longer chains are then followed one by one
+// (path halving, and the endpoint pointed straight at its root).  Out:
+// masks of edges whose endpoints were already connected (same), that hooked
+// a root (won), that lost a root to another lane (lost: retry later).
+template <int F, int kSU>
+__device__ __forceinline__ void bunite(const St& S, uint32_t* bm, const uint32_t (&u)[kSU], const uint32_t (&v)[kSU],
+                                       uint32_t m, uint32_t& same, uint32_t& won, uint32_t& lost) {
+    uint32_t* q = S.q + (F ? S.V : 0u);
+    uint32_t a[kSU], b[kSU], wa[kSU], wb[kSU];
+#pragma unroll
+    for (int j = 0; j < kSU; j++) {
+        if (m >> j & 1) {
+            wa[j] = sld(q + u[j]);
+            wb[j] = sld(q + v[j]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kSU; j++) {
+        if (m >> j & 1) {
+            a[j] = u[j] - S.off(wa[j], u[j]);
+            b[j] = v[j] - S.off(wb[j], v[j]);
+            wa[j] = (a[j] != b[j] && a[j] != u[j]) ? sld(q + a[j]) : 0u;
+            wb[j] = (a[j] != b[j] && b[j] != v[j]) ? sld(q + b[j]) : 0u;
+        }
+    }
+    same = won = lost = 0;
+#pragma unroll
+    for (int j = 0; j < kSU; j++) {
+        // outcome r: 0 connected already, 1 hooked, 2 lost a race (the three
+        // masks are updated without branches: no selected-by-address stores)
+        uint32_t r = 0;
+        if (m >> j & 1) {
+            uint32_t x = a[j], y = b[j];
+            if (x != y) {
+                if (S.off(wa[j], x) != 0) {
+                    x = sfind<F>(S, x);
+                    sst(q + u[j], S.word(u[j] - x));
+                }
+                if (S.off(wb[j], y) != 0) {
+                    y = sfind<F>(S, y);
+                    sst(q + v[j], S.word(v[j] - y));
+                }
+            }
+            if (x != y) {
+                const uint32_t hi = max(x, y), lo = min(x, y);
+                const uint32_t bit = 1u << (hi & 31);
+                r = (atomicOr(&bm[hi >> 5], bit) & bit) ? 2u : 1u;
+                if (r == 1) sst(q + hi, S.word(hi - lo));
+            }
+        }
+        const uint32_t jb = (m >> j & 1) << j;
+        same |= (r == 0 ? jb : 0u);
+        won |= (r == 1 ? jb : 0u);
+        lost |= (r == 2 ? jb : 0u);
+    }
+}
+
+// Full path compression of a slot (no hook runs concurrently).
+template <int kSB>
+__device__ void compress_slot(const St& S) {
+    for (int f = 0; f < 2; f++) {
+        uint32_t* q = S.q + (f ? S.V : 0u);
+        for (uint32_t x = threadIdx.x; x < S.V; x += kSB) {
+            const uint32_t d = S.off(sld(q + x), x);
+            if (d == 0) continue;
+            uint32_t r = x - d;
+            for (uint32_t e = S.off(sld(q + r), r); e != 0; e = S.off(sld(q + r), r)) r -= e;
+            if (r != x - d) sst(q + x, S.word(x - r));
+        }
+    }
+}
+
+// Offer a run of edges to the slot.  src 0: the input edge list, ids checked;
+// src 1: a node region's certificate (F part [0, rn1), F' part after it).
+// stage0: where every edge starts (0: F, then F' if F rejects it; 1: F'
+// only).  out: write accepted edges to (off, cap).  stages: compress the slot
+// after 2V and 8V edges (phase 0 over long chunks).  Each thread takes kSU
+// edges of a tile and offers them together; edges that lost a race are
+// retried, after a barrier, until none is left.
+template <int kSB, int kSU>
+__device__ void stream(SoloLds& L, const SoloArgs& A, const St& S, uint32_t* bm1, uint32_t* bm2, int src, int64_t t0,
+                       int64_t t1, int64_t roff, int64_t rcap, uint32_t rn1, uint32_t rn2, uint32_t stage0, bool out,
+                       bool stages, int64_t off, int64_t cap, int& ph) {
+    constexpr int64_t kST = (int64_t)kSB * kSU;      // edges per tile
+    int64_t next_cmp = stages ? t0 + 2 * (int64_t)S.V : INT64_MAX;
+    auto load = [&](int64_t i) -> int2 {
+        if (src == 0) return i < A.split ? A.edges[i] : A.edges2[i - A.split];
+        return A.cert[i < rn1 ? roff + i : roff + rcap - rn2 + (i - rn1)];
+    };
+    for (int64_t base = t0; base < t1; base += kST) {
+        if (base >= next_cmp) {
+            __syncthreads();
+            compress_slot<kSB>(S);
+            __syncthreads();
+            next_cmp = next_cmp == t0 + 2 * (int64_t)S.V ? t0 + 8 * (int64_t)S.V : INT64_MAX;
+        }
+        uint32_t u[kSU], v[kSU];
+        uint32_t pend = 0, st1 = stage0 ? 0xffffffffu : 0u;   // st1 bit j: edge j is past F
+#pragma unroll
+        for (int j = 0; j < kSU; j++) {
+            const int64_t i = base + j * kSB + threadIdx.x;
+            const int2 e = i < t1 ? load(i) : make_int2(0, 0);
+            u[j] = (uint32_t)e.x;
+            v[j] = (uint32_t)e.y;
+        }
+#pragma unroll
+        for (int j = 0; j < kSU; j++) {
+            if (base + j * kSB + threadIdx.x < t1) {
+                if (u[j] < S.V && v[j] < S.V) pend |= 1u << j;
+                else atomicOr(A.err, src == 0 ? 1u : 2u);
+            }
+        }
+        for (;;) {
+            uint32_t same = 0, won1 = 0, won2 = 0, lost = 0;
+            const uint32_t m1 = pend & ~st1;
+            if (m1) {
+                uint32_t l1 = 0;
+                bunite<0, kSU>(S, bm1, u, v, m1, same, won1, l1);
+                lost |= l1;
+                st1 |= same;                    // F rejected them: on to F'
+            }
+            const uint32_t m2 = pend & st1;
+            if (m2) {
+                uint32_t s2 = 0, l2 = 0;
+                bunite<1, kSU>(S, bm2, u, v, m2, s2, won2, l2);
+                lost |= l2;
+            }
+            if (out) {
+#pragma unroll
+                for (int j = 0; j < kSU; j++)
+                    emit(L, A, off, cap, (won1 >> j & 1) ? 0 : ((won2 >> j & 1) ? 1 : -1),
+                         make_int2((int32_t)u[j], (int32_t)v[j]));
+            }
+            pend = lost;
+            if (!block_any(L, pend != 0, ph)) break;
+        }
+    }
+}
+
+__device__ __forceinline__ int64_t part_lo(int64_t E, int64_t M, int64_t i) { return i * (E / M) + (i * (E % M)) / M; }
+
+// a free slot from the pool (thread 0), -1 if none; acquire on success
+__device__ int pool_pop(const SoloArgs& A) {
+    const int words = (A.nslots + 31) / 32;
+    for (int w = 0; w < words; w++) {
+        uint32_t v = __hip_atomic_load(&A.pool[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        while (v) {
+            const uint32_t bit = v & (~v + 1u);
+            const uint32_t old = atomicAnd(&A.pool[w], ~bit);
+            if (old & bit) {
+                __threadfence();
+                return w * 32 + __ffs((int)bit) - 1;
+            }
+            v = old & ~bit;
+        }
+    }
+    return -1;
+}
+
+// give a slot back (thread 0; the caller has released what it wrote)
+__device__ void pool_push(const SoloArgs& A, int s) { atomicOr(&A.pool[s >> 5], 1u << (s & 31)); }
+
+}  // namespace
+
+template <int kSB, int kSU>
+__global__ void __launch_bounds__(kSB) k_solo(SoloArgs A) {
+    extern __shared__ uint4 lds_raw[];
+    SoloLds& L = *reinterpret_cast<SoloLds*>(lds_raw);
+    uint32_t* bm1 = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(lds_raw) + sizeof(SoloLds));
+    uint32_t* bm2 = bm1 + A.bm_words;
+    const uint32_t V = (uint32_t)A.V;
+    const uint32_t mask = A.ob >= 32 ? 0xffffffffu : ((1u << A.ob) - 1u);
+    const uint32_t tag_max = A.ob >= 31 ? 1u : ((1u << (32 - A.ob)) - 1u);
+    const int64_t top_step = int64_t(1) << A.top;
+    if (threadIdx.x == 0) {
+        L.slot = blockIdx.x;        // every worker starts with its own slot
+        L.flag[0] = L.flag[1] = 0u;
+    }
+    int ph = 0;
+    __syncthreads();
+    for (;;) {
+        if (threadIdx.x == 0) L.item = (int32_t)atomicAdd(A.queue, 1u);
+        __syncthreads();
+        const int64_t c = L.item;
+        if (c >= A.M) break;
+        // ---- phase 0: the certificate of chunk c in a fresh tag of my slot
+        if (threadIdx.x == 0) {
+            uint32_t t = A.slot_tag[L.slot] + 1;
+            L.act = 0;
+            if (t > tag_max) { t = 1; L.act = 1; }
+            A.slot_tag[L.slot] = t;
+            L.tag = t;
+            L.n1 = L.n2 = 0;
+        }
+        __syncthreads();
+        St S{A.slots + (size_t)L.slot * 2 * V, V, L.tag, (uint32_t)A.ob, mask};
+        if (L.act == 1)         // tags ran out: every word back to "root"
+            for (uint32_t x = threadIdx.x; x < 2 * V; x += kSB) S.q[x] = 0u;
+        for (int x = threadIdx.x; x < 2 * A.bm_words; x += kSB) bm1[x] = 0u;
+        __syncthreads();
+        stream<kSB, kSU>(L, A, S, bm1, bm2, 0, part_lo(A.E, A.M, c), part_lo(A.E, A.M, c + 1), 0, 0, 0, 0, 0, true, true, A.off[c],
+               A.cap[c], ph);
+        // ---- climb the merge tree while this worker finishes a pair second
+        int64_t node = c, step = 1;
+        for (;;) {
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                A.cnt[2 * node] = L.n1;
+                A.cnt[2 * node + 1] = L.n2;
+                if ((int64_t)L.n1 + L.n2 > A.cap[node]) atomicOr(A.err, 2u);
+            }
+            if (step >= A.M || step >= top_step) {
+                // the node's state, fully compressed and untagged, for the
+                // merge rounds above (and, at the top, the final step)
+                uint2* dn = reinterpret_cast<uint2*>(A.dense) + (size_t)(node >> A.top) * V;
+                for (uint32_t x = threadIdx.x; x < V; x += kSB) {
+                    uint32_t r[2];
+                    for (int f = 0; f < 2; f++) {
+                        const uint32_t* q = S.q + (f ? V : 0u);
+                        uint32_t y = x;
+                        for (uint32_t e = S.off(sld(q + y), y); e != 0; e = S.off(sld(q + y), y)) y -= e;
+                        r[f] = x - y;
+                    }
+                    dn[x] = make_uint2(r[0], r[1]);
+                }
+                break;
+            }
+            const int64_t i = node & ~(2 * step - 1), j = i + step;
+            if (j >= A.M) {                                   // no partner: passes through
+                node = i;
+                step *= 2;
+                continue;
+            }
+            __syncthreads();   // every lane's writes (region, state) done before thread 0 publishes
+            if (threadIdx.x == 0) {
+                int spare = -1;
+                if (node == i) {       // park my state for the right node's worker, in case it comes last
+                    spare = pool_pop(A);
+                    A.park[i] = spare >= 0 ? (uint32_t)L.slot + 1 : 0u;
+                }
+                __threadfence();       // release: region, counts, state, parking
+                const uint32_t prev = atomicAdd(&A.arrive[j], 1u);
+                int act;
+                if (prev == 0) {       // first of the pair: the partner merges
+                    if (spare >= 0) L.slot = spare;     // the parked slot is no longer mine
+                    act = 0;
+                } else {
+                    __threadfence();   // acquire the partner's region, counts and parking
+                    if (node == i) {   // my own state is still here
+                        if (spare >= 0) pool_push(A, spare);
+                        A.park[i] = 0;
+                        act = 1;
+                    } else {
+                        const uint32_t p = __hip_atomic_load(&A.park[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (p) {       // adopt the left node's state, give mine back
+                            pool_push(A, L.slot);
+                            L.slot = (int32_t)p - 1;
+                            A.park[i] = 0;
+                            act = 1;
+                        } else {
+                            act = 2;   // the left state is gone: rebuild it in my slot
+                        }
+                    }
+                }
+                L.act = act;
+                if (act == 2) {
+                    uint32_t t = A.slot_tag[L.slot] + 1;
+                    if (t > tag_max) { t = 1; L.act = 3; }
+                    A.slot_tag[L.slot] = t;
+                }
+                L.tag = A.slot_tag[L.slot];
+                L.n1 = A.cnt[2 * i];
+                L.n2 = A.cnt[2 * i + 1];
+                L.nj1 = A.cnt[2 * j];
+                L.nj2 = A.cnt[2 * j + 1];
+            }
+            __syncthreads();
+            const int act = L.act;
+            if (act == 0) break;
+            S.q = A.slots + (size_t)L.slot * 2 * V;
+            S.tag = L.tag;
+            for (int x = threadIdx.x; x < 2 * A.bm_words; x += kSB) bm1[x] = 0u;
+            if (act == 3)
+                for (uint32_t x = threadIdx.x; x < 2 * V; x += kSB) S.q[x] = 0u;
+            const int64_t offi = A.off[i], capi = A.cap[i];
+            const uint32_t ni1 = min(L.n1, (uint32_t)capi), ni2 = min(L.n2, (uint32_t)capi - ni1);
+            __syncthreads();
+            if (act >= 2) {
+                // node i's state from its certificate: F's edges into F (a
+                // forest: all accepted), then F''s into F' (all accepted)
+                stream<kSB, kSU>(L, A, S, bm1, bm2, 1, 0, ni1, offi, capi, ni1, ni2, 0, false, false, 0, 0, ph);
+                stream<kSB, kSU>(L, A, S, bm1, bm2, 1, ni1, (int64_t)ni1 + ni2, offi, capi, ni1, ni2, 1, false, false, 0, 0, ph);
+            }
+            // X_j into node i's state; accepted edges extend node i's region
+            const int64_t offj = A.off[j], capj = A.cap[j];
+            const uint32_t nj1 = min(L.nj1, (uint32_t)capj), nj2 = min(L.nj2, (uint32_t)capj - nj1);
+            if ((int64_t)nj1 + nj2 >= (int64_t)V / 2) {
+                compress_slot<kSB>(S);
+                __syncthreads();
+            }
+            stream<kSB, kSU>(L, A, S, bm1, bm2, 1, 0, (int64_t)nj1 + nj2, offj, capj, nj1, nj2, 0, true, false, offi, capi, ph);
+            node = i;
+            step *= 2;
+        }
+    }
+}
+
+namespace {
+// per call: the free pool (slots past the workers'), no parking, no arrivals, queue at 0
+__global__ void k_solo_init(uint32_t* pool, int32_t nslots, int32_t first_free, uint32_t* park_arrive, int64_t n,
+                            uint32_t* queue) {
+    const int words = (nslots + 31) / 32;
+    GRID_LOOP(k, n) park_arrive[k] = 0u;
+    GRID_LOOP(w, words) {
+        uint32_t v = 0;
+        for (int b = 0; b < 32; b++) {
+            const int s = (int)w * 32 + b;
+            if (s >= first_free && s < nslots) v |= 1u << b;
+        }
+        pool[w] = v;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *queue = 0u;
+}
+}  // namespace
+
+size_t solo_lds_bytes(int32_t V) { return sizeof(SoloLds) + 2 * 4 * (size_t)((V + 31) / 32); }
+
+// Worker shapes: (threads, edges per thread offered together), chosen per
+// plan (the tuner measures them).
+struct SoloVariant {
+    const void* fn;
+    int sb;
+};
+static const SoloVariant kVariants[] = {
+    {reinterpret_cast<const void*>(&k_solo<512, 2>), 512},
+    {reinterpret_cast<const void*>(&k_solo<1024, 1>), 1024},
+    {reinterpret_cast<const void*>(&k_solo<1024, 2>), 1024},
+    {reinterpret_cast<const void*>(&k_solo<512, 1>), 512},
+};
+int solo_variants() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
+int solo_block(int variant) { return kVariants[std::max(0, std::min(variant, solo_variants() - 1))].sb; }
+
+int solo_prepare(int32_t V) {
+    const size_t b = solo_lds_bytes(V);
+    if (b > (size_t)g_max_lds) return fail(BR_EINTERNAL, "solo: V = %d needs %zu bytes of LDS", V, b);
+    static std::once_flag once;
+    static hipError_t e = hipSuccess;
+    std::call_once(once, [] {
+        for (const SoloVariant& k : kVariants) {
+            if (e != hipSuccess) break;
+            e = hipFuncSetAttribute(k.fn, hipFuncAttributeMaxDynamicSharedMemorySize, g_max_lds);
+        }
+    });
+    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(k_solo)");
+    return BR_OK;
+}
+
+void launch_solo(const Plan& P, const DevBufs& B, const SoloBufs& Sb, hipStream_t s) {
+    const int64_t n = 2 * (int64_t)P.M;
+    hipLaunchKernelGGL(k_solo_init, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1024))),
+                       dim3(256), 0, s, Sb.pool, Sb.nslots, Sb.workers, Sb.park, n, Sb.queue);
+    SoloArgs A;
+    A.edges = B.edges;
+    A.edges2 = B.edges2;
+    A.split = B.split;
+    A.E = P.E;
+    A.V = P.V;
+    A.M = P.M;
+    int ob = 1;
+    while (ob < 31 && (int64_t(1) << ob) <= (int64_t)P.V - 1) ob++;
+    A.ob = ob;
+    A.top = P.solo_top;
+    A.nslots = Sb.nslots;
+    A.bm_words = (P.V + 31) / 32;
+    A.slots = Sb.slots;
+    A.slot_tag = Sb.slot_tag;
+    A.pool = Sb.pool;
+    A.park = Sb.park;
+    A.arrive = Sb.park + P.M;
+    A.queue = Sb.queue;
+    A.dense = Sb.dense;
+    A.cert = B.cert;
+    A.off = B.off;
+    A.cap = B.cap;
+    A.cnt = B.cnt;
+    A.err = B.err;
+    const SoloVariant& k = kVariants[std::max(0, std::min(P.solo_variant, solo_variants() - 1))];
+    void* args[] = {&A};
+    (void)hipLaunchKernel(k.fn, dim3((unsigned)Sb.workers), dim3(k.sb), args, solo_lds_bytes(P.V), s);
+}
+
+// largest V whose two LDS bitmaps fit next to the deferred-edge buffers
+int32_t solo_max_v() {
+    const int64_t room = (int64_t)g_max_lds - (int64_t)sizeof(SoloLds);
+    return room <= 0 ? 0 : (int32_t)std::min<int64_t>(INT32_MAX, room / 8 * 32);
+}
+
+}  // namespace br

@@ -85,7 +85,7 @@ extern "C" int br_cert_build_static(br_ctx* c, const int32_t* d_edges, int64_t E
     if (cert_cap < need)
         return fail(BR_ECAP, "br_cert_build_static: cert_cap %lld < min(E, 2(V-1)) = %lld", (long long)cert_cap,
                     (long long)need);
-    Plan P = make_plan(E, V, M);
+    Plan P = make_plan(E, V, M, false);
     P.qs = 2;   // packed state only: no spread copy to compress into
     size_t o = 0;
     const size_t o_err = o; o += 256;

@@ -272,3 +272,65 @@ def test_two_edge_connected_classes(ctx, small, dense):
     assert ei.value.code == br.BR_ERANGE
     lab, n = ctx.two_edge_components(dev([[0, 1], [1, 2], [2, 0]]), 3)     # still usable
     assert n == 1 and lab.tolist() == [0, 0, 0]
+
+
+def test_bridge_tree(ctx, small, dense):
+    # the classes contracted, the bridges kept: labels and tree edges equal the
+    # oracle's bridge tree (itself pinned by the definitions on tiny graphs)
+    g, _, d = dense
+    for M in (1, 16):
+        say("bridge tree dense M=%d" % M)
+        lab, tree = ctx.bridge_tree(d, g.V, M)
+        wl, wt = oracle.bridge_tree(g.edges, g.V)
+        assert np.array_equal(lab, wl) and np.array_equal(tree, wt)
+    lab, tree = ctx.bridge_tree(dev(small.edges), small.V, 4)
+    wl, wt = oracle.bridge_tree(small.edges, small.V)
+    assert np.array_equal(lab, wl) and np.array_equal(tree, wt)
+    rng = np.random.default_rng(26)
+    for t in range(40):
+        V = int(rng.integers(1, 300))
+        e = rng.integers(0, V, size=(int(rng.integers(0, 3 * V)), 2)).astype(np.int32)
+        M = int(rng.choice([1, 3, 16]))
+        lab, tree = ctx.bridge_tree(dev(e), V, M)
+        wl, wt = oracle.bridge_tree(e, V)
+        assert np.array_equal(lab, wl) and np.array_equal(tree, wt), (V, e.shape[0], M)
+    empty = torch.zeros((0, 2), dtype=torch.int32, device="cuda")
+    lab, tree = ctx.bridge_tree(empty, 3)
+    assert lab.tolist() == [0, 1, 2] and tree.shape[0] == 0
+    lab, tree = ctx.bridge_tree(dev([[0, 1], [1, 2], [2, 0], [2, 3], [3, 4], [4, 3]]), 5)
+    assert lab.tolist() == [0, 0, 0, 3, 3] and tree.tolist() == [[0, 3]]
+
+
+@pytest.mark.parametrize("V", [4096, 4097, 40944, 40945])
+def test_lds_limits(ctx, V):
+    # the whole phase tree in LDS up to the kernels' limits (4,096 vertices in
+    # the small kernel, 40,944 in the one that takes a CU's whole LDS) and the
+    # other plans just past them
+    import paper_2108_07346_amd as br
+    rng = np.random.default_rng(V)
+    k = 8
+    g = graphgen.planted(V, k=k, vc=V - 20, p=min(1.0, 40.0 / (V / k)), n_extra=1, n_pend=20)
+    assert g.V == V
+    want = oracle.bridges(g.edges, V)
+    d = dev(g.edges)
+    for M in (1, 7, 64):
+        say("lds limit V=%d E=%d M=%d" % (V, g.E, M))
+        ctx.set_profiling(True)
+        got = ctx.find(d, V, M)
+        kind = ctx.profile()["plan_kind"]
+        ctx.set_profiling(False)
+        assert np.array_equal(got, want), (V, M, kind)
+        if V <= br.lds_max_v() and g.E // M <= (1 << 18):
+            assert kind == 2, kind
+        f1, f2 = ctx.cert_build(d, V, M)
+        assert oracle.check_certificate(f1.cpu().numpy(), f2.cpu().numpy(), g.edges, V) == []
+    e = rng.integers(0, V, size=(3 * V, 2)).astype(np.int32)
+    assert np.array_equal(ctx.find(dev(e), V, 5), oracle.bridges(e, V))
+
+
+def test_small_config_runs_in_lds(ctx, small):
+    ctx.set_profiling(True)
+    got = ctx.find(dev(small.edges), small.V, 4)
+    assert ctx.profile()["plan_kind"] == 2
+    ctx.set_profiling(False)
+    assert np.array_equal(got, oracle.bridges(small.edges, small.V))

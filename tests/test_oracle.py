@@ -248,3 +248,46 @@ def test_two_edge_labels_brute_force_and_invariants():
     assert np.all(oracle.two_edge_labels(cyc, 6) == 0)
     tree = np.array([[0, 1], [1, 2], [1, 3]])
     assert np.array_equal(oracle.two_edge_labels(tree, 4), [0, 1, 2, 3])
+
+
+def test_bridge_tree_definition_forest_and_closed_forms():
+    # the bridge tree: classes contracted, bridges kept.  Pinned by the
+    # brute-force definitions of classes and bridges on tiny multigraphs, by
+    # the forest invariants (one tree per component of G, as many nodes as
+    # classes, as many edges as bridges) and by closed forms.
+    rng = np.random.default_rng(41)
+    for _ in range(150):
+        V = int(rng.integers(1, 11))
+        e = rng.integers(0, V, size=(int(rng.integers(0, 16)), 2)).astype(np.int32)
+        lab, t = oracle.bridge_tree(e, V)
+        bl = oracle.brute_two_edge_labels(e, V)
+        bb = oracle.brute_bridges(e, V)
+        want = sorted(tuple(sorted((int(bl[a]), int(b)))) for a, b in
+                      ((u, bl[v]) for u, v in bb.tolist()))
+        assert np.array_equal(lab, bl)
+        assert [tuple(x) for x in t.tolist()] == want
+        nodes = np.unique(lab)
+        assert t.shape[0] == bb.shape[0]
+        assert np.all(t[:, 0] < t[:, 1]) if t.shape[0] else True
+        # a forest over the classes with one tree per component of the graph
+        idx = {int(c): k for k, c in enumerate(nodes)}
+        tt = np.array([[idx[int(a)], idx[int(b)]] for a, b in t.tolist()], dtype=np.int32).reshape(-1, 2)
+        assert oracle.components(tt, nodes.shape[0]) == nodes.shape[0] - t.shape[0]
+        assert oracle.components(tt, nodes.shape[0]) == oracle.components(e, V)
+    # k triangles in a row joined by single edges: a path of k classes
+    k = 6
+    tri = []
+    for i in range(k):
+        a, b, c = 3 * i, 3 * i + 1, 3 * i + 2
+        tri += [[a, b], [b, c], [c, a]]
+        if i:
+            tri.append([3 * i - 1, a])
+    lab, t = oracle.bridge_tree(np.array(tri, np.int32), 3 * k)
+    assert np.array_equal(lab, np.repeat(np.arange(k) * 3, 3))
+    assert t.tolist() == [[3 * i, 3 * i + 3] for i in range(k - 1)]
+    # a tree graph is its own bridge tree; a cycle contracts to one node
+    par = [[i, (i - 1) // 2] for i in range(1, 15)]
+    lab, t = oracle.bridge_tree(np.array(par, np.int32), 15)
+    assert np.array_equal(lab, np.arange(15)) and t.shape[0] == 14
+    lab, t = oracle.bridge_tree(np.array([[i, (i + 1) % 7] for i in range(7)], np.int32), 7)
+    assert np.all(lab == 0) and t.shape[0] == 0
