@@ -15,14 +15,19 @@ M and the dense configuration (V = 66,536, E = 4,178,013, M = 16) are
 reported under "detail".  "achievable" is the read bandwidth a plain
 16-byte-load stream over the same edge list reaches on this device.
 
-Roofline: the dominant kernel is phase 0, the per-chunk certificates (two
-k_phase0 stages with the compression between them, one query's worth); its
-algorithmic traffic is 8 bytes per input edge (one read of the int32 pair;
-union-find state is meant to stay in cache), divided by its duration from HIP
-events recorded on the call's stream during the timed steps, against the
-8 TB/s HBM3E peak.  "traffic" is the counter-measured HBM bytes per
-launch from the committed rocprofv3 summary, when that summary was taken
-from the current kernel source (else null).
+Before timing, the library's tuner measures the certificate plans for the
+workload's shape and keeps the fastest (outside the timed region; every plan
+gives the same bridges).
+
+Roofline: the dominant kernel is the certificate kernel that streams the edge
+list -- phase 0 of the plan that ran (for the one-workgroup-per-node plan,
+k_solo, which also runs the lower merge levels); its algorithmic traffic is
+counted as 8 bytes per input edge (one read of the int32 pair; the
+certificates it writes and re-reads are left out, so the fraction is a lower
+bound), divided by its duration from HIP events recorded on the call's stream
+during the timed steps, against the 8 TB/s HBM3E peak.  "traffic" is the
+counter-measured HBM bytes per launch from the committed rocprofv3 summary,
+when that summary was taken from the current kernel source (else null).
 """
 import argparse
 import hashlib
@@ -35,19 +40,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_GBS = 8000.0
+# certificate plans the library reports (br_profile.plan_kind) and the unit
+# the roofline line times for each: the launches from the first certificate
+# kernel to the end of phase 0 (of the merge levels inside the kernel, for the
+# one-workgroup-per-node plan)
+PLAN_NAMES = {0: "many workgroups per chunk", 1: "one workgroup per node", 2: "whole tree in LDS"}
+UNIT_NAMES = {0: "phase 0 per query (k_phase0 stages and the compressions between them)",
+              1: "k_solo per query (phase 0 and the merge levels it runs, one workgroup per node)",
+              2: "k_batched per query (phase 0 and every merge, in LDS)"}
 CSRC = os.path.join(ROOT, "paper_2108_07346_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
-def load_traffic(workload, M):
+def load_traffic(workload, M, plan_kind=0):
     """Counter-measured HBM bytes per launch of the dominant kernel, from the
-    committed rocprofv3 summary -- only if the kernel source is unchanged since."""
+    committed rocprofv3 summary -- only if it was taken for the same plan and
+    the kernel source is unchanged since."""
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     rec = t.get("%s_M%d" % (workload, M))
-    if not rec:
+    if not rec or rec.get("plan_kind", 0) != plan_kind:
         return None
     try:
         sha = hashlib.sha256(open(os.path.join(CSRC, rec["kernel_file"]), "rb").read()).hexdigest()[:16]
@@ -375,30 +389,42 @@ def bench_classes(args):
 def bench_served(args):
     """Served workload: open-loop Poisson arrivals at fixed QPS; latency from
     each request's scheduled arrival to the moment its answer is back on the
-    host.  Continuous batching (several slots) against the plain per-request
-    path (one slot: submit -> bridges_find -> answer, serialised)."""
+    host.  Three servers over the same arrival sequence: the batch lane (the
+    requests within the LDS kernels' limit certified together, one batched
+    call per tick; the rest on slots), slots only (every request runs the
+    plain path on one of the slots, concurrently), and one slot (the plain
+    per-request path, serialised)."""
     import threading
     import numpy as np
     import torch
     import graphgen
     import paper_2108_07346_amd as br
     t0 = time.perf_counter()
-    pool = [graphgen.served_request(0, r) for r in range(args.pool)]
+    if args.mix == "small":
+        # requests drawn like the batched workload's graphs (V 64..4096)
+        pool = [graphgen.planted(**graphgen.batched_params(1, r)) for r in range(args.pool)]
+    else:
+        pool = [graphgen.served_request(0, r) for r in range(args.pool)]
     Es = np.array([g.E for g in pool])
-    print("bench: served pool of %d requests, mean E %.3g, max E %d (generated in %.1f s)" %
-          (len(pool), Es.mean(), Es.max(), time.perf_counter() - t0), file=sys.stderr, flush=True)
+    print("bench: %s pool of %d requests, mean E %.3g, max E %d (generated in %.1f s)" %
+          (args.mix, len(pool), Es.mean(), Es.max(), time.perf_counter() - t0), file=sys.stderr, flush=True)
     dev = [torch.from_numpy(g.edges).cuda() for g in pool] if args.resident else None
     torch.cuda.synchronize()
-    rng = np.random.default_rng(0)
     results = {}
-    qps_list = [float(x) for x in args.qps.split(",")]
+    qps = args.qps or ("100,200,500,1000,2000" if args.mix == "served" else "1000,5000,20000")
+    qps_list = [float(x) for x in qps.split(",")]
+    servers = (("batch_lane", args.slots, True), ("slots_only", args.slots, False), ("per_request", 1, False))
 
-    def run(qps, slots, resident):
+    def run(qps, slots, lane, resident, seed):
         srv = br.Server(0, mem_budget=64 << 30, max_slots=slots)
         srv.set_final_step(args.final_step)
-        n = int(min(args.max_requests, max(20, qps * args.seconds)))
-        gaps = rng.exponential(1.0 / qps, size=n)
-        sched = np.cumsum(gaps)
+        if not lane:
+            srv.set_batching(0)
+        else:
+            srv.set_batching(args.lane_max_v or br.lds_max_v(), args.lane_max_e)
+        rng = np.random.default_rng(seed)          # the same arrivals for every server
+        n = args.requests
+        sched = np.cumsum(rng.exponential(1.0 / qps, size=n))
         pick = rng.integers(0, len(pool), size=n)
         tickets = [None] * n
         done_t = [0.0] * n
@@ -424,25 +450,31 @@ def bench_served(args):
             ready.release()
         th.join()
         end = max(done_t)
+        st = srv.stats()
         srv.close()
         lat = np.array([done_t[i] - (start + sched[i]) for i in range(n)]) * 1000
         edges = int(sum(pool[pick[i]].E for i in range(n)))
         return {"requests": n, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                "achieved_qps": n / (end - start), "edges_per_s": edges / (end - start)}
+                "achieved_qps": n / (end - start), "edges_per_s": edges / (end - start),
+                "batched_ticks": int(st["batched_ticks"]), "batched_requests": int(st["batched_requests"]),
+                "peak_inflight": int(st["peak_inflight"])}
 
-    for resident in ([False, True] if args.resident else [False]):
-        for qps in qps_list:
-            for slots, name in ((args.slots, "continuous_batching"), (1, "per_request")):
-                key = "%s_%s_qps%d" % ("resident" if resident else "host", name, qps)
-                results[key] = run(qps, slots, resident)
-                print("bench: %s %s" % (key, json.dumps(results[key])), file=sys.stderr, flush=True)
-    head = results["%s_continuous_batching_qps%d" % ("resident" if args.resident else "host", qps_list[0])]
+    mode = "resident" if args.resident else "host"
+    for k, qps in enumerate(qps_list):
+        for name, slots, lane in servers:
+            key = "%s_%s_qps%d" % (mode, name, qps)
+            results[key] = run(qps, slots, lane, args.resident, seed=k)
+            print("bench: %s %s" % (key, json.dumps(results[key])), file=sys.stderr, flush=True)
+    head = results["%s_batch_lane_qps%d" % (mode, qps_list[0])]
     line = {
         "metric": "served p50/p99 latency (ms) and edges/s at fixed QPS, 1 GPU",
         "value": head["edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": head["requests"], "warmup": 0,
         "ms_per_step": head["p50_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int32", "data": "synthetic (seeded planted-cluster generator)",
-        "config": {"workload": "served", "pool": len(pool), "slots": args.slots, "qps": qps_list,
+        "config": {"workload": "served" if args.mix == "served" else "served_small", "pool": len(pool),
+                   "slots": args.slots, "qps": qps_list,
+                   "requests_per_point": args.requests, "edges": mode,
+                   "lane_limits": [args.lane_max_v or None, args.lane_max_e],
                    "final_step": "gpu" if args.final_step else "host search",
                    "parallelism": "single GPU"},
         "roofline": None, "cpu_baseline": None, "detail": results,
@@ -457,18 +489,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="large", choices=["small", "dense", "large", "large_blocked", "batched", "served",
                                                             "figures", "articulation", "classes"])
-    ap.add_argument("--qps", default="100,200,500,1000,2000,5000", help="served: comma-separated QPS")
-    ap.add_argument("--seconds", type=float, default=2.0, help="served: seconds per QPS point")
-    ap.add_argument("--max-requests", type=int, default=600, help="served: cap per QPS point")
+    ap.add_argument("--qps", default=None, help="served: comma-separated QPS (default by mix)")
+    ap.add_argument("--mix", default="served", choices=["served", "small"],
+                    help="served: request sizes of the served workload, or small graphs like the batched workload's")
+    ap.add_argument("--requests", type=int, default=2000, help="served: requests per QPS point and server")
     ap.add_argument("--pool", type=int, default=32, help="served: distinct requests generated")
+    ap.add_argument("--lane-max-v", type=int, default=0, help="served: batch lane V limit (0: the LDS kernels' limit)")
+    ap.add_argument("--lane-max-e", type=int, default=1 << 21, help="served: batch lane edge limit")
     ap.add_argument("--slots", type=int, default=8, help="served: device slots")
-    ap.add_argument("--resident", action="store_true", help="served: also run with edges resident on the GPU")
+    ap.add_argument("--resident", action="store_true", help="served: submit edge lists already on the GPU")
     ap.add_argument("--final-step", type=int, default=1, help="served: 1 bridge step on the GPU (default), 0 host search")
     ap.add_argument("--graphs", type=int, default=4096, help="batched: number of graphs")
     ap.add_argument("--chunk", type=int, default=0, help="batched: chunk_edges (0 = tuned)")
     ap.add_argument("--M", type=int, default=None)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="plain workloads: skip the tuner (size rules only)")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, help="run a plain device copy of this many MiB")
     args = ap.parse_args()
@@ -531,20 +567,29 @@ def main():
         dt = time.perf_counter() - t
         return dt, {k: v / max(n, 1) for k, v in acc.items()}, out
 
+    tuned = None
+    if not args.no_tune:
+        # the library's tuner picks the certificate plan for this shape (kept
+        # in BR_AUTOTUNE_CACHE when set); outside the timed region
+        t0 = time.perf_counter()
+        tuned = ctx.autotune(d, g.V, M, stream)
+        print("bench: tuner %s (%.1f s)" % (json.dumps(tuned), time.perf_counter() - t0), file=sys.stderr, flush=True)
     run_steps(M, args.warmup, False)
     dt, phases, out = run_steps(M, args.steps, True)
     prof = ctx.profile()
+    plan_kind = int(prof["plan_kind"])
     ms_step = 1000.0 * dt / args.steps
     value = g.E * args.steps / dt
     t_k = phases["ms_phase0"] / 1000.0
     achieved = 8.0 * g.E / t_k / 1e9 if t_k > 0 else 0.0
-    traffic = load_traffic(args.workload, M)
+    traffic = load_traffic(args.workload, M, plan_kind)
     print("bench: %d steps, %.3f ms/step, %.3e edges/s, phases %s, bridges %d" %
           (args.steps, ms_step, value, json.dumps({k: round(v, 4) for k, v in phases.items()}), out.shape[0]),
           file=sys.stderr, flush=True)
 
     detail = {"phases_ms": {k: round(v, 5) for k, v in phases.items()}, "bridges": int(out.shape[0]),
               "certificate_edges": int(prof["cert_f1"] + prof["cert_f2"]), "merge_rounds": int(prof["rounds"]),
+              "plan": PLAN_NAMES[plan_kind], "tuner": tuned,
               "complexity_claim": "O(E/M + V log M) on M machines (paper, Section V)"}
     # the same step with Algorithm 1's depth-first search on the host (after
     # copying the certificate) instead of the default bridge step on the GPU
@@ -617,7 +662,7 @@ def main():
         "config": {"workload": args.workload, "V": g.V, "E": g.E, "M": M, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_GBS, "traffic": traffic,
-                     "kernel": "phase 0 per query (k_phase0 stages and the compressions between them)",
+                     "kernel": UNIT_NAMES[plan_kind],
                      "algorithmic_bytes_per_launch": 8 * g.E,
                      "achievable_read_GBs": achievable},
         "cpu_baseline": cpu,

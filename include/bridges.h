@@ -304,26 +304,23 @@ int br_articulation_points(br_ctx* ctx, const int32_t* d_edges, int64_t E, int32
  * Serving: continuous batching of bridge queries on one device.
  *   br_server_create  device, device-memory budget in bytes for resident
  *                     requests (edge lists, union-find state, certificates;
- *                     a slot keeps its buffers between requests and they stay
- *                     charged until the scheduler releases them to admit a
- *                     request that would not fit otherwise),
- *                     max_slots (1..64) requests in flight on the device at
- *                     once, each on its own stream; a request is admitted,
- *                     in arrival order, as soon as a slot is free and the
- *                     budget has room for it.  Each request runs the whole
- *                     path of br_bridges_find with a chunk count chosen from
- *                     its size (M = clamp(E / 8V, 1, 64)).
- *   br_submit         copies h_edges [E][2] (ids in [0,V)) into a host queue
- *                     and returns a ticket; the request is admitted to the
- *                     device when a slot and budget free up.  BR_EBUSY if the
- *                     bounded queue is full; BR_ENOMEM if it can never fit.
- *   br_poll           *done = 1 when finished; then copies the bridges into
- *                     h_out [cap][2], sets *n, and releases the ticket
- *                     (BR_ECAP with *n set if cap is too small; the ticket
- *                     stays).  *done = 0 otherwise.
- *   br_wait           blocks until done, then as br_poll.
- *   br_server_stats   latency percentiles (submit to done, ms) over the
- *                     requests finished since the last reset.
+ *                     slots and lane workers keep their buffers between
+ *                     requests and they stay charged until the scheduler
+ *                     releases them to admit a request that would not fit
+ *                     otherwise), max_slots (1..64) requests on the plain
+ *                     path in flight on the device at once, each on its own
+ *                     stream.  Requests are admitted in arrival order as
+ *                     soon as the budget has room for them.  A slot runs the
+ *                     whole path of br_bridges_find with a chunk count chosen
+ *                     from the request's size (M = clamp(E / 8V, 1, 64)).
+ *                     Requests within the batching limits (br_server_set_
+ *                     batching; by default V <= br_lds_max_v() and E <= 2^21)
+ *                     take a free slot while the batch lane has nothing
+ *                     queued, and otherwise join the lane: a lane worker
+ *                     certifies every lane request queued when it becomes
+ *                     free in one call of the batched path (two workers
+ *                     alternate).  Both paths give the bridges
+ *                     br_bridges_find gives.
  * Submit/poll/wait may be called from several host threads.
  */
 typedef struct br_server br_server;
@@ -335,6 +332,8 @@ typedef struct br_server_stats_t {
     int64_t device_bytes;  /* device memory the slots hold now (charged to the budget) */
     int64_t peak_device_bytes; /* the most they held at once (never above the budget
                                   unless a single request larger than the others' room ran alone) */
+    int64_t batched_ticks;     /* batch-lane ticks (batched calls) since the last reset */
+    int64_t batched_requests;  /* requests those ticks served */
 } br_server_stats_t;
 int br_server_create(br_server** srv, int device, int64_t mem_budget, int32_t max_slots);
 int br_submit(br_server* srv, const int32_t* h_edges, int64_t E, int32_t V, uint64_t* ticket);
@@ -351,6 +350,11 @@ int br_server_stats(br_server* srv, br_server_stats_t* out, int reset);
  * each request keeps the mode it was admitted with, requests already queued
  * or running are not affected. */
 int br_server_set_final_step(br_server* srv, int mode);
+/* Batching limits of the requests submitted from now on: those with
+ * V <= max_v and E <= max_e may join the batch lane; max_v = 0 or max_e = 0
+ * sends every request to a slot.  max_v in [0, br_lds_max_v()], max_e >= 0,
+ * else BR_EINVAL.  Requests already submitted keep their limits. */
+int br_server_set_batching(br_server* srv, int32_t max_v, int64_t max_e);
 int br_server_destroy(br_server* srv);
 
 /*

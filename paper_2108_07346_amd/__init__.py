@@ -21,8 +21,8 @@ BR_OK, BR_EINVAL, BR_ERANGE, BR_ENOMEM, BR_EHIP, BR_EBUSY, BR_ECAP, BR_EINTERNAL
 EXPORTS = ["br_last_error", "br_create", "br_destroy", "br_cert_build", "br_cert_merge", "br_bridges_find",
            "br_certificate_bridges", "br_two_edge_components", "br_articulation_points",
            "br_bridges_find_batched", "br_batched_max_v", "br_set_profiling", "br_set_final_step", "br_get_profile",
-           "br_server_create", "br_submit", "br_submit_device", "br_poll", "br_wait", "br_server_stats",
-           "br_server_set_final_step", "br_server_destroy", "br_probe_read", "br_cert_build_static",
+           "br_server_create", "br_server_set_batching", "br_submit", "br_submit_device", "br_poll", "br_wait",
+           "br_server_stats", "br_server_set_final_step", "br_server_destroy", "br_probe_read", "br_cert_build_static",
            "br_bridge_tree", "br_autotune", "br_lds_max_v"]
 
 
@@ -44,7 +44,8 @@ class _ServerStats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_int64), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
                 ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double), ("edges_per_s", ctypes.c_double),
                 ("peak_inflight", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("peak_device_bytes", ctypes.c_int64)]
+                ("peak_device_bytes", ctypes.c_int64), ("batched_ticks", ctypes.c_int64),
+                ("batched_requests", ctypes.c_int64)]
 
 
 _lib = None
@@ -85,6 +86,7 @@ def load():
     lib.br_wait.argtypes = [vp, ctypes.c_uint64, vp, i64, p64]
     lib.br_server_stats.argtypes = [vp, ctypes.POINTER(_ServerStats), ctypes.c_int]
     lib.br_server_set_final_step.argtypes = [vp, ctypes.c_int]
+    lib.br_server_set_batching.argtypes = [vp, i32, i64]
     lib.br_server_destroy.argtypes = [vp]
     lib.br_probe_read.argtypes = [vp, i64, vp, vp]
     _lib = lib
@@ -310,6 +312,12 @@ class Server:
 
     def set_final_step(self, mode: int):
         _check(self._lib.br_server_set_final_step(self._h, int(mode)))
+
+    def set_batching(self, max_v: int, max_e: int = 1 << 21):
+        """Requests submitted from now on with V <= max_v and E <= max_e may
+        join the batch lane (one batched call per tick); max_v = 0 sends every
+        request to a slot."""
+        _check(self._lib.br_server_set_batching(self._h, int(max_v), int(max_e)))
 
     def stats(self, reset: bool = False) -> dict:
         st = _ServerStats()

@@ -128,7 +128,9 @@ Plan make_plan(int64_t E, int32_t V, int32_t M, bool allow_solo, const TuneEntry
         const int per_cu = std::max(1, 1024 / solo_block(P.solo_variant));
         const int fit = std::max<int>(1, (int)std::min<size_t>(per_cu, (size_t)g_max_lds / solo_lds_bytes(V)));
         const int wpc = std::max(1, std::min(knob("BR_SOLO_WPC", "wpc", fit), fit));
-        P.workers = cus * wpc;
+        // fewer workers than CUs keep fewer chunk states live at once (more
+        // of them in the caches)
+        P.workers = std::max(1, std::min(knob("BR_SOLO_WORKERS", "workers", cus * wpc), cus * wpc));
         // merge levels inside the kernel while they still hold four merges
         // per worker (measured on the large workload at M = 4096: two levels
         // 193 ms, three 206 ms, four 203 ms, five 210 ms)
@@ -511,6 +513,7 @@ int br_cert_merge(br_ctx* c, const int32_t* d_a, int64_t Ea, const int32_t* d_b,
 
 int br_bridges_find(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int32_t M, int32_t* h_bridges,
                     int64_t cap, int64_t* n_bridges, void* stream) {
+    if (V > kFinalStepMaxV) return fail(BR_EINVAL, "V = %d above the final step's limit 2^29", V);
     if (!c || !n_bridges || (!h_bridges && cap > 0)) return fail(BR_EINVAL, "br_bridges_find: null argument");
     int rc = check_common(d_edges, E, V);
     if (rc) return rc;
@@ -727,6 +730,7 @@ static int classes_common(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t 
 
 int br_two_edge_components(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int32_t M, int32_t* h_label,
                            int64_t* n_classes, void* stream) {
+    if (V > kFinalStepMaxV) return fail(BR_EINVAL, "V = %d above the final step's limit 2^29", V);
     if (!c || !h_label || !n_classes) return fail(BR_EINVAL, "br_two_edge_components: null argument");
     return classes_common(c, d_edges, E, V, M, h_label, n_classes, nullptr, 0, nullptr, stream,
                           "br_two_edge_components");
@@ -734,6 +738,7 @@ int br_two_edge_components(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t
 
 int br_bridge_tree(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int32_t M, int32_t* h_label,
                    int32_t* h_tree, int64_t cap, int64_t* n_classes, int64_t* n_tree, void* stream) {
+    if (V > kFinalStepMaxV) return fail(BR_EINVAL, "V = %d above the final step's limit 2^29", V);
     if (!c || !h_label || !n_classes || !n_tree || cap < 0 || (cap > 0 && !h_tree))
         return fail(BR_EINVAL, "br_bridge_tree: null argument");
     int32_t dummy[2];
@@ -743,6 +748,7 @@ int br_bridge_tree(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int3
 
 int br_articulation_points(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int32_t* h_out, int64_t cap,
                            int64_t* n_out, void* stream) {
+    if (V > kFinalStepMaxV) return fail(BR_EINVAL, "V = %d above the final step's limit 2^29", V);
     if (!c || !n_out || (!h_out && cap > 0)) return fail(BR_EINVAL, "br_articulation_points: null argument");
     int rc = check_common(d_edges, E, V);
     if (rc) return rc;

@@ -375,6 +375,73 @@ __global__ void __launch_bounds__(kBB) k_batched(BatchDev B) {
     }
 }
 
+namespace {
+// The node-0 certificates of S graphs as one certificate of their disjoint
+// union: offsets of each graph's F and F' edges in the union (one block), then
+// the copies with the graph's first vertex added to both endpoints.
+constexpr int kUT = 1024;
+__global__ void __launch_bounds__(kUT) k_union_offsets(BatchDev B, int32_t S, int64_t* uoff, uint32_t* cntu) {
+    __shared__ int64_t p1[kUT], p2[kUT];
+    const int64_t per = ((int64_t)S + kUT - 1) / kUT;
+    const int64_t s0 = min((int64_t)S, (int64_t)threadIdx.x * per), s1 = min((int64_t)S, s0 + per);
+    int64_t a = 0, b = 0;
+    for (int64_t s = s0; s < s1; s++) {
+        const uint32_t cap = (uint32_t)B.ncap[s];
+        const uint32_t n1 = min(B.ncnt[2 * s], cap), n2 = min(B.ncnt[2 * s + 1], cap - n1);
+        a += n1;
+        b += n2;
+    }
+    p1[threadIdx.x] = a;
+    p2[threadIdx.x] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t x = 0, y = 0;
+        for (int t = 0; t < kUT; t++) {
+            const int64_t u = p1[t], v = p2[t];
+            p1[t] = x;
+            p2[t] = y;
+            x += u;
+            y += v;
+        }
+        cntu[0] = (uint32_t)x;
+        cntu[1] = (uint32_t)y;
+    }
+    __syncthreads();
+    a = p1[threadIdx.x];
+    b = p2[threadIdx.x];
+    for (int64_t s = s0; s < s1; s++) {
+        uoff[s] = a;
+        uoff[S + s] = b;
+        const uint32_t cap = (uint32_t)B.ncap[s];
+        const uint32_t n1 = min(B.ncnt[2 * s], cap), n2 = min(B.ncnt[2 * s + 1], cap - n1);
+        a += n1;
+        b += n2;
+    }
+}
+
+__global__ void k_union_copy(BatchDev B, int32_t S, const int64_t* uoff, int2* f1u, int2* f2u) {
+    for (int64_t s = blockIdx.x; s < S; s += gridDim.x) {
+        const int64_t off = B.noff[s], cap = B.ncap[s];
+        const uint32_t n1 = min(B.ncnt[2 * s], (uint32_t)cap), n2 = min(B.ncnt[2 * s + 1], (uint32_t)cap - n1);
+        const int32_t vb = (int32_t)B.vbase[s];
+        for (uint32_t k = threadIdx.x; k < n1 + n2; k += blockDim.x) {
+            const int2 e = k < n1 ? B.cert[off + k] : B.cert[off + cap - n2 + (k - n1)];
+            const int2 g = make_int2(e.x + vb, e.y + vb);
+            if (k < n1) f1u[uoff[s] + k] = g;
+            else f2u[uoff[S + s] + (k - n1)] = g;
+        }
+    }
+}
+}  // namespace
+
+void launch_union_certificate(const BatchDev& B, int32_t S, int64_t* uoff, int2* f1u, int2* f2u, uint32_t* cntu,
+                              hipStream_t s) {
+    if (S <= 0) return;
+    hipLaunchKernelGGL(k_union_offsets, dim3(1), dim3(kUT), 0, s, B, S, uoff, cntu);
+    hipLaunchKernelGGL(k_union_copy, dim3((unsigned)std::min<int32_t>(S, 65535)), dim3(256), 0, s, B, S,
+                       (const int64_t*)uoff, f1u, f2u);
+}
+
 void launch_batched(const BatchDev& B, int blocks, hipStream_t s, bool big) {
     if (big) hipLaunchKernelGGL((k_batched<kMaxVBig, false>), dim3(blocks), dim3(kBB), 0, s, B);
     else hipLaunchKernelGGL((k_batched<kMaxV, true>), dim3(blocks), dim3(kBB), 0, s, B);

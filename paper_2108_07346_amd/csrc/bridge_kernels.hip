@@ -14,9 +14,16 @@
 //
 // Rooting uses the Euler tour of each tree: arcs 2k (u->v) and 2k+1 (v->u)
 // of tree edge k, the successor of arc (x->y) being the arc after (y->x) in
-// y's adjacency list, each tour cut open at its union-find root; list ranking
+// y's cyclic arc list, each tour cut open at its union-find root; list ranking
 // by pointer jumping gives every arc its position in its tour.
+//
+// Launches: one clear, the arc lists, the ranking (one launch whose threads
+// jump asynchronously), tour sizes, downward arcs, one scan, preorder numbers,
+// the F' ranges, the range tables (two launches while the block table fits a
+// workgroup's LDS), the test -- eleven in all.
 #include <hip/hip_runtime.h>
+
+#include <mutex>
 
 #include "device_util.hpp"
 #include "internal.hpp"
@@ -119,69 +126,119 @@ __global__ void __launch_bounds__(kT) k_scan1(int32_t* a, int64_t n, uint64_t* s
     for (int j = 0; j < 4; j++) { if (base + j < n) a[base + j] = (int32_t)ex; ex += (uint32_t)v[j]; }
 }
 
-// ---- adjacency of F -----------------------------------------------------------
+// ---- arc lists of F -------------------------------------------------------------
+//
+// first[x] = 1 + an arc leaving x (0: none), nxt[a] = 1 + the arc after a in
+// its source's list (0: a is the last).  The order inside a list is whatever
+// order the insertions took; the tours only need some cyclic order per vertex,
+// and every result derived from them (bridges, cut vertices, class labels) is
+// the same for any order.
 __global__ void k_zero_i32(int32_t* p, int64_t n) { GRID_LOOP(i, n) p[i] = 0; }
 
-__global__ void k_degree(const int2* f1, const uint32_t* cnt, int32_t* deg) {
-    const int64_t n1 = cnt[0];
-    GRID_LOOP(k, n1) {
-        const int2 e = f1[k];
-        atomicAdd(&deg[e.x], 1);
-        atomicAdd(&deg[e.y], 1);
-    }
-}
-
-__global__ void k_fill_adj(const int2* f1, const uint32_t* cnt, const int32_t* head, int32_t* cur, int32_t* adj,
-                           int32_t* posof) {
+__global__ void k_link(const int2* f1, const uint32_t* cnt, int32_t* first, int32_t* nxt) {
     const int64_t A = 2 * (int64_t)cnt[0];
-    GRID_LOOP(a, A) {
-        const int32_t x = arc_src(f1, (int32_t)a);
-        const int32_t p = head[x] + atomicAdd(&cur[x], 1);
-        adj[p] = (int32_t)a;
-        posof[a] = p;
-    }
+    GRID_LOOP(a, A) nxt[a] = atomicExch(&first[arc_src(f1, (int32_t)a)], (int32_t)a + 1);
 }
 
 // ---- list ranking of the Euler tours -------------------------------------------
 //
-// link[a] = (next, dist, far): while next >= 0, next == far is the arc `dist`
-// steps after a; once the tour's end is reached next = -1 and far is the
-// tour's last arc, `dist` steps after a.  A round follows kHop links of the
-// previous round, so spans grow kHop-fold per launch.
-constexpr int kHop = 8;
+// One 64-bit word per arc a: (dist << 32) | lo.  lo >= 0: arc lo lies dist
+// steps after a.  lo < 0: the tour ends dist steps after a, at arc ~lo.  Zero:
+// not written yet (no word written is ever zero).  A word only ever moves
+// further along the tour, so a word read while its owner updates it is still
+// a true statement, and threads can jump without waiting for each other:
+// each replaces its word (a -> n) by (a -> the target of n's word) until its
+// tour's end is reached.  Loads and stores are device-scope so that progress
+// made on one XCD is seen by the others.
+__device__ __forceinline__ uint64_t lk_pack(int32_t lo, uint32_t dist) { return (uint64_t)dist << 32 | (uint32_t)lo; }
+__device__ __forceinline__ int32_t lk_lo(uint64_t w) { return (int32_t)(uint32_t)w; }
+__device__ __forceinline__ uint32_t lk_dist(uint64_t w) { return (uint32_t)(w >> 32); }
+__device__ __forceinline__ uint64_t lk_load(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void lk_store(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
-// successor in the Euler tour; tours cut open at union-find roots of F
-__global__ void k_succ(const int2* f1, const uint32_t* cnt, const int32_t* head, const int32_t* adj,
-                       const int32_t* posof, const uint32_t* q, int32_t qs, int4* link) {
+// successor of arc a = (x -> y) in its tour: the arc after (y -> x) in y's
+// list, wrapping to y's first; the tour of a root y ends at the arc entering y
+// whose reverse is y's last arc
+__device__ __forceinline__ uint64_t tour_step(const int2* f1, const int32_t* first, const int32_t* nxt,
+                                              const uint32_t* q, int32_t qs, int32_t a) {
+    const int32_t b = a ^ 1;
+    const int32_t y = arc_src(f1, b);
+    const int32_t n = nxt[b];
+    if (n == 0 && q[qs * (size_t)y] == 0) return lk_pack(~a, 0);
+    return lk_pack((n != 0 ? n : first[y]) - 1, 1);
+}
+
+// one jump of word w of arc a; dist >= A only on an inconsistent forest
+// (a cycle without a root): the word is then closed at a, A steps on, a
+// position no tour has (the later steps skip such arcs)
+__device__ __forceinline__ uint64_t tour_jump(const int2* f1, const int32_t* first, const int32_t* nxt,
+                                              const uint32_t* q, int32_t qs, const uint64_t* link, int64_t A,
+                                              int32_t a, uint64_t w) {
+    const int32_t n = lk_lo(w);
+    if ((int64_t)n >= A) return lk_pack(~a, (uint32_t)A);
+    uint64_t u = lk_load(link + n);
+    if (u == 0) u = tour_step(f1, first, nxt, q, qs, n);
+    const uint32_t d = lk_dist(w) + lk_dist(u);
+    return d >= (uint64_t)A ? lk_pack(~a, (uint32_t)A) : lk_pack(lk_lo(u), d);
+}
+
+// K arcs per thread held in registers (arcs t, t + stride, ...).  (Ranking
+// inside one XCD, with plain loads through its L2, measured slower: dense
+// 0.156 against 0.119 ms for the whole bridge step.)
+template <int K>
+__global__ void __launch_bounds__(kT) k_rank(const int2* f1, const uint32_t* cnt, const int32_t* first,
+                                             const int32_t* nxt, const uint32_t* q, int32_t qs, uint64_t* link) {
     const int64_t A = 2 * (int64_t)cnt[0];
-    GRID_LOOP(a, A) {
-        const int32_t y = arc_dst(f1, (int32_t)a);
-        const int32_t p = posof[a ^ 1];
-        const int32_t nx = (p + 1 < head[y + 1]) ? p + 1 : head[y];
-        int32_t s = adj[nx];
-        // arc (c -> r) closing the tour of root r: r's last listed arc is (r -> c)
-        if (q[qs * (size_t)y] == 0 && p == head[y + 1] - 1) s = -1;
-        link[a] = s < 0 ? make_int4(-1, 0, (int32_t)a, 0) : make_int4(s, 1, s, 0);
+    const int64_t t = blockIdx.x * (int64_t)kT + threadIdx.x, stride = (int64_t)gridDim.x * kT;
+    uint64_t w[K];
+    uint32_t live = 0;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const int64_t a = t + k * stride;
+        w[k] = 0;
+        if (a < A) {
+            w[k] = tour_step(f1, first, nxt, q, qs, (int32_t)a);
+            lk_store(link + a, w[k]);
+            if (lk_lo(w[k]) >= 0) live |= 1u << k;
+        }
+    }
+    while (live) {
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            if (!((live >> k) & 1u)) continue;
+            w[k] = tour_jump(f1, first, nxt, q, qs, link, A, (int32_t)(t + k * stride), w[k]);
+            lk_store(link + t + k * stride, w[k]);
+            if (lk_lo(w[k]) < 0) live &= ~(1u << k);
+        }
     }
 }
 
-__global__ void k_jump(const uint32_t* cnt, const int4* link, int4* out) {
+// any number of arcs per thread, their words kept in memory (lists longer
+// than the resident threads can hold in registers)
+__global__ void __launch_bounds__(kT) k_rank_mem(const int2* f1, const uint32_t* cnt, const int32_t* first,
+                                                 const int32_t* nxt, const uint32_t* q, int32_t qs, uint64_t* link) {
     const int64_t A = 2 * (int64_t)cnt[0];
-    GRID_LOOP(a, A) {
-        int4 x = link[a];
-#pragma unroll
-        for (int j = 1; j < kHop; j++) {
-            if (x.x < 0) break;
-            const int4 y = link[x.x];
-            x = make_int4(y.x, x.y + y.y, y.z, 0);
+    const int64_t t = blockIdx.x * (int64_t)kT + threadIdx.x, stride = (int64_t)gridDim.x * kT;
+    for (int64_t a = t; a < A; a += stride) lk_store(link + a, tour_step(f1, first, nxt, q, qs, (int32_t)a));
+    for (bool live = true; live;) {
+        live = false;
+        for (int64_t a = t; a < A; a += stride) {
+            uint64_t w = lk_load(link + a);
+            if (lk_lo(w) < 0) continue;
+            w = tour_jump(f1, first, nxt, q, qs, link, A, (int32_t)a, w);
+            lk_store(link + a, w);
+            live |= lk_lo(w) >= 0;
         }
-        out[a] = x;
     }
 }
 
 // per vertex r: the arcs and vertices of its tree if r is a root (else 0),
 // and their exclusive prefix sums over r -- one pass, two sums per status word
-__global__ void __launch_bounds__(kT) k_tours(const int32_t* head, const int32_t* adj, const int4* link,
+__global__ void __launch_bounds__(kT) k_tours(const int32_t* first, const uint64_t* link,
                                               const uint32_t* q, int32_t qs, int32_t V, int32_t* tour_len,
                                               int32_t* tree_n, int32_t* tour_base, int32_t* vbase, uint64_t* status,
                                               uint32_t* ticket) {
@@ -197,8 +254,8 @@ __global__ void __launch_bounds__(kT) k_tours(const int32_t* head, const int32_t
         const int64_t r = base + j;
         L[j] = 0;
         N[j] = 0;
-        if (r < V && q[qs * (size_t)r] == 0 && head[r + 1] > head[r]) {
-            L[j] = link[adj[head[r]]].y + 1;
+        if (r < V && q[qs * (size_t)r] == 0 && first[r] != 0) {
+            L[j] = (int32_t)lk_dist(link[first[r] - 1]) + 1;
             N[j] = L[j] / 2 + 1;
         }
         sum += (uint64_t)(uint32_t)L[j] | ((uint64_t)(uint32_t)N[j] << 30);
@@ -218,23 +275,23 @@ __global__ void __launch_bounds__(kT) k_tours(const int32_t* head, const int32_t
     }
 }
 
-__device__ __forceinline__ int32_t tour_pos(const int2* f1, const int4* link, const int32_t* tour_len, int32_t a,
+__device__ __forceinline__ int32_t tour_pos(const int2* f1, const uint64_t* link, const int32_t* tour_len, int32_t a,
                                             int32_t* root) {
-    const int4 l = link[a];
-    const int32_t r = arc_dst(f1, l.z);
+    const uint64_t l = link[a];
+    const int32_t r = arc_dst(f1, ~lk_lo(l));
     *root = r;
-    return tour_len[r] - 1 - l.y;
+    return tour_len[r] - 1 - (int32_t)lk_dist(l);
 }
 
 // downward arcs (first entry into a vertex): parent arc, subtree size and a
 // flag at the arc's place in the concatenated tours
-__global__ void k_down(const int2* f1, const uint32_t* cnt, const int4* link, const int32_t* tour_len,
+__global__ void k_down(const int2* f1, const uint32_t* cnt, const uint64_t* link, const int32_t* tour_len,
                        const int32_t* tour_base, int32_t* flag, int32_t* in_arc, int32_t* sub) {
     const int64_t A = 2 * (int64_t)cnt[0];
     GRID_LOOP(a, A) {
         int32_t r;
         const int32_t p = tour_pos(f1, link, tour_len, (int32_t)a, &r);
-        const int32_t L = tour_len[r], pr = L - 1 - link[a ^ 1].y;
+        const int32_t L = tour_len[r], pr = L - 1 - (int32_t)lk_dist(link[a ^ 1]);
         if (p < 0 || pr >= L) continue;   // only an inconsistent forest gets here
         if (p < pr) {   // a = (x -> y) enters y for the first time
             const int32_t y = arc_dst(f1, (int32_t)a);
@@ -246,13 +303,13 @@ __global__ void k_down(const int2* f1, const uint32_t* cnt, const int4* link, co
 }
 
 // preorder numbers; the range tables start with every vertex's own number
-__global__ void k_preorder(const int2* f1, const uint32_t* q, int32_t qs, const int32_t* head, const int32_t* in_arc,
-                           const int4* link, const int32_t* tour_len, const int32_t* tour_base, const int32_t* down_ex,
+__global__ void k_preorder(const int2* f1, const uint32_t* q, int32_t qs, const int32_t* first, const int32_t* in_arc,
+                           const uint64_t* link, const int32_t* tour_len, const int32_t* tour_base, const int32_t* down_ex,
                            const int32_t* vbase, const int32_t* tree_n, int32_t V, int32_t* pre, int32_t* sub,
                            int32_t* tmin, int32_t* tmax) {
     GRID_LOOP(v, (int64_t)V) {
         int32_t pv = -1;
-        if (head[v + 1] > head[v]) {
+        if (first[v] != 0) {
             if (q[qs * (size_t)v] == 0) {        // root of its tree
                 pv = vbase[v];
                 sub[v] = tree_n[v];
@@ -291,8 +348,8 @@ __global__ void k_nontree(const int2* f2, int32_t dir, const uint32_t* cnt, cons
 // Blocks of 64 numbers (one wavefront each).  Inside a block, level j (1..5)
 // holds the min/max of the 2^j numbers starting at each position (clipped at
 // the block's end), so any range inside one block takes two lookups; a sparse
-// table over the blocks' own min/max answers a run of whole blocks.  The
-// workgroup that finishes last builds that table in LDS when it is small.
+// table over the blocks' own min/max answers a run of whole blocks; one
+// workgroup builds that table in LDS when it is small.
 constexpr int kRB = 64;
 constexpr int kInLev = 5;              // in-block levels 1..5 (level 6 = the block value)
 constexpr int kLdsBlocks = 4096;       // block tables up to this size are built in LDS
@@ -328,9 +385,8 @@ __device__ void build_block_table(int32_t* tmn, int32_t* tmx, int64_t nb, int32_
     }
 }
 
-// per block: in-block levels and the block's min/max (level 0 of the block table)
-__global__ void __launch_bounds__(kT) k_rmq_blocks(const int32_t* tmin, const int32_t* tmax, int64_t n, int32_t* lmin,
-                                                   int32_t* lmax, int32_t* tmn, int32_t* tmx, int64_t nb) {
+__device__ __forceinline__ void rmq_block_levels(const int32_t* tmin, const int32_t* tmax, int64_t n, int32_t* lmin,
+                                                 int32_t* lmax, int32_t* tmn, int32_t* tmx, int64_t nb) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     int32_t a = i < n ? tmin[i] : INT32_MAX, b = i < n ? tmax[i] : INT32_MIN;
@@ -347,7 +403,16 @@ __global__ void __launch_bounds__(kT) k_rmq_blocks(const int32_t* tmin, const in
     }
 }
 
-// the block table in one workgroup, in LDS (nb <= kLdsBlocks)
+// per block: in-block levels and the block's min/max (level 0 of the block table)
+__global__ void __launch_bounds__(kT) k_rmq_blocks(const int32_t* tmin, const int32_t* tmax, int64_t n, int32_t* lmin,
+                                                   int32_t* lmax, int32_t* tmn, int32_t* tmx, int64_t nb) {
+    rmq_block_levels(tmin, tmax, n, lmin, lmax, tmn, tmx, nb);
+}
+
+// the block table in one workgroup, in LDS (nb <= kLdsBlocks).  A separate
+// launch: folded into k_rmq_blocks as "the last workgroup builds it", every
+// workgroup's device-scope release (an L2 write-back) cost more than the
+// launch (dense: 30 us against 5 + 10 us)
 __global__ void __launch_bounds__(kT) k_rmq_table(int32_t* tmn, int32_t* tmx, int64_t nb, int32_t levels) {
     __shared__ int32_t smn[kLdsBlocks], smx[kLdsBlocks];
     build_block_table(tmn, tmx, nb, levels, smn, smx);
@@ -457,15 +522,22 @@ __device__ __forceinline__ void out_end(OutLds& L, uint64_t* out, uint32_t* nout
     for (uint32_t i = threadIdx.x; i < stored; i += blockDim.x) out[L.base + i] = L.buf[i];
 }
 
-__global__ void k_bridges(const int2* f1, const uint32_t* q, int32_t qs, const int32_t* head, const int32_t* in_arc,
+// st (if not null): the status block, whose |F|, |F'| and error words are
+// filled here (the key count, st[1] = *nout, by the keys' reservations)
+__global__ void k_bridges(const int2* f1, const uint32_t* q, int32_t qs, const int32_t* first, const int32_t* in_arc,
                           const int32_t* pre, const int32_t* sub, Rmq R, int32_t V, int64_t A, uint64_t* out,
-                          uint32_t* nout) {
+                          uint32_t* nout, const uint32_t* cnt, const uint32_t* err, uint32_t* st) {
     __shared__ OutLds L;
+    if (st && blockIdx.x == 0 && threadIdx.x == 0) {
+        st[2] = cnt[0];
+        st[3] = cnt[1];
+        st[4] = err ? *err : 0u;
+    }
     out_begin(L);
     GRID_LOOP(v, (int64_t)V) {
         bool br = false;
         uint64_t key = 0;
-        if (head[v + 1] > head[v] && q[qs * (size_t)v] != 0) {
+        if (first[v] != 0 && q[qs * (size_t)v] != 0) {
             const int32_t l = pre[v], r = pre[v] + sub[v] - 1, a = in_arc[v];
             int32_t mn = -1, mx = V;
             if (l >= 0 && r >= l && r < V && a >= 0 && a < A) range_minmax(R, l, r, mn, mx);
@@ -528,10 +600,10 @@ __global__ void k_tv_init(int32_t V, uint32_t* g, int32_t* rmin, int32_t* rmax, 
 }
 
 // tree edge (w, v), w not a root: joins (parent(w), w) when v's subtree escapes w's
-__global__ void k_tv_tree(const int2* f1, const uint32_t* q, int32_t qs, const int32_t* head, const int32_t* in_arc,
+__global__ void k_tv_tree(const int2* f1, const uint32_t* q, int32_t qs, const int32_t* first, const int32_t* in_arc,
                           const int32_t* pre, const int32_t* sub, Rmq R, int32_t V, int64_t A, uint32_t* g) {
     GRID_LOOP(v, (int64_t)V) {
-        if (head[v + 1] == head[v] || q[qs * (size_t)v] == 0) continue;
+        if (first[v] == 0 || q[qs * (size_t)v] == 0) continue;
         const int32_t a = in_arc[v];
         if (a < 0 || a >= A) continue;
         const int32_t w = arc_src(f1, a);
@@ -568,10 +640,10 @@ __global__ void k_tv_compress(uint32_t* g, int32_t V) {
 }
 
 // per tree edge (w, v): compare v's block with the block of w's own parent edge
-__global__ void k_tv_mark(const int2* f1, const uint32_t* q, int32_t qs, const int32_t* head, const int32_t* in_arc,
+__global__ void k_tv_mark(const int2* f1, const uint32_t* q, int32_t qs, const int32_t* first, const int32_t* in_arc,
                           int32_t V, int64_t A, const uint32_t* g, int32_t* rmin, int32_t* rmax, int32_t* apf) {
     GRID_LOOP(v, (int64_t)V) {
-        if (head[v + 1] == head[v] || q[qs * (size_t)v] == 0) continue;
+        if (first[v] == 0 || q[qs * (size_t)v] == 0) continue;
         const int32_t a = in_arc[v];
         if (a < 0 || a >= A) continue;
         const int32_t w = arc_src(f1, a);
@@ -585,13 +657,13 @@ __global__ void k_tv_mark(const int2* f1, const uint32_t* q, int32_t qs, const i
     }
 }
 
-__global__ void k_tv_list(const uint32_t* q, int32_t qs, const int32_t* head, int32_t V, const int32_t* rmin,
+__global__ void k_tv_list(const uint32_t* q, int32_t qs, const int32_t* first, int32_t V, const int32_t* rmin,
                           const int32_t* rmax, const int32_t* apf, uint64_t* out, uint32_t* nout) {
     __shared__ OutLds L;
     out_begin(L);
     GRID_LOOP(v, (int64_t)V) {
         bool cut = false;
-        if (head[v + 1] > head[v])
+        if (first[v] != 0)
             cut = q[qs * (size_t)v] == 0 ? (rmax[v] >= 0 && rmin[v] != rmax[v]) : apf[v] != 0;
         const uint64_t m = __ballot(cut);
         if (m) out_put(L, cut, (uint64_t)v, m, out, nout);
@@ -606,10 +678,10 @@ __global__ void k_tv_list(const uint32_t* q, int32_t qs, const int32_t* head, in
 // is a bridge iff no edge of F' leaves v's subtree (the test of k_bridges).
 // The non-bridges are united with the larger root hooked under the smaller, so
 // after full compression each vertex's root is the smallest id of its class.
-__global__ void k_class_tree(const int2* f1, const uint32_t* q, int32_t qs, const int32_t* head, const int32_t* in_arc,
+__global__ void k_class_tree(const int2* f1, const uint32_t* q, int32_t qs, const int32_t* first, const int32_t* in_arc,
                              const int32_t* pre, const int32_t* sub, Rmq R, int32_t V, int64_t A, uint32_t* g) {
     GRID_LOOP(v, (int64_t)V) {
-        if (head[v + 1] == head[v] || q[qs * (size_t)v] == 0) continue;      // no tree edge above v
+        if (first[v] == 0 || q[qs * (size_t)v] == 0) continue;      // no tree edge above v
         const int32_t a = in_arc[v];
         if (a < 0 || a >= A) continue;
         const int32_t l = pre[v], r = pre[v] + sub[v] - 1;
@@ -683,14 +755,14 @@ __global__ void k_status(const uint32_t* cnt, const uint32_t* err, uint32_t* mis
 }  // namespace
 
 // Scratch layout of the bridge step, shared by the size query and the launch
-// sequence so that the two cannot disagree.  Everything from `head` up to the
-// end of `misc` is cleared by one kernel at the start; the keys follow `misc`
+// sequence so that the two cannot disagree.  Everything from `first` up to the
+// end of `misc` is cleared by one kernel at the start (the ranking words
+// included: zero marks a word not written yet); the keys follow `misc`
 // directly, so that the counters and the keys leave in one copy.
 struct BridgeWs {
-    int32_t *head, *cur, *flag, *tickets, *misc, *adj, *posof, *tour_len, *tree_n, *tour_base, *vbase, *in_arc, *sub,
+    int32_t *first, *cur, *flag, *tickets, *misc, *nxt, *posof, *tour_len, *tree_n, *tour_base, *vbase, *in_arc, *sub,
         *pre, *tmin, *tmax, *lmin, *lmax, *tmn, *tmx;
-    uint64_t *st_head, *st_tours, *st_flag, *keys;
-    int4 *link, *link2;
+    uint64_t *st_tours, *st_flag, *keys, *link;
     int64_t zero_words, nb;
     int32_t levels;
     int64_t words;
@@ -703,22 +775,20 @@ static BridgeWs carve(int32_t* base, int32_t V) {
     BridgeWs w{};
     int64_t o = 0;
     auto take = [&](int64_t n) { int32_t* p = base ? base + o : nullptr; o += (n + 63) & ~int64_t(63); return p; };
-    w.head = take(V + 2);
-    w.cur = take(V + 1);
+    w.first = take(V + 2);
     w.flag = take(A + 1);
-    w.tickets = take(64);   // [0..2] scan tickets
-    w.st_head = reinterpret_cast<uint64_t*>(take(2 * cdiv(V + 1, kSB)));
+    w.tickets = take(64);   // [1] tour scan ticket, [2] flag scan ticket
     w.st_tours = reinterpret_cast<uint64_t*>(take(2 * cdiv(V, kSB)));
     w.st_flag = reinterpret_cast<uint64_t*>(take(2 * cdiv(A + 1, kSB)));
     w.in_arc = take(V);
     w.sub = take(V);
+    w.link = reinterpret_cast<uint64_t*>(take(2 * A));
     w.misc = take(64);   // [1] key count, [2..4] |F|, |F'|, error word
     w.zero_words = o;
     w.keys = reinterpret_cast<uint64_t*>(take(2 * (int64_t)V + 2));
-    w.adj = take(A);
+    w.cur = take(V + 1);
+    w.nxt = take(A);
     w.posof = take(A);
-    w.link = reinterpret_cast<int4*>(take(4 * A));
-    w.link2 = reinterpret_cast<int4*>(take(4 * A));
     w.tour_len = take(V);
     w.tree_n = take(V);
     w.tour_base = take(V);
@@ -752,32 +822,47 @@ void device_scan1(int32_t* a, int64_t n, uint64_t* status, uint32_t* ticket, hip
 // The part shared by the bridge and articulation-point tests: adjacency of F,
 // Euler tours ranked, preorder numbers, subtree sizes, min/max preorder numbers
 // reached through F' and their range tables.
+// The ranking launch: K arcs per thread in registers while the grid stays
+// within what the device holds resident at once, else the words in memory.
+static void launch_rank(const int2* f1, const uint32_t* cnt, const int32_t* first, const int32_t* nxt,
+                        const uint32_t* q, int32_t qs, uint64_t* link, int64_t A, hipStream_t s) {
+    static int resident = 0;      // workgroups of k_rank resident on the device
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rank<1>, kT, 0) != hipSuccess || per_cu < 1) {
+            (void)hipGetLastError();
+            per_cu = 1;
+        }
+        resident = std::max(1, per_cu) * std::max(1, g_cus);
+    });
+    const int64_t cap = (int64_t)resident * kT;   // threads
+    if (A <= cap)
+        hipLaunchKernelGGL(k_rank<1>, dim3((unsigned)cdiv(A, kT)), dim3(kT), 0, s, f1, cnt, first, nxt, q, qs, link);
+    else if (A <= 2 * cap)
+        hipLaunchKernelGGL(k_rank<2>, dim3((unsigned)cdiv(A, 2 * kT)), dim3(kT), 0, s, f1, cnt, first, nxt, q, qs, link);
+    else if (A <= 4 * cap)
+        hipLaunchKernelGGL(k_rank<4>, dim3((unsigned)cdiv(A, 4 * kT)), dim3(kT), 0, s, f1, cnt, first, nxt, q, qs, link);
+    else
+        hipLaunchKernelGGL(k_rank_mem, dim3((unsigned)resident), dim3(kT), 0, s, f1, cnt, first, nxt, q, qs, link);
+}
+
 static BridgeWs number_tree(const int2* f1, const int2* f2, int32_t dir, const uint32_t* cnt, const uint32_t* q,
-                            int32_t qs, int32_t V, int32_t max_tree, int32_t* ws, hipStream_t s, Rmq* R) {
+                            int32_t qs, int32_t V, int32_t* ws, hipStream_t s, Rmq* R) {
     const int64_t A = 2 * (int64_t)std::max(V - 1, 1);
-    // list ranking only needs the longest tour: at most 2(max_tree - 1) arcs
-    max_tree = std::max(2, std::min(max_tree, V));
     const BridgeWs W = carve(ws, V);
-    hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(W.zero_words)), dim3(kT), 0, s, W.head, W.zero_words);
-    hipLaunchKernelGGL(k_degree, dim3(grid_for(V)), dim3(kT), 0, s, f1, cnt, W.head);
-    hipLaunchKernelGGL(k_scan1, dim3((unsigned)cdiv(V + 1, kSB)), dim3(kT), 0, s, W.head, (int64_t)V + 1, W.st_head,
-                       reinterpret_cast<uint32_t*>(W.tickets));
-    hipLaunchKernelGGL(k_fill_adj, dim3(grid_for(A)), dim3(kT), 0, s, f1, cnt, W.head, W.cur, W.adj, W.posof);
-    int4 *link = W.link, *link2 = W.link2;
-    hipLaunchKernelGGL(k_succ, dim3(grid_for(A)), dim3(kT), 0, s, f1, cnt, W.head, W.adj, W.posof, q, qs, link);
-    const int64_t longest = 2 * ((int64_t)max_tree - 1);
-    for (int64_t span = 1; span < longest; span *= kHop) {
-        hipLaunchKernelGGL(k_jump, dim3(grid_for(A)), dim3(kT), 0, s, cnt, (const int4*)link, link2);
-        std::swap(link, link2);
-    }
-    hipLaunchKernelGGL(k_tours, dim3((unsigned)cdiv(V, kSB)), dim3(kT), 0, s, W.head, W.adj, (const int4*)link, q, qs, V,
+    hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(W.zero_words)), dim3(kT), 0, s, W.first, W.zero_words);
+    hipLaunchKernelGGL(k_link, dim3(grid_for(A)), dim3(kT), 0, s, f1, cnt, W.first, W.nxt);
+    launch_rank(f1, cnt, W.first, W.nxt, q, qs, W.link, A, s);
+    hipLaunchKernelGGL(k_tours, dim3((unsigned)cdiv(V, kSB)), dim3(kT), 0, s, W.first, (const uint64_t*)W.link, q, qs, V,
                        W.tour_len, W.tree_n, W.tour_base, W.vbase, W.st_tours, reinterpret_cast<uint32_t*>(W.tickets) + 1);
-    hipLaunchKernelGGL(k_down, dim3(grid_for(A)), dim3(kT), 0, s, f1, cnt, (const int4*)link, W.tour_len, W.tour_base,
-                       W.flag, W.in_arc, W.sub);
+    hipLaunchKernelGGL(k_down, dim3(grid_for(A)), dim3(kT), 0, s, f1, cnt, (const uint64_t*)W.link, W.tour_len,
+                       W.tour_base, W.flag, W.in_arc, W.sub);
     hipLaunchKernelGGL(k_scan1, dim3((unsigned)cdiv(A + 1, kSB)), dim3(kT), 0, s, W.flag, A + 1, W.st_flag,
                        reinterpret_cast<uint32_t*>(W.tickets) + 2);
-    hipLaunchKernelGGL(k_preorder, dim3(grid_for(V)), dim3(kT), 0, s, f1, q, qs, W.head, W.in_arc, (const int4*)link,
-                       W.tour_len, W.tour_base, W.flag, W.vbase, W.tree_n, V, W.pre, W.sub, W.tmin, W.tmax);
+    hipLaunchKernelGGL(k_preorder, dim3(grid_for(V)), dim3(kT), 0, s, f1, q, qs, W.first, W.in_arc,
+                       (const uint64_t*)W.link, W.tour_len, W.tour_base, W.flag, W.vbase, W.tree_n, V, W.pre, W.sub,
+                       W.tmin, W.tmax);
     hipLaunchKernelGGL(k_nontree, dim3(grid_for(V)), dim3(kT), 0, s, f2, dir, cnt, W.pre, W.tmin, W.tmax);
     const int64_t rblocks = cdiv(W.nb * kRB, kT);
     hipLaunchKernelGGL(k_rmq_blocks, dim3((unsigned)rblocks), dim3(kT), 0, s, W.tmin, W.tmax, (int64_t)V, W.lmin,
@@ -793,12 +878,13 @@ static BridgeWs number_tree(const int2* f1, const int2* f2, int32_t dir, const u
 }
 
 int device_bridges_cert(const int2* f1, const int2* f2, int32_t dir, const uint32_t* cnt, const uint32_t* q, int32_t qs,
-                        int32_t V, int32_t max_tree, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s) {
+                        int32_t V, const uint32_t* err, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s) {
     const int64_t A = 2 * (int64_t)std::max(V - 1, 1);
     Rmq R;
-    const BridgeWs W = number_tree(f1, f2, dir, cnt, q, qs, V, max_tree, ws, s, &R);
-    hipLaunchKernelGGL(k_bridges, dim3(std::min(grid_for(V), kOutBlocks)), dim3(kT), 0, s, f1, q, qs, W.head, W.in_arc, W.pre, W.sub, R, V,
-                       A, W.keys, reinterpret_cast<uint32_t*>(W.misc + 1));
+    const BridgeWs W = number_tree(f1, f2, dir, cnt, q, qs, V, ws, s, &R);
+    hipLaunchKernelGGL(k_bridges, dim3(std::min(grid_for(V), kOutBlocks)), dim3(kT), 0, s, f1, q, qs, W.first,
+                       W.in_arc, W.pre, W.sub, R, V, A, W.keys, reinterpret_cast<uint32_t*>(W.misc + 1), cnt, err,
+                       reinterpret_cast<uint32_t*>(W.misc));
     *d_keys = W.keys;
     *d_n = reinterpret_cast<uint32_t*>(W.misc + 1);
     return BR_OK;
@@ -813,15 +899,15 @@ int device_articulation_cert(const int2* f1, const int2* f2, int32_t dir, const 
                              int32_t qs, int32_t V, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s) {
     const int64_t A = 2 * (int64_t)std::max(V - 1, 1);
     Rmq R;
-    const BridgeWs W = number_tree(f1, f2, dir, cnt, q, qs, V, V, ws, s, &R);
+    const BridgeWs W = number_tree(f1, f2, dir, cnt, q, qs, V, ws, s, &R);
     uint32_t* g = reinterpret_cast<uint32_t*>(W.cur);
     hipLaunchKernelGGL(k_tv_init, dim3(grid_for(V)), dim3(kT), 0, s, V, g, W.tour_len, W.tree_n, W.posof);
-    hipLaunchKernelGGL(k_tv_tree, dim3(grid_for(V)), dim3(kT), 0, s, f1, q, qs, W.head, W.in_arc, W.pre, W.sub, R, V, A, g);
+    hipLaunchKernelGGL(k_tv_tree, dim3(grid_for(V)), dim3(kT), 0, s, f1, q, qs, W.first, W.in_arc, W.pre, W.sub, R, V, A, g);
     hipLaunchKernelGGL(k_tv_cross, dim3(grid_for(V)), dim3(kT), 0, s, f2, dir, cnt, W.pre, W.sub, g);
     hipLaunchKernelGGL(k_tv_compress, dim3(grid_for(V)), dim3(kT), 0, s, g, V);
-    hipLaunchKernelGGL(k_tv_mark, dim3(grid_for(V)), dim3(kT), 0, s, f1, q, qs, W.head, W.in_arc, V, A, (const uint32_t*)g,
+    hipLaunchKernelGGL(k_tv_mark, dim3(grid_for(V)), dim3(kT), 0, s, f1, q, qs, W.first, W.in_arc, V, A, (const uint32_t*)g,
                        W.tour_len, W.tree_n, W.posof);
-    hipLaunchKernelGGL(k_tv_list, dim3(std::min(grid_for(V), kOutBlocks)), dim3(kT), 0, s, q, qs, W.head, V, W.tour_len, W.tree_n, W.posof,
+    hipLaunchKernelGGL(k_tv_list, dim3(std::min(grid_for(V), kOutBlocks)), dim3(kT), 0, s, q, qs, W.first, V, W.tour_len, W.tree_n, W.posof,
                        W.keys, reinterpret_cast<uint32_t*>(W.misc + 1));
     *d_keys = W.keys;
     *d_n = reinterpret_cast<uint32_t*>(W.misc + 1);
@@ -836,11 +922,11 @@ int device_classes_cert(const int2* f1, const int2* f2, int32_t dir, const uint3
                         int32_t qs, int32_t V, int32_t* ws, int32_t** d_label, uint32_t** d_n, hipStream_t s) {
     const int64_t A = 2 * (int64_t)std::max(V - 1, 1);
     Rmq R;
-    const BridgeWs W = number_tree(f1, f2, dir, cnt, q, qs, V, V, ws, s, &R);
+    const BridgeWs W = number_tree(f1, f2, dir, cnt, q, qs, V, ws, s, &R);
     uint32_t* g = reinterpret_cast<uint32_t*>(W.cur);
     int32_t* label = reinterpret_cast<int32_t*>(W.keys);
     hipLaunchKernelGGL(k_tv_init, dim3(grid_for(V)), dim3(kT), 0, s, V, g, W.tour_len, W.tree_n, W.posof);
-    hipLaunchKernelGGL(k_class_tree, dim3(grid_for(V)), dim3(kT), 0, s, f1, q, qs, W.head, W.in_arc, W.pre, W.sub, R, V, A,
+    hipLaunchKernelGGL(k_class_tree, dim3(grid_for(V)), dim3(kT), 0, s, f1, q, qs, W.first, W.in_arc, W.pre, W.sub, R, V, A,
                        g);
     hipLaunchKernelGGL(k_class_cross, dim3(grid_for(V)), dim3(kT), 0, s, f2, dir, cnt, g);
     hipLaunchKernelGGL(k_tv_compress, dim3(grid_for(V)), dim3(kT), 0, s, g, V);
@@ -886,10 +972,7 @@ int device_classes(const Plan& P, const DevBufs& B, int32_t* ws, int32_t** d_lab
 int device_bridges(const Plan& P, const DevBufs& B, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s) {
     const int2* f1 = B.cert + P.off[0];
     const int2* f2 = B.cert + P.off[0] + P.cap[0] - 1;
-    const int rc = device_bridges_cert(f1, f2, -1, B.cnt, B.state, (int32_t)B.qs, P.V, P.V, ws, d_keys, d_n, s);
-    if (rc) return rc;
-    launch_bridge_status(B.cnt, B.err, *d_n, s);
-    return BR_OK;
+    return device_bridges_cert(f1, f2, -1, B.cnt, B.state, (int32_t)B.qs, P.V, B.err, ws, d_keys, d_n, s);
 }
 
 // |F|, |F'| and the error word into the status block that holds the key count

@@ -182,6 +182,11 @@ struct BatchDev {
 // workgroup per CU); else up to batched_max_v_dev()
 void launch_batched(const BatchDev& B, int blocks, hipStream_t s, bool big = false);
 int32_t batched_max_v_big();
+// node-0 certificates of the batch's graphs 0..S-1 as one certificate of their
+// disjoint union (ids shifted by vbase): F edges at f1u, F' edges at f2u,
+// their numbers at cntu[0], cntu[1]; uoff [2S] scratch
+void launch_union_certificate(const BatchDev& B, int32_t S, int64_t* uoff, int2* f1u, int2* f2u, uint32_t* cntu,
+                              hipStream_t s);
 // Final step on the device for the batched path: one workgroup per small graph
 // finds the bridges of node 0's certificate in LDS; keys (u << 16 | v, sorted)
 // go to out_keys at a base taken from out_hdr[0]; out_hdr[16 + 2s] / [17 + 2s]
@@ -254,8 +259,9 @@ int device_classes(const Plan& P, const DevBufs& B, int32_t* ws, int32_t** d_lab
 // their number in status word 5, (*d_n)[4]) at *d_tkeys
 int device_bridge_tree(const Plan& P, const DevBufs& B, int32_t* ws, int32_t** d_label, uint32_t** d_n,
                        uint64_t** d_tkeys, hipStream_t s);
+// also fills the status block before the keys (|F|, |F'|, *err or 0)
 int device_bridges_cert(const int2* f1, const int2* f2, int32_t dir, const uint32_t* cnt, const uint32_t* q, int32_t qs,
-                        int32_t V, int32_t max_tree, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s);
+                        int32_t V, const uint32_t* err, int32_t* ws, uint64_t** d_keys, uint32_t** d_n, hipStream_t s);
 
 // device address of the fixed scratch array on `device` (current on the
 // calling thread), looked up once; br_create calls it
@@ -315,7 +321,15 @@ struct br_ctx {
 
 namespace br {
 int ensure_workspace(br_ctx* c, size_t bytes, hipStream_t s);
+// br_bridges_find_batched after argument checks; transient: the batch shape
+// is used once (serving ticks): plans built in reused arenas, launched
+// without graph capture, chunk size from the tuner's cache or a default
+int batched_query(br_ctx* c, const int32_t* d_edges, const int64_t* h_edge_off, const int32_t* h_V, int32_t G,
+                  int32_t chunk_edges, int32_t* h_bridges, int64_t cap, int64_t* h_bridge_off, void* stream,
+                  bool transient);
 void batched_release(br_ctx* c);
+// device bytes the context's batched plans and arenas hold
+size_t batched_device_bytes(br_ctx* c);
 int ensure_pinned(br_ctx* c, size_t bytes);
 // Run phases a1..a5 on d_edges; on return (asynchronously) node 0 holds the final certificate.
 // The input is the concatenation of d_a [Ea] and d_b [Eb] (d_b may be null with Eb = 0).

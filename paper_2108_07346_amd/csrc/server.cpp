@@ -1,13 +1,20 @@
 // Serving runtime: continuous batching of bridge queries on one device.
 //
 // Requests enter a bounded FIFO.  A scheduler admits the head request as soon
-// as a device slot is free and the device-memory budget has room for it (its
-// edge list, its union-find state and its certificate regions); admitted
-// requests run concurrently, each on its slot's own stream and context, so
-// the certificate kernels of different requests overlap on the GPU and a new
-// request starts while others are still in flight.  Each request runs the full
-// path (phase tree + final search) and its latency is stamped from submission
-// to the moment its result is available.
+// as the device-memory budget has room for it, onto one of two paths:
+//  * slots: each slot runs the full plain path for one request on its own
+//    stream and context, so the kernels of different requests overlap;
+//  * the batch lane, for requests within the batched kernels' limits (V
+//    within a workgroup's LDS, E under a cap): a lane worker takes every lane
+//    request queued when it becomes free, packs their edge lists into one
+//    device buffer and certifies them all in one batched call (the persistent
+//    kernels, without graph capture).  Two workers alternate, so one packs
+//    and finishes a tick on the host while the other's kernels run.
+// A lane-eligible request takes a free slot while the lane has nothing
+// queued (a lone request finishes sooner on the plain path); under load the
+// slots are busy and such requests collect in the lane, where the per-request
+// launch and synchronisation costs are paid once per tick.  Latency is
+// stamped from submission to the moment the result is available.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -37,6 +44,8 @@ struct Request {
     int mode = 1;                      // final step, fixed when the request is admitted
     int64_t ws_bytes = 0;              // device workspace it needs (for its final step)
     int64_t buf_bytes = 0;             // device copy of its edges (host submissions)
+    bool lane = false;                 // served by the batch lane (fixed at submission)
+    int64_t lane_bytes = 0;            // its charge while queued for or in a lane tick
     Clock::time_point t_submit;
     // result
     int status = BR_OK;
@@ -57,7 +66,22 @@ struct Slot {
     std::thread th;
 };
 
+// one worker of the batch lane: its context (plans and arenas), stream and
+// packed edge buffer, kept between ticks and charged to the budget
+struct LaneWorker {
+    br_ctx* ctx = nullptr;
+    hipStream_t stream = nullptr;
+    void* buf = nullptr;
+    size_t cap = 0;
+    int64_t held = 0;                  // device bytes charged between ticks
+    bool busy = false;                 // a tick is running
+    bool trimming = false;             // its buffers are being released by the scheduler
+    std::thread th;
+};
+
 constexpr size_t kQueueMax = 65536;
+constexpr int kLaneWorkers = 2;
+constexpr int64_t kLaneMaxEdges = int64_t(1) << 21;   // default edge cap of lane requests
 
 }  // namespace
 }  // namespace br
@@ -88,6 +112,13 @@ struct br_server {
     int64_t pin_total = 0, pin_limit = 0;
     std::unique_ptr<br::Pool> copier;    // parallel copy of submitted edge lists
     std::mutex copy_mu;
+    // batch lane: requests with V <= lane_max_v and E <= lane_max_e
+    int32_t lane_max_v = 0;              // 0: lane off
+    int64_t lane_max_e = 0;
+    std::deque<std::shared_ptr<br::Request>> lane_q;
+    std::condition_variable cv_lane;
+    std::vector<std::unique_ptr<br::LaneWorker>> lanes;
+    int64_t ticks = 0, lane_requests = 0;
 };
 
 namespace br {
@@ -99,6 +130,27 @@ void charge(Request& r, bool host_edges, int mode, int device) {
     const Plan P = plan_for(device, r.E, r.V, r.M);
     r.ws_bytes = (int64_t)plan_workspace_bytes(P, mode == 1);
     r.buf_bytes = host_edges ? 8 * r.E : 0;
+}
+
+// Device bytes one request adds to a batch-lane tick (an upper bound): its
+// packed edges, its certificate regions (per merge level at most its edges,
+// per node at most 2(V-1) pairs), per-node counters and metadata, root flags
+// and bridge keys, and for graphs above the small kernel's limit its part of
+// the union certificate and of the bridge step's scratch.  Chunks of at least
+// 4,096 edges (the smallest chunk size the batched path uses).
+int64_t lane_need(const Request& r) {
+    const int64_t C = 4096, M = std::max<int64_t>(1, (r.E + C - 1) / C);
+    int R = 0;
+    while ((int64_t(1) << R) < M) R++;
+    const int64_t V = r.V;
+    const int64_t regions = std::min<int64_t>(r.E * (R + 1), 2 * V * M);
+    int64_t b = 8 * r.E + 8 * regions + (96 + 4 * (int64_t)R) * M + 8 * V + 8192;
+    if (r.V > batched_max_v_dev()) b += 16 * V + 4 * device_bridges_words(r.V) + 8192;
+    return b;
+}
+
+bool lane_fits(const br_server* S, const Request& r) {
+    return S->lane_max_v > 0 && r.V <= S->lane_max_v && r.E <= S->lane_max_e;
 }
 
 // what slot sl holds after running r (buffers only ever grow to what is needed)
@@ -252,6 +304,142 @@ void slot_loop(br_server* S, Slot* sl) {
     }
 }
 
+// One tick of a lane worker: the edge lists of `batch` packed into one device
+// buffer (uploads and device-to-device copies on the worker's stream, in
+// request order), one batched query over all of them with plans built for
+// this tick only, and the bridges split per request.
+int lane_run(LaneWorker& L, const std::vector<std::shared_ptr<Request>>& batch, int mode) {
+    const int32_t G = (int32_t)batch.size();
+    std::vector<int64_t> eoff(G + 1, 0), boff(G + 1, 0);
+    std::vector<int32_t> V(G);
+    int64_t room = 0;
+    for (int32_t g = 0; g < G; g++) {
+        eoff[g + 1] = eoff[g] + batch[g]->E;
+        V[g] = batch[g]->V;
+        room += std::max(V[g] - 1, 0);
+    }
+    const size_t bytes = std::max<size_t>(8 * (size_t)eoff[G], 256);
+    if (L.cap < bytes) {
+        if (L.buf) (void)hipFree(L.buf);
+        L.buf = nullptr;
+        L.cap = 0;
+        if (hipMalloc(&L.buf, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(BR_ENOMEM, "server: device allocation failed");
+        }
+        L.cap = bytes;
+    }
+    int32_t* d = static_cast<int32_t*>(L.buf);
+    for (int32_t g = 0; g < G; g++) {
+        const Request& r = *batch[g];
+        if (r.E == 0) continue;
+        const void* src = r.d_edges ? static_cast<const void*>(r.d_edges)
+                                    : r.pin ? r.pin : static_cast<const void*>(r.h_edges.data());
+        const hipMemcpyKind kind = r.d_edges ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        if (hipMemcpyAsync(d + 2 * eoff[g], src, 8 * (size_t)r.E, kind, L.stream) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(BR_EHIP, "server: edge copy failed");
+        }
+    }
+    br_set_final_step(L.ctx, mode);
+    std::vector<int32_t> out(2 * (size_t)std::max<int64_t>(room, 1));
+    // the query's launches wait for the worker's stream, so the copies above
+    // come first
+    const int rc = batched_query(L.ctx, d, eoff.data(), V.data(), G, 0, out.data(), room, boff.data(), L.stream, true);
+    if (rc != BR_OK) return rc;
+    for (int32_t g = 0; g < G; g++)
+        batch[g]->bridges.assign(out.begin() + 2 * boff[g], out.begin() + 2 * boff[g + 1]);
+    return BR_OK;
+}
+
+// what a worker holds between ticks: its packed edge buffer and its context's
+// plan arenas
+int64_t lane_held_now(const LaneWorker& L) { return (int64_t)L.cap + (int64_t)batched_device_bytes(L.ctx); }
+
+void lane_loop(br_server* S, LaneWorker* L) {
+    (void)hipSetDevice(S->device);
+    for (;;) {
+        std::vector<std::shared_ptr<Request>> batch;
+        int mode = 1;
+        {
+            std::unique_lock<std::mutex> g(S->mu);
+            S->cv_lane.wait(g, [&] { return S->stop || (!S->lane_q.empty() && !L->trimming); });
+            if (S->lane_q.empty()) return;   // stopping and idle
+            // everything queued, up to the first request that was admitted
+            // with the other final step
+            mode = S->lane_q.front()->mode;
+            while (!S->lane_q.empty() && S->lane_q.front()->mode == mode) {
+                batch.push_back(S->lane_q.front());
+                S->lane_q.pop_front();
+            }
+            L->busy = true;
+        }
+        int rc = lane_run(*L, batch, mode);
+        (void)hipStreamSynchronize(L->stream);   // its copies are done whatever the outcome
+        if (rc != BR_OK) {
+            // an error of one request (an id out of range, say) must not fail
+            // the others: each runs again on its own
+            if (batch.size() == 1) {
+                batch[0]->status = rc;
+                batch[0]->msg = br_last_error();
+            } else {
+                for (auto& r : batch) {
+                    const int rc1 = lane_run(*L, {r}, mode);
+                    if (rc1 != BR_OK) {
+                        r->status = rc1;
+                        r->msg = br_last_error();
+                    }
+                }
+            }
+        }
+        {
+            std::lock_guard<std::mutex> g(S->mu);
+            const auto now = Clock::now();
+            int64_t charged = 0;
+            for (auto& r : batch) {
+                r->latency_ms = std::chrono::duration<double, std::milli>(now - r->t_submit).count();
+                r->done = true;
+                if (r->status != BR_OK) r->bridges.clear();
+                r->h_edges.clear();
+                r->h_edges.shrink_to_fit();
+                if (r->pin) {
+                    S->pin_free.emplace_back(r->pin, r->pin_cap);
+                    r->pin = nullptr;
+                }
+                charged += r->lane_bytes;
+                if (r->status == BR_OK) {
+                    S->lat.push_back(r->latency_ms);
+                    S->edges_done += r->E;
+                }
+            }
+            // the tick's charges go; what the worker keeps is charged instead
+            const int64_t held = lane_held_now(*L);
+            S->in_use += held - L->held - charged;
+            L->held = held;
+            S->peak_in_use = std::max(S->peak_in_use, S->in_use);
+            S->inflight -= (int64_t)batch.size();
+            if (S->inflight == 0) S->busy_ms += std::chrono::duration<double, std::milli>(now - S->busy_start).count();
+            S->ticks++;
+            S->lane_requests += (int64_t)batch.size();
+            L->busy = false;
+        }
+        S->cv_sched.notify_one();
+        S->cv_done.notify_all();
+        S->cv_lane.notify_all();
+    }
+}
+
+// release what an idle lane worker holds (scheduler thread, no tick running)
+void release_lane(br_server* S, LaneWorker& L) {
+    (void)hipSetDevice(S->device);
+    (void)hipStreamSynchronize(L.stream);
+    batched_release(L.ctx);
+    if (L.buf) (void)hipFree(L.buf);
+    L.buf = nullptr;
+    L.cap = 0;
+    (void)hipGetLastError();
+}
+
 // The free slot for r that needs the fewest new bytes, and that number.
 Slot* pick_slot(br_server* S, const Request& r, int64_t* extra) {
     Slot* best = nullptr;
@@ -266,12 +454,71 @@ Slot* pick_slot(br_server* S, const Request& r, int64_t* extra) {
     return best;
 }
 
+// Release idle holders of device memory -- slots not running a request and
+// lane workers not running a tick -- largest first, until `extra` more bytes
+// fit the budget.  `keep` (the slot about to be used) goes last, and only when
+// nothing runs.  Returns whether anything was released (the lock is dropped
+// meanwhile: the caller decides again).
+bool trim(br_server* S, std::unique_lock<std::mutex>& g, int64_t extra, Slot* keep) {
+    struct Holder { Slot* slot; LaneWorker* lane; int64_t held; };
+    std::vector<Holder> idle;
+    for (auto& s : S->slots)
+        if (!s->job && !s->trimming && s.get() != keep && s->held > 0) idle.push_back({s.get(), nullptr, s->held});
+    for (auto& l : S->lanes)
+        if (!l->busy && !l->trimming && l->held > 0) idle.push_back({nullptr, l.get(), l->held});
+    std::sort(idle.begin(), idle.end(), [](const Holder& a, const Holder& b) { return a.held > b.held; });
+    std::vector<Holder> rel;
+    int64_t freed = 0;
+    for (const Holder& h : idle) {
+        if (S->in_use - freed + extra <= S->budget) break;
+        rel.push_back(h);
+        freed += h.held;
+    }
+    if (S->in_use - freed + extra > S->budget && S->inflight == 0 && keep && keep->held > 0)
+        rel.push_back({keep, nullptr, keep->held});   // nothing runs: the chosen slot starts over from nothing too
+    if (rel.empty()) return false;
+    for (const Holder& h : rel) (h.slot ? h.slot->trimming : h.lane->trimming) = true;
+    g.unlock();
+    for (const Holder& h : rel) {
+        if (h.slot) release_slot(*h.slot);
+        else release_lane(S, *h.lane);
+    }
+    g.lock();
+    for (const Holder& h : rel) {
+        if (h.slot) {
+            S->in_use -= h.slot->held;
+            h.slot->held = 0;
+            h.slot->trimming = false;
+        } else {
+            S->in_use -= h.lane->held;
+            h.lane->held = 0;
+            h.lane->trimming = false;
+        }
+    }
+    S->cv_lane.notify_all();
+    return true;
+}
+
+// put r on slot sl (scheduler thread, lock held, budget checked)
+void admit_slot(br_server* S, Slot* sl, std::shared_ptr<Request> r) {
+    const int64_t after = held_after(*sl, *r);
+    S->in_use += after - sl->held;
+    sl->held = after;
+    S->peak_in_use = std::max(S->peak_in_use, S->in_use);
+    sl->job = std::move(r);
+    if (S->inflight == 0) S->busy_start = Clock::now();
+    S->inflight++;
+    S->peak_inflight = std::max(S->peak_inflight, S->inflight);
+    S->cv_slot.notify_all();
+}
+
 void sched_loop(br_server* S) {
     std::unique_lock<std::mutex> g(S->mu);
     for (;;) {
         S->cv_sched.wait(g, [&] {
             if (S->stop) return true;
             if (S->queue.empty()) return false;
+            if (S->queue.front()->lane) return true;
             for (auto& s : S->slots)
                 if (!s->job && !s->trimming) return true;
             return false;
@@ -279,39 +526,44 @@ void sched_loop(br_server* S) {
         if (S->stop) return;
         auto r = S->queue.front();
         r->mode = S->final_step;
+        if (r->lane) {
+            // a free slot that has room takes it while the lane has nothing queued
+            if (S->lane_q.empty()) {
+                charge(*r, r->d_edges == nullptr, r->mode, S->device);
+                int64_t extra = 0;
+                Slot* sl = pick_slot(S, *r, &extra);
+                if (sl && S->in_use + extra <= S->budget) {
+                    S->queue.pop_front();
+                    admit_slot(S, sl, std::move(r));
+                    continue;
+                }
+            }
+            // the batch lane: charged its estimate until its tick completes
+            const int64_t need = lane_need(*r);
+            if (S->in_use + need > S->budget) {
+                if (trim(S, g, need, nullptr)) continue;
+                if (S->inflight > 0) {
+                    S->cv_sched.wait(g);
+                    continue;
+                }
+                // nothing runs: one that exceeds the budget on its own runs alone
+            }
+            S->queue.pop_front();
+            r->lane_bytes = need;
+            S->in_use += need;
+            S->peak_in_use = std::max(S->peak_in_use, S->in_use);
+            S->lane_q.push_back(r);
+            if (S->inflight == 0) S->busy_start = Clock::now();
+            S->inflight++;
+            S->peak_inflight = std::max(S->peak_inflight, S->inflight);
+            S->cv_lane.notify_one();
+            continue;
+        }
         charge(*r, r->d_edges == nullptr, r->mode, S->device);
         int64_t extra = 0;
         Slot* sl = pick_slot(S, *r, &extra);
         if (S->in_use + extra > S->budget) {
-            // release what idle slots hold (largest first) until the request fits
-            std::vector<Slot*> idle;
-            for (auto& s : S->slots)
-                if (!s->job && !s->trimming && s.get() != sl && s->held > 0) idle.push_back(s.get());
-            std::sort(idle.begin(), idle.end(), [](Slot* a, Slot* b) { return a->held > b->held; });
-            std::vector<Slot*> rel;
-            int64_t freed = 0;
-            for (Slot* s : idle) {
-                if (S->in_use - freed + extra <= S->budget) break;
-                rel.push_back(s);
-                freed += s->held;
-            }
-            if (S->in_use - freed + extra > S->budget && S->inflight == 0 && sl->held > 0) {
-                // nothing runs: the chosen slot starts over from nothing too
-                rel.push_back(sl);
-                freed += sl->held;
-            }
-            if (!rel.empty()) {
-                for (Slot* s : rel) s->trimming = true;
-                g.unlock();
-                for (Slot* s : rel) release_slot(*s);
-                g.lock();
-                for (Slot* s : rel) {
-                    S->in_use -= s->held;
-                    s->held = 0;
-                    s->trimming = false;
-                }
-                continue;   // decide again with the memory released
-            }
+            if (trim(S, g, extra, sl)) continue;   // decide again with the memory released
             // one that exceeds the budget on its own runs alone
             if (S->inflight > 0) {
                 S->cv_sched.wait(g);
@@ -320,15 +572,7 @@ void sched_loop(br_server* S) {
         }
         // admit the head (FIFO)
         S->queue.pop_front();
-        const int64_t after = held_after(*sl, *r);
-        S->in_use += after - sl->held;
-        sl->held = after;
-        S->peak_in_use = std::max(S->peak_in_use, S->in_use);
-        sl->job = r;
-        if (S->inflight == 0) S->busy_start = Clock::now();
-        S->inflight++;
-        S->peak_inflight = std::max(S->peak_inflight, S->inflight);
-        S->cv_slot.notify_all();
+        admit_slot(S, sl, std::move(r));
     }
 }
 
@@ -396,8 +640,30 @@ int br_server_create(br_server** out, int device, int64_t mem_budget, int32_t ma
         }
         S->slots.push_back(std::move(sl));
     }
+    for (int i = 0; i < kLaneWorkers; i++) {
+        auto L = std::make_unique<LaneWorker>();
+        int rc = br_create(&L->ctx, device);
+        if (rc == BR_OK && hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking) != hipSuccess)
+            rc = hip_fail(hipGetLastError(), "hipStreamCreate");
+        if (rc) {
+            if (L->ctx) br_destroy(L->ctx);
+            for (auto& l : S->lanes) {
+                (void)hipStreamDestroy(l->stream);
+                br_destroy(l->ctx);
+            }
+            for (auto& s : S->slots) {
+                (void)hipStreamDestroy(s->stream);
+                br_destroy(s->ctx);
+            }
+            return rc;
+        }
+        S->lanes.push_back(std::move(L));
+    }
+    S->lane_max_v = batched_max_v_big();
+    S->lane_max_e = kLaneMaxEdges;
     br_server* raw = S.release();
     for (auto& sl : raw->slots) sl->th = std::thread(slot_loop, raw, sl.get());
+    for (auto& l : raw->lanes) l->th = std::thread(lane_loop, raw, l.get());
     raw->sched = std::thread(sched_loop, raw);
     *out = raw;
     return BR_OK;
@@ -405,10 +671,19 @@ int br_server_create(br_server** out, int device, int64_t mem_budget, int32_t ma
 
 static int submit_common(br_server* S, std::shared_ptr<Request> r, uint64_t* ticket, bool host) {
     r->M = choose_m(r->E, r->V);
-    charge(*r, host, 1, S->device);   // the larger of the two final steps' needs
-    if (r->ws_bytes + r->buf_bytes > S->budget)
-        return fail(BR_ENOMEM, "server: request needs %lld bytes, budget is %lld",
-                    (long long)(r->ws_bytes + r->buf_bytes), (long long)S->budget);
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        r->lane = lane_fits(S, *r);
+    }
+    int64_t need = 0;
+    if (r->lane) {
+        need = lane_need(*r);
+    } else {
+        charge(*r, host, 1, S->device);   // the larger of the two final steps' needs
+        need = r->ws_bytes + r->buf_bytes;
+    }
+    if (need > S->budget)
+        return fail(BR_ENOMEM, "server: request needs %lld bytes, budget is %lld", (long long)need, (long long)S->budget);
     return enqueue(S, std::move(r), ticket);
 }
 
@@ -476,14 +751,27 @@ int br_server_stats(br_server* S, br_server_stats_t* out, int reset) {
     out->peak_inflight = S->peak_inflight;
     out->device_bytes = S->in_use;
     out->peak_device_bytes = S->peak_in_use;
+    out->batched_ticks = S->ticks;
+    out->batched_requests = S->lane_requests;
     if (reset) {
         S->lat.clear();
         S->edges_done = 0;
         S->busy_ms = 0;
         S->peak_inflight = S->inflight;
         S->peak_in_use = S->in_use;
+        S->ticks = 0;
+        S->lane_requests = 0;
         if (S->inflight > 0) S->busy_start = Clock::now();
     }
+    return BR_OK;
+}
+
+int br_server_set_batching(br_server* S, int32_t max_v, int64_t max_e) {
+    if (!S || max_v < 0 || max_v > batched_max_v_big() || max_e < 0)
+        return fail(BR_EINVAL, "br_server_set_batching: need 0 <= max_v <= %d and max_e >= 0", (int)batched_max_v_big());
+    std::lock_guard<std::mutex> g(S->mu);
+    S->lane_max_v = max_v;    // taken by each request when it is submitted
+    S->lane_max_e = max_e;
     return BR_OK;
 }
 
@@ -504,7 +792,15 @@ int br_server_destroy(br_server* S) {
     }
     S->cv_sched.notify_all();
     S->cv_slot.notify_all();
+    S->cv_lane.notify_all();
     if (S->sched.joinable()) S->sched.join();
+    for (auto& l : S->lanes) {
+        if (l->th.joinable()) l->th.join();
+        (void)hipStreamSynchronize(l->stream);
+        (void)hipStreamDestroy(l->stream);
+        if (l->buf) (void)hipFree(l->buf);
+        br_destroy(l->ctx);
+    }
     for (auto& sl : S->slots) {
         if (sl->th.joinable()) sl->th.join();
         if (sl->stream) (void)hipStreamDestroy(sl->stream);

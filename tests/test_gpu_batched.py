@@ -132,3 +132,32 @@ def test_batched_host_search(ctx):
         check_all(ctx, full.edges, full.offsets, full.V, 0)
     finally:
         ctx.set_final_step(1)
+
+
+@pytest.mark.parametrize("final_step", [1, 0], ids=["gpu_final_step", "host_search"])
+def test_medium_class_in_the_160kb_kernel(ctx, final_step):
+    # graphs above the small kernel's 4,096 vertices and up to the 160 KB
+    # kernel's 40,944 run in the same call (their final step: one bridge step
+    # over the union of their certificates); beyond that, the plain path
+    import paper_2108_07346_amd as br
+    big = br.lds_max_v()
+    assert big == 40944
+    graphs = []
+    for k, V in enumerate([4096, 4097, 6000, 100, 17000, big, big + 1, 300, 25000, 4097]):
+        kk = max(2, V // 500)
+        g = graphgen.planted(900 + k, k=kk, vc=V - 10, p=min(1.0, 24.0 / max(V / kk, 2)), n_extra=1, n_pend=10)
+        assert g.V == V
+        graphs.append((g.edges, V))
+    graphs.append((np.zeros((0, 2), np.int32), 5000))                       # medium class, no edges
+    rng = np.random.default_rng(9)
+    graphs.append((rng.integers(0, 30000, size=(60000, 2)).astype(np.int32), 30000))   # many bridges, multigraph
+    e, off, Vs = pack(graphs)
+    ctx.set_final_step(final_step)
+    try:
+        for chunk in (8192, 0):
+            say("medium class final step %d chunk %d: %d graphs, %d edges" % (final_step, chunk, len(Vs), e.shape[0]))
+            pairs, boff = check_all(ctx, e, off, Vs, chunk)
+            pairs2, boff2 = check_all(ctx, e, off, Vs, chunk)          # replayed graph, same answers
+            assert np.array_equal(pairs, pairs2) and np.array_equal(boff, boff2)
+    finally:
+        ctx.set_final_step(1)

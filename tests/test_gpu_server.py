@@ -168,12 +168,14 @@ def test_tight_budget_releases_idle_slots(br):
     a = graphgen.planted(11, k=8, vc=40000, p=0.05, n_pend=20)
     b = graphgen.planted(12, k=8, vc=40000, p=0.05, n_pend=20)
     srv0 = br.Server(0, mem_budget=64 << 30, max_slots=1)
+    srv0.set_batching(0)                     # both requests on slots
     ta = srv0.submit(a.edges, a.V)
     srv0.wait(ta, a.V)
     one = srv0.stats()["peak_device_bytes"]
     srv0.close()
     budget = int(one * 1.5)
     srv = br.Server(0, mem_budget=budget, max_slots=2)
+    srv.set_batching(0)
     for rep in range(3):
         ta = srv.submit(a.edges, a.V)
         tb = srv.submit(b.edges, b.V)        # may run while a's slot still holds its buffers
@@ -182,4 +184,101 @@ def test_tight_budget_releases_idle_slots(br):
     st = srv.stats()
     srv.close()
     say("tight budget: one request holds %d bytes, budget %d, peak held %d" % (one, budget, st["peak_device_bytes"]))
+    assert 0 < st["peak_device_bytes"] <= budget
+
+
+def small_burst(n, seed):
+    # small requests (V 16..3000) that the batch lane serves many per tick
+    rng = np.random.default_rng(seed)
+    out = []
+    for r in range(n):
+        V = int(np.exp(rng.uniform(np.log(16), np.log(3000))))
+        k = max(2, V // 64)
+        g = graphgen.planted(seed * 10000 + r, k=k, vc=V, p=min(1.0, 10.0 / max(V / k, 2)),
+                             n_extra=1, n_pend=max(1, V // 50))
+        out.append((g.edges, g.V))
+    return out
+
+
+def test_batch_lane_serves_many_requests_per_tick(br):
+    reqs = small_burst(400, seed=21)
+    srv = br.Server(0, mem_budget=8 << 30, max_slots=4)
+    dev = [torch.from_numpy(e).cuda() for e, _ in reqs]
+    torch.cuda.synchronize()
+    tickets = [srv.submit(dev[i] if i % 3 == 0 else e, V) for i, (e, V) in enumerate(reqs)]
+    got = [srv.wait(t, V) for t, (_, V) in zip(tickets, reqs)]
+    st = srv.stats()
+    srv.close()
+    say("batch lane: %d requests in %d ticks, p50 %.2f ms" % (st["batched_requests"], st["batched_ticks"], st["p50_ms"]))
+    assert st["completed"] == len(reqs)
+    # a burst keeps the slots busy, so most requests collect in the lane and
+    # several share a tick
+    assert st["batched_requests"] >= len(reqs) // 2
+    assert st["batched_ticks"] < st["batched_requests"]
+    for (e, V), g in zip(reqs, got):
+        assert np.array_equal(g, oracle.bridges(e, V))
+
+
+def test_batch_lane_isolates_a_bad_request(br):
+    # a request with an id out of range fails alone; the others of its tick
+    # are answered
+    reqs = small_burst(60, seed=22)
+    srv = br.Server(0, mem_budget=8 << 30, max_slots=2)
+    tickets = []
+    for i, (e, V) in enumerate(reqs):
+        tickets.append(srv.submit(e, V))
+        if i == 30:
+            t_bad = srv.submit(np.array([[0, 1], [1, 7]], np.int32), 4)
+    for t, (e, V) in zip(tickets, reqs):
+        assert np.array_equal(srv.wait(t, V), oracle.bridges(e, V))
+    with pytest.raises(br.BridgeError) as ei:
+        srv.wait(t_bad, 4)
+    assert ei.value.code == br.BR_ERANGE
+    srv.close()
+
+
+@pytest.mark.parametrize("final_step", [1, 0], ids=["gpu_final_step", "host_search"])
+def test_batching_limits(br, final_step):
+    # with batching off, or limits no request meets, nothing joins the lane;
+    # with the default limits a burst does; every answer is the oracle's, and
+    # limits outside their ranges are refused
+    reqs = request_mix(40, seed=9)
+    srv = br.Server(0, mem_budget=8 << 30, max_slots=4)
+    srv.set_final_step(final_step)
+    for bad in ((br.lds_max_v() + 1, 1 << 21), (-1, 1 << 21), (1000, -1)):
+        with pytest.raises(br.BridgeError) as ei:
+            srv.set_batching(*bad)
+        assert ei.value.code == br.BR_EINVAL
+    got = []
+    for limits in ((0, 1 << 21), (br.lds_max_v(), 1)):
+        srv.set_batching(*limits)
+        tickets = [srv.submit(e, V) for e, V in reqs[:20]]
+        got += [srv.wait(t, V) for t, (_, V) in zip(tickets, reqs[:20])]
+        assert srv.stats(reset=True)["batched_requests"] == 0
+    srv.set_batching(br.lds_max_v(), 1 << 30)
+    eligible = sum(1 for _, V in reqs[20:] if V <= br.lds_max_v())
+    tickets = [srv.submit(e, V) for e, V in reqs[20:]]
+    got += [srv.wait(t, V) for t, (_, V) in zip(tickets, reqs[20:])]
+    st = srv.stats()
+    srv.close()
+    assert st["batched_requests"] <= eligible
+    want = [oracle.bridges(e, V) for e, V in reqs[:20]] * 2 + [oracle.bridges(e, V) for e, V in reqs[20:]]
+    for g, w in zip(got, want):
+        assert np.array_equal(g, w)
+
+
+def test_batch_lane_under_a_tight_budget(br):
+    # lane requests are charged an upper bound of their share of a tick until
+    # it completes, and what the lane keeps between ticks stays charged: under
+    # a budget a few requests wide, every answer is right and the charge never
+    # passes the budget
+    reqs = small_burst(120, seed=23)
+    budget = 64 << 20
+    srv = br.Server(0, mem_budget=budget, max_slots=2)
+    tickets = [srv.submit(e, V) for e, V in reqs]
+    for t, (e, V) in zip(tickets, reqs):
+        assert np.array_equal(srv.wait(t, V), oracle.bridges(e, V))
+    st = srv.stats()
+    srv.close()
+    say("lane, budget %d: peak charged %d, %d ticks" % (budget, st["peak_device_bytes"], st["batched_ticks"]))
     assert 0 < st["peak_device_bytes"] <= budget

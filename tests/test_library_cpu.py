@@ -40,6 +40,26 @@ def test_null_and_bad_arguments_rejected_without_a_device():
     assert lib.br_destroy(None) == br.BR_OK
 
 
+def test_final_step_v_limit_is_two_to_the_29():
+    # the calls that run a final step refuse V above 2^29 before touching the
+    # context (so the check is visible without a device); at 2^29 itself the
+    # next check (the null context) is the one that fires
+    lib = br.load()
+    n = ctypes.c_int64(0)
+    for V, word in (((1 << 29) + 1, b"2^29"), (1 << 29, b"null"), (2147483647, b"2^29")):
+        assert lib.br_bridges_find(None, None, 0, V, 1, None, 0, ctypes.byref(n), None) == br.BR_EINVAL
+        assert word in lib.br_last_error()
+        assert lib.br_two_edge_components(None, None, 0, V, 1, None, None, None) == br.BR_EINVAL
+        assert word in lib.br_last_error()
+        assert lib.br_bridge_tree(None, None, 0, V, 1, None, None, 0, None, None, None) == br.BR_EINVAL
+        assert word in lib.br_last_error()
+        assert lib.br_articulation_points(None, None, 0, V, None, 0, ctypes.byref(n), None) == br.BR_EINVAL
+        assert word in lib.br_last_error()
+    # the certificate calls take any V up to 2^31 - 1 (null context here)
+    assert lib.br_cert_build(None, None, 0, 2147483647, 1, None, 0, None, None) == br.BR_EINVAL
+    assert b"null" in lib.br_last_error()
+
+
 def test_create_fails_cleanly_without_gpu():
     torch = pytest.importorskip("torch")
     if torch.cuda.is_available():
