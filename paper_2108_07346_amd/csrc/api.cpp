@@ -123,21 +123,22 @@ Plan make_plan(int64_t E, int32_t V, int32_t M, bool allow_solo, const TuneEntry
         (want == 1 || (want < 0 && M >= cus && per <= (int64_t)V && V >= (1 << 17)))) {
         P.solo = true;
         P.solo_variant = std::max(0, std::min(knob("BR_SOLO_VARIANT", "variant", 2), solo_variants() - 1));
-        // 1024 threads per CU, as many workers as that takes where their LDS
-        // bitmaps fit side by side
-        const int per_cu = std::max(1, 1024 / solo_block(P.solo_variant));
-        const int fit = std::max<int>(1, (int)std::min<size_t>(per_cu, (size_t)g_max_lds / solo_lds_bytes(V)));
+        // 1,024 threads of workers per CU where registers and LDS hold them
+        // (large workload, M = 4096: 64 → 256 workers of 1,024 threads
+        // 276 → 149 ms, but 768 workers of 512 threads slower than 512)
+        const int fit = std::min(solo_blocks_per_cu(P.solo_variant, V), std::max(1, 1024 / solo_block(P.solo_variant)));
         const int wpc = std::max(1, std::min(knob("BR_SOLO_WPC", "wpc", fit), fit));
-        // fewer workers than CUs keep fewer chunk states live at once (more
-        // of them in the caches)
-        P.workers = std::max(1, std::min(knob("BR_SOLO_WORKERS", "workers", cus * wpc), cus * wpc));
+        // every worker needs a slot of 8 V bytes; all slots within 8 GiB
+        const int64_t max_slots = std::max<int64_t>(1, (int64_t(8) << 30) / (8 * (int64_t)V));
+        P.workers = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)knob("BR_SOLO_WORKERS", "workers", cus * wpc),
+                                                                  (int64_t)cus * wpc, max_slots}));
         // merge levels inside the kernel while they still hold four merges
         // per worker (measured on the large workload at M = 4096: two levels
         // 193 ms, three 206 ms, four 203 ms, five 210 ms)
         int top = 0;
         while (top < P.rounds && (int64_t)(M >> (top + 1)) >= 4 * (int64_t)P.workers) top++;
         P.solo_top = std::max(0, std::min(P.rounds, knob("BR_SOLO_TOP", "top", top)));
-        P.nslots = 3 * P.workers;
+        P.nslots = (int)std::min<int64_t>(3 * (int64_t)P.workers, max_slots);
         P.qs = 2;
     }
     return P;
@@ -849,22 +850,24 @@ int br_autotune(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int32_t
     int source = 0;   // 0: from the cache, 1: measured now
     if (!tune_get(key, best)) {
         source = 1;
-        // candidate plans: the team path with three first-stage tiles, and
-        // (where its bitmaps fit) the one-workgroup-per-node path in each
-        // worker shape with three merge depths
+        // candidate plans: the team path with three first-stage tiles, the
+        // whole-tree LDS kernel where V fits, and the one-workgroup-per-node
+        // path in each worker shape with the merge depths around its default
+        // (and depths 1 and 2)
         std::vector<TuneEntry> cands;
         for (int tile : {4096, 2048, 1024}) cands.push_back({{"lds", 0}, {"solo", 0}, {"tile", tile}});
         if (E > 0 && V <= batched_max_v_big() && M < (1 << 20)) cands.push_back({{"lds", 1}});
         if (E > 0 && V <= solo_max_v()) {
             const Plan d = make_plan(E, V, M, true, nullptr);
-            TuneEntry on{{"lds", 0}, {"solo", 1}};
-            const Plan ds = make_plan(E, V, M, true, &on);
-            for (int v = 0; v < solo_variants(); v++)
-                for (int dt : {-1, 0, 1}) {
-                    const int top = ds.solo_top + dt;
-                    if (top < 0 || top > d.rounds) continue;
-                    cands.push_back({{"lds", 0}, {"solo", 1}, {"variant", v}, {"top", top}});
-                }
+            for (int v = 0; v < solo_variants(); v++) {
+                TuneEntry on{{"lds", 0}, {"solo", 1}, {"variant", v}};
+                const Plan dv = make_plan(E, V, M, true, &on);
+                std::vector<int> tops;
+                for (int top : {dv.solo_top - 1, dv.solo_top, dv.solo_top + 1, 1, 2})
+                    if (top >= 0 && top <= d.rounds && std::find(tops.begin(), tops.end(), top) == tops.end())
+                        tops.push_back(top);
+                for (int top : tops) cands.push_back({{"lds", 0}, {"solo", 1}, {"variant", v}, {"top", top}});
+            }
         }
         double best_ms = 1e30;
         BR_HIP(hipEventSynchronize(c->ev[7]));

@@ -147,6 +147,7 @@ struct SoloBufs {
 size_t solo_lds_bytes(int32_t V);
 int solo_prepare(int32_t V);       // once per process: the kernel's LDS limit
 int32_t solo_max_v();
+int solo_blocks_per_cu(int variant, int32_t V);
 int solo_block(int variant);       // threads per worker of a worker shape
 int solo_variants();
 void launch_solo(const Plan& P, const DevBufs& B, const SoloBufs& S, hipStream_t s);

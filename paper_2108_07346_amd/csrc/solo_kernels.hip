@@ -18,19 +18,25 @@
 // out).  Parents always have smaller ids than their children.
 //
 // Hooks without global atomics.  Only the owning workgroup touches a slot
-// while it works on it, so two lanes can race only within the workgroup: a
-// hook first sets the root's bit in a bitmap in LDS (one bit per vertex and
-// forest, cleared per task) and only the lane that sets it writes the root's
-// parent word, with a plain store.  The bit is the root test that cannot be
-// stale; a lane that finds the bit already set lost a race whose winner's
-// store it may not see yet, and retries the edge after the next barrier, when
-// every store of the workgroup is visible.  Lanes read parent words with plain
-// loads: a value, however stale, names a vertex of the same component with a
-// smaller id, so finds that meet prove the endpoints connected; and the root
-// a winning lane hooks is a root of a component other than the one of the
-// vertex it hooks it under (that vertex has the smaller id, and chains only
-// decrease).  So F is a maximal forest of the edges offered to it and F' of
-// the edges F rejected, as Algorithm 2 requires.
+// while it works on it, so two lanes can race only within the workgroup, and
+// only within one round: the lanes offer their edges, then meet at a barrier
+// after which every parent word the workgroup stored is visible to all of
+// them.  A hook first claims the root in a claim table in LDS (one table per
+// forest, a bit per root hashed by its low bits, emptied at every barrier by
+// the lanes that set its bits),
+// and only the lane whose claim sets the bit writes the root's parent word,
+// with a plain store.  A root hooked in an earlier round is no root to any
+// finds of this round (its word is visible); two lanes that reach the same
+// root in this round meet at its bit; a lane whose claim finds the bit set
+// (that root, or another that shares its bit) retries the edge after the
+// barrier.  Lanes read parent words with plain loads: a value, however stale,
+// names a vertex of the same component with a smaller id, so finds that meet
+// prove the endpoints connected; and the root a winning lane hooks is a root
+// of a component other than the one of the vertex it hooks it under (that
+// vertex has the smaller id, and chains only decrease).  So F is a maximal
+// forest of the edges offered to it and F' of the edges F rejected, as
+// Algorithm 2 requires.  The tables are a few KB, so several workers share a
+// CU whatever V is.
 //
 // Slots change hands between workers only through the free pool and the
 // parking table; whoever gives a slot away first makes its writes visible
@@ -67,7 +73,7 @@ struct SoloArgs {
     int32_t ob;                     // bits of the offset field of a state word
     int32_t top;                    // merges of levels 1..top run here
     int32_t nslots;
-    int32_t bm_words;               // words of one LDS bitmap
+    int32_t bm_words;               // words of one LDS claim table (a power of two)
     uint32_t* slots;                // [nslots][2][V]
     uint32_t* slot_tag;             // [nslots] current tag of each slot (kept across calls)
     uint32_t* pool;                 // [ceil(nslots / 32)] bit set = slot free
@@ -85,6 +91,7 @@ struct SoloArgs {
 struct St {
     uint32_t* q;                    // slot base: F at q[x], F' at q[V + x]
     uint32_t V, tag, ob, mask;
+    uint32_t cmask;                 // claim-table bits - 1
     // x - parent(x) from x's word; a word of another tag, or one that could
     // not belong to x, reads as a root
     __device__ __forceinline__ uint32_t off(uint32_t w, uint32_t x) const {
@@ -137,10 +144,20 @@ __device__ __forceinline__ void emit(SoloLds& L, const SoloArgs& A, int64_t off,
 }
 
 // Barrier for the whole workgroup (global and LDS stores before it are
-// visible after it) that also tells every lane whether any lane had p set.
-__device__ __forceinline__ bool block_any(SoloLds& L, bool p, int& ph) {
+// visible after it) that also tells every lane whether any lane had p set,
+// and empties the claim tables for the next round: every set bit has exactly
+// one winner, which clears it (bits c1[j] of table t1 for j in mask w1, and
+// c2/t2/w2 likewise).
+template <int kSU>
+__device__ __forceinline__ bool block_any(SoloLds& L, bool p, int& ph, uint32_t* t1, const uint32_t (&c1)[kSU],
+                                          uint32_t w1, uint32_t* t2, const uint32_t (&c2)[kSU], uint32_t w2) {
     __syncthreads();
     if (p) L.flag[ph] = 1u;
+#pragma unroll
+    for (int j = 0; j < kSU; j++) {
+        if (w1 >> j & 1) atomicAnd(&t1[c1[j] >> 5], ~(1u << (c1[j] & 31)));
+        if (w2 >> j & 1) atomicAnd(&t2[c2[j] >> 5], ~(1u << (c2[j] & 31)));
+    }
     __syncthreads();
     const bool any = L.flag[ph] != 0;
     if (threadIdx.x == 0) L.flag[ph ^ 1] = 0u;
@@ -157,7 +174,7 @@ __device__ __forceinline__ bool block_any(SoloLds& L, bool p, int& ph) {
 // a root (won), that lost a root to another lane (lost: retry later).
 template <int F, int kSU>
 __device__ __forceinline__ void bunite(const St& S, uint32_t* bm, const uint32_t (&u)[kSU], const uint32_t (&v)[kSU],
-                                       uint32_t m, uint32_t& same, uint32_t& won, uint32_t& lost) {
+                                       uint32_t m, uint32_t& same, uint32_t& won, uint32_t& lost, uint32_t (&cl)[kSU]) {
     uint32_t* q = S.q + (F ? S.V : 0u);
     uint32_t a[kSU], b[kSU], wa[kSU], wb[kSU];
 #pragma unroll
@@ -196,8 +213,10 @@ __device__ __forceinline__ void bunite(const St& S, uint32_t* bm, const uint32_t
             }
             if (x != y) {
                 const uint32_t hi = max(x, y), lo = min(x, y);
-                const uint32_t bit = 1u << (hi & 31);
-                r = (atomicOr(&bm[hi >> 5], bit) & bit) ? 2u : 1u;
+                const uint32_t c = hi & S.cmask;       // the root's claim bit
+                const uint32_t bit = 1u << (c & 31);
+                r = (atomicOr(&bm[c >> 5], bit) & bit) ? 2u : 1u;
+                cl[j] = c;
                 if (r == 1) sst(q + hi, S.word(hi - lo));
             }
         }
@@ -263,19 +282,20 @@ __device__ void stream(SoloLds& L, const SoloArgs& A, const St& S, uint32_t* bm1
                 else atomicOr(A.err, src == 0 ? 1u : 2u);
             }
         }
+        uint32_t c1[kSU], c2[kSU];                         // claim bits this lane set
         for (;;) {
             uint32_t same = 0, won1 = 0, won2 = 0, lost = 0;
             const uint32_t m1 = pend & ~st1;
             if (m1) {
                 uint32_t l1 = 0;
-                bunite<0, kSU>(S, bm1, u, v, m1, same, won1, l1);
+                bunite<0, kSU>(S, bm1, u, v, m1, same, won1, l1, c1);
                 lost |= l1;
                 st1 |= same;                    // F rejected them: on to F'
             }
             const uint32_t m2 = pend & st1;
             if (m2) {
                 uint32_t s2 = 0, l2 = 0;
-                bunite<1, kSU>(S, bm2, u, v, m2, s2, won2, l2);
+                bunite<1, kSU>(S, bm2, u, v, m2, s2, won2, l2, c2);
                 lost |= l2;
             }
             if (out) {
@@ -285,7 +305,7 @@ __device__ void stream(SoloLds& L, const SoloArgs& A, const St& S, uint32_t* bm1
                          make_int2((int32_t)u[j], (int32_t)v[j]));
             }
             pend = lost;
-            if (!block_any(L, pend != 0, ph)) break;
+            if (!block_any<kSU>(L, pend != 0, ph, bm1, c1, won1, bm2, c2, won2)) break;
         }
     }
 }
@@ -346,7 +366,7 @@ __global__ void __launch_bounds__(kSB) k_solo(SoloArgs A) {
             L.n1 = L.n2 = 0;
         }
         __syncthreads();
-        St S{A.slots + (size_t)L.slot * 2 * V, V, L.tag, (uint32_t)A.ob, mask};
+        St S{A.slots + (size_t)L.slot * 2 * V, V, L.tag, (uint32_t)A.ob, mask, 32u * (uint32_t)A.bm_words - 1u};
         if (L.act == 1)         // tags ran out: every word back to "root"
             for (uint32_t x = threadIdx.x; x < 2 * V; x += kSB) S.q[x] = 0u;
         for (int x = threadIdx.x; x < 2 * A.bm_words; x += kSB) bm1[x] = 0u;
@@ -476,7 +496,15 @@ __global__ void k_solo_init(uint32_t* pool, int32_t nslots, int32_t first_free, 
 }
 }  // namespace
 
-size_t solo_lds_bytes(int32_t V) { return sizeof(SoloLds) + 2 * 4 * (size_t)((V + 31) / 32); }
+// Claim-table words per forest: V bits rounded up to a power of two, at most
+// 2^18 bits (32 KB); a larger V shares bits between roots.
+static int32_t claim_words(int32_t V) {
+    int64_t bits = 32;
+    while (bits < (int64_t)V && bits < (int64_t(1) << 18)) bits <<= 1;
+    return (int32_t)(bits / 32);
+}
+
+size_t solo_lds_bytes(int32_t V) { return sizeof(SoloLds) + 2 * 4 * (size_t)claim_words(V); }
 
 // Worker shapes: (threads, edges per thread offered together), chosen per
 // plan (the tuner measures them).
@@ -524,7 +552,7 @@ void launch_solo(const Plan& P, const DevBufs& B, const SoloBufs& Sb, hipStream_
     A.ob = ob;
     A.top = P.solo_top;
     A.nslots = Sb.nslots;
-    A.bm_words = (P.V + 31) / 32;
+    A.bm_words = claim_words(P.V);
     A.slots = Sb.slots;
     A.slot_tag = Sb.slot_tag;
     A.pool = Sb.pool;
@@ -542,10 +570,19 @@ void launch_solo(const Plan& P, const DevBufs& B, const SoloBufs& Sb, hipStream_
     (void)hipLaunchKernel(k.fn, dim3((unsigned)Sb.workers), dim3(k.sb), args, solo_lds_bytes(P.V), s);
 }
 
-// largest V whose two LDS bitmaps fit next to the deferred-edge buffers
-int32_t solo_max_v() {
-    const int64_t room = (int64_t)g_max_lds - (int64_t)sizeof(SoloLds);
-    return room <= 0 ? 0 : (int32_t)std::min<int64_t>(INT32_MAX, room / 8 * 32);
+// largest V of the plan (the slots hold 8 V bytes each)
+int32_t solo_max_v() { return 1 << 24; }
+
+// workgroups of the variant that fit on one CU with the LDS V needs
+int solo_blocks_per_cu(int variant, int32_t V) {
+    const SoloVariant& k = kVariants[std::max(0, std::min(variant, solo_variants() - 1))];
+    int n = 0;
+    if (solo_prepare(V) != BR_OK ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k.fn, k.sb, solo_lds_bytes(V)) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return std::max(1, n);
 }
 
 }  // namespace br

@@ -70,18 +70,20 @@ def test_tuned_choice_reloaded_by_a_later_process(tmp_path):
 
 def test_every_tuner_candidate_is_exact():
     # each plan the tuner may pick gives the oracle's bridges (dense, large-state
-    # random graph)
+    # random graph); the second graph has more vertices than the solo kernel's
+    # claim tables have bits, so roots share claim bits
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    import paper_2108_07346_amd as br
-    ctx = br.Context(0)
     rng = np.random.default_rng(31)
+    cases = []
     V = 150_000
     e = rng.integers(0, V, size=(600_000, 2)).astype(np.int32)
-    want = oracle.bridges(e, V)
-    d = torch.from_numpy(e).cuda()
-    envs = [{"BR_SOLO": "0", "BR_TILE0": "1024"}] + \
-           [{"BR_SOLO": "1", "BR_SOLO_VARIANT": str(v), "BR_SOLO_TOP": str(t)} for v in range(4) for t in (0, 3)]
+    cases.append((e, V, 256, [{"BR_SOLO": "0", "BR_TILE0": "1024"}] +
+                  [{"BR_SOLO": "1", "BR_SOLO_VARIANT": str(v), "BR_SOLO_TOP": str(t)} for v in range(4) for t in (0, 3)]))
+    V2 = 700_000
+    e2 = rng.integers(0, V2, size=(1_400_000, 2)).astype(np.int32)
+    cases.append((e2, V2, 512, [{"BR_SOLO": "1", "BR_SOLO_VARIANT": str(v), "BR_SOLO_TOP": str(t)}
+                                for v in (0, 2) for t in (0, 2)]))
     code = r"""
 import os, sys
 sys.path.insert(0, %r)
@@ -89,17 +91,19 @@ import numpy as np, torch
 import paper_2108_07346_amd as br
 e = np.load(sys.argv[1])
 ctx = br.Context(0)
-got = ctx.find(torch.from_numpy(e).cuda(), %d, 256)
+got = ctx.find(torch.from_numpy(e).cuda(), int(sys.argv[3]), int(sys.argv[4]))
 np.save(sys.argv[2], got)
-""" % (ROOT, V)
+""" % (ROOT,)
     import tempfile
     with tempfile.TemporaryDirectory() as td:
-        ein = os.path.join(td, "e.npy")
-        np.save(ein, e)
-        for k, env in enumerate(envs):
-            out = os.path.join(td, "o%d.npy" % k)
-            r = subprocess.run([sys.executable, "-u", "-c", code, ein, out], env=dict(os.environ, **env),
-                               capture_output=True, text=True, timeout=300)
-            assert r.returncode == 0, (env, r.stderr[-1500:])
-            assert np.array_equal(np.load(out), want), env
-            print("candidate", env, "exact", flush=True)
+        for ci, (e, V, M, envs) in enumerate(cases):
+            want = oracle.bridges(e, V)
+            ein = os.path.join(td, "e%d.npy" % ci)
+            np.save(ein, e)
+            for k, env in enumerate(envs):
+                out = os.path.join(td, "o%d_%d.npy" % (ci, k))
+                r = subprocess.run([sys.executable, "-u", "-c", code, ein, out, str(V), str(M)],
+                                   env=dict(os.environ, **env), capture_output=True, text=True, timeout=300)
+                assert r.returncode == 0, (env, r.stderr[-1500:])
+                assert np.array_equal(np.load(out), want), (V, env)
+                print("V", V, "candidate", env, "exact", flush=True)
