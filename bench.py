@@ -411,7 +411,7 @@ def bench_served(args):
     dev = [torch.from_numpy(g.edges).cuda() for g in pool] if args.resident else None
     torch.cuda.synchronize()
     results = {}
-    qps = args.qps or ("100,200,500,1000,2000" if args.mix == "served" else "1000,5000,20000")
+    qps = args.qps or ("100,200,500,1000,2000,5000" if args.mix == "served" else "1000,5000,20000,50000")
     qps_list = [float(x) for x in qps.split(",")]
     servers = (("batch_lane", args.slots, True), ("slots_only", args.slots, False), ("per_request", 1, False))
 

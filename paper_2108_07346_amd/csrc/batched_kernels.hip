@@ -449,6 +449,28 @@ void launch_batched(const BatchDev& B, int blocks, hipStream_t s, bool big) {
 
 int32_t batched_max_v_dev() { return kMaxV; }
 int32_t batched_max_v_big() { return kMaxVBig; }
+
+namespace {
+// Gather of several device edge lists into one packed buffer: item x copies
+// items[x].n edges from items[x].src to dst + items[x].at, the blocks of
+// column y taking runs y, y + gridDim.y, ... of kGatherRun edges.
+constexpr int64_t kGatherRun = 16384;
+__global__ void __launch_bounds__(256) k_gather_edges(const GatherItem* items, int2* dst) {
+    const GatherItem it = items[blockIdx.x];
+    const int2* src = reinterpret_cast<const int2*>(it.src);
+    for (int64_t lo = blockIdx.y * kGatherRun; lo < it.n; lo += (int64_t)gridDim.y * kGatherRun) {
+        const int64_t hi = min(lo + kGatherRun, it.n);
+        for (int64_t k = lo + threadIdx.x; k < hi; k += 256) dst[it.at + k] = src[k];
+    }
+}
+}  // namespace
+
+void launch_gather_edges(const GatherItem* d_items, int32_t n, int64_t max_edges, int32_t* dst, hipStream_t s) {
+    if (n <= 0 || max_edges <= 0) return;
+    const int64_t runs = std::min<int64_t>((max_edges + kGatherRun - 1) / kGatherRun, 1024);
+    hipLaunchKernelGGL(k_gather_edges, dim3((unsigned)n, (unsigned)runs), dim3(256), 0, s, d_items,
+                       reinterpret_cast<int2*>(dst));
+}
 int32_t batched_blocks_per_cu() { return 3; }
 // workgroups of the small kernel that fit one CU's LDS together
 int32_t batched_max_blocks_per_cu() {

@@ -106,6 +106,8 @@ struct Plan {
     bool solo = false;
     int32_t solo_top = 0;
     int32_t solo_variant = 0;      // worker shape (solo_kernels.hip)
+    bool prem = false;             // team merges: each thread's edges of a tile requested at once
+    int32_t solo_cmp = 16;         // phase 0 compresses its slot after every cmp * V / 8 edges (then 8 V)
     int32_t workers = 0;           // persistent workgroups
     int32_t nslots = 0;            // union-find slots (workers' own + free pool)
     int32_t tile0_max = 0;         // team path: largest first-stage tile (0 = the kernel's)
@@ -186,6 +188,14 @@ int32_t batched_max_v_big();
 // node-0 certificates of the batch's graphs 0..S-1 as one certificate of their
 // disjoint union (ids shifted by vbase): F edges at f1u, F' edges at f2u,
 // their numbers at cntu[0], cntu[1]; uoff [2S] scratch
+// one device edge list to gather: n edges from src to edge offset `at`
+struct GatherItem {
+    const int32_t* src;
+    int64_t at, n;
+};
+// copies every item's edges into dst in one launch (items in device memory;
+// max_edges = the largest n)
+void launch_gather_edges(const GatherItem* d_items, int32_t n, int64_t max_edges, int32_t* dst, hipStream_t s);
 void launch_union_certificate(const BatchDev& B, int32_t S, int64_t* uoff, int2* f1u, int2* f2u, uint32_t* cntu,
                               hipStream_t s);
 // Final step on the device for the batched path: one workgroup per small graph

@@ -11,9 +11,10 @@
 //    kernels, without graph capture).  Two workers alternate, so one packs
 //    and finishes a tick on the host while the other's kernels run.
 // A lane-eligible request takes a free slot while the lane has nothing
-// queued (a lone request finishes sooner on the plain path); under load the
-// slots are busy and such requests collect in the lane, where the per-request
-// launch and synchronisation costs are paid once per tick.  Latency is
+// queued (a lone request finishes sooner on the plain path), and waits for
+// one while fewer requests wait than there are slots; beyond that backlog
+// such requests collect in the lane, where the per-request launch and
+// synchronisation costs are paid once per tick.  Latency is
 // stamped from submission to the moment the result is available.
 #include <algorithm>
 #include <chrono>
@@ -71,8 +72,10 @@ struct Slot {
 struct LaneWorker {
     br_ctx* ctx = nullptr;
     hipStream_t stream = nullptr;
-    void* buf = nullptr;
+    void* buf = nullptr;               // packed edges, then the gather table
     size_t cap = 0;
+    GatherItem* h_items = nullptr;     // pinned staging of the gather table
+    int32_t h_items_cap = 0;
     int64_t held = 0;                  // device bytes charged between ticks
     bool busy = false;                 // a tick is running
     bool trimming = false;             // its buffers are being released by the scheduler
@@ -318,7 +321,23 @@ int lane_run(LaneWorker& L, const std::vector<std::shared_ptr<Request>>& batch, 
         V[g] = batch[g]->V;
         room += std::max(V[g] - 1, 0);
     }
-    const size_t bytes = std::max<size_t>(8 * (size_t)eoff[G], 256);
+    int32_t ndev = 0;
+    for (int32_t g = 0; g < G; g++) ndev += (batch[g]->d_edges && batch[g]->E > 0) ? 1 : 0;
+    const size_t ebytes = (8 * (size_t)eoff[G] + 255) & ~size_t(255);
+    const size_t bytes = std::max<size_t>(ebytes + sizeof(GatherItem) * (size_t)ndev, 256);
+    if (ndev > L.h_items_cap) {
+        if (L.h_items) (void)hipHostFree(L.h_items);
+        L.h_items = nullptr;
+        L.h_items_cap = 0;
+        int32_t c = 64;
+        while (c < ndev) c *= 2;
+        if (hipHostMalloc(reinterpret_cast<void**>(&L.h_items), sizeof(GatherItem) * (size_t)c, hipHostMallocDefault) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            return fail(BR_ENOMEM, "server: pinned allocation failed");
+        }
+        L.h_items_cap = c;
+    }
     if (L.cap < bytes) {
         if (L.buf) (void)hipFree(L.buf);
         L.buf = nullptr;
@@ -330,16 +349,32 @@ int lane_run(LaneWorker& L, const std::vector<std::shared_ptr<Request>>& batch, 
         L.cap = bytes;
     }
     int32_t* d = static_cast<int32_t*>(L.buf);
+    // host sources: one upload each; device sources: one gather launch
+    int32_t k = 0;
+    int64_t longest = 0;
     for (int32_t g = 0; g < G; g++) {
         const Request& r = *batch[g];
         if (r.E == 0) continue;
-        const void* src = r.d_edges ? static_cast<const void*>(r.d_edges)
-                                    : r.pin ? r.pin : static_cast<const void*>(r.h_edges.data());
-        const hipMemcpyKind kind = r.d_edges ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-        if (hipMemcpyAsync(d + 2 * eoff[g], src, 8 * (size_t)r.E, kind, L.stream) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(BR_EHIP, "server: edge copy failed");
+        if (r.d_edges) {
+            L.h_items[k++] = GatherItem{r.d_edges, eoff[g], r.E};
+            longest = std::max(longest, r.E);
+            continue;
         }
+        const void* src = r.pin ? r.pin : static_cast<const void*>(r.h_edges.data());
+        if (hipMemcpyAsync(d + 2 * eoff[g], src, 8 * (size_t)r.E, hipMemcpyHostToDevice, L.stream) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(BR_EHIP, "server: edge upload failed");
+        }
+    }
+    if (k > 0) {
+        GatherItem* d_items = reinterpret_cast<GatherItem*>(static_cast<char*>(L.buf) + ebytes);
+        if (hipMemcpyAsync(d_items, L.h_items, sizeof(GatherItem) * (size_t)k, hipMemcpyHostToDevice, L.stream) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            return fail(BR_EHIP, "server: gather table upload failed");
+        }
+        launch_gather_edges(d_items, k, longest, d, L.stream);
+        if (hipGetLastError() != hipSuccess) return fail(BR_EHIP, "server: gather launch failed");
     }
     br_set_final_step(L.ctx, mode);
     std::vector<int32_t> out(2 * (size_t)std::max<int64_t>(room, 1));
@@ -528,6 +563,7 @@ void sched_loop(br_server* S) {
         r->mode = S->final_step;
         if (r->lane) {
             // a free slot that has room takes it while the lane has nothing queued
+            bool free_slot = false;
             if (S->lane_q.empty()) {
                 charge(*r, r->d_edges == nullptr, r->mode, S->device);
                 int64_t extra = 0;
@@ -537,6 +573,15 @@ void sched_loop(br_server* S) {
                     admit_slot(S, sl, std::move(r));
                     continue;
                 }
+                free_slot = sl != nullptr;
+            }
+            // no slot: the lane takes it once requests back up (as many
+            // waiting as there are slots); below that, waiting for a slot is
+            // quicker than a tick (small requests at 20k QPS: p50 0.49 ms on
+            // slots against 1.36 ms through the lane)
+            if (!free_slot && S->lane_q.empty() && S->queue.size() < S->slots.size() && S->inflight > 0) {
+                S->cv_sched.wait(g);
+                continue;
             }
             // the batch lane: charged its estimate until its tick completes
             const int64_t need = lane_need(*r);
@@ -799,6 +844,7 @@ int br_server_destroy(br_server* S) {
         (void)hipStreamSynchronize(l->stream);
         (void)hipStreamDestroy(l->stream);
         if (l->buf) (void)hipFree(l->buf);
+        if (l->h_items) (void)hipHostFree(l->h_items);
         br_destroy(l->ctx);
     }
     for (auto& sl : S->slots) {

@@ -74,6 +74,7 @@ struct SoloArgs {
     int32_t top;                    // merges of levels 1..top run here
     int32_t nslots;
     int32_t bm_words;               // words of one LDS claim table (a power of two)
+    int64_t cmp_first;              // phase 0: first full compression after this many edges
     uint32_t* slots;                // [nslots][2][V]
     uint32_t* slot_tag;             // [nslots] current tag of each slot (kept across calls)
     uint32_t* pool;                 // [ceil(nslots / 32)] bit set = slot free
@@ -246,7 +247,7 @@ __device__ void compress_slot(const St& S) {
 // src 1: a node region's certificate (F part [0, rn1), F' part after it).
 // stage0: where every edge starts (0: F, then F' if F rejects it; 1: F'
 // only).  out: write accepted edges to (off, cap).  stages: compress the slot
-// after 2V and 8V edges (phase 0 over long chunks).  Each thread takes kSU
+// every cmp_first edges up to 2V, then at 8V (phase 0).  Each thread takes kSU
 // edges of a tile and offers them together; edges that lost a race are
 // retried, after a barrier, until none is left.
 template <int kSB, int kSU>
@@ -254,7 +255,9 @@ __device__ void stream(SoloLds& L, const SoloArgs& A, const St& S, uint32_t* bm1
                        int64_t t1, int64_t roff, int64_t rcap, uint32_t rn1, uint32_t rn2, uint32_t stage0, bool out,
                        bool stages, int64_t off, int64_t cap, int& ph) {
     constexpr int64_t kST = (int64_t)kSB * kSU;      // edges per tile
-    int64_t next_cmp = stages ? t0 + 2 * (int64_t)S.V : INT64_MAX;
+    // phase 0: compress after cmp_first edges, then every cmp_first edges
+    // up to 2 V, then at 8 V
+    int64_t next_cmp = stages ? t0 + A.cmp_first : INT64_MAX;
     auto load = [&](int64_t i) -> int2 {
         if (src == 0) return i < A.split ? A.edges[i] : A.edges2[i - A.split];
         return A.cert[i < rn1 ? roff + i : roff + rcap - rn2 + (i - rn1)];
@@ -264,7 +267,9 @@ __device__ void stream(SoloLds& L, const SoloArgs& A, const St& S, uint32_t* bm1
             __syncthreads();
             compress_slot<kSB>(S);
             __syncthreads();
-            next_cmp = next_cmp == t0 + 2 * (int64_t)S.V ? t0 + 8 * (int64_t)S.V : INT64_MAX;
+            const int64_t done = next_cmp - t0;
+            next_cmp = done < 2 * (int64_t)S.V ? next_cmp + A.cmp_first
+                                                 : (done < 8 * (int64_t)S.V ? t0 + 8 * (int64_t)S.V : INT64_MAX);
         }
         uint32_t u[kSU], v[kSU];
         uint32_t pend = 0, st1 = stage0 ? 0xffffffffu : 0u;   // st1 bit j: edge j is past F
@@ -553,6 +558,7 @@ void launch_solo(const Plan& P, const DevBufs& B, const SoloBufs& Sb, hipStream_
     A.top = P.solo_top;
     A.nslots = Sb.nslots;
     A.bm_words = claim_words(P.V);
+    A.cmp_first = std::max<int64_t>(1024, (int64_t)P.solo_cmp * P.V / 8);
     A.slots = Sb.slots;
     A.slot_tag = Sb.slot_tag;
     A.pool = Sb.pool;
