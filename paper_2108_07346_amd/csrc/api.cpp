@@ -141,6 +141,13 @@ Plan make_plan(int64_t E, int32_t V, int32_t M, bool allow_solo, const TuneEntry
         P.solo_top = std::max(0, std::min(P.rounds, knob("BR_SOLO_TOP", "top", top)));
         P.nslots = (int)std::min<int64_t>(3 * (int64_t)P.workers, max_slots);
         P.solo_cmp = std::max(1, knob("BR_SOLO_CMP", "cmp", 16));
+        // phase 0 reads each chunk bucketed by (smaller endpoint / V/8,
+        // larger endpoint / V/128): large workload, M = 4096, merge level 1
+        // in the kernel: 190.0 ms per query in input order, 181.6 with 256
+        // buckets by the smaller endpoint, 175.2 with 1,024 by the larger,
+        // 173.8 / 170.5 / 169.7 with 4x64 / 4x256 / 8x128
+        P.solo_nbk = std::max(0, std::min(1024, knob("BR_SOLO_NBK", "nbk", 8)));
+        P.solo_nbk2 = std::max(1, knob("BR_SOLO_NBK2", "nbk2", 128));
         P.qs = 2;
     }
     return P;
@@ -195,11 +202,15 @@ int ensure_pinned(br_ctx* c, size_t bytes) {
 // solo: pool | park + arrivals | queue | dense node states | slot tags | slots |
 // bridge step]; everything before `cert` is cleared per call.
 struct Layout {
-    size_t err, cnt, state, packed, cert, off, cap, pool, park, queue, dense, tags, slots, lmeta, rootw, bws, total;
+    size_t err, cnt, state, packed, cert, off, cap, pool, park, queue, dense, tags, slots, sbuf, lmeta, rootw, bws,
+        total;
 };
 // the one-graph batch description of the LDS plan: eoff[2], then V, M,
 // rbase, cbase, vbase, n_items (one int64 word each), then the M work items
 constexpr size_t kLdsMetaWords = 8;
+// the largest chunk, in edges
+static int64_t solo_chunk_max(const Plan& P) { return P.M > 0 ? (P.E + P.M - 1) / P.M : 0; }
+
 static Layout layout(const Plan& P, bool device_final) {
     Layout L;
     size_t o = 0;
@@ -212,7 +223,7 @@ static Layout layout(const Plan& P, bool device_final) {
     L.cert = o; o = align256(o + sizeof(int2) * (size_t)std::max<int64_t>(P.cert_pairs, 1));
     L.off = o; o = align256(o + sizeof(int64_t) * (size_t)P.M);
     L.cap = o; o = align256(o + sizeof(int64_t) * (size_t)P.M);
-    L.pool = L.park = L.queue = L.dense = L.tags = L.slots = L.lmeta = L.rootw = o;
+    L.pool = L.park = L.queue = L.dense = L.tags = L.slots = L.sbuf = L.lmeta = L.rootw = o;
     if (P.lds) {
         L.lmeta = o; o = align256(o + sizeof(int64_t) * (kLdsMetaWords + (size_t)P.M));
         L.rootw = o; o = align256(o + sizeof(uint32_t) * (size_t)P.V);
@@ -225,6 +236,8 @@ static Layout layout(const Plan& P, bool device_final) {
         L.dense = o; o = align256(o + 4 * 2 * (size_t)P.V * (size_t)top_nodes);
         L.tags = o; o = align256(o + 4 * (size_t)P.nslots);
         L.slots = o; o = align256(o + 4 * 2 * (size_t)P.V * (size_t)P.nslots);
+        L.sbuf = o;
+        if (P.solo_nbk > 0) o = align256(o + sizeof(int2) * (size_t)solo_chunk_max(P) * (size_t)P.workers);
     }
     L.bws = o; if (device_final) o = align256(o + sizeof(int32_t) * (size_t)device_bridges_words(P.V));
     L.total = o;
@@ -346,6 +359,8 @@ int run_certificate(br_ctx* c, const int32_t* d_a, int64_t Ea, const int32_t* d_
         Sb.park = reinterpret_cast<uint32_t*>(base + L.park);
         Sb.queue = reinterpret_cast<uint32_t*>(base + L.queue);
         Sb.dense = reinterpret_cast<uint32_t*>(base + L.dense);
+        Sb.sbuf = P.solo_nbk > 0 ? reinterpret_cast<int2*>(base + L.sbuf) : nullptr;
+        Sb.sbuf_stride = solo_chunk_max(P);
         Sb.nslots = P.nslots;
         Sb.workers = P.workers;
         // slot words carry tags from earlier calls on this workspace; a new
@@ -906,17 +921,27 @@ int br_autotune(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int32_t
         }
         // then the winner with its team merges requesting each thread's edges
         // of a tile at once (measured: large M = 256 merges 3.12 -> 2.35 ms,
-        // dense M = 256 0.83 -> 0.87 ms)
-        if (M > 1 && !(best.count("lds") && best["lds"] == 1)) {
+        // dense M = 256 0.83 -> 0.87 ms), and a one-workgroup-per-node winner
+        // with its chunks in input order
+        auto try_alt = [&](const char* name, double v) -> int {
             TuneEntry alt = best;
-            alt["prem"] = 1;
+            alt[name] = v;
             double ms = 0;
-            rc = time_plan(alt, &ms);
-            if (rc) return rc;
+            const int r = time_plan(alt, &ms);
+            if (r) return r;
             if (ms < best_ms) {
                 best_ms = ms;
                 best = alt;
             }
+            return BR_OK;
+        };
+        if (M > 1 && !(best.count("lds") && best["lds"] == 1)) {
+            rc = try_alt("prem", 1);
+            if (rc) return rc;
+        }
+        if (best.count("solo") && best["solo"] == 1) {
+            rc = try_alt("nbk", 0);
+            if (rc) return rc;
         }
         rc = ctx_end(c, s);
         if (rc) return rc;

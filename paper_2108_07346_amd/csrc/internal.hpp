@@ -107,7 +107,9 @@ struct Plan {
     int32_t solo_top = 0;
     int32_t solo_variant = 0;      // worker shape (solo_kernels.hip)
     bool prem = false;             // team merges: each thread's edges of a tile requested at once
-    int32_t solo_cmp = 16;         // phase 0 compresses its slot after every cmp * V / 8 edges (then 8 V)
+    int32_t solo_cmp = 16;
+    int32_t solo_nbk = 0;          // phase 0 reads its chunk bucketed: buckets by the smaller endpoint (0: input order)
+    int32_t solo_nbk2 = 1;         // ... times buckets by the larger endpoint (at most 1,024 in all)         // phase 0 compresses its slot after every cmp * V / 8 edges (then 8 V)
     int32_t workers = 0;           // persistent workgroups
     int32_t nslots = 0;            // union-find slots (workers' own + free pool)
     int32_t tile0_max = 0;         // team path: largest first-stage tile (0 = the kernel's)
@@ -144,6 +146,8 @@ struct SoloBufs {
     uint32_t* park = nullptr;      // [2M]: parked slot per left node, then arrival counters
     uint32_t* queue = nullptr;     // [1]
     uint32_t* dense = nullptr;     // [ceil(M / 2^top)][V][2] node states at level top
+    int2* sbuf = nullptr;          // [workers][sbuf_stride] reordered chunk copies (solo_nbk > 0)
+    int64_t sbuf_stride = 0;
     int32_t nslots = 0, workers = 0;
 };
 size_t solo_lds_bytes(int32_t V);

@@ -75,6 +75,10 @@ struct SoloArgs {
     int32_t nslots;
     int32_t bm_words;               // words of one LDS claim table (a power of two)
     int64_t cmp_first;              // phase 0: first full compression after this many edges
+    int2* sbuf;                     // phase 0 reordering: [workers][sbuf_stride] edges (nbk > 0)
+    int64_t sbuf_stride;
+    int32_t nbk, bshift;            // buckets by the smaller endpoint (id >> bshift), 0: edges in input order
+    int32_t nbk2, bshift2;          // ... times buckets by the larger one (id >> bshift2; 1: none)
     uint32_t* slots;                // [nslots][2][V]
     uint32_t* slot_tag;             // [nslots] current tag of each slot (kept across calls)
     uint32_t* pool;                 // [ceil(nslots / 32)] bit set = slot free
@@ -244,7 +248,8 @@ __device__ void compress_slot(const St& S) {
 }
 
 // Offer a run of edges to the slot.  src 0: the input edge list, ids checked;
-// src 1: a node region's certificate (F part [0, rn1), F' part after it).
+// src 1: a node region's certificate (F part [0, rn1), F' part after it);
+// src 2: the worker's reordered copy of its chunk (sb).
 // stage0: where every edge starts (0: F, then F' if F rejects it; 1: F'
 // only).  out: write accepted edges to (off, cap).  stages: compress the slot
 // every cmp_first edges up to 2V, then at 8V (phase 0).  Each thread takes kSU
@@ -253,13 +258,14 @@ __device__ void compress_slot(const St& S) {
 template <int kSB, int kSU>
 __device__ void stream(SoloLds& L, const SoloArgs& A, const St& S, uint32_t* bm1, uint32_t* bm2, int src, int64_t t0,
                        int64_t t1, int64_t roff, int64_t rcap, uint32_t rn1, uint32_t rn2, uint32_t stage0, bool out,
-                       bool stages, int64_t off, int64_t cap, int& ph) {
+                       bool stages, int64_t off, int64_t cap, int& ph, const int2* sb = nullptr) {
     constexpr int64_t kST = (int64_t)kSB * kSU;      // edges per tile
     // phase 0: compress after cmp_first edges, then every cmp_first edges
     // up to 2 V, then at 8 V
     int64_t next_cmp = stages ? t0 + A.cmp_first : INT64_MAX;
     auto load = [&](int64_t i) -> int2 {
         if (src == 0) return i < A.split ? A.edges[i] : A.edges2[i - A.split];
+        if (src == 2) return sb[i];
         return A.cert[i < rn1 ? roff + i : roff + rcap - rn2 + (i - rn1)];
     };
     for (int64_t base = t0; base < t1; base += kST) {
@@ -316,6 +322,50 @@ __device__ void stream(SoloLds& L, const SoloArgs& A, const St& S, uint32_t* bm1
 }
 
 __device__ __forceinline__ int64_t part_lo(int64_t E, int64_t M, int64_t i) { return i * (E / M) + (i * (E % M)) / M; }
+
+// Copy the valid edges of input [lo, hi) to sb grouped by bucket -- the
+// smaller endpoint's id >> bshift, then the larger's id >> bshift2 (a
+// counting sort over nbk * nbk2 <= kMaxBuckets buckets: one pass to count,
+// one to place) -- so that phase 0 then reads the endpoints' words from
+// narrow id ranges.  Any order of a chunk's edges gives a pair of maximal
+// forests; ids out of range are flagged and left out, as in input order.
+// cnt: kMaxBuckets + 1 words of LDS.  Returns the number of edges copied
+// (every lane).
+constexpr int kMaxBuckets = 1024;
+template <int kSB>
+__device__ int64_t bucket_chunk(const SoloArgs& A, int64_t lo, int64_t hi, int2* sb, uint32_t V, uint32_t* cnt) {
+    uint32_t& total = cnt[kMaxBuckets];
+    const int nb = A.nbk * A.nbk2;
+    auto load = [&](int64_t i) -> int2 { return i < A.split ? A.edges[i] : A.edges2[i - A.split]; };
+    auto key = [&](int2 e) -> uint32_t {
+        const uint32_t a = min((uint32_t)e.x, (uint32_t)e.y), b = max((uint32_t)e.x, (uint32_t)e.y);
+        return (a >> A.bshift) * (uint32_t)A.nbk2 + (b >> A.bshift2);
+    };
+    for (int b = threadIdx.x; b < nb; b += kSB) cnt[b] = 0u;
+    __syncthreads();
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kSB) {
+        const int2 e = load(i);
+        if ((uint32_t)e.x < V && (uint32_t)e.y < V) atomicAdd(&cnt[key(e)], 1u);
+        else atomicOr(A.err, 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int b = 0; b < nb; b++) {
+            const uint32_t c = cnt[b];
+            cnt[b] = acc;
+            acc += c;
+        }
+        total = acc;
+    }
+    __syncthreads();
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kSB) {
+        const int2 e = load(i);
+        if ((uint32_t)e.x < V && (uint32_t)e.y < V) sb[atomicAdd(&cnt[key(e)], 1u)] = e;
+    }
+    __syncthreads();        // sb written by the workgroup, read back by it
+    return (int64_t)total;
+}
 
 // a free slot from the pool (thread 0), -1 if none; acquire on success
 __device__ int pool_pop(const SoloArgs& A) {
@@ -376,8 +426,15 @@ __global__ void __launch_bounds__(kSB) k_solo(SoloArgs A) {
             for (uint32_t x = threadIdx.x; x < 2 * V; x += kSB) S.q[x] = 0u;
         for (int x = threadIdx.x; x < 2 * A.bm_words; x += kSB) bm1[x] = 0u;
         __syncthreads();
-        stream<kSB, kSU>(L, A, S, bm1, bm2, 0, part_lo(A.E, A.M, c), part_lo(A.E, A.M, c + 1), 0, 0, 0, 0, 0, true, true, A.off[c],
-               A.cap[c], ph);
+        if (A.nbk > 0) {
+            int2* sb = A.sbuf + (size_t)blockIdx.x * (size_t)A.sbuf_stride;
+            const int64_t n = bucket_chunk<kSB>(A, part_lo(A.E, A.M, c), part_lo(A.E, A.M, c + 1), sb, V,
+                                                 bm2 + A.bm_words);
+            stream<kSB, kSU>(L, A, S, bm1, bm2, 2, 0, n, 0, 0, 0, 0, 0, true, true, A.off[c], A.cap[c], ph, sb);
+        } else {
+            stream<kSB, kSU>(L, A, S, bm1, bm2, 0, part_lo(A.E, A.M, c), part_lo(A.E, A.M, c + 1), 0, 0, 0, 0, 0, true,
+                             true, A.off[c], A.cap[c], ph);
+        }
         // ---- climb the merge tree while this worker finishes a pair second
         int64_t node = c, step = 1;
         for (;;) {
@@ -509,7 +566,10 @@ static int32_t claim_words(int32_t V) {
     return (int32_t)(bits / 32);
 }
 
-size_t solo_lds_bytes(int32_t V) { return sizeof(SoloLds) + 2 * 4 * (size_t)claim_words(V); }
+// the control block, the two claim tables, the bucket counters of phase 0
+size_t solo_lds_bytes(int32_t V) {
+    return sizeof(SoloLds) + 2 * 4 * (size_t)claim_words(V) + 4 * (size_t)(kMaxBuckets + 1);
+}
 
 // Worker shapes: (threads, edges per thread offered together), chosen per
 // plan (the tuner measures them).
@@ -559,6 +619,17 @@ void launch_solo(const Plan& P, const DevBufs& B, const SoloBufs& Sb, hipStream_
     A.nslots = Sb.nslots;
     A.bm_words = claim_words(P.V);
     A.cmp_first = std::max<int64_t>(1024, (int64_t)P.solo_cmp * P.V / 8);
+    A.sbuf = Sb.sbuf;
+    A.sbuf_stride = Sb.sbuf_stride;
+    A.nbk = Sb.sbuf ? P.solo_nbk : 0;
+    A.nbk2 = std::max(1, std::min(P.solo_nbk2, kMaxBuckets / std::max(1, A.nbk)));
+    auto shift_for = [&](int n) {
+        int b = 0;
+        while (n > 0 && ((int64_t)(P.V - 1) >> b) >= n) b++;
+        return b;
+    };
+    A.bshift = shift_for(A.nbk);
+    A.bshift2 = shift_for(A.nbk2);
     A.slots = Sb.slots;
     A.slot_tag = Sb.slot_tag;
     A.pool = Sb.pool;

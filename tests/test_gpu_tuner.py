@@ -79,7 +79,8 @@ def test_every_tuner_candidate_is_exact():
     V = 150_000
     e = rng.integers(0, V, size=(600_000, 2)).astype(np.int32)
     cases.append((e, V, 256, [{"BR_SOLO": "0", "BR_TILE0": "1024"}, {"BR_SOLO": "0", "BR_PREM": "1"},
-                              {"BR_SOLO": "1", "BR_SOLO_TOP": "1", "BR_PREM": "1"}] +
+                              {"BR_SOLO": "1", "BR_SOLO_TOP": "1", "BR_PREM": "1"},
+                              {"BR_SOLO": "1", "BR_SOLO_NBK": "0"}, {"BR_SOLO": "1", "BR_SOLO_NBK": "16", "BR_SOLO_NBK2": "1"}] +
                   [{"BR_SOLO": "1", "BR_SOLO_VARIANT": str(v), "BR_SOLO_TOP": str(t)} for v in range(4) for t in (0, 3)]))
     V2 = 700_000
     e2 = rng.integers(0, V2, size=(1_400_000, 2)).astype(np.int32)
