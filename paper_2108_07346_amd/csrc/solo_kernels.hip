@@ -647,8 +647,9 @@ void launch_solo(const Plan& P, const DevBufs& B, const SoloBufs& Sb, hipStream_
     (void)hipLaunchKernel(k.fn, dim3((unsigned)Sb.workers), dim3(k.sb), args, solo_lds_bytes(P.V), s);
 }
 
-// largest V of the plan (the slots hold 8 V bytes each)
-int32_t solo_max_v() { return 1 << 24; }
+// largest V of the plan (the slots hold 8 V bytes each, all of them within
+// 8 GiB: at least 8 slots)
+int32_t solo_max_v() { return 1 << 27; }
 
 // workgroups of the variant that fit on one CU with the LDS V needs
 int solo_blocks_per_cu(int variant, int32_t V) {
