@@ -608,9 +608,12 @@ def main():
         sweep = {}
         reps = 10 if args.workload == "dense" else 2
         for Mx in sweep_ms:
+            tuned_x = ctx.autotune(d, g.V, Mx, stream) if not args.no_tune else None   # each M its own plan
             run_steps(Mx, 1, False)
             sdt, sph, _ = run_steps(Mx, reps, True)
             sweep[str(Mx)] = {"edges_per_s": g.E * reps / sdt, "ms_per_step": 1000 * sdt / reps,
+                              "plan": PLAN_NAMES[int(ctx.profile()["plan_kind"])],
+                              "tuner": {k: v for k, v in (tuned_x or {}).items() if k not in ("key", "source")},
                               "ms_phase0": round(sph["ms_phase0"], 5), "ms_merge": round(sph["ms_merge"], 5),
                               "ms_bridge_step": round(sph["ms_bridge_dev"], 5),
                               "phase0_frac_hbm": (8.0 * g.E / (sph["ms_phase0"] / 1000) / 1e9) / PEAK_GBS
@@ -622,6 +625,8 @@ def main():
         # the dense configuration beside it (M = 16), whole query
         gd = graphgen.config("dense")
         dd = torch.from_numpy(gd.edges).cuda()
+        if not args.no_tune:
+            ctx.autotune(dd, gd.V, 16, stream)
         for _ in range(3):
             ctx.find(dd, gd.V, 16, stream)
         ctx.set_profiling(True)

@@ -213,9 +213,12 @@ int32_t br_lds_max_v(void);
  * br_autotune -- measure the launch shapes of the certificate path for this
  * device and input shape and keep the fastest for later calls on inputs of
  * the same shape bucket (V and E in powers of two, the same M): the team
- * path (many workgroups per chunk) with three first-stage tiles, and, where
- * its LDS bitmaps fit, the one-workgroup-per-node path in each worker shape
- * with three depths of the merges it does itself.  Each candidate computes
+ * path (many workgroups per chunk) with three first-stage tiles, the
+ * whole-tree LDS kernel where V fits, and the one-workgroup-per-node path in
+ * each worker shape with the depths of the merges it does itself around its
+ * default; then the winner again with its team merges requesting each
+ * thread's edges at once, and (one-workgroup-per-node) with its chunks in
+ * input order instead of bucketed by endpoint ranges.  Each candidate computes
  * the certificate of d_edges (one settling run, best of two timed runs, HIP
  * events on `stream`).  The choice is kept in memory and, when the
  * environment variable BR_AUTOTUNE_CACHE names a file, in that file (JSON,
