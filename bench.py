@@ -28,6 +28,10 @@ bound), divided by its duration from HIP events recorded on the call's stream
 during the timed steps, against the 8 TB/s HBM3E peak.  "traffic" is the
 counter-measured HBM bytes per launch from the committed rocprofv3 summary,
 when that summary was taken from the current kernel source (else null).
+"method_bytes_at_M" is the method's own traffic at the configured M -- the
+edge list read once, every certificate edge written to its node's region and
+read once more by its merge, from the library's per-node counts -- over the
+timed certificate phases (phase 0 and every merge).
 """
 import argparse
 import hashlib
@@ -587,6 +591,16 @@ def main():
           (args.steps, ms_step, value, json.dumps({k: round(v, 4) for k, v in phases.items()}), out.shape[0]),
           file=sys.stderr, flush=True)
 
+    # the method's own bytes at this M (edge list, certificates written and
+    # read by the merges), over the timed certificate phases
+    ctx.set_profiling(2)
+    ctx.find(d, g.V, M, stream)
+    alg_m = int(ctx.profile()["alg_bytes"])
+    ctx.set_profiling(1)
+    method_at_m = None
+    if alg_m > 0 and phases["ms_cert"] > 0:
+        gbs = alg_m / (phases["ms_cert"] / 1000) / 1e9
+        method_at_m = {"bytes": alg_m, "ms_cert": round(phases["ms_cert"], 4), "GBs": gbs, "frac": gbs / PEAK_GBS}
     detail = {"phases_ms": {k: round(v, 5) for k, v in phases.items()}, "bridges": int(out.shape[0]),
               "certificate_edges": int(prof["cert_f1"] + prof["cert_f2"]), "merge_rounds": int(prof["rounds"]),
               "plan": PLAN_NAMES[plan_kind], "tuner": tuned,
@@ -669,7 +683,8 @@ def main():
                      "frac": achieved / PEAK_GBS, "traffic": traffic,
                      "kernel": UNIT_NAMES[plan_kind],
                      "algorithmic_bytes_per_launch": 8 * g.E,
-                     "achievable_read_GBs": achievable},
+                     "achievable_read_GBs": achievable,
+                     "method_bytes_at_M": method_at_m},
         "cpu_baseline": cpu,
         "detail": detail,
     }

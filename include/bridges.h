@@ -217,8 +217,9 @@ int32_t br_lds_max_v(void);
  * whole-tree LDS kernel where V fits, and the one-workgroup-per-node path in
  * each worker shape with the depths of the merges it does itself around its
  * default; then the winner again with its team merges requesting each
- * thread's edges at once, and (one-workgroup-per-node) with its chunks in
- * input order instead of bucketed by endpoint ranges.  Each candidate computes
+ * thread's edges at once, and (one-workgroup-per-node) with the siblings'
+ * certificates of its own merges, then also its chunks, in input order
+ * instead of bucketed by endpoint ranges.  Each candidate computes
  * the certificate of d_edges (one settling run, best of two timed runs, HIP
  * events on `stream`).  The choice is kept in memory and, when the
  * environment variable BR_AUTOTUNE_CACHE names a file, in that file (JSON,
@@ -237,7 +238,9 @@ int br_autotune(br_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t V, int32
  * Phase timings of the last br_bridges_find / br_bridges_find_batched on this
  * context, in milliseconds, measured with HIP events on the call's stream
  * (device phases) and a steady clock (host phases).  Filled only when
- * profiling is enabled with br_set_profiling(ctx, 1) (it adds event records).
+ * profiling is enabled with br_set_profiling(ctx, 1) (it adds event records);
+ * br_set_profiling(ctx, 2) also fills alg_bytes (one more copy of the
+ * per-node counters after each call).
  */
 typedef struct br_profile {
     double ms_phase0;      /* per-chunk certificate kernel (Section III, phase 0) */
@@ -254,6 +257,14 @@ typedef struct br_profile {
     int64_t plan_kind;     /* certificate plan of the last plain-path call: 0 many
                               workgroups per chunk, 1 one workgroup per node
                               (resident slots), 2 the whole tree in LDS        */
+    int64_t alg_bytes;     /* br_bridges_find at profiling level 2, plans 0 and 1:
+                              the bytes the method itself moves at this M
+                              (Section III): 8 per input edge read by phase 0,
+                              8 per certificate edge written to a node's region,
+                              8 per edge of a right sibling's certificate read
+                              by its merge (the merges carry state, so a
+                              region's final size counts every edge written
+                              to it once); 0 otherwise                         */
 } br_profile;
 int br_set_profiling(br_ctx* ctx, int on);
 

@@ -37,7 +37,7 @@ class _Profile(ctypes.Structure):
                 ("ms_d2h", ctypes.c_double), ("ms_dfs", ctypes.c_double), ("ms_canon", ctypes.c_double),
                 ("ms_total", ctypes.c_double), ("cert_f1", ctypes.c_int64), ("cert_f2", ctypes.c_int64),
                 ("rounds", ctypes.c_int64), ("launches", ctypes.c_int64), ("ms_bridge_dev", ctypes.c_double),
-                ("plan_kind", ctypes.c_int64)]
+                ("plan_kind", ctypes.c_int64), ("alg_bytes", ctypes.c_int64)]
 
 
 class _ServerStats(ctypes.Structure):
@@ -137,8 +137,9 @@ class Context:
         except Exception:
             pass
 
-    def set_profiling(self, on: bool = True):
-        _check(self._lib.br_set_profiling(self._h, int(on)))
+    def set_profiling(self, level: int = 1):
+        """0 off; 1 phase timings; 2 also the method's bytes (alg_bytes)."""
+        _check(self._lib.br_set_profiling(self._h, int(level)))
 
     def set_final_step(self, mode: int):
         """1: bridge step on the GPU (the library's default); 0: Algorithm 1's

@@ -148,6 +148,9 @@ Plan make_plan(int64_t E, int32_t V, int32_t M, bool allow_solo, const TuneEntry
         // 173.8 / 170.5 / 169.7 with 4x64 / 4x256 / 8x128
         P.solo_nbk = std::max(0, std::min(1024, knob("BR_SOLO_NBK", "nbk", 8)));
         P.solo_nbk2 = std::max(1, knob("BR_SOLO_NBK2", "nbk2", 128));
+        // the merges inside the kernel read the sibling's certificate the
+        // same way
+        P.solo_mbk = knob("BR_SOLO_MBK", "mbk", 1) != 0;
         P.qs = 2;
     }
     return P;
@@ -210,6 +213,16 @@ struct Layout {
 constexpr size_t kLdsMetaWords = 8;
 // the largest chunk, in edges
 static int64_t solo_chunk_max(const Plan& P) { return P.M > 0 ? (P.E + P.M - 1) / P.M : 0; }
+// edges of a worker's reordering buffer: a chunk, and with bucketed merges
+// also the largest right sibling merged inside the kernel (a node of level
+// top - 1 spans 2^(top-1) chunks; a certificate holds at most 2(V-1) edges)
+static int64_t solo_sbuf_stride(const Plan& P) {
+    int64_t s = solo_chunk_max(P);
+    const int64_t bound = 2 * (int64_t(P.V) - 1);
+    if (P.solo_mbk)
+        for (int l = 2; l <= P.solo_top && s < bound; l++) s = std::max(s, std::min(bound, 2 * s));
+    return s;
+}
 
 static Layout layout(const Plan& P, bool device_final) {
     Layout L;
@@ -237,7 +250,7 @@ static Layout layout(const Plan& P, bool device_final) {
         L.tags = o; o = align256(o + 4 * (size_t)P.nslots);
         L.slots = o; o = align256(o + 4 * 2 * (size_t)P.V * (size_t)P.nslots);
         L.sbuf = o;
-        if (P.solo_nbk > 0) o = align256(o + sizeof(int2) * (size_t)solo_chunk_max(P) * (size_t)P.workers);
+        if (P.solo_nbk > 0) o = align256(o + sizeof(int2) * (size_t)solo_sbuf_stride(P) * (size_t)P.workers);
     }
     L.bws = o; if (device_final) o = align256(o + sizeof(int32_t) * (size_t)device_bridges_words(P.V));
     L.total = o;
@@ -360,7 +373,7 @@ int run_certificate(br_ctx* c, const int32_t* d_a, int64_t Ea, const int32_t* d_
         Sb.queue = reinterpret_cast<uint32_t*>(base + L.queue);
         Sb.dense = reinterpret_cast<uint32_t*>(base + L.dense);
         Sb.sbuf = P.solo_nbk > 0 ? reinterpret_cast<int2*>(base + L.sbuf) : nullptr;
-        Sb.sbuf_stride = solo_chunk_max(P);
+        Sb.sbuf_stride = solo_sbuf_stride(P);
         Sb.nslots = P.nslots;
         Sb.workers = P.workers;
         // slot words carry tags from earlier calls on this workspace; a new
@@ -455,7 +468,7 @@ int br_destroy(br_ctx* c) {
 
 int br_set_profiling(br_ctx* c, int on) {
     if (!c) return fail(BR_EINVAL, "br_set_profiling: null context");
-    c->profiling = on ? 1 : 0;
+    c->profiling = on <= 0 ? 0 : (on == 1 ? 1 : 2);
     return BR_OK;
 }
 
@@ -624,6 +637,19 @@ int br_bridges_find(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int
         c->prof.ms_bridge_dev = mode == 1 ? ev_ms(c, 3, 5) : 0.0;
         c->prof.cert_f1 = n1;
         c->prof.cert_f2 = n2;
+        c->prof.alg_bytes = 0;
+        if (c->profiling >= 2 && !P.lds) {
+            // every node's final region size (after the call: outside the
+            // timed phases)
+            std::vector<uint32_t> hn(2 * (size_t)P.M);
+            BR_HIP(hipMemcpy(hn.data(), B.cnt, sizeof(uint32_t) * hn.size(), hipMemcpyDeviceToHost));
+            int64_t bytes = 8 * E;
+            for (int64_t i = 0; i < P.M; i++) {
+                const int64_t x = std::min<int64_t>((int64_t)hn[2 * i] + hn[2 * i + 1], P.cap[i]);
+                bytes += (i == 0 ? 8 : 16) * x;      // written; read once more by the merge of a right node
+            }
+            c->prof.alg_bytes = bytes;
+        }
     }
     c->prof.ms_dfs = std::chrono::duration<double, std::milli>(t2 - t1).count();
     c->prof.ms_canon = std::chrono::duration<double, std::milli>(t3 - t2).count();
@@ -922,7 +948,7 @@ int br_autotune(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int32_t
         // then the winner with its team merges requesting each thread's edges
         // of a tile at once (measured: large M = 256 merges 3.12 -> 2.35 ms,
         // dense M = 256 0.83 -> 0.87 ms), and a one-workgroup-per-node winner
-        // with its chunks in input order
+        // with its merges' siblings, then also its chunks, in input order
         auto try_alt = [&](const char* name, double v) -> int {
             TuneEntry alt = best;
             alt[name] = v;
@@ -940,6 +966,10 @@ int br_autotune(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int32_t
             if (rc) return rc;
         }
         if (best.count("solo") && best["solo"] == 1) {
+            if (!(best.count("top") && best["top"] == 0)) {
+                rc = try_alt("mbk", 0);
+                if (rc) return rc;
+            }
             rc = try_alt("nbk", 0);
             if (rc) return rc;
         }

@@ -107,9 +107,10 @@ struct Plan {
     int32_t solo_top = 0;
     int32_t solo_variant = 0;      // worker shape (solo_kernels.hip)
     bool prem = false;             // team merges: each thread's edges of a tile requested at once
-    int32_t solo_cmp = 16;
+    int32_t solo_cmp = 16;         // phase 0 compresses its slot every cmp * V / 8 edges up to 2 V, then at 8 V
     int32_t solo_nbk = 0;          // phase 0 reads its chunk bucketed: buckets by the smaller endpoint (0: input order)
-    int32_t solo_nbk2 = 1;         // ... times buckets by the larger endpoint (at most 1,024 in all)         // phase 0 compresses its slot after every cmp * V / 8 edges (then 8 V)
+    int32_t solo_nbk2 = 1;         // ... times buckets by the larger endpoint (at most 1,024 in all)
+    bool solo_mbk = false;         // ... and so do the merges inside the kernel (solo_nbk > 0)
     int32_t workers = 0;           // persistent workgroups
     int32_t nslots = 0;            // union-find slots (workers' own + free pool)
     int32_t tile0_max = 0;         // team path: largest first-stage tile (0 = the kernel's)

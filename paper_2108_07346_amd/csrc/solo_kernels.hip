@@ -75,10 +75,11 @@ struct SoloArgs {
     int32_t nslots;
     int32_t bm_words;               // words of one LDS claim table (a power of two)
     int64_t cmp_first;              // phase 0: first full compression after this many edges
-    int2* sbuf;                     // phase 0 reordering: [workers][sbuf_stride] edges (nbk > 0)
+    int2* sbuf;                     // reordering: [workers][sbuf_stride] edges (nbk > 0)
     int64_t sbuf_stride;
     int32_t nbk, bshift;            // buckets by the smaller endpoint (id >> bshift), 0: edges in input order
     int32_t nbk2, bshift2;          // ... times buckets by the larger one (id >> bshift2; 1: none)
+    int32_t mbk;                    // merges inside the kernel read the sibling's certificate bucketed too
     uint32_t* slots;                // [nslots][2][V]
     uint32_t* slot_tag;             // [nslots] current tag of each slot (kept across calls)
     uint32_t* pool;                 // [ceil(nslots / 32)] bit set = slot free
@@ -323,30 +324,30 @@ __device__ void stream(SoloLds& L, const SoloArgs& A, const St& S, uint32_t* bm1
 
 __device__ __forceinline__ int64_t part_lo(int64_t E, int64_t M, int64_t i) { return i * (E / M) + (i * (E % M)) / M; }
 
-// Copy the valid edges of input [lo, hi) to sb grouped by bucket -- the
-// smaller endpoint's id >> bshift, then the larger's id >> bshift2 (a
-// counting sort over nbk * nbk2 <= kMaxBuckets buckets: one pass to count,
-// one to place) -- so that phase 0 then reads the endpoints' words from
-// narrow id ranges.  Any order of a chunk's edges gives a pair of maximal
-// forests; ids out of range are flagged and left out, as in input order.
-// cnt: kMaxBuckets + 1 words of LDS.  Returns the number of edges copied
-// (every lane).
+// Copy the n edges load(0 .. n-1) with both ids below V to sb grouped by
+// bucket -- the smaller endpoint's id >> bshift, then the larger's id >>
+// bshift2 (a counting sort over nbk * nbk2 <= kMaxBuckets buckets: one pass
+// to count, one to place) -- so that the stream then reads the endpoints'
+// words from narrow id ranges.  Any order of the edges offered to a slot
+// gives a pair of maximal forests; an id out of range sets `bad` in err and
+// its edge is left out, as in input order.  cnt: kMaxBuckets + 1 words of
+// LDS.  Returns the number of edges copied (every lane).
 constexpr int kMaxBuckets = 1024;
-template <int kSB>
-__device__ int64_t bucket_chunk(const SoloArgs& A, int64_t lo, int64_t hi, int2* sb, uint32_t V, uint32_t* cnt) {
+template <int kSB, class Load>
+__device__ int64_t bucket_into(const SoloArgs& A, int64_t n, Load load, uint32_t bad, int2* sb, uint32_t V,
+                               uint32_t* cnt) {
     uint32_t& total = cnt[kMaxBuckets];
     const int nb = A.nbk * A.nbk2;
-    auto load = [&](int64_t i) -> int2 { return i < A.split ? A.edges[i] : A.edges2[i - A.split]; };
     auto key = [&](int2 e) -> uint32_t {
         const uint32_t a = min((uint32_t)e.x, (uint32_t)e.y), b = max((uint32_t)e.x, (uint32_t)e.y);
         return (a >> A.bshift) * (uint32_t)A.nbk2 + (b >> A.bshift2);
     };
     for (int b = threadIdx.x; b < nb; b += kSB) cnt[b] = 0u;
     __syncthreads();
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kSB) {
+    for (int64_t i = threadIdx.x; i < n; i += kSB) {
         const int2 e = load(i);
         if ((uint32_t)e.x < V && (uint32_t)e.y < V) atomicAdd(&cnt[key(e)], 1u);
-        else atomicOr(A.err, 1u);
+        else atomicOr(A.err, bad);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -359,7 +360,7 @@ __device__ int64_t bucket_chunk(const SoloArgs& A, int64_t lo, int64_t hi, int2*
         total = acc;
     }
     __syncthreads();
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kSB) {
+    for (int64_t i = threadIdx.x; i < n; i += kSB) {
         const int2 e = load(i);
         if ((uint32_t)e.x < V && (uint32_t)e.y < V) sb[atomicAdd(&cnt[key(e)], 1u)] = e;
     }
@@ -428,8 +429,11 @@ __global__ void __launch_bounds__(kSB) k_solo(SoloArgs A) {
         __syncthreads();
         if (A.nbk > 0) {
             int2* sb = A.sbuf + (size_t)blockIdx.x * (size_t)A.sbuf_stride;
-            const int64_t n = bucket_chunk<kSB>(A, part_lo(A.E, A.M, c), part_lo(A.E, A.M, c + 1), sb, V,
-                                                 bm2 + A.bm_words);
+            const int64_t lo = part_lo(A.E, A.M, c);
+            const int64_t n = bucket_into<kSB>(
+                A, part_lo(A.E, A.M, c + 1) - lo,
+                [&](int64_t k) { return lo + k < A.split ? A.edges[lo + k] : A.edges2[lo + k - A.split]; }, 1u, sb, V,
+                bm2 + A.bm_words);
             stream<kSB, kSU>(L, A, S, bm1, bm2, 2, 0, n, 0, 0, 0, 0, 0, true, true, A.off[c], A.cap[c], ph, sb);
         } else {
             stream<kSB, kSU>(L, A, S, bm1, bm2, 0, part_lo(A.E, A.M, c), part_lo(A.E, A.M, c + 1), 0, 0, 0, 0, 0, true,
@@ -533,7 +537,17 @@ __global__ void __launch_bounds__(kSB) k_solo(SoloArgs A) {
                 compress_slot<kSB>(S);
                 __syncthreads();
             }
-            stream<kSB, kSU>(L, A, S, bm1, bm2, 1, 0, (int64_t)nj1 + nj2, offj, capj, nj1, nj2, 0, true, false, offi, capi, ph);
+            const int64_t nj = (int64_t)nj1 + nj2;
+            if (A.mbk && A.nbk > 0 && nj <= A.sbuf_stride) {
+                // X_j bucketed like a phase-0 chunk (sb's last reads came before a barrier)
+                int2* sb = A.sbuf + (size_t)blockIdx.x * (size_t)A.sbuf_stride;
+                const int64_t n = bucket_into<kSB>(
+                    A, nj, [&](int64_t k) { return A.cert[k < nj1 ? offj + k : offj + capj - nj2 + (k - nj1)]; }, 2u,
+                    sb, V, bm2 + A.bm_words);
+                stream<kSB, kSU>(L, A, S, bm1, bm2, 2, 0, n, 0, 0, 0, 0, 0, true, false, offi, capi, ph, sb);
+            } else {
+                stream<kSB, kSU>(L, A, S, bm1, bm2, 1, 0, nj, offj, capj, nj1, nj2, 0, true, false, offi, capi, ph);
+            }
             node = i;
             step *= 2;
         }
@@ -630,6 +644,7 @@ void launch_solo(const Plan& P, const DevBufs& B, const SoloBufs& Sb, hipStream_
     };
     A.bshift = shift_for(A.nbk);
     A.bshift2 = shift_for(A.nbk2);
+    A.mbk = P.solo_mbk ? 1 : 0;
     A.slots = Sb.slots;
     A.slot_tag = Sb.slot_tag;
     A.pool = Sb.pool;

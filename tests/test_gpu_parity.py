@@ -334,3 +334,24 @@ def test_small_config_runs_in_lds(ctx, small):
     assert ctx.profile()["plan_kind"] == 2
     ctx.set_profiling(False)
     assert np.array_equal(got, oracle.bridges(small.edges, small.V))
+
+
+@pytest.mark.parametrize("plan", ["team", "solo"])
+def test_method_bytes_on_a_path(ctx, monkeypatch, plan):
+    # a path of 2k edges in two chunks: each chunk is a forest, so each
+    # certificate keeps its whole chunk and node 0's region ends with the
+    # whole path -- 8 * 2k bytes read by phase 0, 8 * 2k written to node 0,
+    # 8 * k written to node 1 and read again by the merge
+    monkeypatch.setenv("BR_LDS", "0")
+    monkeypatch.setenv("BR_SOLO", "1" if plan == "solo" else "0")
+    k = 5000
+    V = 2 * k + 1
+    e = np.stack([np.arange(2 * k), np.arange(1, 2 * k + 1)], 1).astype(np.int32)
+    ctx.set_profiling(2)
+    got = ctx.find(dev(e), V, 2)
+    p = ctx.profile()
+    ctx.set_profiling(0)
+    assert np.array_equal(got, oracle.bridges(e, V))
+    assert p["plan_kind"] == (1 if plan == "solo" else 0)
+    assert p["cert_f1"] == 2 * k and p["cert_f2"] == 0
+    assert p["alg_bytes"] == 8 * 2 * k + 8 * 2 * k + 16 * k
