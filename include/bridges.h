@@ -218,8 +218,8 @@ int32_t br_lds_max_v(void);
  * each worker shape with the depths of the merges it does itself around its
  * default; then the winner again with its team merges requesting each
  * thread's edges at once, and (one-workgroup-per-node) with the siblings'
- * certificates of its own merges, then also its chunks, in input order
- * instead of bucketed by endpoint ranges.  Each candidate computes
+ * certificates of its own merges bucketed by endpoint ranges, then with its
+ * chunks in input order instead of bucketed.  Each candidate computes
  * the certificate of d_edges (one settling run, best of two timed runs, HIP
  * events on `stream`).  The choice is kept in memory and, when the
  * environment variable BR_AUTOTUNE_CACHE names a file, in that file (JSON,

@@ -148,9 +148,11 @@ Plan make_plan(int64_t E, int32_t V, int32_t M, bool allow_solo, const TuneEntry
         // 173.8 / 170.5 / 169.7 with 4x64 / 4x256 / 8x128
         P.solo_nbk = std::max(0, std::min(1024, knob("BR_SOLO_NBK", "nbk", 8)));
         P.solo_nbk2 = std::max(1, knob("BR_SOLO_NBK2", "nbk2", 128));
-        // the merges inside the kernel read the sibling's certificate the
-        // same way
-        P.solo_mbk = knob("BR_SOLO_MBK", "mbk", 1) != 0;
+        // the merges inside the kernel can read the sibling's certificate
+        // the same way (off by default: large workload, M = 4096, two merge
+        // levels in the kernel, 161.5 ms per query with the siblings in
+        // their written order, 166.0 bucketed)
+        P.solo_mbk = knob("BR_SOLO_MBK", "mbk", 0) != 0;
         P.qs = 2;
     }
     return P;
@@ -948,7 +950,8 @@ int br_autotune(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int32_t
         // then the winner with its team merges requesting each thread's edges
         // of a tile at once (measured: large M = 256 merges 3.12 -> 2.35 ms,
         // dense M = 256 0.83 -> 0.87 ms), and a one-workgroup-per-node winner
-        // with its merges' siblings, then also its chunks, in input order
+        // with the siblings of its own merges bucketed, then with its chunks
+        // in input order
         auto try_alt = [&](const char* name, double v) -> int {
             TuneEntry alt = best;
             alt[name] = v;
@@ -967,7 +970,7 @@ int br_autotune(br_ctx* c, const int32_t* d_edges, int64_t E, int32_t V, int32_t
         }
         if (best.count("solo") && best["solo"] == 1) {
             if (!(best.count("top") && best["top"] == 0)) {
-                rc = try_alt("mbk", 0);
+                rc = try_alt("mbk", 1);
                 if (rc) return rc;
             }
             rc = try_alt("nbk", 0);

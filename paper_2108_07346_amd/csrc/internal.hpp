@@ -110,7 +110,7 @@ struct Plan {
     int32_t solo_cmp = 16;         // phase 0 compresses its slot every cmp * V / 8 edges up to 2 V, then at 8 V
     int32_t solo_nbk = 0;          // phase 0 reads its chunk bucketed: buckets by the smaller endpoint (0: input order)
     int32_t solo_nbk2 = 1;         // ... times buckets by the larger endpoint (at most 1,024 in all)
-    bool solo_mbk = false;         // ... and so do the merges inside the kernel (solo_nbk > 0)
+    bool solo_mbk = false;         // ... and the merges inside the kernel read their siblings so too
     int32_t workers = 0;           // persistent workgroups
     int32_t nslots = 0;            // union-find slots (workers' own + free pool)
     int32_t tile0_max = 0;         // team path: largest first-stage tile (0 = the kernel's)

@@ -338,16 +338,18 @@ __device__ int64_t bucket_into(const SoloArgs& A, int64_t n, Load load, uint32_t
                                uint32_t* cnt) {
     uint32_t& total = cnt[kMaxBuckets];
     const int nb = A.nbk * A.nbk2;
-    auto key = [&](int2 e) -> uint32_t {
+    const uint32_t nbk2 = (uint32_t)A.nbk2, s1 = (uint32_t)A.bshift, s2 = (uint32_t)A.bshift2;
+    uint32_t* err = A.err;
+    auto key = [=](int2 e) -> uint32_t {
         const uint32_t a = min((uint32_t)e.x, (uint32_t)e.y), b = max((uint32_t)e.x, (uint32_t)e.y);
-        return (a >> A.bshift) * (uint32_t)A.nbk2 + (b >> A.bshift2);
+        return (a >> s1) * nbk2 + (b >> s2);
     };
     for (int b = threadIdx.x; b < nb; b += kSB) cnt[b] = 0u;
     __syncthreads();
     for (int64_t i = threadIdx.x; i < n; i += kSB) {
         const int2 e = load(i);
         if ((uint32_t)e.x < V && (uint32_t)e.y < V) atomicAdd(&cnt[key(e)], 1u);
-        else atomicOr(A.err, bad);
+        else atomicOr(err, bad);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -367,6 +369,20 @@ __device__ int64_t bucket_into(const SoloArgs& A, int64_t n, Load load, uint32_t
     __syncthreads();        // sb written by the workgroup, read back by it
     return (int64_t)total;
 }
+
+// the edges of input chunk [lo, ...) and of a node region's certificate (F
+// part [0, n1), F' part after it), as loaders by index (captured by value:
+// a reference to the kernel's argument block would move it to private memory)
+struct InputLoad {
+    const int2 *e1, *e2;
+    int64_t split, lo;
+    __device__ int2 operator()(int64_t k) const { return lo + k < split ? e1[lo + k] : e2[lo + k - split]; }
+};
+struct RegionLoad {
+    const int2* c;
+    int64_t off, cap, n1, n2;
+    __device__ int2 operator()(int64_t k) const { return c[k < n1 ? off + k : off + cap - n2 + (k - n1)]; }
+};
 
 // a free slot from the pool (thread 0), -1 if none; acquire on success
 __device__ int pool_pop(const SoloArgs& A) {
@@ -427,17 +443,19 @@ __global__ void __launch_bounds__(kSB) k_solo(SoloArgs A) {
             for (uint32_t x = threadIdx.x; x < 2 * V; x += kSB) S.q[x] = 0u;
         for (int x = threadIdx.x; x < 2 * A.bm_words; x += kSB) bm1[x] = 0u;
         __syncthreads();
-        if (A.nbk > 0) {
-            int2* sb = A.sbuf + (size_t)blockIdx.x * (size_t)A.sbuf_stride;
-            const int64_t lo = part_lo(A.E, A.M, c);
-            const int64_t n = bucket_into<kSB>(
-                A, part_lo(A.E, A.M, c + 1) - lo,
-                [&](int64_t k) { return lo + k < A.split ? A.edges[lo + k] : A.edges2[lo + k - A.split]; }, 1u, sb, V,
-                bm2 + A.bm_words);
-            stream<kSB, kSU>(L, A, S, bm1, bm2, 2, 0, n, 0, 0, 0, 0, 0, true, true, A.off[c], A.cap[c], ph, sb);
-        } else {
-            stream<kSB, kSU>(L, A, S, bm1, bm2, 0, part_lo(A.E, A.M, c), part_lo(A.E, A.M, c + 1), 0, 0, 0, 0, 0, true,
-                             true, A.off[c], A.cap[c], ph);
+        {
+            // the chunk in input order, or bucketed into the worker's buffer
+            // (one call site of the stream: each one costs registers)
+            int64_t t0 = part_lo(A.E, A.M, c), t1 = part_lo(A.E, A.M, c + 1);
+            int src = 0;
+            int2* sb = nullptr;
+            if (A.nbk > 0) {
+                sb = A.sbuf + (size_t)blockIdx.x * (size_t)A.sbuf_stride;
+                t1 = bucket_into<kSB>(A, t1 - t0, InputLoad{A.edges, A.edges2, A.split, t0}, 1u, sb, V, bm2 + A.bm_words);
+                t0 = 0;
+                src = 2;
+            }
+            stream<kSB, kSU>(L, A, S, bm1, bm2, src, t0, t1, 0, 0, 0, 0, 0, true, true, A.off[c], A.cap[c], ph, sb);
         }
         // ---- climb the merge tree while this worker finishes a pair second
         int64_t node = c, step = 1;
@@ -537,17 +555,17 @@ __global__ void __launch_bounds__(kSB) k_solo(SoloArgs A) {
                 compress_slot<kSB>(S);
                 __syncthreads();
             }
-            const int64_t nj = (int64_t)nj1 + nj2;
+            int64_t nj = (int64_t)nj1 + nj2;
+            int src = 1;
+            int2* sb = nullptr;
             if (A.mbk && A.nbk > 0 && nj <= A.sbuf_stride) {
                 // X_j bucketed like a phase-0 chunk (sb's last reads came before a barrier)
-                int2* sb = A.sbuf + (size_t)blockIdx.x * (size_t)A.sbuf_stride;
-                const int64_t n = bucket_into<kSB>(
-                    A, nj, [&](int64_t k) { return A.cert[k < nj1 ? offj + k : offj + capj - nj2 + (k - nj1)]; }, 2u,
-                    sb, V, bm2 + A.bm_words);
-                stream<kSB, kSU>(L, A, S, bm1, bm2, 2, 0, n, 0, 0, 0, 0, 0, true, false, offi, capi, ph, sb);
-            } else {
-                stream<kSB, kSU>(L, A, S, bm1, bm2, 1, 0, nj, offj, capj, nj1, nj2, 0, true, false, offi, capi, ph);
+                sb = A.sbuf + (size_t)blockIdx.x * (size_t)A.sbuf_stride;
+                nj = bucket_into<kSB>(A, nj, RegionLoad{A.cert, offj, capj, (int64_t)nj1, (int64_t)nj2}, 2u, sb, V,
+                                      bm2 + A.bm_words);
+                src = 2;
             }
+            stream<kSB, kSU>(L, A, S, bm1, bm2, src, 0, nj, offj, capj, nj1, nj2, 0, true, false, offi, capi, ph, sb);
             node = i;
             step *= 2;
         }

@@ -1,8 +1,8 @@
 """The one-workgroup-per-node plan forced onto graphs the size rules would not
 give it: tiny and empty graphs, more chunks than edges, self-loops and
 parallel edges, a star (every hook on one root), a long path, both chunk
-orders, and a slot whose tags run out and is cleared.  Every bridge set must
-equal the oracle's."""
+orders (and siblings bucketed in the merges), and a slot whose tags run
+out and is cleared.  Every bridge set must equal the oracle's."""
 import sys
 
 import numpy as np
@@ -64,10 +64,12 @@ def test_forced_solo_edge_cases(ctx, M):
     say("M=%d: all cases exact" % M)
 
 
-@pytest.mark.parametrize("order", ["bucketed", "input"])
+@pytest.mark.parametrize("order", ["bucketed", "input", "bucketed_merges"])
 def test_forced_solo_both_chunk_orders(ctx, monkeypatch, order):
     if order == "input":
         monkeypatch.setenv("BR_SOLO_NBK", "0")
+    if order == "bucketed_merges":      # the merges inside the kernel bucket their siblings too
+        monkeypatch.setenv("BR_SOLO_MBK", "1")
     g = graphgen.planted(77, k=40, vc=6000, p=0.05, n_extra=2, n_pend=60)
     want = oracle.bridges(g.edges, g.V)
     for M in (16, 257):
