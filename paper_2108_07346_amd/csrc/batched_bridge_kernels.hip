@@ -75,8 +75,10 @@ template <int kST>
 __device__ void scan_u16(uint16_t* a, int n, uint32_t* wsum, uint32_t* tot) {
     const int b = threadIdx.x * 8;
     uint32_t v[8], s = 0;
+#pragma unroll
     for (int j = 0; j < 8; j++) { v[j] = b + j < n ? a[b + j] : 0u; s += v[j]; }
     uint32_t ex = wg_exclusive<kST>(s, wsum, tot);
+#pragma unroll
     for (int j = 0; j < 8; j++) { if (b + j < n) a[b + j] = (uint16_t)ex; ex += v[j]; }
     __syncthreads();
 }
@@ -135,8 +137,10 @@ __global__ void __launch_bounds__(kST) k_small_bridges(const BatchDev B, const i
         {   // exclusive scan of head[0..V] (V + 1 <= 4097 entries, 8 per thread)
             const int b = tid * 8;
             uint32_t v[8], sm = 0;
+#pragma unroll
             for (int j = 0; j < 8; j++) { v[j] = b + j <= (int)V ? L.head[b + j] : 0u; sm += v[j]; }
             uint32_t ex = wg_exclusive<kST>(sm, L.wsum, &L.total);
+#pragma unroll
             for (int j = 0; j < 8; j++) { if (b + j <= (int)V) L.head[b + j] = ex; ex += v[j]; }
             __syncthreads();
         }
@@ -188,6 +192,7 @@ __global__ void __launch_bounds__(kST) k_small_bridges(const BatchDev B, const i
         {
             const int b = tid * 4;
             uint32_t v[4], sm = 0;
+#pragma unroll
             for (int j = 0; j < 4; j++) {
                 const uint32_t r = b + j;
                 uint32_t Lr = 0;
@@ -196,6 +201,7 @@ __global__ void __launch_bounds__(kST) k_small_bridges(const BatchDev B, const i
                 sm += v[j];
             }
             uint32_t ex = wg_exclusive<kST>(sm, L.wsum, &L.total);
+#pragma unroll
             for (int j = 0; j < 4; j++) {
                 const uint32_t r = b + j;
                 if (r < V) { L.cur[r] = ex; L.posof[r] = (uint16_t)(v[j] & 0xffffu); }

@@ -46,7 +46,8 @@ struct LdsState {
     static constexpr int kStage = Staged ? 2 * (MaxV - 1) : 1;
     uint32_t q[MaxV];             // packed F / F' offsets
     uint32_t stage[kStage];       // merged certificate: (u | v << 16), F from front, F' from back
-    uint32_t n1, n2;              // counters of the current certificate
+    uint32_t n12;                 // edges of the current certificate: F in the low half, F' in the high
+                                  // (each a forest count, at most V - 1 < 2^16, so no carry)
     int32_t item, last, errv;
 };
 
@@ -124,14 +125,19 @@ __device__ void lcompress(uint32_t* q, uint32_t V) {
 }
 
 
-// wavefront-aggregated reservation of slots on an LDS counter
-__device__ __forceinline__ uint32_t reserve(uint32_t* ctr, bool want, uint64_t& mask) {
-    mask = __ballot(want);
-    if (mask == 0) return 0;
-    const int leader = __ffsll((unsigned long long)mask) - 1;
+// wavefront-aggregated reservation of slots for F's and F''s accepted edges
+// on the packed LDS counter: one atomic and one broadcast per wavefront step
+// for both forests (the two were each an LDS atomic plus a permute)
+__device__ __forceinline__ void reserve2(uint32_t* ctr, bool a1, bool a2, uint32_t& p1, uint32_t& p2) {
+    const uint64_t m1 = __ballot(a1), m2 = __ballot(a2);
+    p1 = p2 = 0;
+    if ((m1 | m2) == 0) return;
+    const int leader = __ffsll((unsigned long long)(m1 | m2)) - 1;
     uint32_t base = 0;
-    if (__lane_id() == leader) base = atomicAdd(ctr, (uint32_t)__popcll(mask));
-    return __shfl(base, leader) + lane_rank(mask);
+    if (__lane_id() == leader) base = atomicAdd(ctr, (uint32_t)__popcll(m1) | ((uint32_t)__popcll(m2) << 16));
+    base = __shfl(base, leader);
+    p1 = (base & 0xffffu) + lane_rank(m1);
+    p2 = (base >> 16) + lane_rank(m2);
 }
 
 __device__ __forceinline__ int64_t part_lo(int64_t E, int64_t M, int64_t i) { return i * (E / M) + (i * (E % M)) / M; }
@@ -143,13 +149,14 @@ __device__ __forceinline__ int64_t part_lo(int64_t E, int64_t M, int64_t i) { re
 namespace {
 
 // Certify edges [t0, t1) of graph g (ids < V) into an empty LDS state and write
-// the accepted edges to node region (off, cap).  Counts go to S.n1, S.n2.
+// the accepted edges to node region (off, cap).  Counts go to S.n12.
 // Each thread takes kU edges per step and the next step's edges are loaded
 // before the current ones are offered, so that enough loads are in flight to
 // cover HBM latency while the LDS work proceeds.
 constexpr int kU = 4;
 
 __device__ __forceinline__ void load_step(const BatchDev& B, int64_t base, int64_t t1, int2 (&e)[kU]) {
+#pragma unroll
     for (int j = 0; j < kU; j++) {
         const int64_t i = base + j * kBB + threadIdx.x;
         e[j] = i < t1 ? B.edges[i] : make_int2(-1, -1);
@@ -160,7 +167,7 @@ template <class LS>
 __device__ void certify_chunk(LS& S, const BatchDev& B, int64_t t0, int64_t t1, uint32_t V, int64_t off,
                               int64_t cap) {
     for (uint32_t x = threadIdx.x; x < V; x += kBB) S.q[x] = 0;
-    if (threadIdx.x == 0) { S.n1 = 0; S.n2 = 0; }
+    if (threadIdx.x == 0) S.n12 = 0;
     __syncthreads();
     // compress after the first 2V and 8V edges (dense chunks are then mostly
     // rejected by the shared-parent test)
@@ -176,20 +183,64 @@ __device__ void certify_chunk(LS& S, const BatchDev& B, int64_t t0, int64_t t1, 
             next_cmp = next_cmp == t0 + 2 * (int64_t)V ? t0 + 8 * (int64_t)V : INT64_MAX;
         }
         if (base + kStep < t1) load_step(B, base + kStep, t1, nxt);
-        for (int j = 0; j < kU; j++) {
-            const int2 e = cur[j];
-            const bool live = base + j * kBB + threadIdx.x < t1;
-            bool a1 = false, a2 = false;
-            if (live) {
-                if ((uint32_t)e.x < V && (uint32_t)e.y < V) loffer(S.q, (uint32_t)e.x, (uint32_t)e.y, a1, a2);
-                else atomicOr(B.err, 1u);
+        if constexpr (LS::kStage >= kBB * kU) {
+            // Where the stage area is free (it only serves merges), each
+            // wavefront first applies the shared-parent test to all of its
+            // kU x 64 edges and packs the ones the test cannot reject into a
+            // list of its own there; those are then offered 64 at a time, so
+            // that the searches of a few lanes no longer hold a whole
+            // wavefront (in a dense chunk most edges are rejected by the test).
+            uint32_t* wl = S.stage + (threadIdx.x / 64) * (64 * kU);
+            uint32_t nh = 0;
+#pragma unroll
+            for (int j = 0; j < kU; j++) {
+                const uint32_t x = (uint32_t)cur[j].x, y = (uint32_t)cur[j].y;
+                bool hard = false;
+                if (base + j * kBB + threadIdx.x < t1) {
+                    if (x < V && y < V) {
+                        const uint32_t wu = S.q[x], wv = S.q[y];
+                        hard = x - (wu & 0xffffu) != y - (wv & 0xffffu) || x - (wu >> 16) != y - (wv >> 16);
+                    } else {
+                        atomicOr(B.err, 1u);
+                    }
+                }
+                const uint64_t m = __ballot(hard);
+                if (hard) wl[nh + lane_rank(m)] = x | (y << 16);
+                nh += (uint32_t)__popcll(m);
             }
-            uint64_t m;
-            const uint32_t p1 = reserve(&S.n1, a1, m);
-            if (a1) { if (p1 < cap) B.cert[off + p1] = e; else atomicOr(B.err, 2u); }
-            const uint32_t p2 = reserve(&S.n2, a2, m);
-            if (a2) { if (p2 < cap) B.cert[off + cap - 1 - p2] = e; else atomicOr(B.err, 2u); }
+            __builtin_amdgcn_wave_barrier();     // the list, written by the wavefront's lanes, is read back by them
+            for (uint32_t k0 = 0; k0 < nh; k0 += 64) {
+                const uint32_t k = k0 + __lane_id();
+                bool a1 = false, a2 = false;
+                int2 e = make_int2(0, 0);
+                if (k < nh) {
+                    const uint32_t w = wl[k];
+                    e = make_int2((int32_t)(w & 0xffffu), (int32_t)(w >> 16));
+                    loffer(S.q, (uint32_t)e.x, (uint32_t)e.y, a1, a2);
+                }
+                uint32_t p1, p2;
+                reserve2(&S.n12, a1, a2, p1, p2);
+                if (a1) { if (p1 < cap) B.cert[off + p1] = e; else atomicOr(B.err, 2u); }
+                if (a2) { if (p2 < cap) B.cert[off + cap - 1 - p2] = e; else atomicOr(B.err, 2u); }
+            }
+            __builtin_amdgcn_wave_barrier();     // every lane's reads of the list before the next step's writes
+        } else {
+#pragma unroll
+            for (int j = 0; j < kU; j++) {
+                const int2 e = cur[j];
+                const bool live = base + j * kBB + threadIdx.x < t1;
+                bool a1 = false, a2 = false;
+                if (live) {
+                    if ((uint32_t)e.x < V && (uint32_t)e.y < V) loffer(S.q, (uint32_t)e.x, (uint32_t)e.y, a1, a2);
+                    else atomicOr(B.err, 1u);
+                }
+                uint32_t p1, p2;
+                reserve2(&S.n12, a1, a2, p1, p2);
+                if (a1) { if (p1 < cap) B.cert[off + p1] = e; else atomicOr(B.err, 2u); }
+                if (a2) { if (p2 < cap) B.cert[off + cap - 1 - p2] = e; else atomicOr(B.err, 2u); }
+            }
         }
+#pragma unroll
         for (int j = 0; j < kU; j++) cur[j] = nxt[j];
     }
     __syncthreads();
@@ -214,10 +265,9 @@ __device__ void offer_region(LS& S, const BatchDev& B, int64_t off, int64_t cap,
             else atomicOr(B.err, 2u);
         }
         const uint32_t w = (uint32_t)e.x | ((uint32_t)e.y << 16);
-        uint64_t m;
-        const uint32_t p1 = reserve(&S.n1, a1, m);
+        uint32_t p1, p2;
+        reserve2(&S.n12, a1, a2, p1, p2);
         if (a1) { if (p1 < kStage) S.stage[p1] = w; else atomicOr(B.err, 2u); }
-        const uint32_t p2 = reserve(&S.n2, a2, m);
         if (a2) { if (p2 < kStage) S.stage[kStage - 1 - p2] = w; else atomicOr(B.err, 2u); }
     }
 }
@@ -249,7 +299,7 @@ __device__ void rebuild_state(LS& S, const BatchDev& B, int64_t off, int64_t cap
 }
 
 // The certificate in (offj, capj) offered to the state; accepted edges are
-// appended to region (offi, capi) after the S.n1 / S.n2 edges already there.
+// appended to region (offi, capi) after the edges S.n12 already counts.
 template <class LS>
 __device__ void offer_region_append(LS& S, const BatchDev& B, int64_t offj, int64_t capj, uint32_t n1, uint32_t n2,
                                     uint32_t V, int64_t offi, int64_t capi) {
@@ -263,10 +313,9 @@ __device__ void offer_region_append(LS& S, const BatchDev& B, int64_t offj, int6
             if ((uint32_t)e.x < V && (uint32_t)e.y < V) loffer(S.q, (uint32_t)e.x, (uint32_t)e.y, a1, a2);
             else atomicOr(B.err, 2u);
         }
-        uint64_t m;
-        const uint32_t p1 = reserve(&S.n1, a1, m);
+        uint32_t p1, p2;
+        reserve2(&S.n12, a1, a2, p1, p2);
         if (a1) { if (p1 < capi) B.cert[offi + p1] = e; else atomicOr(B.err, 2u); }
-        const uint32_t p2 = reserve(&S.n2, a2, m);
         if (a2) { if (p2 < capi) B.cert[offi + capi - 1 - p2] = e; else atomicOr(B.err, 2u); }
     }
 }
@@ -294,7 +343,7 @@ __global__ void __launch_bounds__(kBB) k_batched(BatchDev B) {
         // phase 0: chunk `node` of graph g
         certify_chunk(S, B, e0 + part_lo(Eg, Mg, node), e0 + part_lo(Eg, Mg, node + 1), V, B.noff[nidx(node)],
                       B.ncap[nidx(node)]);
-        uint32_t n1 = S.n1, n2 = S.n2;
+        uint32_t n1 = S.n12 & 0xffffu, n2 = S.n12 >> 16;
         // merge rounds: climb while this workgroup is the second of a pair to finish
         int64_t step = 1, level = 0, cb = B.cbase[g];
         for (;;) {
@@ -330,7 +379,7 @@ __global__ void __launch_bounds__(kBB) k_batched(BatchDev B) {
             if (!S.last) break;                             // the partner will merge
             // merge: Certificate(X_i u X_j), staged in LDS, written back to node i
             for (uint32_t x = threadIdx.x; x < V; x += kBB) S.q[x] = 0;
-            if (threadIdx.x == 0) { S.n1 = 0; S.n2 = 0; }
+            if (threadIdx.x == 0) S.n12 = 0;
             __syncthreads();
             const uint32_t ai1 = __hip_atomic_load(&B.ncnt[2 * nidx(i)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t ai2 = __hip_atomic_load(&B.ncnt[2 * nidx(i) + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -344,8 +393,8 @@ __global__ void __launch_bounds__(kBB) k_batched(BatchDev B) {
                 offer_region(S, B, offi, capi, ci1, ci2, (uint32_t)MaxV);
                 offer_region(S, B, offj, capj, cj1, cj2, (uint32_t)MaxV);
                 __syncthreads();
-                n1 = min(S.n1, (uint32_t)kStage);
-                n2 = min(S.n2, (uint32_t)kStage - n1);
+                n1 = min(S.n12 & 0xffffu, (uint32_t)kStage);
+                n2 = min(S.n12 >> 16, (uint32_t)kStage - n1);
                 if ((int64_t)n1 + n2 > capi) {
                     if (threadIdx.x == 0) atomicOr(B.err, 2u);
                     n1 = 0;
@@ -358,12 +407,12 @@ __global__ void __launch_bounds__(kBB) k_batched(BatchDev B) {
                 }
             } else {
                 rebuild_state(S, B, offi, capi, ci1, ci2, V);
-                if (threadIdx.x == 0) { S.n1 = ci1; S.n2 = ci2; }
+                if (threadIdx.x == 0) S.n12 = ci1 | (ci2 << 16);
                 __syncthreads();
                 offer_region_append(S, B, offj, capj, cj1, cj2, V, offi, capi);
                 __syncthreads();
-                n1 = S.n1;
-                n2 = S.n2;
+                n1 = S.n12 & 0xffffu;
+                n2 = S.n12 >> 16;
                 if ((int64_t)n1 + n2 > capi && threadIdx.x == 0) atomicOr(B.err, 2u);
             }
             __syncthreads();
