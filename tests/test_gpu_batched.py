@@ -80,6 +80,36 @@ def test_mixed_sizes_and_edge_cases(ctx):
         check_all(ctx, e, off, Vs, chunk)
 
 
+def test_shared_parent_lists(ctx):
+    # graphs that drive the per-wavefront lists of edges the shared-parent
+    # test cannot reject to both ends: paths and trees (every edge is such an
+    # edge and is accepted), complete graphs and dense multigraphs (after the
+    # first compression nearly none is), a star (every hook on one vertex),
+    # parallel edges and self-loops, at chunk sizes below and above one
+    # workgroup step (512 threads x 4 edges)
+    rng = np.random.default_rng(97)
+    graphs = []
+    for V in (2, 64, 700, 4096):
+        p = rng.permutation(V)
+        graphs.append((np.stack([p[:-1], p[1:]], 1).astype(np.int32), V))                 # a path
+    for n in (40, 90):
+        iu = np.triu_indices(n, 1)
+        k = np.stack(iu, 1).astype(np.int32)
+        graphs.append((np.concatenate([k, k[::3]])[rng.permutation(len(k) + len(k[::3]))], n))   # complete, doubled in part
+    graphs.append((np.stack([np.zeros(3000, np.int64), np.arange(1, 3001)], 1).astype(np.int32), 3001))   # a star
+    V = 500
+    dense = rng.integers(0, V, size=(60 * V, 2)).astype(np.int32)
+    dense[::17, 1] = dense[::17, 0]                                                     # self-loops
+    graphs.append((dense, V))
+    parent = np.array([rng.integers(0, i) for i in range(1, 2000)])
+    tree = np.stack([parent, np.arange(1, 2000)], 1).astype(np.int32)
+    graphs.append((np.concatenate([tree, tree[:50]])[rng.permutation(2049)], 2000))    # a tree, 50 edges doubled
+    e, off, Vs = pack(graphs)
+    for chunk in (1000, 2048, 4096, 0):
+        say("shared-parent lists chunk=%d" % chunk)
+        check_all(ctx, e, off, Vs, chunk)
+
+
 def test_replay_and_alone_vs_batched(ctx):
     b = graphgen.batched(7, n_graphs=64)
     d = torch.from_numpy(b.edges).cuda()
