@@ -6,10 +6,9 @@
 // buffer is the all-singletons state.  qs = 2 packs 16 vertices into a
 // 128-byte line; qs = 8 gives each vertex 32 bytes, so that a hook (a swap
 // performed at the memory side, which takes the line out of L2) disturbs the
-// words of fewer other vertices -- faster where the whole state stays small.
-// Parents always have smaller ids than their children (a root is hooked under
-// the smaller root), which makes every pointer chain strictly decreasing and
-// the structure acyclic.
+// words of fewer other vertices -- faster where the whole state stays small.  Parents always have smaller ids than
+// their children (a root is hooked under the smaller root), which makes
+// every pointer chain strictly decreasing and the structure acyclic.
 //
 // Concurrency.  Many lanes update one chunk's state at once.  Lanes read
 // parent words with plain cached loads; any value they see, however stale,
