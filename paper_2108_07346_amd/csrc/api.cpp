@@ -127,7 +127,10 @@ Plan make_plan(int64_t E, int32_t V, int32_t M, bool allow_solo, const TuneEntry
         // 1,024 threads of workers per CU where registers and LDS hold them
         // (large workload, M = 4096: 64 → 256 workers of 1,024 threads
         // 276 → 149 ms, but 768 workers of 512 threads slower than 512)
-        const int fit = std::min(solo_blocks_per_cu(P.solo_variant, V), std::max(1, 1024 / solo_block(P.solo_variant)));
+        // written-bits maps in LDS where they fit beside the claim tables
+        P.solo_wm = knob("BR_SOLO_WM", "wm", 1) != 0 && solo_wm_fits(V);
+        const int fit = std::min(solo_blocks_per_cu(P.solo_variant, V, P.solo_wm),
+                                 std::max(1, 1024 / solo_block(P.solo_variant)));
         const int wpc = std::max(1, std::min(knob("BR_SOLO_WPC", "wpc", fit), fit));
         // every worker needs a slot of 8 V bytes; all slots within 8 GiB
         const int64_t max_slots = std::max<int64_t>(1, (int64_t(8) << 30) / (8 * (int64_t)V));

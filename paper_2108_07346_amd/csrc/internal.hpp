@@ -111,6 +111,7 @@ struct Plan {
     int32_t solo_nbk = 0;          // phase 0 reads its chunk bucketed: buckets by the smaller endpoint (0: input order)
     int32_t solo_nbk2 = 1;         // ... times buckets by the larger endpoint (at most 1,024 in all)
     bool solo_mbk = false;         // ... and the merges inside the kernel read their siblings so too
+    bool solo_wm = false;          // written-bits maps in LDS: loads of words never stored are skipped
     int32_t workers = 0;           // persistent workgroups
     int32_t nslots = 0;            // union-find slots (workers' own + free pool)
     int32_t tile0_max = 0;         // team path: largest first-stage tile (0 = the kernel's)
@@ -151,10 +152,11 @@ struct SoloBufs {
     int64_t sbuf_stride = 0;
     int32_t nslots = 0, workers = 0;
 };
-size_t solo_lds_bytes(int32_t V);
+size_t solo_lds_bytes(int32_t V, bool wm);
+bool solo_wm_fits(int32_t V);              // the written-bits maps fit beside the claim tables
 int solo_prepare(int32_t V);       // once per process: the kernel's LDS limit
 int32_t solo_max_v();
-int solo_blocks_per_cu(int variant, int32_t V);
+int solo_blocks_per_cu(int variant, int32_t V, bool wm);
 int solo_block(int variant);       // threads per worker of a worker shape
 int solo_variants();
 void launch_solo(const Plan& P, const DevBufs& B, const SoloBufs& S, hipStream_t s);

@@ -59,7 +59,7 @@ namespace {
 struct SoloLds {
     uint32_t flag[2];               // block_any
     uint32_t n1, n2;                // counts of the node being written
-    int32_t item, slot, act, pad0;
+    int32_t item, slot, act, adopted;   // adopted: the merge continues in another worker's slot
     uint32_t tag, nj1, nj2, pad1;
 };
 
@@ -80,6 +80,7 @@ struct SoloArgs {
     int32_t nbk, bshift;            // buckets by the smaller endpoint (id >> bshift), 0: edges in input order
     int32_t nbk2, bshift2;          // ... times buckets by the larger one (id >> bshift2; 1: none)
     int32_t mbk;                    // merges inside the kernel read the sibling's certificate bucketed too
+    int32_t wm_words;               // words of one written-bits map in LDS (0: no maps)
     uint32_t* slots;                // [nslots][2][V]
     uint32_t* slot_tag;             // [nslots] current tag of each slot (kept across calls)
     uint32_t* pool;                 // [ceil(nslots / 32)] bit set = slot free
@@ -98,6 +99,8 @@ struct St {
     uint32_t* q;                    // slot base: F at q[x], F' at q[V + x]
     uint32_t V, tag, ob, mask;
     uint32_t cmask;                 // claim-table bits - 1
+    uint32_t* wm;                   // LDS: bit x of F's map (first wmw words) / F''s map set once x's
+    uint32_t wmw;                   //   word of the current tag may have been stored; null: no maps
     // x - parent(x) from x's word; a word of another tag, or one that could
     // not belong to x, reads as a root
     __device__ __forceinline__ uint32_t off(uint32_t w, uint32_t x) const {
@@ -114,18 +117,40 @@ __device__ __forceinline__ void sst(uint32_t* p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// x's word in forest F (q: that forest's words), or 0 -- which reads as a
+// root -- when x's bit in F's written-bits map (wm, the F map first, then
+// F''s, wmw words each) is clear.  A map bit is set by the lane that stores
+// the word turning x from a root into a child (the claim winner; every other
+// store rewrites a child's word), so a clear bit proves no such store
+// happened in an earlier round: the word in memory is of an older tag and
+// reads as a root anyway.  A bit set in this round may be missed, like a word
+// stored in this round; the claim tables settle that case as they do for
+// words.  In a fresh chunk most words read were never written (endpoints seen
+// for the first time, roots): the map saves their global loads.
+template <int F>
+__device__ __forceinline__ uint32_t wld(const uint32_t* wm, uint32_t wmw, const uint32_t* q, uint32_t x) {
+    const bool stored = !wm || ((wm[(F ? wmw : 0u) + (x >> 5)] >> (x & 31)) & 1u);
+    uint32_t w = 0u;
+    if (stored) w = sld(q + x);
+    return w;
+}
+template <int F>
+__device__ __forceinline__ void wmark(uint32_t* wm, uint32_t wmw, uint32_t x) {
+    if (wm) atomicOr(&wm[(F ? wmw : 0u) + (x >> 5)], 1u << (x & 31));
+}
+
 // representative of x in forest F (path halving on the way)
 template <int F>
 __device__ __forceinline__ uint32_t sfind(const St& S, uint32_t x) {
     uint32_t* q = S.q + (F ? S.V : 0u);
-    uint32_t d = S.off(sld(q + x), x);
+    uint32_t d = S.off(wld<F>(S.wm, S.wmw, q, x), x);
     while (d != 0) {
         const uint32_t p = x - d;
-        const uint32_t dp = S.off(sld(q + p), p);
+        const uint32_t dp = S.off(wld<F>(S.wm, S.wmw, q, p), p);
         if (dp == 0) return p;
         sst(q + x, S.word(d + dp));
         x = p - dp;
-        d = S.off(sld(q + x), x);
+        d = S.off(wld<F>(S.wm, S.wmw, q, x), x);
     }
     return x;
 }
@@ -186,8 +211,8 @@ __device__ __forceinline__ void bunite(const St& S, uint32_t* bm, const uint32_t
 #pragma unroll
     for (int j = 0; j < kSU; j++) {
         if (m >> j & 1) {
-            wa[j] = sld(q + u[j]);
-            wb[j] = sld(q + v[j]);
+            wa[j] = wld<F>(S.wm, S.wmw, q, u[j]);
+            wb[j] = wld<F>(S.wm, S.wmw, q, v[j]);
         }
     }
 #pragma unroll
@@ -195,8 +220,8 @@ __device__ __forceinline__ void bunite(const St& S, uint32_t* bm, const uint32_t
         if (m >> j & 1) {
             a[j] = u[j] - S.off(wa[j], u[j]);
             b[j] = v[j] - S.off(wb[j], v[j]);
-            wa[j] = (a[j] != b[j] && a[j] != u[j]) ? sld(q + a[j]) : 0u;
-            wb[j] = (a[j] != b[j] && b[j] != v[j]) ? sld(q + b[j]) : 0u;
+            wa[j] = (a[j] != b[j] && a[j] != u[j]) ? wld<F>(S.wm, S.wmw, q, a[j]) : 0u;
+            wb[j] = (a[j] != b[j] && b[j] != v[j]) ? wld<F>(S.wm, S.wmw, q, b[j]) : 0u;
         }
     }
     same = won = lost = 0;
@@ -223,7 +248,10 @@ __device__ __forceinline__ void bunite(const St& S, uint32_t* bm, const uint32_t
                 const uint32_t bit = 1u << (c & 31);
                 r = (atomicOr(&bm[c >> 5], bit) & bit) ? 2u : 1u;
                 cl[j] = c;
-                if (r == 1) sst(q + hi, S.word(hi - lo));
+                if (r == 1) {
+                    sst(q + hi, S.word(hi - lo));
+                    wmark<F>(S.wm, S.wmw, hi);
+                }
             }
         }
         const uint32_t jb = (m >> j & 1) << j;
@@ -235,7 +263,7 @@ __device__ __forceinline__ void bunite(const St& S, uint32_t* bm, const uint32_t
 
 // Full path compression of a slot (no hook runs concurrently).
 template <int kSB>
-__device__ void compress_slot(const St& S) {
+__device__ __forceinline__ void compress_slot(const St& S) {
     for (int f = 0; f < 2; f++) {
         uint32_t* q = S.q + (f ? S.V : 0u);
         for (uint32_t x = threadIdx.x; x < S.V; x += kSB) {
@@ -257,7 +285,7 @@ __device__ void compress_slot(const St& S) {
 // edges of a tile and offers them together; edges that lost a race are
 // retried, after a barrier, until none is left.
 template <int kSB, int kSU>
-__device__ void stream(SoloLds& L, const SoloArgs& A, const St& S, uint32_t* bm1, uint32_t* bm2, int src, int64_t t0,
+__device__ __forceinline__ void stream(SoloLds& L, const SoloArgs& A, const St& S, uint32_t* bm1, uint32_t* bm2, int src, int64_t t0,
                        int64_t t1, int64_t roff, int64_t rcap, uint32_t rn1, uint32_t rn2, uint32_t stage0, bool out,
                        bool stages, int64_t off, int64_t cap, int& ph, const int2* sb = nullptr) {
     constexpr int64_t kST = (int64_t)kSB * kSU;      // edges per tile
@@ -334,7 +362,7 @@ __device__ __forceinline__ int64_t part_lo(int64_t E, int64_t M, int64_t i) { re
 // LDS.  Returns the number of edges copied (every lane).
 constexpr int kMaxBuckets = 1024;
 template <int kSB, class Load>
-__device__ int64_t bucket_into(const SoloArgs& A, int64_t n, Load load, uint32_t bad, int2* sb, uint32_t V,
+__device__ __forceinline__ int64_t bucket_into(const SoloArgs& A, int64_t n, Load load, uint32_t bad, int2* sb, uint32_t V,
                                uint32_t* cnt) {
     uint32_t& total = cnt[kMaxBuckets];
     const int nb = A.nbk * A.nbk2;
@@ -385,7 +413,7 @@ struct RegionLoad {
 };
 
 // a free slot from the pool (thread 0), -1 if none; acquire on success
-__device__ int pool_pop(const SoloArgs& A) {
+__device__ __forceinline__ int pool_pop(const SoloArgs& A) {
     const int words = (A.nslots + 31) / 32;
     for (int w = 0; w < words; w++) {
         uint32_t v = __hip_atomic_load(&A.pool[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -403,7 +431,7 @@ __device__ int pool_pop(const SoloArgs& A) {
 }
 
 // give a slot back (thread 0; the caller has released what it wrote)
-__device__ void pool_push(const SoloArgs& A, int s) { atomicOr(&A.pool[s >> 5], 1u << (s & 31)); }
+__device__ __forceinline__ void pool_push(const SoloArgs& A, int s) { atomicOr(&A.pool[s >> 5], 1u << (s & 31)); }
 
 }  // namespace
 
@@ -413,6 +441,8 @@ __global__ void __launch_bounds__(kSB) k_solo(SoloArgs A) {
     SoloLds& L = *reinterpret_cast<SoloLds*>(lds_raw);
     uint32_t* bm1 = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(lds_raw) + sizeof(SoloLds));
     uint32_t* bm2 = bm1 + A.bm_words;
+    // after the claim tables and the bucket counters: the written-bits maps
+    uint32_t* wmap = A.wm_words ? bm2 + A.bm_words + (kMaxBuckets + 1) : nullptr;
     const uint32_t V = (uint32_t)A.V;
     const uint32_t mask = A.ob >= 32 ? 0xffffffffu : ((1u << A.ob) - 1u);
     const uint32_t tag_max = A.ob >= 31 ? 1u : ((1u << (32 - A.ob)) - 1u);
@@ -438,10 +468,13 @@ __global__ void __launch_bounds__(kSB) k_solo(SoloArgs A) {
             L.n1 = L.n2 = 0;
         }
         __syncthreads();
-        St S{A.slots + (size_t)L.slot * 2 * V, V, L.tag, (uint32_t)A.ob, mask, 32u * (uint32_t)A.bm_words - 1u};
+        St S{A.slots + (size_t)L.slot * 2 * V, V, L.tag, (uint32_t)A.ob, mask, 32u * (uint32_t)A.bm_words - 1u,
+             wmap, (uint32_t)A.wm_words};
         if (L.act == 1)         // tags ran out: every word back to "root"
             for (uint32_t x = threadIdx.x; x < 2 * V; x += kSB) S.q[x] = 0u;
         for (int x = threadIdx.x; x < 2 * A.bm_words; x += kSB) bm1[x] = 0u;
+        if (wmap)               // a fresh tag: no word of it stored yet
+            for (int x = threadIdx.x; x < 2 * A.wm_words; x += kSB) wmap[x] = 0u;
         __syncthreads();
         {
             // the chunk in input order, or bucketed into the worker's buffer
@@ -491,6 +524,7 @@ __global__ void __launch_bounds__(kSB) k_solo(SoloArgs A) {
             __syncthreads();   // every lane's writes (region, state) done before thread 0 publishes
             if (threadIdx.x == 0) {
                 int spare = -1;
+                L.adopted = 0;
                 if (node == i) {       // park my state for the right node's worker, in case it comes last
                     spare = pool_pop(A);
                     A.park[i] = spare >= 0 ? (uint32_t)L.slot + 1 : 0u;
@@ -513,6 +547,7 @@ __global__ void __launch_bounds__(kSB) k_solo(SoloArgs A) {
                             pool_push(A, L.slot);
                             L.slot = (int32_t)p - 1;
                             A.park[i] = 0;
+                            L.adopted = 1;
                             act = 1;
                         } else {
                             act = 2;   // the left state is gone: rebuild it in my slot
@@ -536,7 +571,10 @@ __global__ void __launch_bounds__(kSB) k_solo(SoloArgs A) {
             if (act == 0) break;
             S.q = A.slots + (size_t)L.slot * 2 * V;
             S.tag = L.tag;
+            if (L.adopted) S.wm = nullptr;     // my maps describe my old slot, not the adopted one
             for (int x = threadIdx.x; x < 2 * A.bm_words; x += kSB) bm1[x] = 0u;
+            if (act >= 2 && S.wm)              // rebuilt under a fresh tag
+                for (int x = threadIdx.x; x < 2 * A.wm_words; x += kSB) S.wm[x] = 0u;
             if (act == 3)
                 for (uint32_t x = threadIdx.x; x < 2 * V; x += kSB) S.q[x] = 0u;
             const int64_t offi = A.off[i], capi = A.cap[i];
@@ -598,10 +636,14 @@ static int32_t claim_words(int32_t V) {
     return (int32_t)(bits / 32);
 }
 
-// the control block, the two claim tables, the bucket counters of phase 0
-size_t solo_lds_bytes(int32_t V) {
-    return sizeof(SoloLds) + 2 * 4 * (size_t)claim_words(V) + 4 * (size_t)(kMaxBuckets + 1);
+// the control block, the two claim tables, the bucket counters of phase 0,
+// and (wm) the two written-bits maps of V bits each
+static int32_t written_words(int32_t V) { return (int32_t)(((int64_t)V + 31) / 32); }
+size_t solo_lds_bytes(int32_t V, bool wm) {
+    return sizeof(SoloLds) + 2 * 4 * (size_t)claim_words(V) + 4 * (size_t)(kMaxBuckets + 1) +
+           (wm ? 2 * 4 * (size_t)written_words(V) : 0);
 }
+bool solo_wm_fits(int32_t V) { return solo_lds_bytes(V, true) <= (size_t)g_max_lds; }
 
 // Worker shapes: (threads, edges per thread offered together), chosen per
 // plan (the tuner measures them).
@@ -619,7 +661,7 @@ int solo_variants() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
 int solo_block(int variant) { return kVariants[std::max(0, std::min(variant, solo_variants() - 1))].sb; }
 
 int solo_prepare(int32_t V) {
-    const size_t b = solo_lds_bytes(V);
+    const size_t b = solo_lds_bytes(V, false);
     if (b > (size_t)g_max_lds) return fail(BR_EINTERNAL, "solo: V = %d needs %zu bytes of LDS", V, b);
     static std::once_flag once;
     static hipError_t e = hipSuccess;
@@ -663,6 +705,7 @@ void launch_solo(const Plan& P, const DevBufs& B, const SoloBufs& Sb, hipStream_
     A.bshift = shift_for(A.nbk);
     A.bshift2 = shift_for(A.nbk2);
     A.mbk = P.solo_mbk ? 1 : 0;
+    A.wm_words = P.solo_wm ? written_words(P.V) : 0;
     A.slots = Sb.slots;
     A.slot_tag = Sb.slot_tag;
     A.pool = Sb.pool;
@@ -677,7 +720,7 @@ void launch_solo(const Plan& P, const DevBufs& B, const SoloBufs& Sb, hipStream_
     A.err = B.err;
     const SoloVariant& k = kVariants[std::max(0, std::min(P.solo_variant, solo_variants() - 1))];
     void* args[] = {&A};
-    (void)hipLaunchKernel(k.fn, dim3((unsigned)Sb.workers), dim3(k.sb), args, solo_lds_bytes(P.V), s);
+    (void)hipLaunchKernel(k.fn, dim3((unsigned)Sb.workers), dim3(k.sb), args, solo_lds_bytes(P.V, P.solo_wm), s);
 }
 
 // largest V of the plan (the slots hold 8 V bytes each, all of them within
@@ -685,11 +728,11 @@ void launch_solo(const Plan& P, const DevBufs& B, const SoloBufs& Sb, hipStream_
 int32_t solo_max_v() { return 1 << 27; }
 
 // workgroups of the variant that fit on one CU with the LDS V needs
-int solo_blocks_per_cu(int variant, int32_t V) {
+int solo_blocks_per_cu(int variant, int32_t V, bool wm) {
     const SoloVariant& k = kVariants[std::max(0, std::min(variant, solo_variants() - 1))];
     int n = 0;
     if (solo_prepare(V) != BR_OK ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k.fn, k.sb, solo_lds_bytes(V)) != hipSuccess) {
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k.fn, k.sb, solo_lds_bytes(V, wm)) != hipSuccess) {
         (void)hipGetLastError();
         return 1;
     }
