@@ -64,12 +64,14 @@ def test_forced_solo_edge_cases(ctx, M):
     say("M=%d: all cases exact" % M)
 
 
-@pytest.mark.parametrize("order", ["bucketed", "input", "bucketed_merges"])
+@pytest.mark.parametrize("order", ["bucketed", "input", "bucketed_merges", "no_maps"])
 def test_forced_solo_both_chunk_orders(ctx, monkeypatch, order):
     if order == "input":
         monkeypatch.setenv("BR_SOLO_NBK", "0")
     if order == "bucketed_merges":      # the merges inside the kernel bucket their siblings too
         monkeypatch.setenv("BR_SOLO_MBK", "1")
+    if order == "no_maps":              # every word loaded, no written-bits maps
+        monkeypatch.setenv("BR_SOLO_WM", "0")
     g = graphgen.planted(77, k=40, vc=6000, p=0.05, n_extra=2, n_pend=60)
     want = oracle.bridges(g.edges, g.V)
     for M in (16, 257):
@@ -102,4 +104,35 @@ def test_slot_tags_run_out_and_the_slot_is_cleared(monkeypatch):
             assert np.array_equal(got, want), call
             say("call %d exact" % call)
     assert np.array_equal(got, want)
+    ctx.close()
+
+
+def test_slot_tags_run_out_with_written_bits_maps(monkeypatch):
+    # V = 300,000: 19 bits of offset leave 13 of tag (8,191 chunks per slot
+    # before it is cleared), and the maps fit in LDS; 100,000 chunks of four
+    # edges spread over the slots (three per worker, handed round through the
+    # pool and the parking table) give each slot ~130 chunks per call, so 150
+    # calls drive the slots through the clear (twice over) with the maps in use
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_07346_amd as br
+    monkeypatch.setenv("BR_SOLO", "1")
+    rng = np.random.default_rng(9)
+    V = 300000
+    hub = rng.permutation(V)[:20000]
+    e = np.concatenate([np.stack([hub[:-1], hub[1:]], 1),                   # a path over 20,000 vertices
+                        np.stack([hub[::5][:-1], hub[::5][1:]], 1),         # chords over part of it
+                        rng.integers(0, V, size=(376001, 2))]).astype(np.int32)
+    e = e[rng.permutation(len(e))]
+    want = oracle.bridges(e, V)
+    ctx = br.Context(0)
+    ctx.set_profiling(1)
+    d = dev(e)
+    for call in range(150):
+        got = ctx.find(d, V, 100000)
+        if call == 0:
+            assert ctx.profile()["plan_kind"] == 1
+        if call % 25 == 24:
+            assert np.array_equal(got, want), call
+            say("call %d exact" % call)
     ctx.close()
