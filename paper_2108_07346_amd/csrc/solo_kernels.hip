@@ -646,7 +646,8 @@ size_t solo_lds_bytes(int32_t V, bool wm) {
 bool solo_wm_fits(int32_t V) { return solo_lds_bytes(V, true) <= (size_t)g_max_lds; }
 
 // Worker shapes: (threads, edges per thread offered together), chosen per
-// plan (the tuner measures them).
+// plan (the tuner measures them).  Three edges per thread at 1,024 threads
+// still fits the 128 registers such a workgroup allows; four does not.
 struct SoloVariant {
     const void* fn;
     int sb;
@@ -656,6 +657,7 @@ static const SoloVariant kVariants[] = {
     {reinterpret_cast<const void*>(&k_solo<1024, 1>), 1024},
     {reinterpret_cast<const void*>(&k_solo<1024, 2>), 1024},
     {reinterpret_cast<const void*>(&k_solo<512, 1>), 512},
+    {reinterpret_cast<const void*>(&k_solo<1024, 3>), 1024},
 };
 int solo_variants() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
 int solo_block(int variant) { return kVariants[std::max(0, std::min(variant, solo_variants() - 1))].sb; }

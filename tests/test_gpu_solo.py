@@ -64,8 +64,10 @@ def test_forced_solo_edge_cases(ctx, M):
     say("M=%d: all cases exact" % M)
 
 
-@pytest.mark.parametrize("order", ["bucketed", "input", "bucketed_merges", "no_maps"])
+@pytest.mark.parametrize("order", ["bucketed", "input", "bucketed_merges", "no_maps", "three_edges"])
 def test_forced_solo_both_chunk_orders(ctx, monkeypatch, order):
+    if order == "three_edges":          # 1,024-thread workers offering three edges per thread
+        monkeypatch.setenv("BR_SOLO_VARIANT", "4")
     if order == "input":
         monkeypatch.setenv("BR_SOLO_NBK", "0")
     if order == "bucketed_merges":      # the merges inside the kernel bucket their siblings too
