@@ -65,15 +65,20 @@ def generate_checked(name, head):
     return g
 
 
-def run_both_final_steps(name, d, V, Ms, want):
+def run_both_final_steps(name, d, V, Ms, want, tuned=False):
+    # the plan the size rules give, then (tuned) the one the tuner picks for
+    # this shape -- the launch configuration bench.py times
     import paper_2108_07346_amd as br
     ctx = br.Context(0)
     for M in Ms:
-        for mode in (1, 0):
-            ctx.set_final_step(mode)
-            say("%s: M=%d final step %d" % (name, M, mode))
-            got = ctx.find(d, V, M)
-            assert np.array_equal(got, want), (M, mode)
+        for plan in (("size rules", "tuned") if tuned else ("size rules",)):
+            if plan == "tuned":
+                say("%s: M=%d tuner %s" % (name, M, ctx.autotune(d, V, M)))
+            for mode in (1, 0):
+                ctx.set_final_step(mode)
+                say("%s: M=%d %s, final step %d" % (name, M, plan, mode))
+                got = ctx.find(d, V, M)
+                assert np.array_equal(got, want), (M, plan, mode)
     ctx.close()
 
 
@@ -89,7 +94,7 @@ def test_large_workload_bit_exact():
     d = torch.from_numpy(g.edges).cuda()
     V = g.V
     del g
-    run_both_final_steps("large", d, V, (4096,), want)
+    run_both_final_steps("large", d, V, (4096,), want, tuned=True)
 
 
 @pytest.mark.skipif(not os.path.exists(os.path.join(HERE, "large_blocked_bridges.txt")),
