@@ -80,12 +80,14 @@ def test_every_tuner_candidate_is_exact():
     e = rng.integers(0, V, size=(600_000, 2)).astype(np.int32)
     cases.append((e, V, 256, [{"BR_SOLO": "0", "BR_TILE0": "1024"}, {"BR_SOLO": "0", "BR_PREM": "1"},
                               {"BR_SOLO": "1", "BR_SOLO_TOP": "1", "BR_PREM": "1"},
-                              {"BR_SOLO": "1", "BR_SOLO_NBK": "0"}, {"BR_SOLO": "1", "BR_SOLO_NBK": "16", "BR_SOLO_NBK2": "1"}] +
-                  [{"BR_SOLO": "1", "BR_SOLO_VARIANT": str(v), "BR_SOLO_TOP": str(t)} for v in range(4) for t in (0, 3)]))
+                              {"BR_SOLO": "1", "BR_SOLO_NBK": "0"}, {"BR_SOLO": "1", "BR_SOLO_NBK": "16", "BR_SOLO_NBK2": "1"},
+                              {"BR_SOLO": "1", "BR_SOLO_TOP": "2", "BR_SOLO_MBK": "1"},
+                              {"BR_SOLO": "1", "BR_SOLO_TOP": "2", "BR_SOLO_WM": "0"}] +
+                  [{"BR_SOLO": "1", "BR_SOLO_VARIANT": str(v), "BR_SOLO_TOP": str(t)} for v in range(5) for t in (0, 3)]))
     V2 = 700_000
     e2 = rng.integers(0, V2, size=(1_400_000, 2)).astype(np.int32)
     cases.append((e2, V2, 512, [{"BR_SOLO": "1", "BR_SOLO_VARIANT": str(v), "BR_SOLO_TOP": str(t)}
-                                for v in (0, 2) for t in (0, 2)]))
+                                for v in (0, 2, 4) for t in (0, 2)]))
     code = r"""
 import os, sys
 sys.path.insert(0, %r)
