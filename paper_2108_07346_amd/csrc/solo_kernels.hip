@@ -60,7 +60,7 @@ struct SoloLds {
     uint32_t flag[2];               // block_any
     uint32_t n1, n2;                // counts of the node being written
     int32_t item, slot, act, adopted;   // adopted: the merge continues in another worker's slot
-    uint32_t tag, nj1, nj2, pad1;
+    uint32_t tag, nj1, nj2, groot;      // groot: the F root most sampled vertices reach (before a merge)
 };
 
 // kernel parameters
@@ -101,6 +101,11 @@ struct St {
     uint32_t cmask;                 // claim-table bits - 1
     uint32_t* wm;                   // LDS: bit x of F's map (first wmw words) / F''s map set once x's
     uint32_t wmw;                   //   word of the current tag may have been stored; null: no maps
+    uint32_t* gm;                   // LDS (in place of F's map): bit x set if x was in one component of F
+                                    //   (the largest, as sampled) when the slot was last compressed; null: none
+    // the written-bits map of forest F (F's is taken by gm while gm is set)
+    template <int F>
+    __device__ __forceinline__ uint32_t* mapf() const { return (F == 0 && gm) ? nullptr : wm; }
     // x - parent(x) from x's word; a word of another tag, or one that could
     // not belong to x, reads as a root
     __device__ __forceinline__ uint32_t off(uint32_t w, uint32_t x) const {
@@ -143,14 +148,15 @@ __device__ __forceinline__ void wmark(uint32_t* wm, uint32_t wmw, uint32_t x) {
 template <int F>
 __device__ __forceinline__ uint32_t sfind(const St& S, uint32_t x) {
     uint32_t* q = S.q + (F ? S.V : 0u);
-    uint32_t d = S.off(wld<F>(S.wm, S.wmw, q, x), x);
+    const uint32_t* wm = S.mapf<F>();
+    uint32_t d = S.off(wld<F>(wm, S.wmw, q, x), x);
     while (d != 0) {
         const uint32_t p = x - d;
-        const uint32_t dp = S.off(wld<F>(S.wm, S.wmw, q, p), p);
+        const uint32_t dp = S.off(wld<F>(wm, S.wmw, q, p), p);
         if (dp == 0) return p;
         sst(q + x, S.word(d + dp));
         x = p - dp;
-        d = S.off(wld<F>(S.wm, S.wmw, q, x), x);
+        d = S.off(wld<F>(wm, S.wmw, q, x), x);
     }
     return x;
 }
@@ -207,21 +213,23 @@ template <int F, int kSU>
 __device__ __forceinline__ void bunite(const St& S, uint32_t* bm, const uint32_t (&u)[kSU], const uint32_t (&v)[kSU],
                                        uint32_t m, uint32_t& same, uint32_t& won, uint32_t& lost, uint32_t (&cl)[kSU]) {
     uint32_t* q = S.q + (F ? S.V : 0u);
+    uint32_t* wm = S.mapf<F>();
+    const uint32_t mm = m;
     uint32_t a[kSU], b[kSU], wa[kSU], wb[kSU];
 #pragma unroll
     for (int j = 0; j < kSU; j++) {
-        if (m >> j & 1) {
-            wa[j] = wld<F>(S.wm, S.wmw, q, u[j]);
-            wb[j] = wld<F>(S.wm, S.wmw, q, v[j]);
+        if (mm >> j & 1) {
+            wa[j] = wld<F>(wm, S.wmw, q, u[j]);
+            wb[j] = wld<F>(wm, S.wmw, q, v[j]);
         }
     }
 #pragma unroll
     for (int j = 0; j < kSU; j++) {
-        if (m >> j & 1) {
+        if (mm >> j & 1) {
             a[j] = u[j] - S.off(wa[j], u[j]);
             b[j] = v[j] - S.off(wb[j], v[j]);
-            wa[j] = (a[j] != b[j] && a[j] != u[j]) ? wld<F>(S.wm, S.wmw, q, a[j]) : 0u;
-            wb[j] = (a[j] != b[j] && b[j] != v[j]) ? wld<F>(S.wm, S.wmw, q, b[j]) : 0u;
+            wa[j] = (a[j] != b[j] && a[j] != u[j]) ? wld<F>(wm, S.wmw, q, a[j]) : 0u;
+            wb[j] = (a[j] != b[j] && b[j] != v[j]) ? wld<F>(wm, S.wmw, q, b[j]) : 0u;
         }
     }
     same = won = lost = 0;
@@ -230,7 +238,7 @@ __device__ __forceinline__ void bunite(const St& S, uint32_t* bm, const uint32_t
         // outcome r: 0 connected already, 1 hooked, 2 lost a race (the three
         // masks are updated without branches: no selected-by-address stores)
         uint32_t r = 0;
-        if (m >> j & 1) {
+        if (mm >> j & 1) {
             uint32_t x = a[j], y = b[j];
             if (x != y) {
                 if (S.off(wa[j], x) != 0) {
@@ -250,7 +258,7 @@ __device__ __forceinline__ void bunite(const St& S, uint32_t* bm, const uint32_t
                 cl[j] = c;
                 if (r == 1) {
                     sst(q + hi, S.word(hi - lo));
-                    wmark<F>(S.wm, S.wmw, hi);
+                    wmark<F>(wm, S.wmw, hi);
                 }
             }
         }
@@ -261,17 +269,31 @@ __device__ __forceinline__ void bunite(const St& S, uint32_t* bm, const uint32_t
     }
 }
 
-// Full path compression of a slot (no hook runs concurrently).
+// Full path compression of a slot (no hook runs concurrently).  With gm,
+// also the component map of F: bit x set iff x's root is groot (gm has
+// ceil(V / 32) words; each wavefront writes the bits of its 64 vertices).
 template <int kSB>
-__device__ __forceinline__ void compress_slot(const St& S) {
+__device__ __forceinline__ void compress_slot(const St& S, uint32_t* gm = nullptr, uint32_t groot = 0) {
+    const uint32_t gwords = (S.V + 31) / 32;
     for (int f = 0; f < 2; f++) {
         uint32_t* q = S.q + (f ? S.V : 0u);
-        for (uint32_t x = threadIdx.x; x < S.V; x += kSB) {
-            const uint32_t d = S.off(sld(q + x), x);
-            if (d == 0) continue;
-            uint32_t r = x - d;
-            for (uint32_t e = S.off(sld(q + r), r); e != 0; e = S.off(sld(q + r), r)) r -= e;
-            if (r != x - d) sst(q + x, S.word(x - r));
+        for (uint32_t x0 = 0; x0 < S.V; x0 += kSB) {      // the same trip count for every lane
+            const uint32_t x = x0 + threadIdx.x;
+            uint32_t r = x;
+            if (x < S.V) {
+                const uint32_t d = S.off(sld(q + x), x);
+                if (d != 0) {
+                    r = x - d;
+                    for (uint32_t e = S.off(sld(q + r), r); e != 0; e = S.off(sld(q + r), r)) r -= e;
+                    if (r != x - d) sst(q + x, S.word(x - r));
+                }
+            }
+            if (f == 0 && gm) {
+                const uint64_t m = __ballot(x < S.V && r == groot);
+                const uint32_t w0 = (x0 + (threadIdx.x & ~63u)) >> 5;
+                if ((threadIdx.x & 63u) == 0 && w0 < gwords) gm[w0] = (uint32_t)m;
+                if ((threadIdx.x & 63u) == 0 && w0 + 1 < gwords) gm[w0 + 1] = (uint32_t)(m >> 32);
+            }
         }
     }
 }
@@ -321,6 +343,15 @@ __device__ __forceinline__ void stream(SoloLds& L, const SoloArgs& A, const St& 
                 if (u[j] < S.V && v[j] < S.V) pend |= 1u << j;
                 else atomicOr(A.err, src == 0 ? 1u : 2u);
             }
+        }
+        // an edge with both endpoints in the component map's component is
+        // rejected by F without a search (components only grow, so they are
+        // still joined): it starts at F'
+        if (S.gm) {
+#pragma unroll
+            for (int j = 0; j < kSU; j++)
+                if ((pend >> j & 1) && ((S.gm[u[j] >> 5] >> (u[j] & 31)) & (S.gm[v[j] >> 5] >> (v[j] & 31)) & 1u))
+                    st1 |= 1u << j;
         }
         uint32_t c1[kSU], c2[kSU];                         // claim bits this lane set
         for (;;) {
@@ -469,7 +500,7 @@ __global__ void __launch_bounds__(kSB) k_solo(SoloArgs A) {
         }
         __syncthreads();
         St S{A.slots + (size_t)L.slot * 2 * V, V, L.tag, (uint32_t)A.ob, mask, 32u * (uint32_t)A.bm_words - 1u,
-             wmap, (uint32_t)A.wm_words};
+             wmap, (uint32_t)A.wm_words, nullptr};
         if (L.act == 1)         // tags ran out: every word back to "root"
             for (uint32_t x = threadIdx.x; x < 2 * V; x += kSB) S.q[x] = 0u;
         for (int x = threadIdx.x; x < 2 * A.bm_words; x += kSB) bm1[x] = 0u;
@@ -572,6 +603,7 @@ __global__ void __launch_bounds__(kSB) k_solo(SoloArgs A) {
             S.q = A.slots + (size_t)L.slot * 2 * V;
             S.tag = L.tag;
             if (L.adopted) S.wm = nullptr;     // my maps describe my old slot, not the adopted one
+            if (L.adopted || act >= 2) S.gm = nullptr;   // and so does the component map
             for (int x = threadIdx.x; x < 2 * A.bm_words; x += kSB) bm1[x] = 0u;
             if (act >= 2 && S.wm)              // rebuilt under a fresh tag
                 for (int x = threadIdx.x; x < 2 * A.wm_words; x += kSB) S.wm[x] = 0u;
@@ -590,7 +622,24 @@ __global__ void __launch_bounds__(kSB) k_solo(SoloArgs A) {
             const int64_t offj = A.off[j], capj = A.cap[j];
             const uint32_t nj1 = min(L.nj1, (uint32_t)capj), nj2 = min(L.nj2, (uint32_t)capj - nj1);
             if ((int64_t)nj1 + nj2 >= (int64_t)V / 2) {
-                compress_slot<kSB>(S);
+                if (wmap) {
+                    // the root most of 64 evenly spread vertices reach in F
+                    // (the largest component, as a rule): its members get
+                    // marked while the slot is compressed
+                    if (threadIdx.x < 64) {
+                        const uint32_t r = sfind<0>(S, (uint32_t)(((uint64_t)threadIdx.x * V) >> 6));
+                        uint32_t c = 0;
+                        for (int k = 0; k < 64; k++) c += __shfl(r, k) == r ? 1u : 0u;
+                        uint32_t key = (c << 6) | threadIdx.x;
+                        for (int o = 32; o > 0; o >>= 1) key = max(key, (uint32_t)__shfl_xor((int)key, o));
+                        if (threadIdx.x == (key & 63u)) L.groot = r;
+                    }
+                    __syncthreads();
+                    compress_slot<kSB>(S, wmap, L.groot);
+                    S.gm = wmap;                   // F's written-bits map gives way to the component map
+                } else {
+                    compress_slot<kSB>(S);
+                }
                 __syncthreads();
             }
             int64_t nj = (int64_t)nj1 + nj2;
