@@ -144,12 +144,12 @@ __device__ __forceinline__ void wmark(uint32_t* wm, uint32_t wmw, uint32_t x) {
     if (wm) atomicOr(&wm[(F ? wmw : 0u) + (x >> 5)], 1u << (x & 31));
 }
 
-// representative of x in forest F (path halving on the way)
+// representative of x in forest F (path halving on the way), d = x - its
+// parent as read from x's word already (0: x reads as a root)
 template <int F>
-__device__ __forceinline__ uint32_t sfind(const St& S, uint32_t x) {
+__device__ __forceinline__ uint32_t sfind_at(const St& S, uint32_t x, uint32_t d) {
     uint32_t* q = S.q + (F ? S.V : 0u);
     const uint32_t* wm = S.mapf<F>();
-    uint32_t d = S.off(wld<F>(wm, S.wmw, q, x), x);
     while (d != 0) {
         const uint32_t p = x - d;
         const uint32_t dp = S.off(wld<F>(wm, S.wmw, q, p), p);
@@ -159,6 +159,10 @@ __device__ __forceinline__ uint32_t sfind(const St& S, uint32_t x) {
         d = S.off(wld<F>(wm, S.wmw, q, x), x);
     }
     return x;
+}
+template <int F>
+__device__ __forceinline__ uint32_t sfind(const St& S, uint32_t x) {
+    return sfind_at<F>(S, x, S.off(wld<F>(S.mapf<F>(), S.wmw, S.q + (F ? S.V : 0u), x), x));
 }
 
 // wavefront-aggregated reservation of slots on an LDS counter
@@ -241,12 +245,13 @@ __device__ __forceinline__ void bunite(const St& S, uint32_t* bm, const uint32_t
         if (mm >> j & 1) {
             uint32_t x = a[j], y = b[j];
             if (x != y) {
+                // the parents' words loaded above start the finds
                 if (S.off(wa[j], x) != 0) {
-                    x = sfind<F>(S, x);
+                    x = sfind_at<F>(S, x, S.off(wa[j], x));
                     sst(q + u[j], S.word(u[j] - x));
                 }
                 if (S.off(wb[j], y) != 0) {
-                    y = sfind<F>(S, y);
+                    y = sfind_at<F>(S, y, S.off(wb[j], y));
                     sst(q + v[j], S.word(v[j] - y));
                 }
             }
