@@ -61,6 +61,7 @@ struct SoloLds {
     uint32_t n1, n2;                // counts of the node being written
     int32_t item, slot, act, adopted;   // adopted: the merge continues in another worker's slot
     uint32_t tag, nj1, nj2, groot;      // groot: the F root most sampled vertices reach (before a merge)
+    uint32_t nr, nr_snap;           // phase 0: edges waiting for a retry at the front of the worker's copy
 };
 
 // kernel parameters
@@ -188,12 +189,14 @@ __device__ __forceinline__ void emit(SoloLds& L, const SoloArgs& A, int64_t off,
 // visible after it) that also tells every lane whether any lane had p set,
 // and empties the claim tables for the next round: every set bit has exactly
 // one winner, which clears it (bits c1[j] of table t1 for j in mask w1, and
-// c2/t2/w2 likewise).
+// c2/t2/w2 likewise).  It also copies the count of waiting edges for the
+// lanes to read until the next such barrier.
 template <int kSU>
 __device__ __forceinline__ bool block_any(SoloLds& L, bool p, int& ph, uint32_t* t1, const uint32_t (&c1)[kSU],
                                           uint32_t w1, uint32_t* t2, const uint32_t (&c2)[kSU], uint32_t w2) {
     __syncthreads();
     if (p) L.flag[ph] = 1u;
+    if (threadIdx.x == 0) L.nr_snap = L.nr;
 #pragma unroll
     for (int j = 0; j < kSU; j++) {
         if (w1 >> j & 1) atomicAnd(&t1[c1[j] >> 5], ~(1u << (c1[j] & 31)));
@@ -305,7 +308,12 @@ __device__ __forceinline__ void compress_slot(const St& S, uint32_t* gm = nullpt
 
 // Offer a run of edges to the slot.  src 0: the input edge list, ids checked;
 // src 1: a node region's certificate (F part [0, rn1), F' part after it);
-// src 2: the worker's reordered copy of its chunk (sb).
+// src 2: the worker's reordered copy of its chunk (sb).  In phase 0 over sb,
+// the edges of a tile that lose a race do not hold the workgroup for a round
+// of their own: they wait at the front of sb, over edges already offered
+// (while that room is certain to hold a whole tile's losses), with their
+// stage in bit 31 of the first id, and are offered again as tiles of their
+// own after the last one (any order of the edges gives maximal forests).
 // stage0: where every edge starts (0: F, then F' if F rejects it; 1: F'
 // only).  out: write accepted edges to (off, cap).  stages: compress the slot
 // every cmp_first edges up to 2V, then at 8V (phase 0).  Each thread takes kSU
@@ -314,17 +322,29 @@ __device__ __forceinline__ void compress_slot(const St& S, uint32_t* gm = nullpt
 template <int kSB, int kSU>
 __device__ __forceinline__ void stream(SoloLds& L, const SoloArgs& A, const St& S, uint32_t* bm1, uint32_t* bm2, int src, int64_t t0,
                        int64_t t1, int64_t roff, int64_t rcap, uint32_t rn1, uint32_t rn2, uint32_t stage0, bool out,
-                       bool stages, int64_t off, int64_t cap, int& ph, const int2* sb = nullptr) {
+                       bool stages, int64_t off, int64_t cap, int& ph, int2* sb = nullptr) {
     constexpr int64_t kST = (int64_t)kSB * kSU;      // edges per tile
     // phase 0: compress after cmp_first edges, then every cmp_first edges
     // up to 2 V, then at 8 V
     int64_t next_cmp = stages ? t0 + A.cmp_first : INT64_MAX;
     auto load = [&](int64_t i) -> int2 {
         if (src == 0) return i < A.split ? A.edges[i] : A.edges2[i - A.split];
-        if (src == 2) return sb[i];
+        if (src == 2) return sb[i < t1 ? i : i - t1];        // past t1: the waiting edges
         return A.cert[i < rn1 ? roff + i : roff + rcap - rn2 + (i - rn1)];
     };
-    for (int64_t base = t0; base < t1; base += kST) {
+    const bool defer = sb != nullptr && stages;
+    bool late = false;                                   // tiles of waiting edges (indices t1 + k: sb[k])
+    int64_t tend = t1;
+    for (int64_t base = t0;; base += kST) {
+        if (base >= tend) {
+            if (!defer || late) break;
+            late = true;
+            base = t1;
+            tend = t1 + (int64_t)L.nr_snap;
+            if (base >= tend) break;
+        }
+        // losses of this tile wait in sb if [nr, nr + kST) lies below it
+        const bool dtile = defer && !late && (int64_t)L.nr_snap + kST <= base;
         if (base >= next_cmp) {
             __syncthreads();
             compress_slot<kSB>(S);
@@ -338,13 +358,17 @@ __device__ __forceinline__ void stream(SoloLds& L, const SoloArgs& A, const St& 
 #pragma unroll
         for (int j = 0; j < kSU; j++) {
             const int64_t i = base + j * kSB + threadIdx.x;
-            const int2 e = i < t1 ? load(i) : make_int2(0, 0);
+            const int2 e = i < tend ? load(i) : make_int2(0, 0);
             u[j] = (uint32_t)e.x;
             v[j] = (uint32_t)e.y;
+            if (late) {
+                st1 |= (u[j] >> 31) << j;
+                u[j] &= 0x7fffffffu;
+            }
         }
 #pragma unroll
         for (int j = 0; j < kSU; j++) {
-            if (base + j * kSB + threadIdx.x < t1) {
+            if (base + j * kSB + threadIdx.x < tend) {
                 if (u[j] < S.V && v[j] < S.V) pend |= 1u << j;
                 else atomicOr(A.err, src == 0 ? 1u : 2u);
             }
@@ -381,6 +405,15 @@ __device__ __forceinline__ void stream(SoloLds& L, const SoloArgs& A, const St& 
                          make_int2((int32_t)u[j], (int32_t)v[j]));
             }
             pend = lost;
+            if (dtile) {
+#pragma unroll
+                for (int j = 0; j < kSU; j++) {
+                    const bool w = pend >> j & 1;
+                    const uint32_t p = lreserve(&L.nr, w);
+                    if (w) sb[p] = make_int2((int32_t)(u[j] | (st1 >> j & 1) << 31), (int32_t)v[j]);
+                }
+                pend = 0;
+            }
             if (!block_any<kSU>(L, pend != 0, ph, bm1, c1, won1, bm2, c2, won2)) break;
         }
     }
@@ -502,6 +535,7 @@ __global__ void __launch_bounds__(kSB) k_solo(SoloArgs A) {
             A.slot_tag[L.slot] = t;
             L.tag = t;
             L.n1 = L.n2 = 0;
+            L.nr = L.nr_snap = 0;
         }
         __syncthreads();
         St S{A.slots + (size_t)L.slot * 2 * V, V, L.tag, (uint32_t)A.ob, mask, 32u * (uint32_t)A.bm_words - 1u,
