@@ -308,12 +308,13 @@ __device__ __forceinline__ void compress_slot(const St& S, uint32_t* gm = nullpt
 
 // Offer a run of edges to the slot.  src 0: the input edge list, ids checked;
 // src 1: a node region's certificate (F part [0, rn1), F' part after it);
-// src 2: the worker's reordered copy of its chunk (sb).  In phase 0 over sb,
-// the edges of a tile that lose a race do not hold the workgroup for a round
-// of their own: they wait at the front of sb, over edges already offered
-// (while that room is certain to hold a whole tile's losses), with their
-// stage in bit 31 of the first id, and are offered again as tiles of their
-// own after the last one (any order of the edges gives maximal forests).
+// src 2: the worker's reordered copy of its chunk (sb).  With a wait buffer
+// wb, the edges of a tile that lose a race do not hold the workgroup for a
+// round of their own: they wait in wb, with their stage in bit 31 of the
+// first id, and are offered again as tiles of their own after the last one
+// (any order of the edges gives maximal forests).  wcap: wb's capacity in
+// edges, or -1 when wb is sb itself (its front, over edges already offered);
+// a tile defers only while the room left is certain to hold all its edges.
 // stage0: where every edge starts (0: F, then F' if F rejects it; 1: F'
 // only).  out: write accepted edges to (off, cap).  stages: compress the slot
 // every cmp_first edges up to 2V, then at 8V (phase 0).  Each thread takes kSU
@@ -322,18 +323,20 @@ __device__ __forceinline__ void compress_slot(const St& S, uint32_t* gm = nullpt
 template <int kSB, int kSU>
 __device__ __forceinline__ void stream(SoloLds& L, const SoloArgs& A, const St& S, uint32_t* bm1, uint32_t* bm2, int src, int64_t t0,
                        int64_t t1, int64_t roff, int64_t rcap, uint32_t rn1, uint32_t rn2, uint32_t stage0, bool out,
-                       bool stages, int64_t off, int64_t cap, int& ph, int2* sb = nullptr) {
+                       bool stages, int64_t off, int64_t cap, int& ph, int2* sb = nullptr,
+                       int2* wb = nullptr, int64_t wcap = -1) {
     constexpr int64_t kST = (int64_t)kSB * kSU;      // edges per tile
     // phase 0: compress after cmp_first edges, then every cmp_first edges
     // up to 2 V, then at 8 V
     int64_t next_cmp = stages ? t0 + A.cmp_first : INT64_MAX;
     auto load = [&](int64_t i) -> int2 {
+        if (i >= t1) return wb[i - t1];                       // the waiting edges
         if (src == 0) return i < A.split ? A.edges[i] : A.edges2[i - A.split];
-        if (src == 2) return sb[i < t1 ? i : i - t1];        // past t1: the waiting edges
+        if (src == 2) return sb[i];
         return A.cert[i < rn1 ? roff + i : roff + rcap - rn2 + (i - rn1)];
     };
-    const bool defer = sb != nullptr && stages;
-    bool late = false;                                   // tiles of waiting edges (indices t1 + k: sb[k])
+    const bool defer = wb != nullptr;
+    bool late = false;                                   // tiles of waiting edges (indices t1 + k: wb[k])
     int64_t tend = t1;
     for (int64_t base = t0;; base += kST) {
         if (base >= tend) {
@@ -343,8 +346,8 @@ __device__ __forceinline__ void stream(SoloLds& L, const SoloArgs& A, const St& 
             tend = t1 + (int64_t)L.nr_snap;
             if (base >= tend) break;
         }
-        // losses of this tile wait in sb if [nr, nr + kST) lies below it
-        const bool dtile = defer && !late && (int64_t)L.nr_snap + kST <= base;
+        // losses of this tile wait in wb if [nr, nr + kST) fits (in sb: below the tile)
+        const bool dtile = defer && !late && (int64_t)L.nr_snap + kST <= (wcap < 0 ? base : wcap);
         if (base >= next_cmp) {
             __syncthreads();
             compress_slot<kSB>(S);
@@ -410,7 +413,7 @@ __device__ __forceinline__ void stream(SoloLds& L, const SoloArgs& A, const St& 
                 for (int j = 0; j < kSU; j++) {
                     const bool w = pend >> j & 1;
                     const uint32_t p = lreserve(&L.nr, w);
-                    if (w) sb[p] = make_int2((int32_t)(u[j] | (st1 >> j & 1) << 31), (int32_t)v[j]);
+                    if (w) wb[p] = make_int2((int32_t)(u[j] | (st1 >> j & 1) << 31), (int32_t)v[j]);
                 }
                 pend = 0;
             }
@@ -558,7 +561,7 @@ __global__ void __launch_bounds__(kSB) k_solo(SoloArgs A) {
                 t0 = 0;
                 src = 2;
             }
-            stream<kSB, kSU>(L, A, S, bm1, bm2, src, t0, t1, 0, 0, 0, 0, 0, true, true, A.off[c], A.cap[c], ph, sb);
+            stream<kSB, kSU>(L, A, S, bm1, bm2, src, t0, t1, 0, 0, 0, 0, 0, true, true, A.off[c], A.cap[c], ph, sb, sb);
         }
         // ---- climb the merge tree while this worker finishes a pair second
         int64_t node = c, step = 1;
@@ -635,6 +638,7 @@ __global__ void __launch_bounds__(kSB) k_solo(SoloArgs A) {
                 L.n2 = A.cnt[2 * i + 1];
                 L.nj1 = A.cnt[2 * j];
                 L.nj2 = A.cnt[2 * j + 1];
+                L.nr = L.nr_snap = 0;
             }
             __syncthreads();
             const int act = L.act;
@@ -684,14 +688,19 @@ __global__ void __launch_bounds__(kSB) k_solo(SoloArgs A) {
             int64_t nj = (int64_t)nj1 + nj2;
             int src = 1;
             int2* sb = nullptr;
+            // the worker's copy buffer is idle in merges: edges that lose a race wait there
+            int2* wb = A.nbk > 0 ? A.sbuf + (size_t)blockIdx.x * (size_t)A.sbuf_stride : nullptr;
+            int64_t wcap = A.sbuf_stride;
             if (A.mbk && A.nbk > 0 && nj <= A.sbuf_stride) {
                 // X_j bucketed like a phase-0 chunk (sb's last reads came before a barrier)
                 sb = A.sbuf + (size_t)blockIdx.x * (size_t)A.sbuf_stride;
                 nj = bucket_into<kSB>(A, nj, RegionLoad{A.cert, offj, capj, (int64_t)nj1, (int64_t)nj2}, 2u, sb, V,
                                       bm2 + A.bm_words);
                 src = 2;
+                wcap = -1;
             }
-            stream<kSB, kSU>(L, A, S, bm1, bm2, src, 0, nj, offj, capj, nj1, nj2, 0, true, false, offi, capi, ph, sb);
+            stream<kSB, kSU>(L, A, S, bm1, bm2, src, 0, nj, offj, capj, nj1, nj2, 0, true, false, offi, capi, ph, sb,
+                             wb, wcap);
             node = i;
             step *= 2;
         }
