@@ -1,8 +1,10 @@
 """The one-workgroup-per-node plan forced onto graphs the size rules would not
-give it: tiny and empty graphs, more chunks than edges, self-loops and
-parallel edges, a star (every hook on one root), a long path, both chunk
-orders (and siblings bucketed in the merges), and a slot whose tags run
-out and is cleared.  Every bridge set must equal the oracle's."""
+give it (the whole-tree LDS plan, which the rules prefer for graphs this
+small, switched off): tiny and empty graphs, more chunks than edges,
+self-loops and parallel edges, a star (every hook on one root), a long path,
+both chunk orders (and siblings bucketed in the merges), tiles full of edges
+that lose hook races, and a slot whose tags run out and is cleared.  Every
+bridge set must equal the oracle's."""
 import sys
 
 import numpy as np
@@ -30,10 +32,21 @@ def ctx(request, monkeypatch):
         pytest.skip("no GPU")
     import paper_2108_07346_amd as br
     monkeypatch.setenv("BR_SOLO", "1")
+    monkeypatch.setenv("BR_LDS", "0")
     c = br.Context(0)
     c.set_final_step(request.param)
+    c.set_profiling(1)
     yield c
     c.close()
+
+
+def find_solo(ctx, e, V, M):
+    """Bridges through the one-workgroup-per-node plan (checked: a graph with
+    edges must not have gone to another plan)."""
+    got = ctx.find(dev(e), V, M)
+    if len(e):
+        assert ctx.profile()["plan_kind"] == 1
+    return got
 
 
 def cases():
@@ -59,7 +72,7 @@ def cases():
 @pytest.mark.parametrize("M", [1, 3, 64, 300])
 def test_forced_solo_edge_cases(ctx, M):
     for name, e, V in cases():
-        got = ctx.find(dev(e), V, M)
+        got = find_solo(ctx, e, V, M)
         assert np.array_equal(got, oracle.bridges(e, V)), (name, M)
     say("M=%d: all cases exact" % M)
 
@@ -79,7 +92,7 @@ def test_forced_solo_both_chunk_orders(ctx, monkeypatch, order):
     for M in (16, 257):
         for top in (0, 2):
             monkeypatch.setenv("BR_SOLO_TOP", str(top))
-            assert np.array_equal(ctx.find(dev(g.edges), g.V, M), want), (order, M, top)
+            assert np.array_equal(find_solo(ctx, g.edges, g.V, M), want), (order, M, top)
 
 
 def test_slot_tags_run_out_and_the_slot_is_cleared(monkeypatch):
@@ -137,4 +150,65 @@ def test_slot_tags_run_out_with_written_bits_maps(monkeypatch):
         if call % 25 == 24:
             assert np.array_equal(got, want), call
             say("call %d exact" % call)
+    ctx.close()
+
+
+def race_cases():
+    """Graphs whose tiles are full of edges that hook one root, so that most of
+    them lose the race for its claim bit, wait, and are offered after the last
+    tile: many copies of a few edges (the copies lose at F, are rejected by it
+    later and lose again at F'), a star whose centre has the largest id, and
+    hubs of high id joined densely to low ids, with a pendant path."""
+    rng = np.random.default_rng(33)
+    out = []
+    base = rng.integers(0, 60, size=(40, 2))
+    dup = np.repeat(base, 1500, axis=0)
+    out.append(("copies of 40 edges", dup[rng.permutation(len(dup))].astype(np.int32), 60))
+    n = 20001
+    star = np.stack([np.full(n - 1, n - 1), rng.permutation(n - 1)], 1)
+    out.append(("star with the centre last", star.astype(np.int32), n))
+    V = 3000
+    bip = np.stack([rng.integers(0, 2000, size=60000), rng.integers(V - 64, V, size=60000)], 1)
+    path = np.stack([np.arange(1999, 2100), np.arange(2000, 2101)], 1)
+    out.append(("hubs over low ids", np.concatenate([bip, path]).astype(np.int32), V))
+    return out
+
+
+def minus_once(e, f):
+    """e without one copy of each edge of f (f: a forest of edges of e)."""
+    key = lambda a: np.minimum(a[:, 0], a[:, 1]).astype(np.int64) << 32 | np.maximum(a[:, 0], a[:, 1])
+    ke, kf = key(e), key(f)
+    order = np.argsort(ke, kind="stable")
+    at = np.searchsorted(ke[order], kf)
+    assert np.all(ke[order][at] == kf)
+    keep = np.ones(len(e), bool)
+    keep[order[at]] = False
+    return e[keep]
+
+
+@pytest.mark.parametrize("variant", [1, 4])
+def test_lost_races_wait_and_are_offered_last(monkeypatch, variant):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_07346_amd as br
+    monkeypatch.setenv("BR_SOLO", "1")
+    monkeypatch.setenv("BR_LDS", "0")
+    monkeypatch.setenv("BR_SOLO_VARIANT", str(variant))
+    ctx = br.Context(0)
+    ctx.set_profiling(1)
+    for name, e, V in race_cases():
+        want = oracle.bridges(e, V)
+        # one chunk: F maximal in G and F' maximal in G - F
+        f1, f2 = ctx.cert_build(dev(e), V, 1)
+        assert ctx.profile()["plan_kind"] == 1
+        f1, f2 = f1.cpu().numpy(), f2.cpu().numpy()
+        assert f1.shape[0] == V - oracle.components(e, V), name
+        assert f2.shape[0] == V - oracle.components(minus_once(e, f1), V), name
+        assert oracle.check_certificate(f1, f2, e, V) == [], name
+        # merges inside the kernel (their losing edges wait in the copy buffer)
+        for M in (2, 8):
+            for top in (1, 3):
+                monkeypatch.setenv("BR_SOLO_TOP", str(top))
+                assert np.array_equal(find_solo(ctx, e, V, M), want), (name, M, top)
+        say("%s: exact" % name)
     ctx.close()
