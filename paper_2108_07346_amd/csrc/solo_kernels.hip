@@ -338,6 +338,16 @@ __device__ __forceinline__ void stream(SoloLds& L, const SoloArgs& A, const St& 
     const bool defer = wb != nullptr;
     bool late = false;                                   // tiles of waiting edges (indices t1 + k: wb[k])
     int64_t tend = t1;
+    // the next tile's edges loaded a round ahead, where the registers allow
+    // (with three edges per thread at 1,024 threads even one edge ahead
+    // spills)
+    constexpr bool kAhead = kSU <= 2;
+    int2 nx[kSU];
+#pragma unroll
+    for (int j = 0; j < kSU; j++) {
+        const int64_t i = t0 + j * kSB + threadIdx.x;
+        nx[j] = (kAhead && i < t1) ? load(i) : make_int2(0, 0);
+    }
     for (int64_t base = t0;; base += kST) {
         if (base >= tend) {
             if (!defer || late) break;
@@ -361,13 +371,17 @@ __device__ __forceinline__ void stream(SoloLds& L, const SoloArgs& A, const St& 
 #pragma unroll
         for (int j = 0; j < kSU; j++) {
             const int64_t i = base + j * kSB + threadIdx.x;
-            const int2 e = i < tend ? load(i) : make_int2(0, 0);
+            const int2 e = (late || !kAhead) ? (i < tend ? load(i) : make_int2(0, 0)) : nx[j];
             u[j] = (uint32_t)e.x;
             v[j] = (uint32_t)e.y;
             if (late) {
                 st1 |= (u[j] >> 31) << j;
                 u[j] &= 0x7fffffffu;
             }
+            // the next fresh tile's edge (the waiting edges are not read ahead:
+            // this round may still add to them)
+            const int64_t in = i + kST;
+            if (kAhead) nx[j] = (!late && in < t1) ? load(in) : make_int2(0, 0);
         }
 #pragma unroll
         for (int j = 0; j < kSU; j++) {
