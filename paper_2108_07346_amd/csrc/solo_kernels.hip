@@ -458,12 +458,23 @@ __device__ __forceinline__ int64_t bucket_into(const SoloArgs& A, int64_t n, Loa
         const uint32_t a = min((uint32_t)e.x, (uint32_t)e.y), b = max((uint32_t)e.x, (uint32_t)e.y);
         return (a >> s1) * nbk2 + (b >> s2);
     };
+    // kBK edges per thread per step, their loads issued together
+    constexpr int kBK = 4;
     for (int b = threadIdx.x; b < nb; b += kSB) cnt[b] = 0u;
     __syncthreads();
-    for (int64_t i = threadIdx.x; i < n; i += kSB) {
-        const int2 e = load(i);
-        if ((uint32_t)e.x < V && (uint32_t)e.y < V) atomicAdd(&cnt[key(e)], 1u);
-        else atomicOr(err, bad);
+    for (int64_t i0 = threadIdx.x; i0 < n; i0 += (int64_t)kBK * kSB) {
+        int2 e[kBK];
+#pragma unroll
+        for (int k = 0; k < kBK; k++) {
+            const int64_t i = i0 + (int64_t)k * kSB;
+            e[k] = i < n ? load(i) : make_int2(0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < kBK; k++) {
+            if (i0 + (int64_t)k * kSB >= n) continue;
+            if ((uint32_t)e[k].x < V && (uint32_t)e[k].y < V) atomicAdd(&cnt[key(e[k])], 1u);
+            else atomicOr(err, bad);
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -476,9 +487,17 @@ __device__ __forceinline__ int64_t bucket_into(const SoloArgs& A, int64_t n, Loa
         total = acc;
     }
     __syncthreads();
-    for (int64_t i = threadIdx.x; i < n; i += kSB) {
-        const int2 e = load(i);
-        if ((uint32_t)e.x < V && (uint32_t)e.y < V) sb[atomicAdd(&cnt[key(e)], 1u)] = e;
+    for (int64_t i0 = threadIdx.x; i0 < n; i0 += (int64_t)kBK * kSB) {
+        int2 e[kBK];
+#pragma unroll
+        for (int k = 0; k < kBK; k++) {
+            const int64_t i = i0 + (int64_t)k * kSB;
+            e[k] = i < n ? load(i) : make_int2(0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < kBK; k++)
+            if (i0 + (int64_t)k * kSB < n && (uint32_t)e[k].x < V && (uint32_t)e[k].y < V)
+                sb[atomicAdd(&cnt[key(e[k])], 1u)] = e[k];
     }
     __syncthreads();        // sb written by the workgroup, read back by it
     return (int64_t)total;
