@@ -608,16 +608,35 @@ __global__ void __launch_bounds__(kSB) k_solo(SoloArgs A) {
             if (step >= A.M || step >= top_step) {
                 // the node's state, fully compressed and untagged, for the
                 // merge rounds above (and, at the top, the final step)
+                // kU vertices per thread at a time, the chains of both forests
+                // followed together (chain c: vertex c / 2, forest c % 2), so
+                // that each step's loads are in flight at once
+                constexpr int kU = 2;
                 uint2* dn = reinterpret_cast<uint2*>(A.dense) + (size_t)(node >> A.top) * V;
-                for (uint32_t x = threadIdx.x; x < V; x += kSB) {
-                    uint32_t r[2];
-                    for (int f = 0; f < 2; f++) {
-                        const uint32_t* q = S.q + (f ? V : 0u);
-                        uint32_t y = x;
-                        for (uint32_t e = S.off(sld(q + y), y); e != 0; e = S.off(sld(q + y), y)) y -= e;
-                        r[f] = x - y;
+                for (uint32_t x0 = 0; x0 < V; x0 += kU * kSB) {
+                    uint32_t y[2 * kU];
+                    uint32_t live = 0;
+#pragma unroll
+                    for (int c = 0; c < 2 * kU; c++) {
+                        y[c] = x0 + (uint32_t)(c / 2) * kSB + threadIdx.x;
+                        if (y[c] < V) live |= 1u << c;
                     }
-                    dn[x] = make_uint2(r[0], r[1]);
+                    while (live) {
+                        uint32_t e[2 * kU];
+#pragma unroll
+                        for (int c = 0; c < 2 * kU; c++)
+                            e[c] = (live >> c & 1) ? S.off(sld(S.q + (c & 1 ? V : 0u) + y[c]), y[c]) : 0u;
+#pragma unroll
+                        for (int c = 0; c < 2 * kU; c++) {
+                            y[c] -= e[c];
+                            if (e[c] == 0) live &= ~(1u << c);
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < kU; k++) {
+                        const uint32_t x = x0 + (uint32_t)k * kSB + threadIdx.x;
+                        if (x < V) dn[x] = make_uint2(x - y[2 * k], x - y[2 * k + 1]);
+                    }
                 }
                 break;
             }
